@@ -1,0 +1,169 @@
+"""Seeded synthetic workloads: grids and binary-black-hole puncture parameters.
+
+This module only draws and lists physical parameters (masses, positions,
+momenta, spins, grid shapes); it holds none of the relaxation arithmetic. It
+serves the tests, the benchmark and catalog users alike.
+
+Conventions (readings; the paper takes its run parameters from its companion
+paper):
+  * total bare mass M = 1, q = m1/m2 >= 1: m1 = q/(1+q), m2 = 1/(1+q);
+  * punctures on the z axis at z = +D/2 (m1) and z = -D/2 (m2), the foci of a
+    SinhSymTP grid with bscale = D/2;
+  * spins S_i = chi_i m_i^2 with |chi_i| uniform and an isotropic direction;
+  * quasi-circular momenta from the Newtonian estimate |P| = mu sqrt(M/D),
+    mu = m1 m2 / M, with P1 = +|P| y_hat and P2 = -|P| y_hat.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SINHSYMTP = 0
+SPHERICAL = 1
+
+
+@dataclass
+class Punctures:
+    m: np.ndarray   # (n,)
+    x: np.ndarray   # (n, 3)
+    P: np.ndarray   # (n, 3)
+    S: np.ndarray   # (n, 3)
+
+    def as_tuple(self):
+        return self.m, self.x, self.P, self.S
+
+
+@dataclass
+class GridSpec:
+    coords: int
+    N0: int
+    N1: int
+    N2: int
+    fd_order: int
+    amax: float = 1.0e6
+    sinhwaa: float = 0.07
+    bscale: float = 1.0
+    rmax: float = 100.0
+
+    @property
+    def shape(self):
+        return (self.N0, self.N1, self.N2)
+
+    @property
+    def n_interior(self) -> int:
+        return self.N0 * self.N1 * self.N2
+
+    def name(self) -> str:
+        c = "SinhSymTP" if self.coords == SINHSYMTP else "Spherical"
+        return f"{c} {self.N0}x{self.N1}x{self.N2} order {self.fd_order}"
+
+
+@dataclass
+class Workload:
+    grid: GridSpec
+    punctures: Punctures
+    eta: float
+    kappa: float = 1.0
+    cfl: float = 0.5
+    n_steps: int = 1000
+    tol: float = 0.0
+    check_every: int = 100
+    label: str = ""
+    extra: dict = field(default_factory=dict)
+
+
+def _pz(m, x, P, S) -> Punctures:
+    return Punctures(np.asarray(m, float), np.asarray(x, float).reshape(-1, 3),
+                     np.asarray(P, float).reshape(-1, 3), np.asarray(S, float).reshape(-1, 3))
+
+
+def equal_mass_small() -> Workload:
+    """32x16x4 SinhSymTP, 8th order: m = 0.5 at z = +-1 (bscale 1), P = (0, +-0.1, 0),
+    no spin; eta = 1, CFL 0.5, 1000 RK4 steps, residual every 100 steps."""
+    g = GridSpec(SINHSYMTP, 32, 16, 4, 8, bscale=1.0)
+    p = _pz([0.5, 0.5], [[0, 0, 1.0], [0, 0, -1.0]], [[0, 0.1, 0], [0, -0.1, 0]],
+            [[0, 0, 0], [0, 0, 0]])
+    return Workload(g, p, eta=1.0, n_steps=1000, tol=0.0, check_every=100,
+                    label="equal-mass 32x16x4 fixed 1000 steps")
+
+
+def brill_lindquist(grid: GridSpec | None = None) -> Workload:
+    """Zero momenta and spins: the source vanishes and u = 0 is exact."""
+    g = grid or GridSpec(SINHSYMTP, 32, 16, 4, 8, bscale=1.0)
+    b = g.bscale
+    p = _pz([0.5, 0.5], [[0, 0, b], [0, 0, -b]], np.zeros((2, 3)), np.zeros((2, 3)))
+    return Workload(g, p, eta=1.0, n_steps=200, label="Brill-Lindquist")
+
+
+# Damping used for the paper-scale solves: a sweep of eta at 128x128x16 (the
+# plain, FP32-bulk and warm-started forms all use the same value).
+ETA_PAPER_SCALE = 48.0
+
+
+def paper_scale(coords: int = SINHSYMTP, fd_order: int = 10) -> Workload:
+    """q = 1, D = 10 (z = +-5), |P| = 0.095 along +-y, S1 = S2 = (0, 0, 0.2); relax to
+    residual 1e-10. SinhSymTP 128x128x16 (bscale 5) or Spherical 128x64x8 (rmax 100)."""
+    if coords == SINHSYMTP:
+        g = GridSpec(SINHSYMTP, 128, 128, 16, fd_order, bscale=5.0)
+    else:
+        g = GridSpec(SPHERICAL, 128, 64, 8, fd_order, rmax=100.0)
+    p = _pz([0.5, 0.5], [[0, 0, 5.0], [0, 0, -5.0]], [[0, 0.095, 0], [0, -0.095, 0]],
+            [[0, 0, 0.2], [0, 0, 0.2]])
+    return Workload(g, p, eta=ETA_PAPER_SCALE, n_steps=2_000_000, tol=1e-10, check_every=100,
+                    label=f"paper-scale {g.name()}")
+
+
+def precision_form(N0: int = 128, N1: int = 128, N2: int = 16) -> Workload:
+    """Equal-mass small-case physics on a larger 8th-order grid, for the FP32-bulk form."""
+    base = equal_mass_small()
+    g = GridSpec(SINHSYMTP, N0, N1, N2, 8, bscale=1.0)
+    return Workload(g, base.punctures, eta=ETA_PAPER_SCALE, n_steps=2_000_000, tol=1e-10,
+                    check_every=100, label=f"precision form {g.name()}")
+
+
+def quasi_circular(q: float, D: float, chi1, chi2) -> Punctures:
+    """Newtonian quasi-circular momenta for mass ratio q >= 1 and separation D."""
+    m1 = q / (1.0 + q)
+    m2 = 1.0 / (1.0 + q)
+    mu = m1 * m2
+    p = mu * np.sqrt(1.0 / D)
+    chi1 = np.asarray(chi1, float)
+    chi2 = np.asarray(chi2, float)
+    return _pz([m1, m2], [[0, 0, D / 2], [0, 0, -D / 2]], [[0, p, 0], [0, -p, 0]],
+               [chi1 * m1 * m1, chi2 * m2 * m2])
+
+
+def _isotropic(rng: np.random.Generator, mag: float) -> np.ndarray:
+    v = rng.normal(size=3)
+    return mag * v / np.linalg.norm(v)
+
+
+CATALOG_SHAPES = ((64, 64, 8), (128, 128, 16), (256, 256, 32))
+
+
+def catalog(n: int = 64, seed: int = 14030, fd_order: int = 10,
+            shapes=CATALOG_SHAPES) -> list[Workload]:
+    """Seed-drawn BBH catalog: q ~ U[1,10], D ~ U[6,20], |chi_i| ~ U[0,0.8] with an
+    isotropic direction, Newtonian quasi-circular momenta, grid shape uniform over
+    ``shapes`` (SinhSymTP with bscale = D/2)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        q = rng.uniform(1.0, 10.0)
+        D = rng.uniform(6.0, 20.0)
+        chi1 = _isotropic(rng, rng.uniform(0.0, 0.8))
+        chi2 = _isotropic(rng, rng.uniform(0.0, 0.8))
+        N0, N1, N2 = shapes[rng.integers(len(shapes))]
+        g = GridSpec(SINHSYMTP, N0, N1, N2, fd_order, bscale=D / 2)
+        w = Workload(g, quasi_circular(q, D, chi1, chi2), eta=ETA_PAPER_SCALE,
+                     n_steps=2_000_000, tol=1e-10, check_every=100, label=f"catalog[{i}]",
+                     extra=dict(q=q, D=D, chi1=chi1, chi2=chi2))
+        out.append(w)
+    return out
+
+
+def random_state(shape, seed: int, scale: float = 1e-3) -> np.ndarray:
+    """Smooth-ish random field for state round trips and linearity checks."""
+    rng = np.random.default_rng(seed)
+    return scale * rng.standard_normal(shape)
