@@ -1,0 +1,222 @@
+"""Benchmark of the hyperbolic-relaxation hot path on one MI355X.
+
+One "step" of this benchmark is one whole solve of the paper-scale workload:
+set the punctures (sources on the device, u = v = 0) and relax with RK4 until
+the residual L2 norm drops below 1e-10, residual checked every 100 steps. The
+workload is the paper's production configuration: SinhSymTP 128x128x16,
+10th-order finite differences, equal-mass punctures at z = +-5 with momenta
++-0.095 y_hat and spins (0,0,0.2), synthetic parameters (no dataset involved).
+
+Printed: one JSON line. ``value`` is grid-point RHS updates per second of the
+FP64 form over the timed solves (N_interior x 4 RK stages x RK4 steps / wall
+time). The FP32-bulk + FP64-finish form and the wall time to residual 1e-10
+are reported beside it, with the stage-kernel roofline and the CPU oracle on
+the host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = ("grid-pt RHS updates/sec (FP64 vs FP32+FP64 finish); wall time to residual 1e-10")
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def stage_bytes_per_point(itemsize: int):
+    """Algorithmic bytes per point of the four fused stage kernels.
+
+    interior point: stage 1 reads u, v, psi, S_src and writes Y2(u,v), acc(u,v);
+    stages 2, 3 read Y(u,v), y_n(u,v), acc(u,v), psi, S_src and write Y(u,v),
+    acc(u,v); stage 4 reads Y4(u,v), acc(u,v), psi, S_src and writes y_{n+1}(u,v).
+    outer point: the same without psi and S_src.
+    """
+    interior = [8, 12, 12, 8]
+    outer = [6, 10, 10, 6]
+    return [itemsize * n for n in interior], [itemsize * n for n in outer]
+
+
+def stage_algorithmic_bytes(spec, itemsize: int):
+    """Per-launch algorithmic bytes of each stage kernel (grid functions plus the
+    2D coefficient tables, each read once)."""
+    N0, N1, N2 = spec.shape
+    ng = spec.fd_order // 2
+    nint = N0 * N1 * N2
+    nout = ng * N1 * N2
+    bi, bo = stage_bytes_per_point(itemsize)
+    tables = itemsize * (6 * N0 * N1 + 3 * ng * N1)
+    return [nint * bi[s] + nout * bo[s] + tables for s in range(4)]
+
+
+def run_solve(hr, g, w, precision):
+    g.set_punctures(*w.punctures.as_tuple())
+    res = g.relax(w.eta, w.kappa, 0.0, w.n_steps, w.tol, check_every=w.check_every,
+                  precision=precision)
+    return res
+
+
+def timed_solves(hr, torch, g, w, precision, steps, warmup, label):
+    for i in range(warmup):
+        r = run_solve(hr, g, w, precision)
+        log(f"{label} warmup {i}: status {r.status} steps {r.steps_taken} residual {r.residual:.3e}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for i in range(steps):
+        r = run_solve(hr, g, w, precision)
+        results.append(r)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i, r in enumerate(results):
+        log(f"{label} solve {i}: status {r.status} rk4 steps {r.steps_taken} "
+            f"(fp32 {r.fp32_steps}) residual {r.residual:.3e}")
+        if r.status != hr.OK:
+            raise RuntimeError(f"{label} solve did not converge: status {r.status}")
+    return results, t1 - t0
+
+
+def cpu_baseline(w, budget_s: float):
+    """The oracle as it is, on the host cores, on a bounded sample of the same
+    workload: RK4 steps of the same grid from the same initial state."""
+    import oracle
+
+    oracle.build()
+    spec = w.grid
+    og = oracle.OracleGrid(spec.coords, spec.N0, spec.N1, spec.N2, spec.fd_order,
+                           amax=spec.amax, sinhwaa=spec.sinhwaa, bscale=spec.bscale,
+                           rmax=spec.rmax)
+    og.set_punctures(*w.punctures.as_tuple())
+    dt = og.suggest_dt(w.cfl)
+    t0 = time.perf_counter()
+    og.rk4_steps(w.eta, w.kappa, dt, 2)
+    per_step = (time.perf_counter() - t0) / 2
+    n = max(2, int(budget_s / max(per_step, 1e-6)))
+    t0 = time.perf_counter()
+    og.rk4_steps(w.eta, w.kappa, dt, n)
+    el = time.perf_counter() - t0
+    upd = spec.n_interior * 4 * n / el
+    return {"value": upd, "unit": "grid-pt RHS updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{n} RK4 steps of {spec.name()} from rest ({el:.1f} s); "
+                      f"time to residual 1e-10 extrapolates as steps_to_tol / "
+                      f"{n / el:.2f} steps/s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed solves")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the relaxation of "
+              "one grid is not sharded across GPUs in this build.", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_2501_14030_amd as hr
+    from paper_2501_14030_amd import workloads
+
+    hr.load_library()
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 2
+    torch.cuda.set_device(0)
+    w = workloads.paper_scale(workloads.SINHSYMTP, 10)
+    spec = w.grid
+    log(f"workload {w.label}: eta {w.eta} cfl {w.cfl} tol {w.tol} check every {w.check_every}")
+    g = hr.grid_create(spec.coords, spec.N0, spec.N1, spec.N2, spec.fd_order,
+                       params=hr.default_params(amax=spec.amax, sinhwaa=spec.sinhwaa,
+                                                bscale=spec.bscale, rmax=spec.rmax))
+    res64, t64 = timed_solves(hr, torch, g, w, hr.FP64, args.steps, args.warmup, "fp64")
+    steps64 = res64[-1].steps_taken
+    upd64 = sum(spec.n_interior * 4 * r.steps_taken for r in res64) / t64
+    u64 = g.get_u()
+    out = {
+        "metric": METRIC,
+        "value": upd64,
+        "unit": "grid-pt RHS updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t64 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "paper-scale single solve: SinhSymTP 128x128x16, 10th-order FD, "
+                        "q=1 punctures at z=+-5, |P|=0.095 along +-y, S=(0,0,0.2), relax from "
+                        "u=v=0 to residual L2 < 1e-10 (one step = one whole solve)",
+            "grid": list(spec.shape), "fd_order": spec.fd_order, "eta": w.eta, "cfl": w.cfl,
+            "tol": w.tol, "check_every": w.check_every,
+        },
+        "time_to_residual_s": t64 / args.steps,
+        "rk4_steps_to_tol": steps64,
+        "final_residual": res64[-1].residual,
+    }
+    if not args.no_mixed:
+        g.set_fp32_switch(1e-6, 2, 0)
+        res32, t32 = timed_solves(hr, torch, g, w, hr.FP32_FP64FINISH, args.steps, 0, "fp32+fp64")
+        u32 = g.get_u()
+        out["mixed"] = {
+            "precision": "FP32 bulk + FP64 finish (residual and stop test FP64)",
+            "value": sum(spec.n_interior * 4 * r.steps_taken for r in res32) / t32,
+            "time_to_residual_s": t32 / args.steps,
+            "rk4_steps_to_tol": res32[-1].steps_taken,
+            "fp32_steps": res32[-1].fp32_steps,
+            "final_residual": res32[-1].residual,
+            "max_rel_diff_u_vs_fp64": float(np.abs(u32 - u64).max() / np.abs(u64).max()),
+            "speedup_time_to_residual": (t64 / args.steps) / (t32 / args.steps),
+        }
+    # roofline of the dominant kernel (the fused RK4 stage kernel), timed with HIP
+    # events on the grid's stream
+    g.set_punctures(*w.punctures.as_tuple())
+    nsteps_t = 50
+    us = g.time_stage_kernels(w.eta, w.kappa, 0.0, nsteps_t, hr.FP64)
+    byts = stage_algorithmic_bytes(spec, 8)
+    gbs = [byts[s] / (us[s] * 1e-6) / 1e9 for s in range(4)]
+    agg = sum(byts) / (sum(us[:4]) * 1e-6) / 1e9
+    out["roofline"] = {
+        "bound": "hbm", "achieved": agg, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": agg / HBM_PEAK_GBS, "traffic": None,
+        "kernel": "k_stage<double,5,s> (fused RHS+BC+RK4 stage), mean over stages 1-4",
+        "avg_launch_us": [float(x) for x in us[:4]],
+        "algorithmic_bytes_per_launch": byts,
+        "per_stage_GBs": gbs,
+    }
+    us32 = g.time_stage_kernels(w.eta, w.kappa, 0.0, nsteps_t, hr.FP32)
+    byts32 = stage_algorithmic_bytes(spec, 4)
+    out["roofline_fp32"] = {
+        "achieved": sum(byts32) / (sum(us32[:4]) * 1e-6) / 1e9, "unit": "GB/s",
+        "avg_launch_us": [float(x) for x in us32[:4]],
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cb = cpu_baseline(w, args.cpu_seconds)
+        cb["time_to_residual_s_extrapolated"] = steps64 * spec.n_interior * 4 / cb["value"]
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+    g.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

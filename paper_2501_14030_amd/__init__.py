@@ -1,0 +1,308 @@
+"""MI355X hyperbolic-relaxation solver for binary-black-hole puncture data.
+
+Thin ctypes binding over the C ABI declared in ``include/hrelax.h``; every
+step of the relaxation runs in the HIP kernels of ``libhrelax.so``. PyTorch
+only provides the device workspace and the HIP stream. The module-level
+functions carry the ABI's names (``grid_create``, ``set_punctures``,
+``relax``, ``get_u``, ``residual_l2``, ...).
+
+The library must be built (``python -m paper_2501_14030_amd.build``); there is
+no fallback implementation, and loading fails loudly when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhrelax.so")
+
+SINHSYMTP = 0
+SPHERICAL = 1
+
+FP64 = 0
+FP32 = 1
+FP32_FP64FINISH = 2
+
+OK = 0
+EINVAL = -1
+ENOMEM = -2
+EDEVICE = -3
+ENOTCONV = -4
+ENONFINITE = -5
+ESTATE = -6
+
+_STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE",
+                 ENOTCONV: "ENOTCONV", ENONFINITE: "ENONFINITE", ESTATE: "ESTATE"}
+
+
+class HRError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class GridParams(ctypes.Structure):
+    _fields_ = [("amax", ctypes.c_double), ("sinhwaa", ctypes.c_double),
+                ("bscale", ctypes.c_double), ("rmax", ctypes.c_double),
+                ("cfl", ctypes.c_double)]
+
+
+class RelaxReport(ctypes.Structure):
+    _fields_ = [("steps_taken", ctypes.c_long), ("fp32_steps", ctypes.c_long),
+                ("residual", ctypes.c_double), ("dt_used", ctypes.c_double),
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_long),
+                ("n_history", ctypes.c_long)]
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_lib = None
+
+# Every symbol the header declares, with (restype, argtypes).
+_SIGNATURES = {
+    "hr_default_params": (None, [ctypes.POINTER(GridParams)]),
+    "hr_grid_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, ctypes.POINTER(GridParams),
+                                      ctypes.POINTER(ctypes.c_void_p)]),
+    "hr_grid_destroy": (None, [ctypes.c_void_p]),
+    "hr_grid_sizes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t),
+                                     ctypes.POINTER(ctypes.c_size_t)]),
+    "hr_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p]),
+    "hr_grid_bind": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                    ctypes.c_void_p]),
+    "hr_set_punctures": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp, _dp]),
+    "hr_relax": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_long, ctypes.c_double, ctypes.c_int,
+                                ctypes.c_int, ctypes.POINTER(RelaxReport)]),
+    "hr_set_fp32_switch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int,
+                                          ctypes.c_long]),
+    "hr_get_u": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_size_t]),
+    "hr_get_v": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_size_t]),
+    "hr_set_u": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_size_t]),
+    "hr_set_v": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_size_t]),
+    "hr_residual_l2": (ctypes.c_int, [ctypes.c_void_p, _dp]),
+    "hr_suggest_dt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, _dp]),
+    "hr_time_stage_kernels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_long, ctypes.c_int, _dp]),
+    "hr_last_error": (ctypes.c_char_p, []),
+}
+
+
+def _hip_runtimes_mapped() -> list:
+    try:
+        with open("/proc/self/maps") as f:
+            return sorted({ln.split()[-1] for ln in f if "libamdhip64" in ln})
+    except OSError:
+        return []
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads ``libhrelax.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"HIP library {path} is missing: build it with "
+            "`python -m paper_2501_14030_amd.build` (there is no fallback path)")
+    # torch owns the device memory and streams; its HIP runtime must be the one
+    # the library binds to, so it is loaded first (same SONAME, so the library's
+    # dependency resolves to the copy already in the process).
+    import torch  # noqa: F401
+    L = ctypes.CDLL(path)
+    runtimes = _hip_runtimes_mapped()
+    if len(runtimes) > 1:
+        raise RuntimeError(f"more than one HIP runtime is loaded in this process: {runtimes}")
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str) -> int:
+    if status != OK:
+        raise HRError(status, where, load_library().hr_last_error().decode())
+    return status
+
+
+def default_params(**overrides) -> GridParams:
+    p = GridParams()
+    load_library().hr_default_params(ctypes.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, float(v))
+    return p
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+@dataclass
+class RelaxResult:
+    status: int
+    steps_taken: int
+    fp32_steps: int
+    residual: float
+    dt: float
+    history: np.ndarray
+
+
+class Grid:
+    """A relaxation grid bound to torch-owned device memory and a HIP stream."""
+
+    def __init__(self, coords: int, N0: int, N1: int, N2: int, fd_order: int,
+                 params: GridParams | None = None, device=None, stream=None):
+        import torch  # device memory and streams only
+
+        L = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the relaxation runs only on the HIP device")
+        h = ctypes.c_void_p()
+        pp = ctypes.byref(params) if params is not None else None
+        _check(L.hr_grid_create(int(coords), N0, N1, N2, fd_order, pp, ctypes.byref(h)),
+               "hr_grid_create")
+        self._h = h
+        self.coords = coords
+        self.N = (N0, N1, N2)
+        self.fd_order = fd_order
+        self.NG = fd_order // 2
+        nint = ctypes.c_size_t()
+        next_ = ctypes.c_size_t()
+        _check(L.hr_grid_sizes(h, ctypes.byref(nint), ctypes.byref(next_)), "hr_grid_sizes")
+        self.n_interior = nint.value
+        self.n_extended = next_.value
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        nbytes = L.hr_workspace_bytes(h)
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = self._ws.data_ptr()
+        aligned = (ptr + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        with torch.cuda.device(self.device):
+            _check(L.hr_grid_bind(h, ctypes.c_void_p(aligned), nbytes,
+                                  ctypes.c_void_p(self.stream.cuda_stream)), "hr_grid_bind")
+
+    def close(self) -> None:
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.hr_grid_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_punctures(self, m, x, P, S) -> None:
+        m = _f64(m)
+        n = len(m)
+        x = _f64(x).reshape(n, 3)
+        P = _f64(P).reshape(n, 3)
+        S = _f64(S).reshape(n, 3)
+        _check(load_library().hr_set_punctures(self._h, n, m.ctypes.data_as(_dp),
+                                               x.ctypes.data_as(_dp), P.ctypes.data_as(_dp),
+                                               S.ctypes.data_as(_dp)), "hr_set_punctures")
+
+    def relax(self, eta: float, c: float = 1.0, dt: float = 0.0, n_steps: int = 1000,
+              tol: float = 0.0, check_every: int = 100, precision: int = FP64,
+              raise_on_error: bool = True) -> RelaxResult:
+        cap = max(1, int(n_steps) // max(1, int(check_every)) + 2)
+        hist = np.zeros(cap)
+        rep = RelaxReport()
+        rep.history = hist.ctypes.data_as(_dp)
+        rep.history_cap = cap
+        st = load_library().hr_relax(self._h, float(eta), float(c), float(dt), int(n_steps),
+                                     float(tol), int(check_every), int(precision),
+                                     ctypes.byref(rep))
+        if st not in (OK, ENOTCONV, ENONFINITE) or (raise_on_error and st == ENONFINITE):
+            _check(st, "hr_relax")
+        return RelaxResult(st, rep.steps_taken, rep.fp32_steps, rep.residual, rep.dt_used,
+                           hist[:min(rep.n_history, cap)].copy())
+
+    def set_fp32_switch(self, switch_residual: float = 1e-6, stall_checks: int = 2,
+                        max_fp32_steps: int = 0) -> None:
+        _check(load_library().hr_set_fp32_switch(self._h, float(switch_residual),
+                                                 int(stall_checks), int(max_fp32_steps)),
+               "hr_set_fp32_switch")
+
+    def _get(self, fn, extended: bool) -> np.ndarray:
+        n = self.n_extended if extended else self.n_interior
+        out = np.zeros(n)
+        _check(fn(self._h, out.ctypes.data_as(_dp), n), fn.__name__)
+        N0, N1, N2 = self.N
+        return out.reshape(N2, N1, N0 + self.NG if extended else N0)
+
+    def get_u(self, extended: bool = False) -> np.ndarray:
+        return self._get(load_library().hr_get_u, extended)
+
+    def get_v(self, extended: bool = False) -> np.ndarray:
+        return self._get(load_library().hr_get_v, extended)
+
+    def _set(self, fn, a) -> None:
+        a = _f64(a).reshape(-1)
+        _check(fn(self._h, a.ctypes.data_as(_dp), a.size), fn.__name__)
+
+    def set_u(self, a) -> None:
+        self._set(load_library().hr_set_u, a)
+
+    def set_v(self, a) -> None:
+        self._set(load_library().hr_set_v, a)
+
+    def residual_l2(self) -> float:
+        out = ctypes.c_double()
+        _check(load_library().hr_residual_l2(self._h, ctypes.byref(out)), "hr_residual_l2")
+        return out.value
+
+    def time_stage_kernels(self, eta: float, c: float = 1.0, dt: float = 0.0, n_steps: int = 50,
+                           precision: int = FP64) -> np.ndarray:
+        """Mean stage-kernel durations (us) for stages 1..4 and their mean, timed with
+        HIP events on the grid's stream. Advances the state by n_steps."""
+        out = np.zeros(5)
+        _check(load_library().hr_time_stage_kernels(self._h, float(eta), float(c), float(dt),
+                                                    int(n_steps), int(precision),
+                                                    out.ctypes.data_as(_dp)),
+               "hr_time_stage_kernels")
+        return out
+
+    def suggest_dt(self, cfl: float = 0.5) -> float:
+        out = ctypes.c_double()
+        _check(load_library().hr_suggest_dt(self._h, float(cfl), ctypes.byref(out)),
+               "hr_suggest_dt")
+        return out.value
+
+
+# Module-level functions named after the C ABI entry points.
+def grid_create(coords: int, N0: int, N1: int, N2: int, fd_order: int,
+                params: GridParams | None = None, **kw) -> Grid:
+    return Grid(coords, N0, N1, N2, fd_order, params=params, **kw)
+
+
+def set_punctures(grid: Grid, m, x, P, S) -> None:
+    grid.set_punctures(m, x, P, S)
+
+
+def relax(grid: Grid, eta: float, c: float = 1.0, dt: float = 0.0, n_steps: int = 1000,
+          tol: float = 0.0, **kw) -> RelaxResult:
+    return grid.relax(eta, c, dt, n_steps, tol, **kw)
+
+
+def get_u(grid: Grid, extended: bool = False) -> np.ndarray:
+    return grid.get_u(extended)
+
+
+def residual_l2(grid: Grid) -> float:
+    return grid.residual_l2()
+
+
+__all__ = ["Grid", "GridParams", "RelaxResult", "HRError", "grid_create", "set_punctures",
+           "relax", "get_u", "residual_l2", "load_library", "default_params",
+           "SINHSYMTP", "SPHERICAL", "FP64", "FP32", "FP32_FP64FINISH"]

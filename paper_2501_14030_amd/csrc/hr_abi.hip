@@ -1,0 +1,600 @@
+// C ABI of the hyperbolic-relaxation library: grid handles, workspace
+// binding, puncture setup, the relaxation driver and state access.
+//
+// The driver follows the paper's Algorithm 1: the host sets up coordinates,
+// reference-metric factors and boundary data once; the device runs every
+// RK stage (RHS + BC + RK fused into one kernel per stage); the residual and
+// its grid L2 norm are computed on the device every check_every steps and
+// read back as one double, which is the only host-device synchronisation of
+// the loop; the host performs the stop test.
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "hr_internal.h"
+
+namespace hr {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+namespace {
+
+hr_status fail(hr_status s, const std::string& msg) {
+  set_error(msg);
+  return s;
+}
+
+hr_status hip_fail(hipError_t e, const char* what) {
+  return fail(HR_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HR_HIP(call)                                   \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);  \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Walks the workspace layout; with base != nullptr also assigns pointers.
+size_t layout(hr_grid* g, char* base) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off = align_up(off + bytes, kAlign);
+    return p;
+  };
+  const size_t G = g->G;
+  const int n2d = g->d.N0 * g->d.N1, o2d = g->d.NG * g->d.N1, e2d = g->d.P0 * g->d.N1;
+  double** d64[] = {&g->f64.un, &g->f64.vn, &g->f64.ua, &g->f64.va, &g->f64.ub,
+                    &g->f64.vb, &g->f64.au, &g->f64.av, &g->f64.psi, &g->f64.ssrc};
+  for (double** p : d64) *p = (double*)take(G * sizeof(double));
+  float** d32[] = {&g->f32.un, &g->f32.vn, &g->f32.ua, &g->f32.va, &g->f32.ub,
+                   &g->f32.vb, &g->f32.au, &g->f32.av, &g->f32.psi, &g->f32.ssrc};
+  for (float** p : d32) *p = (float*)take(G * sizeof(float));
+  g->f64.fac = (double*)take(6 * (size_t)n2d * sizeof(double));
+  g->f32.fac = (float*)take(6 * (size_t)n2d * sizeof(float));
+  g->f64.ofac = (double*)take(3 * (size_t)o2d * sizeof(double));
+  g->f32.ofac = (float*)take(3 * (size_t)o2d * sizeof(float));
+  g->rho = (double*)take(e2d * sizeof(double));
+  g->zc = (double*)take(e2d * sizeof(double));
+  g->cphi = (double*)take(g->d.N2 * sizeof(double));
+  g->sphi = (double*)take(g->d.N2 * sizeof(double));
+  g->partial = (double*)take((size_t)g->nblk_res * sizeof(double));
+  g->result = (double*)take(4 * sizeof(double));
+  return off;
+}
+
+// Uploads the wave-speed-dependent planes for scale kappa.
+hr_status load_kappa(hr_grid* g, double kappa) {
+  if (g->kappa_loaded == kappa) return HR_OK;
+  const Dims& d = g->d;
+  const int n2d = d.N0 * d.N1, o2d = d.NG * d.N1;
+  std::vector<double> fac(6 * (size_t)n2d), ofac(3 * (size_t)o2d);
+  std::memcpy(fac.data(), g->tab.alpha.data(), 5 * (size_t)n2d * sizeof(double));
+  for (int k = 0; k < n2d; ++k) {
+    const double c = kappa * g->tab.crat[k];
+    fac[5 * (size_t)n2d + k] = c * c;
+  }
+  for (int k = 0; k < o2d; ++k) {
+    ofac[k] = kappa * g->tab.ocrat[k];
+    ofac[o2d + k] = g->tab.orinv[k];
+    ofac[2 * (size_t)o2d + k] = g->tab.oq[k];
+  }
+  std::vector<float> fac32(fac.begin(), fac.end()), ofac32(ofac.begin(), ofac.end());
+  HR_HIP(hipMemcpyAsync(g->f64.fac, fac.data(), fac.size() * sizeof(double),
+                        hipMemcpyHostToDevice, g->stream));
+  HR_HIP(hipMemcpyAsync(g->f32.fac, fac32.data(), fac32.size() * sizeof(float),
+                        hipMemcpyHostToDevice, g->stream));
+  HR_HIP(hipMemcpyAsync(g->f64.ofac, ofac.data(), ofac.size() * sizeof(double),
+                        hipMemcpyHostToDevice, g->stream));
+  HR_HIP(hipMemcpyAsync(g->f32.ofac, ofac32.data(), ofac32.size() * sizeof(float),
+                        hipMemcpyHostToDevice, g->stream));
+  HR_HIP(hipStreamSynchronize(g->stream));
+  g->kappa_loaded = kappa;
+  return HR_OK;
+}
+
+template <typename T>
+StageArgs<T> stage_args(const hr_grid* g, const Fields<T>& F, int stage, T eta, T dt) {
+  StageArgs<T> a{};
+  a.d = g->d;
+  a.psi = F.psi;
+  a.ssrc = F.ssrc;
+  a.fac = F.fac;
+  a.ofac = F.ofac;
+  a.eta = eta;
+  a.un = F.un;
+  a.vn = F.vn;
+  a.au = F.au;
+  a.av = F.av;
+  switch (stage) {
+    case 1:  // Y1 = y_n -> A
+      a.uin = F.un; a.vin = F.vn; a.uout = F.ua; a.vout = F.va;
+      a.cy = dt / (T)2; a.ca = dt / (T)6;
+      break;
+    case 2:  // A -> B
+      a.uin = F.ua; a.vin = F.va; a.uout = F.ub; a.vout = F.vb;
+      a.cy = dt / (T)2; a.ca = dt / (T)3;
+      break;
+    case 3:  // B -> A
+      a.uin = F.ub; a.vin = F.vb; a.uout = F.ua; a.vout = F.va;
+      a.cy = dt; a.ca = dt / (T)3;
+      break;
+    default:  // A, acc -> y_{n+1}
+      a.uin = F.ua; a.vin = F.va; a.uout = F.un; a.vout = F.vn;
+      a.cy = dt; a.ca = dt / (T)6;
+      break;
+  }
+  return a;
+}
+
+template <typename T>
+hr_status launch_steps(hr_grid* g, const Fields<T>& F, T eta, T dt, long nsteps) {
+  const StageArgs<T> s1 = stage_args<T>(g, F, 1, eta, dt);
+  const StageArgs<T> s2 = stage_args<T>(g, F, 2, eta, dt);
+  const StageArgs<T> s3 = stage_args<T>(g, F, 3, eta, dt);
+  const StageArgs<T> s4 = stage_args<T>(g, F, 4, eta, dt);
+  for (long n = 0; n < nsteps; ++n) {
+    HR_HIP(launch_stage(g->fd_order, 1, s1, g->stream));
+    HR_HIP(launch_stage(g->fd_order, 2, s2, g->stream));
+    HR_HIP(launch_stage(g->fd_order, 3, s3, g->stream));
+    HR_HIP(launch_stage(g->fd_order, 4, s4, g->stream));
+  }
+  return HR_OK;
+}
+
+// Enqueues the residual of the given state and reads it back (synchronous).
+hr_status residual_of(hr_grid* g, const void* u, bool fp32, double* out) {
+  ResidualArgs r{};
+  r.d = g->d;
+  r.u = u;
+  r.psi = g->f64.psi;
+  r.ssrc = g->f64.ssrc;
+  r.fac = g->f64.fac;
+  r.partial = g->partial;
+  HR_HIP(launch_residual(g->fd_order, fp32, r, g->nblk_res, g->stream));
+  HR_HIP(launch_finalize(g->partial, g->nblk_res, g->d.nint, g->result, g->stream));
+  HR_HIP(hipMemcpyAsync(g->host_res, g->result, sizeof(double), hipMemcpyDeviceToHost,
+                        g->stream));
+  HR_HIP(hipStreamSynchronize(g->stream));
+  *out = g->host_res[0];
+  return HR_OK;
+}
+
+int ext_count(const hr_grid* g) { return g->d.P0 * g->d.N1 * g->d.N2; }
+
+hr_status check_ready(const hr_grid* g, bool need_sources) {
+  if (!g) return fail(HR_EINVAL, "null grid handle");
+  if (!g->bound) return fail(HR_ESTATE, "grid has no bound workspace (call hr_grid_bind)");
+  if (need_sources && !g->have_sources)
+    return fail(HR_ESTATE, "punctures not set (call hr_set_punctures)");
+  return HR_OK;
+}
+
+hr_status get_field(const hr_grid* g, const double* dev, double* host, size_t n) {
+  hr_status st = check_ready(g, false);
+  if (st != HR_OK) return st;
+  if (!host) return fail(HR_EINVAL, "null output pointer");
+  const size_t next = ext_count(g), nint = g->d.nint;
+  if (n != next && n != nint)
+    return fail(HR_EINVAL, "n must equal the interior or the extended point count");
+  std::vector<double> tmp(next);
+  HR_HIP(hipMemcpyAsync(tmp.data(), dev, next * sizeof(double), hipMemcpyDeviceToHost,
+                        g->stream));
+  HR_HIP(hipStreamSynchronize(g->stream));
+  if (n == next) {
+    std::memcpy(host, tmp.data(), next * sizeof(double));
+  } else {
+    const Dims& d = g->d;
+    for (int i2 = 0; i2 < d.N2; ++i2)
+      for (int i1 = 0; i1 < d.N1; ++i1)
+        std::memcpy(host + (size_t)d.N0 * (i1 + (size_t)d.N1 * i2),
+                    tmp.data() + (size_t)d.P0 * (i1 + (size_t)d.N1 * i2),
+                    d.N0 * sizeof(double));
+  }
+  return HR_OK;
+}
+
+hr_status set_field(hr_grid* g, double* dev, const double* host, size_t n) {
+  hr_status st = check_ready(g, false);
+  if (st != HR_OK) return st;
+  if (!host) return fail(HR_EINVAL, "null input pointer");
+  const size_t next = ext_count(g), nint = g->d.nint;
+  if (n != next && n != nint)
+    return fail(HR_EINVAL, "n must equal the interior or the extended point count");
+  std::vector<double> tmp(next);
+  const Dims& d = g->d;
+  if (n == next) {
+    std::memcpy(tmp.data(), host, next * sizeof(double));
+  } else {
+    for (int i2 = 0; i2 < d.N2; ++i2)
+      for (int i1 = 0; i1 < d.N1; ++i1) {
+        const size_t ri = (size_t)d.N0 * (i1 + (size_t)d.N1 * i2);
+        const size_t re = (size_t)d.P0 * (i1 + (size_t)d.N1 * i2);
+        std::memcpy(tmp.data() + re, host + ri, d.N0 * sizeof(double));
+        const double flast = host[ri + d.N0 - 1];
+        const double rlast = g->tab.rcart[(d.N0 - 1) + (size_t)d.P0 * i1];
+        for (int q = 0; q < d.NG; ++q) {
+          const double ro = g->tab.rcart[(d.N0 + q) + (size_t)d.P0 * i1];
+          tmp[re + d.N0 + q] = flast * rlast / ro;
+        }
+      }
+  }
+  for (double x : tmp)
+    if (!std::isfinite(x)) return fail(HR_EINVAL, "non-finite value in input");
+  HR_HIP(hipMemcpyAsync(dev, tmp.data(), next * sizeof(double), hipMemcpyHostToDevice,
+                        g->stream));
+  HR_HIP(hipStreamSynchronize(g->stream));
+  return HR_OK;
+}
+
+// One precision phase of the relaxation: runs until the stop rule fires.
+// Returns the number of steps done in *done; *why: 0 = step cap, 1 = tol,
+// 2 = non-finite, 3 = FP32 switch rule.
+template <typename T>
+hr_status run_phase(hr_grid* g, const Fields<T>& F, bool fp32, double eta, double dt,
+                    long max_steps, double tol, int K, bool switch_rule,
+                    hr_relax_report* rep, long* done, int* why, double* last_res) {
+  long s = 0;
+  int stall = 0;
+  double best = INFINITY;
+  *why = 0;
+  while (s < max_steps) {
+    const long chunk = std::min<long>(K, max_steps - s);
+    hr_status st = launch_steps<T>(g, F, (T)eta, (T)dt, chunk);
+    if (st != HR_OK) return st;
+    s += chunk;
+    if (chunk == K) {
+      // a check after every K steps of this phase; a shorter tail is unchecked
+      double res = 0.0;
+      st = residual_of(g, F.un, fp32, &res);
+      if (st != HR_OK) return st;
+      *last_res = res;
+      if (rep) {
+        if (rep->history && rep->n_history < rep->history_cap)
+          rep->history[rep->n_history] = res;
+        rep->n_history++;
+      }
+      if (!std::isfinite(res)) {
+        *why = 2;
+        break;
+      }
+      if (tol > 0 && res < tol) {
+        *why = 1;
+        break;
+      }
+      if (switch_rule) {
+        if (res < best) {
+          best = res;
+          stall = 0;
+        } else {
+          ++stall;
+        }
+        if (res < g->sw_residual || stall >= g->sw_stall ||
+            (g->sw_max_steps > 0 && s >= g->sw_max_steps)) {
+          *why = 3;
+          break;
+        }
+      }
+    }
+  }
+  *done = s;
+  return HR_OK;
+}
+
+}  // namespace
+}  // namespace hr
+
+using namespace hr;
+
+extern "C" {
+
+void hr_default_params(hr_grid_params* p) {
+  if (!p) return;
+  p->amax = 1.0e6;
+  p->sinhwaa = 0.07;
+  p->bscale = 1.0;
+  p->rmax = 100.0;
+  p->cfl = 0.5;
+}
+
+hr_status hr_grid_create(hr_coords coords, int N0, int N1, int N2, int fd_order,
+                         const hr_grid_params* p, hr_grid** out) {
+  if (!out) return fail(HR_EINVAL, "null output handle pointer");
+  *out = nullptr;
+  if (coords != HR_SINHSYMTP && coords != HR_SPHERICAL)
+    return fail(HR_EINVAL, "unknown coordinate system");
+  if (fd_order != 2 && fd_order != 4 && fd_order != 6 && fd_order != 8 && fd_order != 10)
+    return fail(HR_EINVAL, "fd_order must be 2, 4, 6, 8 or 10");
+  const int NG = fd_order / 2;
+  if (N0 < NG || N0 < 2 || N1 < NG || N2 < 2 || (N2 % 2) != 0)
+    return fail(HR_EINVAL, "need N0 >= max(NG,2), N1 >= NG, N2 even and >= 2");
+  const long long next = (long long)(N0 + NG) * N1 * N2;
+  if (next >= (1LL << 31) - 4096) return fail(HR_EINVAL, "grid too large");
+  hr_grid_params prm;
+  hr_default_params(&prm);
+  if (p) prm = *p;
+  if (coords == HR_SINHSYMTP && !(prm.amax > 0 && prm.sinhwaa > 0 && prm.bscale > 0))
+    return fail(HR_EINVAL, "SinhSymTP needs amax, sinhwaa, bscale > 0");
+  if (coords == HR_SPHERICAL && !(prm.rmax > 0)) return fail(HR_EINVAL, "rmax must be > 0");
+  if (!(prm.cfl > 0)) return fail(HR_EINVAL, "cfl must be > 0");
+  hr_grid* g = new (std::nothrow) hr_grid();
+  if (!g) return fail(HR_ENOMEM, "host allocation failed");
+  g->coords = coords;
+  g->fd_order = fd_order;
+  g->prm = prm;
+  g->d.N0 = N0;
+  g->d.N1 = N1;
+  g->d.N2 = N2;
+  g->d.NG = NG;
+  g->d.P0 = N0 + NG;
+  g->d.nint = N0 * N1 * N2;
+  g->d.nout = NG * N1 * N2;
+  g->d.sph = coords == HR_SPHERICAL ? 1 : 0;
+  g->G = align_up((size_t)next, 64);
+  g->nblk_res = (g->d.nint + kBlock - 1) / kBlock;
+  std::string err;
+  if (!build_tables(coords, g->d, prm, g->tab, err)) {
+    delete g;
+    return fail(HR_EINVAL, err);
+  }
+  *out = g;
+  return HR_OK;
+}
+
+void hr_grid_destroy(hr_grid* g) {
+  if (!g) return;
+  if (g->bound) {
+    (void)hipSetDevice(g->device);
+    (void)hipStreamSynchronize(g->stream);
+    if (g->host_res) (void)hipHostFree(g->host_res);
+    if (g->own_stream) (void)hipStreamDestroy(g->stream);
+  }
+  delete g;
+}
+
+hr_status hr_grid_sizes(const hr_grid* g, size_t* n_interior, size_t* n_extended) {
+  if (!g) return fail(HR_EINVAL, "null grid handle");
+  if (n_interior) *n_interior = g->d.nint;
+  if (n_extended) *n_extended = ext_count(g);
+  return HR_OK;
+}
+
+size_t hr_workspace_bytes(const hr_grid* g) {
+  if (!g) return 0;
+  return layout(const_cast<hr_grid*>(g), nullptr);
+}
+
+hr_status hr_grid_bind(hr_grid* g, void* dev_ptr, size_t bytes, void* hip_stream) {
+  if (!g) return fail(HR_EINVAL, "null grid handle");
+  if (g->bound) return fail(HR_ESTATE, "grid already bound");
+  if (!dev_ptr || ((uintptr_t)dev_ptr % kAlign) != 0)
+    return fail(HR_EINVAL, "workspace pointer must be non-null and 256-byte aligned");
+  const size_t need = layout(g, nullptr);
+  if (bytes < need) return fail(HR_ENOMEM, "workspace smaller than hr_workspace_bytes()");
+  HR_HIP(hipGetDevice(&g->device));
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, dev_ptr) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+    (void)hipGetLastError();
+    return fail(HR_EINVAL, "workspace pointer is not device memory");
+  }
+  if (hip_stream) {
+    g->stream = (hipStream_t)hip_stream;
+    g->own_stream = false;
+  } else {
+    HR_HIP(hipStreamCreate(&g->stream));
+    g->own_stream = true;
+  }
+  HR_HIP(hipHostMalloc((void**)&g->host_res, 4 * sizeof(double), hipHostMallocDefault));
+  g->ws = dev_ptr;
+  g->ws_bytes = bytes;
+  layout(g, (char*)dev_ptr);
+  g->bound = true;
+  const Dims& d = g->d;
+  const int e2d = d.P0 * d.N1;
+  HR_HIP(hipMemcpyAsync(g->rho, g->tab.rho.data(), e2d * sizeof(double),
+                        hipMemcpyHostToDevice, g->stream));
+  HR_HIP(hipMemcpyAsync(g->zc, g->tab.zc.data(), e2d * sizeof(double), hipMemcpyHostToDevice,
+                        g->stream));
+  HR_HIP(hipMemcpyAsync(g->cphi, g->tab.cphi.data(), d.N2 * sizeof(double),
+                        hipMemcpyHostToDevice, g->stream));
+  HR_HIP(hipMemcpyAsync(g->sphi, g->tab.sphi.data(), d.N2 * sizeof(double),
+                        hipMemcpyHostToDevice, g->stream));
+  const int G = (int)g->G;
+  double* z64[] = {g->f64.un, g->f64.vn, g->f64.ua, g->f64.va, g->f64.ub,
+                   g->f64.vb, g->f64.au, g->f64.av, g->f64.psi, g->f64.ssrc};
+  for (double* p : z64) HR_HIP(launch_fill(p, 0.0, G, g->stream));
+  float* z32[] = {g->f32.un, g->f32.vn, g->f32.ua, g->f32.va, g->f32.ub,
+                  g->f32.vb, g->f32.au, g->f32.av, g->f32.psi, g->f32.ssrc};
+  for (float* p : z32) HR_HIP(launch_fill(p, 0.0f, G, g->stream));
+  g->kappa_loaded = -1.0;
+  hr_status st = load_kappa(g, 1.0);
+  if (st != HR_OK) return st;
+  HR_HIP(hipStreamSynchronize(g->stream));
+  return HR_OK;
+}
+
+hr_status hr_set_punctures(hr_grid* g, int n, const double* m, const double* x,
+                           const double* P, const double* S) {
+  hr_status st = check_ready(g, false);
+  if (st != HR_OK) return st;
+  if (n < 1 || n > kMaxPunctures) return fail(HR_EINVAL, "need 1..4 punctures");
+  if (!m || !x || !P || !S) return fail(HR_EINVAL, "null puncture array");
+  Punctures pz{};
+  pz.n = n;
+  for (int i = 0; i < n; ++i) {
+    if (!(m[i] > 0) || !std::isfinite(m[i])) return fail(HR_EINVAL, "masses must be finite and > 0");
+    pz.m[i] = m[i];
+    for (int k = 0; k < 3; ++k) {
+      if (!std::isfinite(x[3 * i + k]) || !std::isfinite(P[3 * i + k]) ||
+          !std::isfinite(S[3 * i + k]))
+        return fail(HR_EINVAL, "non-finite puncture parameter");
+      pz.x[i][k] = x[3 * i + k];
+      pz.P[i][k] = P[3 * i + k];
+      pz.S[i][k] = S[3 * i + k];
+    }
+  }
+  HR_HIP(launch_sources(g->d, g->rho, g->zc, g->cphi, g->sphi, pz, g->f64.psi, g->f64.ssrc,
+                        g->f32.psi, g->f32.ssrc, g->stream));
+  const int G = (int)g->G;
+  HR_HIP(launch_fill(g->f64.un, 0.0, G, g->stream));
+  HR_HIP(launch_fill(g->f64.vn, 0.0, G, g->stream));
+  HR_HIP(hipStreamSynchronize(g->stream));
+  g->have_sources = true;
+  return HR_OK;
+}
+
+hr_status hr_set_fp32_switch(hr_grid* g, double switch_residual, int stall_checks,
+                             long max_fp32_steps) {
+  if (!g) return fail(HR_EINVAL, "null grid handle");
+  if (!(switch_residual >= 0) || stall_checks < 1)
+    return fail(HR_EINVAL, "switch_residual >= 0 and stall_checks >= 1 required");
+  g->sw_residual = switch_residual;
+  g->sw_stall = stall_checks;
+  g->sw_max_steps = max_fp32_steps;
+  return HR_OK;
+}
+
+hr_status hr_relax(hr_grid* g, double eta, double c, double dt, long n_steps, double tol,
+                   int check_every, hr_precision prec, hr_relax_report* rep) {
+  hr_status st = check_ready(g, true);
+  if (st != HR_OK) return st;
+  if (!(eta > 0) || !(c > 0) || !std::isfinite(eta) || !std::isfinite(c) || !std::isfinite(dt))
+    return fail(HR_EINVAL, "eta and c must be finite and > 0");
+  if (n_steps < 0) return fail(HR_EINVAL, "n_steps must be >= 0");
+  if (check_every <= 0) return fail(HR_EINVAL, "check_every must be > 0");
+  if (prec != HR_FP64 && prec != HR_FP32 && prec != HR_FP32_FP64FINISH)
+    return fail(HR_EINVAL, "unknown precision");
+  if (dt <= 0) dt = g->prm.cfl * g->tab.ds_g;
+  HR_HIP(hipSetDevice(g->device));
+  st = load_kappa(g, c);
+  if (st != HR_OK) return st;
+  if (rep) {
+    rep->steps_taken = 0;
+    rep->fp32_steps = 0;
+    rep->residual = NAN;
+    rep->dt_used = dt;
+    rep->n_history = 0;
+  }
+  const int G = (int)g->G;
+  long done = 0, total = 0, f32steps = 0;
+  int why = 0;
+  double last = NAN;
+  if (prec == HR_FP32 || prec == HR_FP32_FP64FINISH) {
+    HR_HIP(launch_to_fp32(g->f64.un, g->f32.un, G, g->stream));
+    HR_HIP(launch_to_fp32(g->f64.vn, g->f32.vn, G, g->stream));
+    const bool sw = prec == HR_FP32_FP64FINISH;
+    st = run_phase<float>(g, g->f32, true, eta, dt, n_steps, sw ? 0.0 : tol, check_every, sw,
+                          rep, &done, &why, &last);
+    if (st != HR_OK) return st;
+    total += done;
+    f32steps = done;
+    HR_HIP(launch_to_fp64(g->f32.un, g->f64.un, G, g->stream));
+    HR_HIP(launch_to_fp64(g->f32.vn, g->f64.vn, G, g->stream));
+    HR_HIP(hipStreamSynchronize(g->stream));
+  }
+  if (prec == HR_FP64 || (prec == HR_FP32_FP64FINISH && why != 2 && total < n_steps)) {
+    st = run_phase<double>(g, g->f64, false, eta, dt, n_steps - total, tol, check_every, false,
+                           rep, &done, &why, &last);
+    if (st != HR_OK) return st;
+    total += done;
+  }
+  if (rep) {
+    rep->steps_taken = total;
+    rep->fp32_steps = f32steps;
+    rep->residual = last;
+  }
+  if (why == 2) return fail(HR_ENONFINITE, "residual is not finite");
+  if (tol > 0 && why != 1) return fail(HR_ENOTCONV, "tolerance not reached within n_steps");
+  return HR_OK;
+}
+
+hr_status hr_get_u(const hr_grid* g, double* host_out, size_t n) {
+  return get_field(g, g ? g->f64.un : nullptr, host_out, n);
+}
+hr_status hr_get_v(const hr_grid* g, double* host_out, size_t n) {
+  return get_field(g, g ? g->f64.vn : nullptr, host_out, n);
+}
+hr_status hr_set_u(hr_grid* g, const double* host_in, size_t n) {
+  return set_field(g, g ? g->f64.un : nullptr, host_in, n);
+}
+hr_status hr_set_v(hr_grid* g, const double* host_in, size_t n) {
+  return set_field(g, g ? g->f64.vn : nullptr, host_in, n);
+}
+
+hr_status hr_residual_l2(hr_grid* g, double* out) {
+  hr_status st = check_ready(g, true);
+  if (st != HR_OK) return st;
+  if (!out) return fail(HR_EINVAL, "null output pointer");
+  HR_HIP(hipSetDevice(g->device));
+  return residual_of(g, g->f64.un, false, out);
+}
+
+hr_status hr_suggest_dt(const hr_grid* g, double cfl, double* dt) {
+  if (!g || !dt) return fail(HR_EINVAL, "null argument");
+  if (!(cfl > 0)) return fail(HR_EINVAL, "cfl must be > 0");
+  *dt = cfl * g->tab.ds_g;
+  return HR_OK;
+}
+
+hr_status hr_time_stage_kernels(hr_grid* g, double eta, double c, double dt, long n_steps,
+                                hr_precision prec, double* avg_us) {
+  hr_status st = check_ready(g, true);
+  if (st != HR_OK) return st;
+  if (!avg_us || n_steps <= 0 || !(eta > 0) || !(c > 0))
+    return fail(HR_EINVAL, "need avg_us, n_steps > 0, eta > 0, c > 0");
+  if (prec != HR_FP64 && prec != HR_FP32) return fail(HR_EINVAL, "prec must be FP64 or FP32");
+  if (dt <= 0) dt = g->prm.cfl * g->tab.ds_g;
+  HR_HIP(hipSetDevice(g->device));
+  st = load_kappa(g, c);
+  if (st != HR_OK) return st;
+  hipEvent_t e0, e1;
+  HR_HIP(hipEventCreate(&e0));
+  HR_HIP(hipEventCreate(&e1));
+  double sum[4] = {0, 0, 0, 0};
+  const int G = (int)g->G;
+  if (prec == HR_FP32) {
+    HR_HIP(launch_to_fp32(g->f64.un, g->f32.un, G, g->stream));
+    HR_HIP(launch_to_fp32(g->f64.vn, g->f32.vn, G, g->stream));
+  }
+  for (long n = 0; n < n_steps; ++n)
+    for (int s = 1; s <= 4; ++s) {
+      HR_HIP(hipEventRecord(e0, g->stream));
+      if (prec == HR_FP64)
+        HR_HIP(launch_stage(g->fd_order, s, stage_args<double>(g, g->f64, s, eta, dt), g->stream));
+      else
+        HR_HIP(launch_stage(g->fd_order, s,
+                            stage_args<float>(g, g->f32, s, (float)eta, (float)dt), g->stream));
+      HR_HIP(hipEventRecord(e1, g->stream));
+      HR_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HR_HIP(hipEventElapsedTime(&ms, e0, e1));
+      sum[s - 1] += ms;
+    }
+  if (prec == HR_FP32) {
+    HR_HIP(launch_to_fp64(g->f32.un, g->f64.un, G, g->stream));
+    HR_HIP(launch_to_fp64(g->f32.vn, g->f64.vn, G, g->stream));
+    HR_HIP(hipStreamSynchronize(g->stream));
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  double tot = 0;
+  for (int s = 0; s < 4; ++s) {
+    avg_us[s] = 1e3 * sum[s] / n_steps;
+    tot += avg_us[s];
+  }
+  avg_us[4] = tot / 4;
+  return HR_OK;
+}
+
+const char* hr_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,164 @@
+// Host-side geometry of the relaxation grids: coordinate maps, scale
+// factors, flat-space Laplacian coefficients, the variable wave speed and the
+// outer-boundary factors. Runs once per grid; the results are uploaded as
+// small 1D/2D tables (every factor depends on xx0 and xx1 only).
+//
+// Coordinates (companion-paper families named in the paper's "Basic
+// equations" section and conclusions; the exact maps are readings):
+//   SinhSymTP  prolate spheroidal with a sinh-stretched radial coordinate,
+//              rho = A(xx0) sin xx1, z = sqrt(A^2 + b^2) cos xx1,
+//              A(xx0) = amax sinh(xx0/w) / sinh(1/w), xx0 in [0,1];
+//   Spherical  rho = r sin xx1, z = r cos xx1, r = xx0 in [0, rmax];
+// with xx1 in [0,pi] and xx2 = phi in [-pi,pi], cell-centred.
+//
+// Both metrics are diagonal, so with scale factors h_i and J = h0 h1 h2
+//   lap f = sum_i  f,ii / h_i^2 + (1/J) d_i (J / h_i^2) f,i .
+// The wave speed is c(x) = kappa ds_min(x)/ds_g with ds_min(x) the smallest
+// proper cell width h_i dxx_i at x and ds_g its interior minimum, so that
+// the local Courant number is the same everywhere (end of the "Basic
+// equations" section: wave speed proportional to the local grid spacing).
+
+#include <cmath>
+
+#include "hr_internal.h"
+
+namespace hr {
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+struct Local {
+  double h0, h1, h2;   // scale factors
+  double a0, a1, a2;   // 1 / h_i^2
+  double b0, b1;       // (1/J) d_i (J / h_i^2), i = 0, 1 (the phi term vanishes)
+  double rho, z;       // cylindrical position at phi = 0
+  double drdx0;        // d r_cartesian / d xx0 along the coordinate line
+};
+
+Local local_sinhsymtp(const hr_grid_params& p, double x0, double x1) {
+  const double w = p.sinhwaa, b = p.bscale;
+  const double norm = std::sinh(1.0 / w);
+  const double A = p.amax * std::sinh(x0 / w) / norm;
+  const double dA = p.amax * std::cosh(x0 / w) / (w * norm);
+  const double d2A = A / (w * w);
+  const double sn = std::sin(x1), cs = std::cos(x1);
+  const double R2 = A * A + b * b;
+  const double S = A * A + b * b * sn * sn;
+  Local L;
+  L.h0 = dA * std::sqrt(S) / std::sqrt(R2);
+  L.h1 = std::sqrt(S);
+  L.h2 = A * sn;
+  L.a0 = R2 / (dA * dA * S);
+  L.a1 = 1.0 / S;
+  L.a2 = 1.0 / (A * A * sn * sn);
+  // J/h0^2 = A sqrt(R2) sin(x1) / A'  ->  derivative along xx0 over J
+  L.b0 = (2.0 * A * A + b * b - A * R2 * d2A / (dA * dA)) / (A * dA * S);
+  // J/h1^2 = A A' sin(x1) / sqrt(R2) ->  derivative along xx1 over J
+  L.b1 = cs / (sn * S);
+  L.rho = A * sn;
+  L.z = std::sqrt(R2) * cs;
+  const double r = std::sqrt(L.rho * L.rho + L.z * L.z);
+  L.drdx0 = A * dA / r;  // r^2 = A^2 + b^2 cos^2 xx1
+  return L;
+}
+
+Local local_spherical(double x0, double x1) {
+  const double r = x0, sn = std::sin(x1), cs = std::cos(x1);
+  Local L;
+  L.h0 = 1.0;
+  L.h1 = r;
+  L.h2 = r * sn;
+  L.a0 = 1.0;
+  L.a1 = 1.0 / (r * r);
+  L.a2 = 1.0 / (r * r * sn * sn);
+  L.b0 = 2.0 / r;
+  L.b1 = cs / (sn * r * r);
+  L.rho = r * sn;
+  L.z = r * cs;
+  L.drdx0 = 1.0;
+  return L;
+}
+
+}  // namespace
+
+bool build_tables(hr_coords coords, const Dims& d, const hr_grid_params& p,
+                  HostTables& t, std::string& err) {
+  const double x0max = (coords == HR_SINHSYMTP) ? 1.0 : p.rmax;
+  const double dx[3] = {x0max / d.N0, kPi / d.N1, 2.0 * kPi / d.N2};
+  auto coord = [&](int dir, int j) {  // j = stored index (0 = first interior)
+    const double lo = (dir == 2) ? -kPi : 0.0;
+    return lo + (j + 0.5) * dx[dir];
+  };
+  auto local = [&](int i0, int i1) {
+    return coords == HR_SINHSYMTP ? local_sinhsymtp(p, coord(0, i0), coord(1, i1))
+                                  : local_spherical(coord(0, i0), coord(1, i1));
+  };
+  auto dsmin = [&](const Local& L) {
+    double s = std::fabs(L.h0) * dx[0];
+    s = std::fmin(s, std::fabs(L.h1) * dx[1]);
+    s = std::fmin(s, std::fabs(L.h2) * dx[2]);
+    return s;
+  };
+  const int n2d = d.N0 * d.N1, o2d = d.NG * d.N1, e2d = d.P0 * d.N1;
+  t.alpha.assign(5 * (size_t)n2d, 0.0);
+  t.crat.assign(n2d, 0.0);
+  t.ocrat.assign(o2d, 0.0);
+  t.orinv.assign(o2d, 0.0);
+  t.oq.assign(o2d, 0.0);
+  t.rho.assign(e2d, 0.0);
+  t.zc.assign(e2d, 0.0);
+  t.rcart.assign(e2d, 0.0);
+  t.cphi.assign(d.N2, 0.0);
+  t.sphi.assign(d.N2, 0.0);
+
+  std::vector<double> ds(e2d);
+  double dsg = INFINITY;
+  for (int i1 = 0; i1 < d.N1; ++i1)
+    for (int i0 = 0; i0 < d.P0; ++i0) {
+      const Local L = local(i0, i1);
+      const int e = i0 + d.P0 * i1;
+      ds[e] = dsmin(L);
+      t.rho[e] = L.rho;
+      t.zc[e] = L.z;
+      t.rcart[e] = std::sqrt(L.rho * L.rho + L.z * L.z);
+      if (i0 < d.N0) {
+        const int k = i0 + d.N0 * i1;
+        t.alpha[0 * (size_t)n2d + k] = L.a0 / (dx[0] * dx[0]);
+        t.alpha[1 * (size_t)n2d + k] = L.a1 / (dx[1] * dx[1]);
+        t.alpha[2 * (size_t)n2d + k] = L.a2 / (dx[2] * dx[2]);
+        t.alpha[3 * (size_t)n2d + k] = L.b0 / dx[0];
+        t.alpha[4 * (size_t)n2d + k] = L.b1 / dx[1];
+        dsg = std::fmin(dsg, ds[e]);
+      } else {
+        const int k = (i0 - d.N0) + d.NG * i1;
+        t.orinv[k] = 1.0 / t.rcart[e];
+        t.oq[k] = 1.0 / (2.0 * dx[0] * L.drdx0);
+      }
+    }
+  if (!(dsg > 0.0) || !std::isfinite(dsg)) {
+    err = "grid has a non-positive or non-finite cell width";
+    return false;
+  }
+  t.ds_g = dsg;
+  for (int i1 = 0; i1 < d.N1; ++i1)
+    for (int i0 = 0; i0 < d.P0; ++i0) {
+      const int e = i0 + d.P0 * i1;
+      if (i0 < d.N0)
+        t.crat[i0 + d.N0 * i1] = ds[e] / dsg;
+      else
+        t.ocrat[(i0 - d.N0) + d.NG * i1] = ds[e] / dsg;
+    }
+  for (int i2 = 0; i2 < d.N2; ++i2) {
+    const double ph = coord(2, i2);
+    t.cphi[i2] = std::cos(ph);
+    t.sphi[i2] = std::sin(ph);
+  }
+  for (double a : t.alpha)
+    if (!std::isfinite(a)) {
+      err = "non-finite Laplacian coefficient (check coordinate parameters)";
+      return false;
+    }
+  return true;
+}
+
+}  // namespace hr

@@ -1,0 +1,100 @@
+"""CPU-side checks of the C ABI library: it loads, exports every symbol the
+header declares, validates arguments and computes its host-side geometry
+(no device calls are made here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2501_14030_amd as hr
+from paper_2501_14030_amd import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hrelax.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hr_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return hr.load_library()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    names = _declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    # and the binding wraps every one of them
+    assert set(names) <= set(hr._SIGNATURES)
+
+
+def _create(lib, coords, N0, N1, N2, order, params=None):
+    h = ctypes.c_void_p()
+    pp = ctypes.byref(params) if params is not None else None
+    st = lib.hr_grid_create(coords, N0, N1, N2, order, pp, ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("args", [
+    (0, 32, 16, 5, 8),     # odd N2
+    (0, 3, 16, 4, 8),      # N0 < NG
+    (0, 32, 3, 4, 8),      # N1 < NG
+    (0, 32, 16, 4, 7),     # odd order
+    (0, 32, 16, 4, 12),    # unsupported order
+    (2, 32, 16, 4, 8),     # unknown coordinates
+    (0, 32, 16, 0, 8),
+])
+def test_create_rejects_invalid_arguments(lib, args):
+    st, h = _create(lib, *args)
+    assert st == hr.EINVAL and not h.value
+    assert len(lib.hr_last_error()) > 0
+
+
+def test_create_rejects_bad_params(lib):
+    p = hr.default_params(sinhwaa=-1.0)
+    st, h = _create(lib, 0, 16, 8, 4, 8, p)
+    assert st == hr.EINVAL
+
+
+def test_workspace_and_sizes(lib):
+    st, h = _create(lib, 0, 128, 128, 16, 10)
+    assert st == hr.OK
+    ni = ctypes.c_size_t()
+    ne = ctypes.c_size_t()
+    assert lib.hr_grid_sizes(h, ctypes.byref(ni), ctypes.byref(ne)) == hr.OK
+    assert ni.value == 128 * 128 * 16
+    assert ne.value == 133 * 128 * 16
+    ws = lib.hr_workspace_bytes(h)
+    # 10 FP64 + 10 FP32 grid functions dominate
+    assert 10 * 12 * ne.value <= ws < 10 * 12 * ne.value * 1.1
+    # calls that need a bound device workspace refuse politely
+    out = ctypes.c_double()
+    assert lib.hr_residual_l2(h, ctypes.byref(out)) == hr.ESTATE
+    lib.hr_grid_destroy(h)
+    lib.hr_grid_destroy(None)
+
+
+@pytest.mark.parametrize("spec", [
+    workloads.GridSpec(0, 32, 16, 4, 8, bscale=1.0),
+    workloads.GridSpec(0, 128, 128, 16, 10, bscale=5.0),
+    workloads.GridSpec(1, 128, 64, 8, 10, rmax=100.0),
+])
+def test_suggested_dt_matches_oracle(lib, oracle_lib, spec):
+    p = hr.default_params(amax=spec.amax, sinhwaa=spec.sinhwaa, bscale=spec.bscale,
+                          rmax=spec.rmax)
+    st, h = _create(lib, spec.coords, spec.N0, spec.N1, spec.N2, spec.fd_order, p)
+    assert st == hr.OK
+    dt = ctypes.c_double()
+    assert lib.hr_suggest_dt(h, 0.5, ctypes.byref(dt)) == hr.OK
+    og = oracle_lib.OracleGrid(spec.coords, spec.N0, spec.N1, spec.N2, spec.fd_order,
+                               amax=spec.amax, sinhwaa=spec.sinhwaa, bscale=spec.bscale,
+                               rmax=spec.rmax)
+    np.testing.assert_allclose(dt.value, og.suggest_dt(0.5), rtol=1e-15)
+    lib.hr_grid_destroy(h)
