@@ -194,6 +194,26 @@ hr_status hr_residual_l2(hr_grid* g, double* out);
 hr_status hr_suggest_dt(const hr_grid* g, double cfl, double* dt);
 
 /*
+ * Kernel configuration of a grid (performance only; results are identical up
+ * to floating-point rounding order, and bitwise identical for the streaming
+ * switch, which changes cache policy only).
+ *   variant    0 = automatic, 1 = plane tiles (one phi plane per block),
+ *              2 = phi-marching columns (a block walks `chunk` phi planes)
+ *   streaming  -1 = automatic (by grid size), 0 = cached, 1 = non-temporal
+ *              loads/stores for fields touched once per stage
+ *   chunk      phi planes per block for variant 2 (0 = automatic)
+ * Errors: HR_EINVAL.
+ */
+typedef struct {
+  int variant;
+  int streaming;
+  int chunk;
+} hr_kernel_config;
+
+hr_status hr_set_kernel_config(hr_grid* g, const hr_kernel_config* cfg);
+hr_status hr_get_kernel_config(const hr_grid* g, hr_kernel_config* cfg);
+
+/*
  * Measurement: runs n_steps RK4 steps of the current state in precision prec
  * (HR_FP64 or HR_FP32), bracketing every stage-kernel launch with hipEvents
  * recorded on the grid's stream, and returns in avg_us[0..3] the mean duration

@@ -51,6 +51,10 @@ class GridParams(ctypes.Structure):
                 ("cfl", ctypes.c_double)]
 
 
+class KernelConfig(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int), ("streaming", ctypes.c_int), ("chunk", ctypes.c_int)]
+
+
 class RelaxReport(ctypes.Structure):
     _fields_ = [("steps_taken", ctypes.c_long), ("fp32_steps", ctypes.c_long),
                 ("residual", ctypes.c_double), ("dt_used", ctypes.c_double),
@@ -87,6 +91,8 @@ _SIGNATURES = {
     "hr_suggest_dt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, _dp]),
     "hr_time_stage_kernels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_double, ctypes.c_long, ctypes.c_int, _dp]),
+    "hr_set_kernel_config": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KernelConfig)]),
+    "hr_get_kernel_config": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KernelConfig)]),
     "hr_last_error": (ctypes.c_char_p, []),
 }
 
@@ -272,6 +278,17 @@ class Grid:
                                                     out.ctypes.data_as(_dp)),
                "hr_time_stage_kernels")
         return out
+
+    def set_kernel_config(self, variant: int = 0, streaming: int = -1, chunk: int = 0) -> None:
+        cfg = KernelConfig(int(variant), int(streaming), int(chunk))
+        _check(load_library().hr_set_kernel_config(self._h, ctypes.byref(cfg)),
+               "hr_set_kernel_config")
+
+    def kernel_config(self) -> dict:
+        cfg = KernelConfig()
+        _check(load_library().hr_get_kernel_config(self._h, ctypes.byref(cfg)),
+               "hr_get_kernel_config")
+        return {"variant": cfg.variant, "streaming": cfg.streaming, "chunk": cfg.chunk}
 
     def suggest_dt(self, cfl: float = 0.5) -> float:
         out = ctypes.c_double()

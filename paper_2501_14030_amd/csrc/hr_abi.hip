@@ -102,6 +102,20 @@ hr_status load_kappa(hr_grid* g, double kappa) {
   return HR_OK;
 }
 
+// Kernel variant for this grid: explicit configuration, else by size (phi
+// columns when there are enough (x0, x1) tiles to fill the device).
+void resolve_variant(const hr_grid* g, int& variant, int& chunk) {
+  variant = g->variant;
+  chunk = g->chunk;
+  const long tiles = (long)((g->d.N0 + 63) / 64) * ((g->d.N1 + 7) / 8);
+  if (variant == 0) variant = (tiles * g->d.N2 >= 4096 && g->d.N2 >= 16) ? 2 : 1;
+  if (variant == 2 && chunk <= 0) {
+    // aim for about 2048 blocks, at least 4 planes per block
+    long c = (tiles * g->d.N2 + 2047) / 2048;
+    chunk = (int)std::max<long>(4, std::min<long>(c, g->d.N2));
+  }
+}
+
 template <typename T>
 StageArgs<T> stage_args(const hr_grid* g, const Fields<T>& F, int stage, T eta, T dt) {
   StageArgs<T> a{};
@@ -111,6 +125,9 @@ StageArgs<T> stage_args(const hr_grid* g, const Fields<T>& F, int stage, T eta, 
   a.fac = F.fac;
   a.ofac = F.ofac;
   a.eta = eta;
+  // non-temporal access measured no faster at any size: off unless asked for
+  a.streaming = g->streaming > 0 ? 1 : 0;
+  resolve_variant(g, a.variant, a.chunk);
   a.un = F.un;
   a.vn = F.vn;
   a.au = F.au;
@@ -160,7 +177,7 @@ hr_status residual_of(hr_grid* g, const void* u, bool fp32, double* out) {
   r.ssrc = g->f64.ssrc;
   r.fac = g->f64.fac;
   r.partial = g->partial;
-  HR_HIP(launch_residual(g->fd_order, fp32, r, g->nblk_res, g->stream));
+  HR_HIP(launch_residual(g->fd_order, fp32, r, g->stream));
   HR_HIP(launch_finalize(g->partial, g->nblk_res, g->d.nint, g->result, g->stream));
   HR_HIP(hipMemcpyAsync(g->host_res, g->result, sizeof(double), hipMemcpyDeviceToHost,
                         g->stream));
@@ -340,7 +357,7 @@ hr_status hr_grid_create(hr_coords coords, int N0, int N1, int N2, int fd_order,
   g->d.nout = NG * N1 * N2;
   g->d.sph = coords == HR_SPHERICAL ? 1 : 0;
   g->G = align_up((size_t)next, 64);
-  g->nblk_res = (g->d.nint + kBlock - 1) / kBlock;
+  g->nblk_res = residual_blocks(g->d);
   std::string err;
   if (!build_tables(coords, g->d, prm, g->tab, err)) {
     delete g;
@@ -567,13 +584,13 @@ hr_status hr_time_stage_kernels(hr_grid* g, double eta, double c, double dt, lon
   }
   for (long n = 0; n < n_steps; ++n)
     for (int s = 1; s <= 4; ++s) {
-      HR_HIP(hipEventRecord(e0, g->stream));
       if (prec == HR_FP64)
-        HR_HIP(launch_stage(g->fd_order, s, stage_args<double>(g, g->f64, s, eta, dt), g->stream));
+        HR_HIP(launch_stage(g->fd_order, s, stage_args<double>(g, g->f64, s, eta, dt), g->stream,
+                            e0, e1));
       else
         HR_HIP(launch_stage(g->fd_order, s,
-                            stage_args<float>(g, g->f32, s, (float)eta, (float)dt), g->stream));
-      HR_HIP(hipEventRecord(e1, g->stream));
+                            stage_args<float>(g, g->f32, s, (float)eta, (float)dt), g->stream,
+                            e0, e1));
       HR_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
       HR_HIP(hipEventElapsedTime(&ms, e0, e1));
@@ -592,6 +609,25 @@ hr_status hr_time_stage_kernels(hr_grid* g, double eta, double c, double dt, lon
     tot += avg_us[s];
   }
   avg_us[4] = tot / 4;
+  return HR_OK;
+}
+
+hr_status hr_set_kernel_config(hr_grid* g, const hr_kernel_config* cfg) {
+  if (!g || !cfg) return fail(HR_EINVAL, "null argument");
+  if (cfg->variant < 0 || cfg->variant > 2 || cfg->streaming < -1 || cfg->streaming > 1 ||
+      cfg->chunk < 0)
+    return fail(HR_EINVAL, "invalid kernel configuration");
+  g->variant = cfg->variant;
+  g->streaming = cfg->streaming;
+  g->chunk = cfg->chunk;
+  return HR_OK;
+}
+
+hr_status hr_get_kernel_config(const hr_grid* g, hr_kernel_config* cfg) {
+  if (!g || !cfg) return fail(HR_EINVAL, "null argument");
+  cfg->variant = g->variant;
+  cfg->streaming = g->streaming;
+  cfg->chunk = g->chunk;
   return HR_OK;
 }
 

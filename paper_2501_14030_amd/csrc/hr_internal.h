@@ -69,6 +69,9 @@ struct StageArgs {
   T eta;
   T cy;           // Y_{s+1} = y_n + cy * k   (cy = dt/2, dt/2, dt)
   T ca;           // acc weight (dt/6, dt/3, dt/3, dt/6)
+  int streaming;  // 1: non-temporal access to fields touched once per stage
+  int variant;    // 1: plane tiles, 2: phi-marching columns
+  int chunk;      // phi planes per block (variant 2)
 };
 
 struct ResidualArgs {
@@ -81,12 +84,16 @@ struct ResidualArgs {
 };
 
 // Launchers (hr_kernels.hip). All return the hipError_t of the launch.
+// Stage launches; with non-null t0/t1 the dispatch records those events
+// around the kernel itself (used for timing).
 hipError_t launch_stage(int order, int stage, const StageArgs<double>& a,
-                        hipStream_t s);
+                        hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t launch_stage(int order, int stage, const StageArgs<float>& a,
-                        hipStream_t s);
+                        hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+// Number of partial sums (blocks) the residual kernel writes for these dims.
+int residual_blocks(const Dims& d);
 hipError_t launch_residual(int order, bool fp32_state, const ResidualArgs& a,
-                           int nblocks, hipStream_t s);
+                           hipStream_t s);
 hipError_t launch_finalize(const double* partial, int nparts, int nint,
                            double* out, hipStream_t s);
 hipError_t launch_sources(const Dims& d, const double* rho, const double* zc,
@@ -147,6 +154,10 @@ struct hr_grid {
   double* host_res = nullptr;   // pinned readback slot
   bool have_sources = false;
   double kappa_loaded = -1.0;   // wave-speed scale currently in fac/ofac
+
+  int variant = 0;              // kernel variant: 0 auto, 1 plane tiles, 2 phi columns
+  int streaming = -1;           // non-temporal field access: -1 auto (by size), 0, 1
+  int chunk = 0;                // phi planes per block of the column variant (0 auto)
 
   // FP32 -> FP64 switch rule
   double sw_residual = 1e-6;

@@ -21,6 +21,8 @@
 // precision; each block reduces its H^2 with wavefront shuffles and writes one
 // partial, and a single block adds the partials in a fixed order.
 
+#include <hip/hip_ext.h>
+
 #include "hr_internal.h"
 
 namespace hr {
@@ -68,78 +70,128 @@ struct Weights {
 };
 
 // ---------------------------------------------------------------------------
-// Neighbour addressing in the extended layout with virtual inner ghosts.
-struct Addr {
-  int i0, i1, i2;
-  int s1, s2;      // strides of x1 and x2
-  int base;        // flat index of the centre
-  int refl0;       // row base of the xx0 = 0 reflection (i1', i2 + N2/2)
-  int i2h;         // i2 + N2/2 (mod N2)
-  int N1, N2;
+// Block tiling. A block owns a TX x TY patch of one (x0, x1) plane of the
+// interior. The patch plus an NG-deep rim is staged in LDS once, with rim
+// taps outside the stored range replaced by their images: reflection through
+// xx0 = 0 (the same plane for SinhSymTP rows, theta mirrored for Spherical,
+// phi + pi), through theta = 0 or pi (phi + pi). The x0 and x1 stencil taps
+// then read LDS; the x2 taps (periodic in phi) read global memory directly,
+// where neighbouring planes' blocks make them cache hits.
+constexpr int TX = 64;   // threads along x0 (one wavefront)
+constexpr int TY = 8;    // threads along x1
+constexpr int kTileThreads = TX * TY;
 
-  __device__ __forceinline__ Addr(const Dims& d, int a0, int a1, int a2)
-      : i0(a0), i1(a1), i2(a2), s1(d.P0), s2(d.P0 * d.N1), N1(d.N1), N2(d.N2) {
-    base = i0 + s1 * i1 + s2 * i2;
-    i2h = i2 + (N2 >> 1);
-    i2h -= (i2h >= N2) ? N2 : 0;
-    const int i1r = d.sph ? (N1 - 1 - i1) : i1;
-    refl0 = s1 * i1r + s2 * i2h;
-  }
-  // x0 - k (k >= 1): interior, or reflected through xx0 = 0
-  __device__ __forceinline__ int x0m(int k) const {
-    const int j = i0 - k;
-    return (j >= 0) ? base - k : refl0 + (-1 - j);
-  }
-  // x0 + k never leaves the stored range for interior centres.
-  __device__ __forceinline__ int x0p(int k) const { return base + k; }
-  __device__ __forceinline__ int x1m(int k) const {
-    const int j = i1 - k;
-    return (j >= 0) ? base - k * s1 : i0 + s1 * (-1 - j) + s2 * i2h;
-  }
-  __device__ __forceinline__ int x1p(int k) const {
-    const int j = i1 + k;
-    return (j < N1) ? base + k * s1 : i0 + s1 * (2 * N1 - 1 - j) + s2 * i2h;
-  }
-  __device__ __forceinline__ int wrap2(int j) const {
-    j %= N2;
-    return j < 0 ? j + N2 : j;
-  }
-  __device__ __forceinline__ int x2m(int k) const { return i0 + s1 * i1 + s2 * wrap2(i2 - k); }
-  __device__ __forceinline__ int x2p(int k) const { return i0 + s1 * i1 + s2 * wrap2(i2 + k); }
+template <int NG>
+struct TileShape {
+  static constexpr int W = TX + 2 * NG;
+  static constexpr int H = TY + 2 * NG;
 };
 
-// Un-normalised centred sums along the three directions; C is the compute
-// type, S the storage type of the field.
+__device__ __forceinline__ int half_turn(int i2, int N2) {
+  const int h = i2 + (N2 >> 1);
+  return h >= N2 ? h - N2 : h;
+}
+
+// Loads and stores of fields that are touched once per point and stage. With
+// NT (large grids) they bypass cache retention so that L2 keeps the u planes
+// the stencil re-reads; small grids keep everything cached between launches.
+template <bool NT, typename T>
+__device__ __forceinline__ T ld(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st(T* p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+// Stage the rim-extended patch of plane i2 of field U into tile (type C).
 template <int NG, typename C, typename S>
+__device__ __forceinline__ void load_tile(C* __restrict__ tile, const S* __restrict__ U,
+                                          const Dims& d, int x0b, int x1b, int i2) {
+  constexpr int W = TileShape<NG>::W, H = TileShape<NG>::H;
+  const int tid = threadIdx.x + TX * threadIdx.y;
+  const unsigned plane = (unsigned)d.P0 * (unsigned)d.N1;
+  const unsigned b0 = plane * (unsigned)i2;
+  const unsigned bh = plane * (unsigned)half_turn(i2, d.N2);
+  for (int e = tid; e < W * H; e += kTileThreads) {
+    const int l1 = e / W;
+    const int l0 = e - l1 * W;
+    const int j0 = x0b + l0 - NG;
+    const int j1 = x1b + l1 - NG;
+    C val = (C)0;
+    if (j1 >= 0 && j1 < d.N1) {
+      if (j0 >= 0) {
+        if (j0 < d.P0) val = (C)U[b0 + (unsigned)j0 + (unsigned)d.P0 * (unsigned)j1];
+      } else {  // reflection through xx0 = 0
+        const int r1 = d.sph ? d.N1 - 1 - j1 : j1;
+        val = (C)U[bh + (unsigned)(-1 - j0) + (unsigned)d.P0 * (unsigned)r1];
+      }
+    } else if (j0 >= 0 && j0 < d.P0 && j1 >= -NG && j1 < d.N1 + NG) {
+      // reflection through theta = 0 or theta = pi
+      const int r1 = j1 < 0 ? -1 - j1 : 2 * d.N1 - 1 - j1;
+      val = (C)U[bh + (unsigned)j0 + (unsigned)d.P0 * (unsigned)r1];
+    }
+    tile[e] = val;
+  }
+}
+
+// Un-normalised centred sums along the three directions, compute type C.
+template <typename C>
 struct Sums {
   C d0, d1, dd0, dd1, dd2, uc;
 };
 
+// The 2*NG phi-direction taps of point (i0, i1, i2) (periodic in phi), read
+// from global memory; issued before the tile barrier so that they are in
+// flight together with every other load of the point.
 template <int NG, typename C, typename S>
-__device__ __forceinline__ Sums<NG, C, S> stencil(const S* __restrict__ U, const Addr& a) {
-  constexpr Weights<NG> W{};
-  Sums<NG, C, S> r;
-  const C uc = (C)U[a.base];
-  r.uc = uc;
+struct PhiTaps {
+  C p[NG], m[NG];
+  __device__ __forceinline__ void load(const S* __restrict__ U, const Dims& d, int i0, int i1,
+                                       int i2) {
+    const unsigned col = (unsigned)i0 + (unsigned)d.P0 * (unsigned)i1;
+    const unsigned plane = (unsigned)d.P0 * (unsigned)d.N1;
+    // planes i2 + k and i2 - k (mod N2), stepped one at a time
+    int jp = i2, jm = i2;
+#pragma unroll
+    for (int k = 1; k <= NG; ++k) {
+      jp = (jp + 1 == d.N2) ? 0 : jp + 1;
+      jm = (jm == 0) ? d.N2 - 1 : jm - 1;
+      p[k - 1] = (C)U[col + plane * (unsigned)jp];
+      m[k - 1] = (C)U[col + plane * (unsigned)jm];
+    }
+  }
+};
+
+template <int NG, typename C, typename S>
+__device__ __forceinline__ Sums<C> stencil(const C* __restrict__ tile,
+                                           const PhiTaps<NG, C, S>& ph) {
+  constexpr Weights<NG> Wt{};
+  constexpr int W = TileShape<NG>::W;
+  const C* r = tile + (threadIdx.y + NG) * W + (threadIdx.x + NG);
+  Sums<C> s;
+  const C uc = r[0];
   C d0 = 0, d1 = 0, e0 = 0, e1 = 0, e2 = 0;
 #pragma unroll
   for (int k = 1; k <= NG; ++k) {
-    const C p0 = (C)U[a.x0p(k)], m0 = (C)U[a.x0m(k)];
-    const C p1 = (C)U[a.x1p(k)], m1 = (C)U[a.x1m(k)];
-    const C p2 = (C)U[a.x2p(k)], m2 = (C)U[a.x2m(k)];
-    d0 += (C)W.d1[k] * (p0 - m0);
-    d1 += (C)W.d1[k] * (p1 - m1);
-    e0 += (C)W.d2[k] * (p0 + m0);
-    e1 += (C)W.d2[k] * (p1 + m1);
-    e2 += (C)W.d2[k] * (p2 + m2);
+    const C p0 = r[k], m0 = r[-k];
+    const C p1 = r[k * W], m1 = r[-k * W];
+    d0 += (C)Wt.d1[k] * (p0 - m0);
+    d1 += (C)Wt.d1[k] * (p1 - m1);
+    e0 += (C)Wt.d2[k] * (p0 + m0);
+    e1 += (C)Wt.d2[k] * (p1 + m1);
+    e2 += (C)Wt.d2[k] * (ph.p[k - 1] + ph.m[k - 1]);
   }
-  const C w0 = (C)W.d2[0];
-  r.d0 = d0;
-  r.d1 = d1;
-  r.dd0 = e0 + w0 * uc;
-  r.dd1 = e1 + w0 * uc;
-  r.dd2 = e2 + w0 * uc;
-  return r;
+  const C w0 = (C)Wt.d2[0];
+  s.uc = uc;
+  s.d0 = d0;
+  s.d1 = d1;
+  s.dd0 = e0 + w0 * uc;
+  s.dd1 = e1 + w0 * uc;
+  s.dd2 = e2 + w0 * uc;
+  return s;
 }
 
 // (psi + u)^-7 times the source, in the compute type.
@@ -151,109 +203,352 @@ __device__ __forceinline__ C source(C ssrc, C psi, C u) {
   return ssrc / (p4 * p2 * p);
 }
 
-// RK4 stage combine for one point, given the stage slopes.
-template <int STAGE, typename T>
-__device__ __forceinline__ void combine(const StageArgs<T>& a, int idx, T uin, T vin, T ku,
+// Per-point operands of the stage combine, loaded ahead of the tile barrier.
+template <int STAGE, bool NT, typename T>
+struct CombineIn {
+  T un, vn, au, av;
+  __device__ __forceinline__ void load(const StageArgs<T>& a, unsigned idx) {
+    if constexpr (STAGE == 2 || STAGE == 3) {
+      un = ld<NT>(a.un + idx);
+      vn = ld<NT>(a.vn + idx);
+    }
+    if constexpr (STAGE != 1) {
+      au = ld<NT>(a.au + idx);
+      av = ld<NT>(a.av + idx);
+    }
+  }
+};
+
+// RK4 stage combine for one point, given the stage slopes. The next stage
+// input (uout) is re-read with stencils, so it is always a cached store.
+template <int STAGE, bool NT, typename T>
+__device__ __forceinline__ void combine(const StageArgs<T>& a, unsigned idx,
+                                        const CombineIn<STAGE, NT, T>& c, T uin, T vin, T ku,
                                         T kv) {
   if constexpr (STAGE == 1) {
     a.uout[idx] = uin + a.cy * ku;
-    a.vout[idx] = vin + a.cy * kv;
-    a.au[idx] = uin + a.ca * ku;
-    a.av[idx] = vin + a.ca * kv;
+    st<NT>(a.vout + idx, vin + a.cy * kv);
+    st<NT>(a.au + idx, uin + a.ca * ku);
+    st<NT>(a.av + idx, vin + a.ca * kv);
   } else if constexpr (STAGE == 4) {
-    a.uout[idx] = a.au[idx] + a.ca * ku;
-    a.vout[idx] = a.av[idx] + a.ca * kv;
+    a.uout[idx] = c.au + a.ca * ku;
+    st<NT>(a.vout + idx, c.av + a.ca * kv);
   } else {
-    const T un = a.un[idx], vn = a.vn[idx];
-    a.uout[idx] = un + a.cy * ku;
-    a.vout[idx] = vn + a.cy * kv;
-    a.au[idx] = a.au[idx] + a.ca * ku;
-    a.av[idx] = a.av[idx] + a.ca * kv;
+    a.uout[idx] = c.un + a.cy * ku;
+    st<NT>(a.vout + idx, c.vn + a.cy * kv);
+    st<NT>(a.au + idx, c.au + a.ca * ku);
+    st<NT>(a.av + idx, c.av + a.ca * kv);
   }
 }
 
-template <typename T, int NG, int STAGE>
-__global__ void __launch_bounds__(kBlock) k_stage(StageArgs<T> a) {
+// One RK4 stage: RHS + boundary conditions + stage combine. Grid:
+// (ceil(N0/TX), ceil(N1/TY), N2). Each interior point is one thread; the
+// threads with i0 in [N0-NG, N0) also update the outer point i0 + NG of their
+// row. Every global load of the interior point is issued before the tile
+// barrier so that the point waits for one memory round trip.
+template <typename T, int NG, int STAGE, bool NT>
+__global__ void __launch_bounds__(kTileThreads) k_stage(StageArgs<T> a) {
+  constexpr int W = TileShape<NG>::W, H = TileShape<NG>::H;
+  __shared__ T tile[W * H];
   const Dims& d = a.d;
-  const int nblk_int = (d.nint + kBlock - 1) / kBlock;
-  if ((int)blockIdx.x < nblk_int) {
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= d.nint) return;
-    const int i0 = t % d.N0;
-    const int r = t / d.N0;
-    const int i1 = r % d.N1;
-    const int i2 = r / d.N1;
-    const Addr ad(d, i0, i1, i2);
-    const Sums<NG, T, T> s = stencil<NG, T, T>(a.uin, ad);
-    const int n2d = d.N0 * d.N1;
-    const int k2 = i0 + d.N0 * i1;
-    const T* F = a.fac;
-    const T lap = F[k2] * s.dd0 + F[n2d + k2] * s.dd1 + F[2 * n2d + k2] * s.dd2 +
-                  F[3 * n2d + k2] * s.d0 + F[4 * n2d + k2] * s.d1;
-    const T c2 = F[5 * n2d + k2];
-    const int idx = ad.base;
-    const T u = s.uc;
-    const T v = a.vin[idx];
-    const T ku = v - a.eta * u;
-    const T kv = c2 * (lap + source<T>(a.ssrc[idx], a.psi[idx], u));
-    combine<STAGE, T>(a, idx, u, v, ku, kv);
-  } else {
-    const int t = (blockIdx.x - nblk_int) * kBlock + threadIdx.x;
-    if (t >= d.nout) return;
-    const int q = t % NG;
-    const int r = t / NG;
-    const int i1 = r % d.N1;
-    const int i2 = r / d.N1;
-    const int idx = d.N0 + q + d.P0 * (i1 + d.N1 * i2);
-    const int o2d = NG * d.N1;
-    const int ko = q + NG * i1;
+  const int x0b = blockIdx.x * TX, x1b = blockIdx.y * TY, i2 = blockIdx.z;
+  const int i0 = x0b + threadIdx.x, i1 = x1b + threadIdx.y;
+  const bool active = i0 < d.N0 && i1 < d.N1;
+  const unsigned n2d = (unsigned)d.N0 * (unsigned)d.N1;
+  const unsigned k2 = (unsigned)i0 + (unsigned)d.N0 * (unsigned)i1;
+  const unsigned row = (unsigned)d.P0 * ((unsigned)i1 + (unsigned)d.N1 * (unsigned)i2);
+  const unsigned idx = row + (unsigned)i0;
+  PhiTaps<NG, T, T> ph;
+  CombineIn<STAGE, NT, T> cin;
+  T v = 0, psi = 0, ssrc = 0, f[6];
+  if (active) {
+    ph.load(a.uin, d, i0, i1, i2);
+    v = ld<NT>(a.vin + idx);
+    psi = ld<NT>(a.psi + idx);
+    ssrc = ld<NT>(a.ssrc + idx);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) f[q] = a.fac[q * n2d + k2];
+    cin.load(a, idx);
+  }
+  load_tile<NG, T, T>(tile, a.uin, d, x0b, x1b, i2);
+  __syncthreads();
+  if (!active) return;
+  const Sums<T> s = stencil<NG, T, T>(tile, ph);
+  const T lap = f[0] * s.dd0 + f[1] * s.dd1 + f[2] * s.dd2 + f[3] * s.d0 + f[4] * s.d1;
+  const T u = s.uc;
+  const T ku = v - a.eta * u;
+  const T kv = f[5] * (lap + source<T>(ssrc, psi, u));
+  combine<STAGE, NT, T>(a, idx, cin, u, v, ku, kv);
+  if (i0 >= d.N0 - NG) {
+    // outer point: radiation condition with a one-sided xx0 derivative
+    const int q = i0 + NG - d.N0;
+    const unsigned o = row + (unsigned)(i0 + NG);
+    const unsigned ko = (unsigned)q + (unsigned)NG * (unsigned)i1;
+    const unsigned o2d = (unsigned)NG * (unsigned)d.N1;
     const T c = a.ofac[ko], rinv = a.ofac[o2d + ko], qd = a.ofac[2 * o2d + ko];
-    const T u0 = a.uin[idx], u1 = a.uin[idx - 1], u2 = a.uin[idx - 2];
-    const T v0 = a.vin[idx], v1 = a.vin[idx - 1], v2 = a.vin[idx - 2];
-    const T ku = -c * (u0 * rinv + ((T)3 * u0 - (T)4 * u1 + u2) * qd);
-    const T kv = -c * (v0 * rinv + ((T)3 * v0 - (T)4 * v1 + v2) * qd);
-    combine<STAGE, T>(a, idx, u0, v0, ku, kv);
+    const T u0 = a.uin[o], u1 = a.uin[o - 1], u2 = a.uin[o - 2];
+    const T v0 = a.vin[o], v1 = a.vin[o - 1], v2 = a.vin[o - 2];
+    CombineIn<STAGE, NT, T> co;
+    co.load(a, o);
+    const T kuo = -c * (u0 * rinv + ((T)3 * u0 - (T)4 * u1 + u2) * qd);
+    const T kvo = -c * (v0 * rinv + ((T)3 * v0 - (T)4 * v1 + v2) * qd);
+    combine<STAGE, NT, T>(a, o, co, u0, v0, kuo, kvo);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Phi-marching variant of the stage kernel. A block owns a TX x TY patch of
+// (x0, x1) columns and walks `chunk` consecutive phi planes. The 2*NG+1 phi
+// taps of each column sit in a register queue (each u value is loaded once per
+// column instead of once per tap), the rim-extended x0-x1 tile is double
+// buffered in LDS, and the next plane's tile, queue value and per-point
+// operands are prefetched while the current plane is computed. The 2D
+// Laplacian coefficients are loaded once per column.
+
+// The rim-extended tile of one plane, split into a global-to-register fetch and
+// a register-to-LDS store so the fetch can run one plane ahead.
+template <int NG, typename T>
+struct TileRegs {
+  static constexpr int W = TileShape<NG>::W, H = TileShape<NG>::H;
+  static constexpr int NE = (W * H + kTileThreads - 1) / kTileThreads;
+  T v[NE];
+  __device__ __forceinline__ void fetch(const T* __restrict__ U, const Dims& d, int x0b, int x1b,
+                                        int i2) {
+    const int tid = threadIdx.x + TX * threadIdx.y;
+    const unsigned plane = (unsigned)d.P0 * (unsigned)d.N1;
+    const unsigned b0 = plane * (unsigned)i2;
+    const unsigned bh = plane * (unsigned)half_turn(i2, d.N2);
+#pragma unroll
+    for (int r = 0; r < NE; ++r) {
+      const int e = tid + r * kTileThreads;
+      const int l1 = e / W;
+      const int l0 = e - l1 * W;
+      const int j0 = x0b + l0 - NG;
+      const int j1 = x1b + l1 - NG;
+      T val = (T)0;
+      if (e < W * H) {
+        if (j1 >= 0 && j1 < d.N1) {
+          if (j0 >= 0) {
+            if (j0 < d.P0) val = U[b0 + (unsigned)j0 + (unsigned)d.P0 * (unsigned)j1];
+          } else {
+            const int r1 = d.sph ? d.N1 - 1 - j1 : j1;
+            val = U[bh + (unsigned)(-1 - j0) + (unsigned)d.P0 * (unsigned)r1];
+          }
+        } else if (j0 >= 0 && j0 < d.P0 && j1 >= -NG && j1 < d.N1 + NG) {
+          const int r1 = j1 < 0 ? -1 - j1 : 2 * d.N1 - 1 - j1;
+          val = U[bh + (unsigned)j0 + (unsigned)d.P0 * (unsigned)r1];
+        }
+      }
+      v[r] = val;
+    }
+  }
+  __device__ __forceinline__ void store(T* __restrict__ tile) const {
+    const int tid = threadIdx.x + TX * threadIdx.y;
+#pragma unroll
+    for (int r = 0; r < NE; ++r) {
+      const int e = tid + r * kTileThreads;
+      if (e < W * H) tile[e] = v[r];
+    }
+  }
+};
+
+// Operands of one interior point that are read once per stage.
+template <int STAGE, typename T>
+struct PointIn {
+  T v, psi, ssrc, un, vn, au, av;
+  __device__ __forceinline__ void load(const StageArgs<T>& a, unsigned idx) {
+    v = a.vin[idx];
+    psi = a.psi[idx];
+    ssrc = a.ssrc[idx];
+    if constexpr (STAGE == 2 || STAGE == 3) {
+      un = a.un[idx];
+      vn = a.vn[idx];
+    }
+    if constexpr (STAGE != 1) {
+      au = a.au[idx];
+      av = a.av[idx];
+    }
+  }
+};
+
+template <int STAGE, typename T>
+__device__ __forceinline__ void combine_pt(const StageArgs<T>& a, unsigned idx,
+                                           const PointIn<STAGE, T>& c, T uin, T ku, T kv) {
+  if constexpr (STAGE == 1) {
+    a.uout[idx] = uin + a.cy * ku;
+    a.vout[idx] = c.v + a.cy * kv;
+    a.au[idx] = uin + a.ca * ku;
+    a.av[idx] = c.v + a.ca * kv;
+  } else if constexpr (STAGE == 4) {
+    a.uout[idx] = c.au + a.ca * ku;
+    a.vout[idx] = c.av + a.ca * kv;
+  } else {
+    a.uout[idx] = c.un + a.cy * ku;
+    a.vout[idx] = c.vn + a.cy * kv;
+    a.au[idx] = c.au + a.ca * ku;
+    a.av[idx] = c.av + a.ca * kv;
+  }
+}
+
+template <int NG>
+__device__ __forceinline__ int step_up(int j, int N) { return j + 1 == N ? 0 : j + 1; }
+
+template <typename T, int NG, int STAGE>
+__global__ void __launch_bounds__(kTileThreads, 4) k_stage_col(StageArgs<T> a, int chunk) {
+  constexpr int W = TileShape<NG>::W, H = TileShape<NG>::H;
+  constexpr Weights<NG> Wt{};
+  __shared__ T tile[2][W * H];
+  const Dims& d = a.d;
+  const int x0b = blockIdx.x * TX, x1b = blockIdx.y * TY;
+  const int z0 = blockIdx.z * chunk;
+  const int z1 = min(z0 + chunk, d.N2);
+  const int i0 = x0b + threadIdx.x, i1 = x1b + threadIdx.y;
+  const bool active = i0 < d.N0 && i1 < d.N1;
+  const unsigned plane = (unsigned)d.P0 * (unsigned)d.N1;
+  const unsigned col = (unsigned)i0 + (unsigned)d.P0 * (unsigned)i1;
+  const unsigned n2d = (unsigned)d.N0 * (unsigned)d.N1;
+  const unsigned k2 = (unsigned)i0 + (unsigned)d.N0 * (unsigned)i1;
+  const bool outer = active && i0 >= d.N0 - NG;
+
+  // phi register queue q[j] = u(z - NG + j), j = 0..2NG, for z = z0
+  T q[2 * NG + 1];
+  int jq = z0;  // (z0 - NG) mod N2, stepping down one plane at a time
+#pragma unroll
+  for (int k = 0; k < NG; ++k) jq = (jq == 0) ? d.N2 - 1 : jq - 1;
+  T f[6];
+  PointIn<STAGE, T> cur;
+  if (active) {
+#pragma unroll
+    for (int j = 0; j <= 2 * NG; ++j) {
+      q[j] = a.uin[col + plane * (unsigned)jq];
+      jq = step_up<NG>(jq, d.N2);
+    }
+#pragma unroll
+    for (int r = 0; r < 6; ++r) f[r] = a.fac[r * n2d + k2];
+    cur.load(a, col + plane * (unsigned)z0);
+  }
+  // jq now holds (z0 + NG + 1) mod N2: the plane the queue needs next
+  {
+    TileRegs<NG, T> t0;
+    t0.fetch(a.uin, d, x0b, x1b, z0);
+    t0.store(tile[0]);
+  }
+  __syncthreads();
+  for (int z = z0; z < z1; ++z) {
+    const int buf = (z - z0) & 1;
+    const bool more = z + 1 < z1;
+    // prefetch plane z + 1
+    TileRegs<NG, T> tn;
+    PointIn<STAGE, T> nxt;
+    T qn = (T)0;
+    if (more) {
+      tn.fetch(a.uin, d, x0b, x1b, z + 1);
+      if (active) {
+        qn = a.uin[col + plane * (unsigned)jq];
+        nxt.load(a, col + plane * (unsigned)(z + 1));
+      }
+    }
+    if (active) {
+      const T* r = tile[buf] + (threadIdx.y + NG) * W + (threadIdx.x + NG);
+      const T uc = r[0];
+      T d0 = 0, d1 = 0, e0 = 0, e1 = 0, e2 = 0;
+#pragma unroll
+      for (int k = 1; k <= NG; ++k) {
+        const T p0 = r[k], m0 = r[-k];
+        const T p1 = r[k * W], m1 = r[-k * W];
+        d0 += (T)Wt.d1[k] * (p0 - m0);
+        d1 += (T)Wt.d1[k] * (p1 - m1);
+        e0 += (T)Wt.d2[k] * (p0 + m0);
+        e1 += (T)Wt.d2[k] * (p1 + m1);
+        e2 += (T)Wt.d2[k] * (q[NG + k] + q[NG - k]);
+      }
+      const T w0 = (T)Wt.d2[0];
+      const T lap = f[0] * (e0 + w0 * uc) + f[1] * (e1 + w0 * uc) + f[2] * (e2 + w0 * uc) +
+                    f[3] * d0 + f[4] * d1;
+      const T ku = cur.v - a.eta * uc;
+      const T kv = f[5] * (lap + source<T>(cur.ssrc, cur.psi, uc));
+      const unsigned idx = col + plane * (unsigned)z;
+      combine_pt<STAGE, T>(a, idx, cur, uc, ku, kv);
+      if (outer) {
+        const int qo = i0 + NG - d.N0;
+        const unsigned o = idx + (unsigned)NG;
+        const unsigned ko = (unsigned)qo + (unsigned)NG * (unsigned)i1;
+        const unsigned o2d = (unsigned)NG * (unsigned)d.N1;
+        const T c = a.ofac[ko], rinv = a.ofac[o2d + ko], qd = a.ofac[2 * o2d + ko];
+        const T u0 = a.uin[o], u1 = a.uin[o - 1], u2 = a.uin[o - 2];
+        const T v0 = a.vin[o], v1 = a.vin[o - 1], v2 = a.vin[o - 2];
+        CombineIn<STAGE, false, T> co;
+        co.load(a, o);
+        const T kuo = -c * (u0 * rinv + ((T)3 * u0 - (T)4 * u1 + u2) * qd);
+        const T kvo = -c * (v0 * rinv + ((T)3 * v0 - (T)4 * v1 + v2) * qd);
+        combine<STAGE, false, T>(a, o, co, u0, v0, kuo, kvo);
+      }
+    }
+    if (more) {
+      tn.store(tile[buf ^ 1]);
+#pragma unroll
+      for (int j = 0; j < 2 * NG; ++j) q[j] = q[j + 1];
+      q[2 * NG] = qn;
+      cur = nxt;
+      jq = step_up<NG>(jq, d.N2);
+    }
+    __syncthreads();
   }
 }
 
 // Sum over a 64-wide wavefront, then over the block's wavefronts in a fixed
 // order. Returns the block total in thread 0.
+template <int NT>
 __device__ __forceinline__ double block_sum(double x) {
-  __shared__ double wsum[kBlock / 64];
+  __shared__ double wsum[NT / 64];
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int t = threadIdx.x + blockDim.x * threadIdx.y;
+  const int lane = t & 63, wid = t >> 6;
   if (lane == 0) wsum[wid] = x;
   __syncthreads();
   double tot = 0.0;
-  if (threadIdx.x == 0)
-    for (int w = 0; w < kBlock / 64; ++w) tot += wsum[w];
+  if (t == 0)
+    for (int w = 0; w < NT / 64; ++w) tot += wsum[w];
   return tot;
 }
 
+// Residual H (left-hand side of Eq. 4) in FP64 from a state of storage type S;
+// one partial sum of H^2 per block, same tiling as the stage kernel.
 template <typename S, int NG>
-__global__ void __launch_bounds__(kBlock) k_residual(ResidualArgs a) {
+__global__ void __launch_bounds__(kTileThreads) k_residual(ResidualArgs a) {
+  constexpr int W = TileShape<NG>::W, H = TileShape<NG>::H;
+  __shared__ double tile[W * H];
   const Dims& d = a.d;
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  double h2 = 0.0;
-  if (t < d.nint) {
-    const int i0 = t % d.N0;
-    const int r = t / d.N0;
-    const int i1 = r % d.N1;
-    const int i2 = r / d.N1;
-    const Addr ad(d, i0, i1, i2);
-    const S* U = static_cast<const S*>(a.u);
-    const Sums<NG, double, S> s = stencil<NG, double, S>(U, ad);
-    const int n2d = d.N0 * d.N1;
-    const int k2 = i0 + d.N0 * i1;
-    const double* F = a.fac;
-    const double lap = F[k2] * s.dd0 + F[n2d + k2] * s.dd1 + F[2 * n2d + k2] * s.dd2 +
-                       F[3 * n2d + k2] * s.d0 + F[4 * n2d + k2] * s.d1;
-    const double H = lap + source<double>(a.ssrc[ad.base], a.psi[ad.base], s.uc);
-    h2 = H * H;
+  const int x0b = blockIdx.x * TX, x1b = blockIdx.y * TY, i2 = blockIdx.z;
+  const S* U = static_cast<const S*>(a.u);
+  const int i0 = x0b + threadIdx.x, i1 = x1b + threadIdx.y;
+  const bool active = i0 < d.N0 && i1 < d.N1;
+  const unsigned n2d = (unsigned)d.N0 * (unsigned)d.N1;
+  const unsigned k2 = (unsigned)i0 + (unsigned)d.N0 * (unsigned)i1;
+  const unsigned idx =
+      (unsigned)i0 + (unsigned)d.P0 * ((unsigned)i1 + (unsigned)d.N1 * (unsigned)i2);
+  PhiTaps<NG, double, S> ph;
+  double psi = 0, ssrc = 0, f[5];
+  if (active) {
+    ph.load(U, d, i0, i1, i2);
+    psi = a.psi[idx];
+    ssrc = a.ssrc[idx];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) f[q] = a.fac[q * n2d + k2];
   }
-  const double tot = block_sum(h2);
-  if (threadIdx.x == 0) a.partial[blockIdx.x] = tot;
+  load_tile<NG, double, S>(tile, U, d, x0b, x1b, i2);
+  __syncthreads();
+  double h2 = 0.0;
+  if (active) {
+    const Sums<double> s = stencil<NG, double, S>(tile, ph);
+    const double lap = f[0] * s.dd0 + f[1] * s.dd1 + f[2] * s.dd2 + f[3] * s.d0 + f[4] * s.d1;
+    const double Hv = lap + source<double>(ssrc, psi, s.uc);
+    h2 = Hv * Hv;
+  }
+  const double tot = block_sum<kTileThreads>(h2);
+  if (threadIdx.x == 0 && threadIdx.y == 0)
+    a.partial[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = tot;
 }
 
 __global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ partial,
@@ -261,7 +556,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ 
                                                      double* __restrict__ out) {
   double s = 0.0;
   for (int j = threadIdx.x; j < nparts; j += kBlock) s += partial[j];
-  const double tot = block_sum(s);
+  const double tot = block_sum<kBlock>(s);
   if (threadIdx.x == 0) {
     out[0] = sqrt(tot / (double)nint);
     out[1] = tot;
@@ -334,57 +629,108 @@ __global__ void __launch_bounds__(kBlock) k_fill(T* __restrict__ dst, T value, i
 
 inline int nblocks(int n) { return (n + kBlock - 1) / kBlock; }
 
-template <typename T, int NG>
-hipError_t stage_dispatch(int stage, const StageArgs<T>& a, hipStream_t s) {
-  const int nb = nblocks(a.d.nint) + nblocks(a.d.nout);
-  switch (stage) {
-    case 1: k_stage<T, NG, 1><<<nb, kBlock, 0, s>>>(a); break;
-    case 2: k_stage<T, NG, 2><<<nb, kBlock, 0, s>>>(a); break;
-    case 3: k_stage<T, NG, 3><<<nb, kBlock, 0, s>>>(a); break;
-    case 4: k_stage<T, NG, 4><<<nb, kBlock, 0, s>>>(a); break;
-    default: return hipErrorInvalidValue;
-  }
+inline dim3 tile_grid(const Dims& d) {
+  return dim3((d.N0 + TX - 1) / TX, (d.N1 + TY - 1) / TY, d.N2);
+}
+
+// Launches kernel k with the tile grid, optionally bracketed by timing events
+// recorded in the same dispatch (hipExtLaunchKernelGGL).
+template <typename K, typename A>
+hipError_t tile_launch(K k, const A& args, const Dims& d, hipStream_t s, hipEvent_t t0,
+                       hipEvent_t t1) {
+  const dim3 grid = tile_grid(d), block(TX, TY, 1);
+  if (t0 && t1)
+    hipExtLaunchKernelGGL(k, grid, block, 0, s, t0, t1, 0, args);
+  else
+    k<<<grid, block, 0, s>>>(args);
   return hipGetLastError();
 }
 
+template <typename T, int NG, bool NT>
+hipError_t stage_dispatch_nt(int stage, const StageArgs<T>& a, hipStream_t s, hipEvent_t t0,
+                             hipEvent_t t1) {
+  switch (stage) {
+    case 1: return tile_launch(k_stage<T, NG, 1, NT>, a, a.d, s, t0, t1);
+    case 2: return tile_launch(k_stage<T, NG, 2, NT>, a, a.d, s, t0, t1);
+    case 3: return tile_launch(k_stage<T, NG, 3, NT>, a, a.d, s, t0, t1);
+    case 4: return tile_launch(k_stage<T, NG, 4, NT>, a, a.d, s, t0, t1);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename K, typename A>
+hipError_t col_launch(K k, const A& args, int chunk, hipStream_t s, hipEvent_t t0,
+                      hipEvent_t t1) {
+  const Dims& d = args.d;
+  const dim3 grid((d.N0 + TX - 1) / TX, (d.N1 + TY - 1) / TY, (d.N2 + chunk - 1) / chunk);
+  const dim3 block(TX, TY, 1);
+  if (t0 && t1)
+    hipExtLaunchKernelGGL(k, grid, block, 0, s, t0, t1, 0, args, chunk);
+  else
+    k<<<grid, block, 0, s>>>(args, chunk);
+  return hipGetLastError();
+}
+
+template <typename T, int NG>
+hipError_t stage_dispatch(int stage, const StageArgs<T>& a, hipStream_t s, hipEvent_t t0,
+                          hipEvent_t t1) {
+  if (a.variant == 2) {
+    const int ch = a.chunk > 0 ? a.chunk : 1;
+    switch (stage) {
+      case 1: return col_launch(k_stage_col<T, NG, 1>, a, ch, s, t0, t1);
+      case 2: return col_launch(k_stage_col<T, NG, 2>, a, ch, s, t0, t1);
+      case 3: return col_launch(k_stage_col<T, NG, 3>, a, ch, s, t0, t1);
+      case 4: return col_launch(k_stage_col<T, NG, 4>, a, ch, s, t0, t1);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return a.streaming ? stage_dispatch_nt<T, NG, true>(stage, a, s, t0, t1)
+                     : stage_dispatch_nt<T, NG, false>(stage, a, s, t0, t1);
+}
+
 template <typename T>
-hipError_t stage_order(int order, int stage, const StageArgs<T>& a, hipStream_t s) {
+hipError_t stage_order(int order, int stage, const StageArgs<T>& a, hipStream_t s,
+                       hipEvent_t t0, hipEvent_t t1) {
   switch (order) {
-    case 2: return stage_dispatch<T, 1>(stage, a, s);
-    case 4: return stage_dispatch<T, 2>(stage, a, s);
-    case 6: return stage_dispatch<T, 3>(stage, a, s);
-    case 8: return stage_dispatch<T, 4>(stage, a, s);
-    case 10: return stage_dispatch<T, 5>(stage, a, s);
+    case 2: return stage_dispatch<T, 1>(stage, a, s, t0, t1);
+    case 4: return stage_dispatch<T, 2>(stage, a, s, t0, t1);
+    case 6: return stage_dispatch<T, 3>(stage, a, s, t0, t1);
+    case 8: return stage_dispatch<T, 4>(stage, a, s, t0, t1);
+    case 10: return stage_dispatch<T, 5>(stage, a, s, t0, t1);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename S>
-hipError_t residual_order(int order, const ResidualArgs& a, int nb, hipStream_t s) {
+hipError_t residual_order(int order, const ResidualArgs& a, hipStream_t s) {
   switch (order) {
-    case 2: k_residual<S, 1><<<nb, kBlock, 0, s>>>(a); break;
-    case 4: k_residual<S, 2><<<nb, kBlock, 0, s>>>(a); break;
-    case 6: k_residual<S, 3><<<nb, kBlock, 0, s>>>(a); break;
-    case 8: k_residual<S, 4><<<nb, kBlock, 0, s>>>(a); break;
-    case 10: k_residual<S, 5><<<nb, kBlock, 0, s>>>(a); break;
+    case 2: return tile_launch(k_residual<S, 1>, a, a.d, s, nullptr, nullptr);
+    case 4: return tile_launch(k_residual<S, 2>, a, a.d, s, nullptr, nullptr);
+    case 6: return tile_launch(k_residual<S, 3>, a, a.d, s, nullptr, nullptr);
+    case 8: return tile_launch(k_residual<S, 4>, a, a.d, s, nullptr, nullptr);
+    case 10: return tile_launch(k_residual<S, 5>, a, a.d, s, nullptr, nullptr);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_stage(int order, int stage, const StageArgs<double>& a, hipStream_t s) {
-  return stage_order<double>(order, stage, a, s);
-}
-hipError_t launch_stage(int order, int stage, const StageArgs<float>& a, hipStream_t s) {
-  return stage_order<float>(order, stage, a, s);
+int residual_blocks(const Dims& d) {
+  const dim3 g = tile_grid(d);
+  return (int)(g.x * g.y * g.z);
 }
 
-hipError_t launch_residual(int order, bool fp32_state, const ResidualArgs& a, int nb,
-                           hipStream_t s) {
-  return fp32_state ? residual_order<float>(order, a, nb, s)
-                    : residual_order<double>(order, a, nb, s);
+hipError_t launch_stage(int order, int stage, const StageArgs<double>& a, hipStream_t s,
+                        hipEvent_t t0, hipEvent_t t1) {
+  return stage_order<double>(order, stage, a, s, t0, t1);
+}
+hipError_t launch_stage(int order, int stage, const StageArgs<float>& a, hipStream_t s,
+                        hipEvent_t t0, hipEvent_t t1) {
+  return stage_order<float>(order, stage, a, s, t0, t1);
+}
+
+hipError_t launch_residual(int order, bool fp32_state, const ResidualArgs& a, hipStream_t s) {
+  return fp32_state ? residual_order<float>(order, a, s) : residual_order<double>(order, a, s);
 }
 
 hipError_t launch_finalize(const double* partial, int nparts, int nint, double* out,

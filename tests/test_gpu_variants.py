@@ -1,0 +1,77 @@
+"""The two stage-kernel variants (plane tiles; phi-marching columns with a
+register queue) and the cache-policy switch compute the same arithmetic in
+the same order: their trajectories must agree with each other (to a few
+roundoff units) and with the oracle, including ragged phi chunks."""
+import numpy as np
+import pytest
+
+import paper_2501_14030_amd as hr
+from paper_2501_14030_amd import workloads
+
+from gpu_common import banner, gpu_grid, oracle_extended, oracle_grid, rel_maxdiff
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    (workloads.GridSpec(0, 32, 16, 4, 8, bscale=1.0), 3),
+    (workloads.GridSpec(0, 37, 19, 6, 10, bscale=1.0), 4),
+    (workloads.GridSpec(1, 33, 18, 10, 8, rmax=50.0), 3),
+    (workloads.GridSpec(0, 70, 20, 2, 10, amax=100.0, sinhwaa=0.2, bscale=1.0), 1),
+]
+
+
+def _relax(spec, pz, cfg, n_steps, dt):
+    g = gpu_grid(spec)
+    g.set_kernel_config(**cfg)
+    g.set_punctures(*pz.as_tuple())
+    res = g.relax(6.0, 1.0, dt, n_steps, 0.0, check_every=100)
+    assert res.status == hr.OK
+    return g.get_u(extended=True), g.get_v(extended=True), res.history
+
+
+@pytest.mark.parametrize("spec,chunk", CASES)
+def test_column_variant_matches_oracle_and_plane_variant(spec, chunk):
+    banner(f"variants {spec.name()} chunk {chunk}")
+    pz = workloads.quasi_circular(2.3, 2 * spec.bscale if spec.coords == 0 else 8.0,
+                                  [0.0, 0.3, 0.1], [0.2, 0.0, -0.3])
+    og = oracle_grid(spec)
+    og.set_punctures(*pz.as_tuple())
+    dt = og.suggest_dt(0.5)
+    og.relax(6.0, 1.0, dt, 300, 0.0, 100)
+    ou, _ = og.state()
+    up, vp, hp = _relax(spec, pz, dict(variant=1, streaming=0), 300, dt)
+    uc, vc, hc = _relax(spec, pz, dict(variant=2, streaming=0, chunk=chunk), 300, dt)
+    un, vn, hn = _relax(spec, pz, dict(variant=1, streaming=1), 300, dt)
+    d_or = rel_maxdiff(uc, oracle_extended(og, ou))
+    d_pc = rel_maxdiff(uc, up)
+    banner(f"column vs oracle {d_or:.2e}, column vs plane {d_pc:.2e}")
+    assert d_or <= 1e-12
+    assert d_pc <= 1e-14 and rel_maxdiff(vc, vp) <= 1e-14
+    np.testing.assert_allclose(hc, hp, rtol=1e-12, atol=1e-16)
+    # the cache-policy switch changes nothing numerically
+    assert np.array_equal(un, up) and np.array_equal(vn, vp)
+
+
+def test_automatic_variant_choice_on_paper_scale():
+    w = workloads.paper_scale()
+    g = gpu_grid(w.grid)
+    cfg = g.kernel_config()
+    assert cfg["variant"] == 0 and cfg["streaming"] == -1
+    g.set_kernel_config(variant=2, streaming=0, chunk=0)
+    g.set_punctures(*w.punctures.as_tuple())
+    r = g.relax(w.eta, 1.0, 0.0, 100, 0.0, check_every=100)
+    uc = g.get_u(extended=True)
+    g.set_kernel_config(variant=1, streaming=0, chunk=0)
+    g.set_punctures(*w.punctures.as_tuple())
+    g.relax(w.eta, 1.0, 0.0, 100, 0.0, check_every=100)
+    assert rel_maxdiff(uc, g.get_u(extended=True)) <= 1e-14
+    assert r.status == hr.OK
+
+
+def test_invalid_kernel_config_rejected():
+    w = workloads.equal_mass_small()
+    g = gpu_grid(w.grid)
+    with pytest.raises(hr.HRError):
+        g.set_kernel_config(variant=5)
+    with pytest.raises(hr.HRError):
+        g.set_kernel_config(variant=2, chunk=-1)
