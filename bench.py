@@ -16,6 +16,7 @@ the host's cores.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,6 +30,34 @@ import numpy as np  # noqa: E402
 
 METRIC = ("grid-pt RHS updates/sec (FP64 vs FP32+FP64 finish); wall time to residual 1e-10")
 HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2501_14030_amd", "csrc", "hr_kernels.hip")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "stage_kernel_pmc.json")
+
+
+def kernel_sha() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(shape, prec: str):
+    """Per-launch HBM bytes (mean over the four stage kernels) from the committed
+    rocprofv3 PMC summary, if it was taken on the current kernel source; FETCH_SIZE
+    and WRITE_SIZE are scaled by what they read for a plain copy of known size."""
+    try:
+        with open(PMC_SUMMARY) as f:
+            pmc = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if pmc.get("kernel_sha") != kernel_sha():
+        return None
+    key = f"{shape[0]}x{shape[1]}x{shape[2]}_{prec}"
+    ent = pmc.get("runs", {}).get(key)
+    if not ent:
+        return None
+    ff = pmc["calibration"]["fetch_factor"]
+    wf = pmc["calibration"]["write_factor"]
+    per = [1024.0 * (ff * fk + wf * wk) for fk, wk in zip(ent["fetch_kib"], ent["write_kib"])]
+    return sum(per) / len(per)
 
 
 def log(msg: str) -> None:
@@ -58,6 +87,61 @@ def stage_algorithmic_bytes(spec, itemsize: int):
     bi, bo = stage_bytes_per_point(itemsize)
     tables = itemsize * (6 * N0 * N1 + 3 * ng * N1)
     return [nint * bi[s] + nout * bo[s] + tables for s in range(4)]
+
+
+def roofline_entry(g, hr, spec, w, prec, nsteps=20):
+    """Stage-kernel roofline on the HBM bound: algorithmic bytes per launch over the
+    mean launch duration (HIP events recorded in each kernel's own dispatch)."""
+    item = 8 if prec == hr.FP64 else 4
+    us = g.time_stage_kernels(w.eta, w.kappa, 0.0, nsteps, prec)
+    byts = stage_algorithmic_bytes(spec, item)
+    agg = sum(byts) / (sum(us[:4]) * 1e-6) / 1e9
+    tr = measured_traffic(spec.shape, "fp64" if prec == hr.FP64 else "fp32")
+    return {
+        "bound": "hbm", "achieved": agg, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": agg / HBM_PEAK_GBS, "traffic": tr,
+        "kernel": f"fused RK4 stage kernel ({'FP64' if prec == hr.FP64 else 'FP32'}, "
+                  f"order {spec.fd_order}, {spec.N0}x{spec.N1}x{spec.N2}, config "
+                  f"{g.kernel_config()}), mean over stages 1-4",
+        "avg_launch_us": [float(x) for x in us[:4]],
+        "algorithmic_bytes_per_launch": byts,
+        "algorithmic_bytes_mean": sum(byts) / 4,
+        "traffic_over_algorithmic": (tr / (sum(byts) / 4)) if tr else None,
+    }
+
+
+def kernel_profile(shape_s: str, prec_s: str) -> int:
+    """Only the stage kernels at one shape (for rocprofv3 counter passes)."""
+    import torch
+
+    import paper_2501_14030_amd as hr
+    from paper_2501_14030_amd import workloads
+
+    shape = tuple(int(x) for x in shape_s.split("x"))
+    w = workloads.paper_scale()
+    torch.cuda.set_device(0)
+    g = hr.grid_create(0, *shape, 10, params=hr.default_params(bscale=w.grid.bscale))
+    g.set_punctures(*w.punctures.as_tuple())
+    prec = hr.FP64 if prec_s == "fp64" else hr.FP32
+    us = g.time_stage_kernels(w.eta, w.kappa, 0.0, 3, prec)
+    print(json.dumps({"shape": shape, "prec": prec_s, "avg_launch_us": list(us),
+                      "config": g.kernel_config(), "kernel_sha": kernel_sha()}), flush=True)
+    return 0
+
+
+def copy_calibration() -> int:
+    """A plain device copy of known size (1 GiB each way), for scaling the
+    FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+
+    n = 1 << 27
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": n * 8}), flush=True)
+    return 0
 
 
 def run_solve(hr, g, w, precision):
@@ -122,7 +206,16 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--kernel-profile", metavar="N0xN1xN2", default=None,
+                    help="only run the stage kernels at this shape (counter passes)")
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
+    if args.kernel_profile:
+        return kernel_profile(args.kernel_profile, args.prec)
+    if args.copy_calibration:
+        return copy_calibration()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the relaxation of "
               "one grid is not sharded across GPUs in this build.", file=sys.stderr)
@@ -186,28 +279,20 @@ def main() -> int:
             "max_rel_diff_u_vs_fp64": float(np.abs(u32 - u64).max() / np.abs(u64).max()),
             "speedup_time_to_residual": (t64 / args.steps) / (t32 / args.steps),
         }
-    # roofline of the dominant kernel (the fused RK4 stage kernel), timed with HIP
-    # events on the grid's stream
+    # roofline of the dominant kernel (the fused RK4 stage kernel)
     g.set_punctures(*w.punctures.as_tuple())
-    nsteps_t = 50
-    us = g.time_stage_kernels(w.eta, w.kappa, 0.0, nsteps_t, hr.FP64)
-    byts = stage_algorithmic_bytes(spec, 8)
-    gbs = [byts[s] / (us[s] * 1e-6) / 1e9 for s in range(4)]
-    agg = sum(byts) / (sum(us[:4]) * 1e-6) / 1e9
-    out["roofline"] = {
-        "bound": "hbm", "achieved": agg, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": agg / HBM_PEAK_GBS, "traffic": None,
-        "kernel": "k_stage<double,5,s> (fused RHS+BC+RK4 stage), mean over stages 1-4",
-        "avg_launch_us": [float(x) for x in us[:4]],
-        "algorithmic_bytes_per_launch": byts,
-        "per_stage_GBs": gbs,
-    }
-    us32 = g.time_stage_kernels(w.eta, w.kappa, 0.0, nsteps_t, hr.FP32)
-    byts32 = stage_algorithmic_bytes(spec, 4)
-    out["roofline_fp32"] = {
-        "achieved": sum(byts32) / (sum(us32[:4]) * 1e-6) / 1e9, "unit": "GB/s",
-        "avg_launch_us": [float(x) for x in us32[:4]],
-    }
+    out["roofline"] = roofline_entry(g, hr, spec, w, hr.FP64)
+    out["roofline_fp32"] = roofline_entry(g, hr, spec, w, hr.FP32)
+    if not args.no_large:
+        # the paper's roofline grid, 512x512x64: working set well beyond the caches
+        big = workloads.GridSpec(0, 512, 512, 64, 10, bscale=spec.bscale)
+        gb = hr.grid_create(0, 512, 512, 64, 10, params=hr.default_params(bscale=spec.bscale))
+        gb.set_punctures(*w.punctures.as_tuple())
+        out["roofline_512x512x64"] = roofline_entry(gb, hr, big, w, hr.FP64, nsteps=5)
+        out["roofline_512x512x64_fp32"] = roofline_entry(gb, hr, big, w, hr.FP32, nsteps=5)
+        gb.close()
+        del gb
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         cb = cpu_baseline(w, args.cpu_seconds)
