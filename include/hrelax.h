@@ -58,8 +58,11 @@ typedef enum {
 
 typedef enum {
   HR_FP64 = 0,            /* every step in double precision */
-  HR_FP32 = 1,            /* bulk steps in single precision only */
-  HR_FP32_FP64FINISH = 2  /* single precision until the switch, then double */
+  HR_FP32 = 1,            /* every step in single precision (state rounded to FP32;
+                             the residual floor is set by single precision) */
+  HR_FP32_FP64FINISH = 2  /* split state: FP64 base + FP32 increment integrated in
+                             single precision, FP64 rebase/residual/stop test every
+                             check, then plain FP64 steps to the tolerance */
 } hr_precision;
 
 /*
@@ -167,10 +170,19 @@ hr_status hr_relax(hr_grid* g, double eta, double c, double dt, long n_steps,
                    hr_relax_report* rep);
 
 /*
- * Switch rule for HR_FP32_FP64FINISH: the single-precision phase ends at the
- * first check whose residual is below switch_residual, or after stall_checks
- * consecutive checks without a new minimum, or after max_fp32_steps steps
- * (<= 0: no cap). Defaults: 1e-6, 2, no cap.
+ * HR_FP32_FP64FINISH, the single-precision bulk with a double-precision finish
+ * (paper: strongly typed single-precision builds, "Roofline Analysis"
+ * subsection). The state is split into an FP64 base y_b and an FP32 increment
+ * e. Every check_every steps: the FP64 slopes k(y_b) are evaluated once, e
+ * starts from 0 and is integrated with RK4 in FP32 using the slope
+ * k(y_b) + L e + S_src[(psi_s + u_b + e_u)^-7 - (psi_s + u_b)^-7] (L the linear
+ * part of Eq. 5 with its boundary conditions), then y_b += e in FP64 and the
+ * FP64 residual of y_b is checked. In exact arithmetic this is the FP64 RK4
+ * trajectory; rounding is relative to the increment, not to u. The phase
+ * ends, and plain FP64 steps continue to the tolerance, at the first check
+ * whose residual is below switch_residual (0: ten times tol), after
+ * stall_checks consecutive checks without a new minimum, or after
+ * max_fp32_steps steps (<= 0: no cap). Defaults: 0, 8, no cap.
  */
 hr_status hr_set_fp32_switch(hr_grid* g, double switch_residual, int stall_checks,
                              long max_fp32_steps);
@@ -214,6 +226,19 @@ hr_status hr_set_kernel_config(hr_grid* g, const hr_kernel_config* cfg);
 hr_status hr_get_kernel_config(const hr_grid* g, hr_kernel_config* cfg);
 
 /*
+ * Autotuner: times the stage kernels of this grid in precision prec (HR_FP64
+ * or HR_FP32) for every candidate configuration -- plane tiles, and phi
+ * columns with chunk 1, 2, 4, ... up to N2 -- over n_steps (>= 1) rounds of
+ * stages 1-3 (which never write the state y_n, so the state is unchanged),
+ * keeps the fastest in the grid (as hr_set_kernel_config would) and in a
+ * process-wide cache keyed by (N0, N1, N2, fd_order, prec); a cached shape is
+ * not timed again. best and best_us (optional) receive the choice and its mean
+ * stage time in microseconds. Errors: HR_EINVAL, HR_ESTATE, HR_EDEVICE.
+ */
+hr_status hr_autotune(hr_grid* g, hr_precision prec, int n_steps, hr_kernel_config* best,
+                      double* best_us);
+
+/*
  * Measurement: runs n_steps RK4 steps of the current state in precision prec
  * (HR_FP64 or HR_FP32), bracketing every stage-kernel launch with hipEvents
  * recorded on the grid's stream, and returns in avg_us[0..3] the mean duration
@@ -222,6 +247,86 @@ hr_status hr_get_kernel_config(const hr_grid* g, hr_kernel_config* cfg);
  */
 hr_status hr_time_stage_kernels(hr_grid* g, double eta, double c, double dt, long n_steps,
                                 hr_precision prec, double* avg_us);
+
+/*
+ * Batched relaxation (catalogs of configurations; the paper relaxes several
+ * independent patches with one CUDA stream each, "Multiple, Independent
+ * Patches" subsection). A batch groups n bound grids of the same fd_order on
+ * one device; the grids stay owned by the caller and must outlive the batch.
+ * Every RK stage is one persistent kernel launch over all grids still
+ * relaxing; the launches of one check interval are captured once in a HIP
+ * graph and replayed. Each grid keeps its own dt (cfl * ds_g), eta and
+ * wave-speed scale, and stops at its own first check below tol.
+ *   hr_batch_create     n >= 1 distinct bound grids (array copied). Errors:
+ *                       HR_EINVAL, HR_ESTATE (a grid not bound).
+ *   hr_batch_workspace_bytes / hr_batch_bind
+ *                       device memory for descriptors and work lists, owned
+ *                       by the caller, 256-byte aligned; hip_stream NULL = the
+ *                       library creates one (default priority).
+ *   hr_batch_relax      eta[n], c[n] per grid; n_steps is rounded up to a
+ *                       multiple of check_every; prec HR_FP64 or
+ *                       HR_FP32_FP64FINISH (each grid switches to FP64 by its
+ *                       own rule, see hr_set_fp32_switch); reps: optional array
+ *                       of n reports. Returns HR_OK when every grid converged
+ *                       (or, with tol <= 0, ran n_steps), else HR_ENONFINITE /
+ *                       HR_ENOTCONV; HR_EINVAL, HR_ESTATE, HR_EDEVICE.
+ *   hr_batch_destroy    frees host resources (never the caller's memory).
+ */
+typedef struct hr_batch hr_batch;
+
+hr_status hr_batch_create(int n, hr_grid* const* grids, hr_batch** out);
+size_t hr_batch_workspace_bytes(const hr_batch* b);
+hr_status hr_batch_bind(hr_batch* b, void* dev_ptr, size_t bytes, void* hip_stream);
+hr_status hr_batch_relax(hr_batch* b, const double* eta, const double* c, long n_steps,
+                         double tol, int check_every, hr_precision prec,
+                         hr_relax_report* reps);
+void hr_batch_destroy(hr_batch* b);
+
+/*
+ * Learned warm start. An MLP (FP32) maps 13 features -- 9 configuration
+ * values (caller-normalised: mass ratio, spins chi1 and chi2, momentum
+ * magnitude, separation) and 4 coordinate values of a grid point
+ * (2 xx0/xx0_max - 1, cos xx1, sin xx1 cos xx2, sin xx1 sin xx2) -- through
+ * two hidden layers of `width` GELU units to y, with log u = scale y + shift.
+ * Trained on the relaxation's own solves; its prediction is only an initial
+ * state, which the relaxation then drives to the residual tolerance.
+ *   hr_mlp_create          width (multiple of 8, 8..1024); He-normal
+ *                          weights from seed, zero biases (host side).
+ *   hr_mlp_param_count     parameters, laid out W1[width x 13], b1, W2[width x
+ *                          width], b2, W3[1 x width], b3 (row-major, FP32).
+ *   hr_mlp_workspace_bytes / hr_mlp_bind
+ *                          caller-owned device memory for parameters, Adam
+ *                          moments and activations of up to max_batch rows
+ *                          (1..262144); 256-byte aligned; stream NULL = own.
+ *   hr_mlp_get/set_params  host copies (count = hr_mlp_param_count).
+ *   hr_mlp_set_output_map  scale (non-zero) and shift of log u.
+ *   hr_mlp_forward         host x[B x 13] -> host y[B] (network output y).
+ *   hr_mlp_gradients       host x, host targets t[B] -> loss = mean (y-t)^2
+ *                          and its gradient w.r.t. every parameter (host).
+ *   hr_mlp_train_step      device x[B x 13], device t[B]: loss, gradient and
+ *                          one Adam step (beta1 0.9, beta2 0.999, eps 1e-8).
+ *   hr_mlp_grid_features   device out[n_extended x 13] for a bound grid.
+ *   hr_warm_start          sets u = exp(scale y + shift) and v = eta u at every
+ *                          stored point of the grid (punctures must be set).
+ * Errors: HR_EINVAL, HR_ESTATE, HR_ENOMEM, HR_EDEVICE.
+ */
+typedef struct hr_mlp hr_mlp;
+
+hr_status hr_mlp_create(int width, unsigned long long seed, hr_mlp** out);
+size_t hr_mlp_param_count(const hr_mlp* n);
+size_t hr_mlp_workspace_bytes(const hr_mlp* n, int max_batch);
+hr_status hr_mlp_bind(hr_mlp* n, void* dev_ptr, size_t bytes, int max_batch, void* hip_stream);
+void hr_mlp_destroy(hr_mlp* n);
+hr_status hr_mlp_get_params(const hr_mlp* n, float* host, size_t count);
+hr_status hr_mlp_set_params(hr_mlp* n, const float* host, size_t count);
+hr_status hr_mlp_set_output_map(hr_mlp* n, float scale, float shift);
+hr_status hr_mlp_forward(hr_mlp* n, const float* host_x, int batch, float* host_y);
+hr_status hr_mlp_gradients(hr_mlp* n, const float* host_x, const float* host_t, int batch,
+                           float* host_grad, float* loss);
+hr_status hr_mlp_train_step(hr_mlp* n, const float* dev_x, const float* dev_t, int batch,
+                            float lr, float* loss);
+hr_status hr_mlp_grid_features(hr_mlp* n, const hr_grid* g, const double* cfg9, float* dev_out);
+hr_status hr_warm_start(hr_grid* g, hr_mlp* n, const double* cfg9, double eta);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* hr_last_error(void);

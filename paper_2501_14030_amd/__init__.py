@@ -93,6 +93,16 @@ _SIGNATURES = {
                                              ctypes.c_double, ctypes.c_long, ctypes.c_int, _dp]),
     "hr_set_kernel_config": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KernelConfig)]),
     "hr_get_kernel_config": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KernelConfig)]),
+    "hr_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(KernelConfig), _dp]),
+    "hr_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.POINTER(ctypes.c_void_p)]),
+    "hr_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p]),
+    "hr_batch_bind": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                     ctypes.c_void_p]),
+    "hr_batch_relax": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, ctypes.c_long, ctypes.c_double,
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
+    "hr_batch_destroy": (None, [ctypes.c_void_p]),
     "hr_last_error": (ctypes.c_char_p, []),
 }
 
@@ -234,7 +244,7 @@ class Grid:
         return RelaxResult(st, rep.steps_taken, rep.fp32_steps, rep.residual, rep.dt_used,
                            hist[:min(rep.n_history, cap)].copy())
 
-    def set_fp32_switch(self, switch_residual: float = 1e-6, stall_checks: int = 2,
+    def set_fp32_switch(self, switch_residual: float = 0.0, stall_checks: int = 8,
                         max_fp32_steps: int = 0) -> None:
         _check(load_library().hr_set_fp32_switch(self._h, float(switch_residual),
                                                  int(stall_checks), int(max_fp32_steps)),
@@ -284,6 +294,15 @@ class Grid:
         _check(load_library().hr_set_kernel_config(self._h, ctypes.byref(cfg)),
                "hr_set_kernel_config")
 
+    def autotune(self, precision: int = FP64, n_steps: int = 5) -> tuple:
+        """Times the candidate kernel configurations, keeps the fastest; returns
+        (config dict, mean stage microseconds). The state is unchanged."""
+        cfg = KernelConfig()
+        us = ctypes.c_double()
+        _check(load_library().hr_autotune(self._h, int(precision), int(n_steps), ctypes.byref(cfg),
+                                          ctypes.byref(us)), "hr_autotune")
+        return {"variant": cfg.variant, "streaming": cfg.streaming, "chunk": cfg.chunk}, us.value
+
     def kernel_config(self) -> dict:
         cfg = KernelConfig()
         _check(load_library().hr_get_kernel_config(self._h, ctypes.byref(cfg)),
@@ -295,6 +314,63 @@ class Grid:
         _check(load_library().hr_suggest_dt(self._h, float(cfl), ctypes.byref(out)),
                "hr_suggest_dt")
         return out.value
+
+
+class Batch:
+    """Many bound grids (same fd_order) relaxed together: one persistent launch per
+    RK stage over every grid still relaxing, graph-captured per check interval."""
+
+    def __init__(self, grids, stream=None):
+        import torch
+
+        L = load_library()
+        self.grids = list(grids)
+        arr = (ctypes.c_void_p * len(self.grids))(*[g.handle.value for g in self.grids])
+        h = ctypes.c_void_p()
+        _check(L.hr_batch_create(len(self.grids), arr, ctypes.byref(h)), "hr_batch_create")
+        self._h = h
+        dev = self.grids[0].device
+        nbytes = L.hr_batch_workspace_bytes(h)
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        aligned = (self._ws.data_ptr() + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
+        with torch.cuda.device(dev):
+            _check(L.hr_batch_bind(h, ctypes.c_void_p(aligned), nbytes,
+                                   ctypes.c_void_p(self.stream.cuda_stream)), "hr_batch_bind")
+
+    def relax(self, eta, c=1.0, n_steps: int = 1000, tol: float = 0.0, check_every: int = 100,
+              precision: int = FP64, raise_on_error: bool = True) -> list:
+        n = len(self.grids)
+        eta = np.ascontiguousarray(np.broadcast_to(np.asarray(eta, dtype=np.float64), (n,)))
+        c = np.ascontiguousarray(np.broadcast_to(np.asarray(c, dtype=np.float64), (n,)))
+        cap = max(1, int(n_steps) // max(1, int(check_every)) + 2)
+        hists = [np.zeros(cap) for _ in range(n)]
+        reps = (RelaxReport * n)()
+        for i in range(n):
+            reps[i].history = hists[i].ctypes.data_as(_dp)
+            reps[i].history_cap = cap
+        st = load_library().hr_batch_relax(self._h, eta.ctypes.data_as(_dp), c.ctypes.data_as(_dp),
+                                           int(n_steps), float(tol), int(check_every),
+                                           int(precision), ctypes.cast(reps, ctypes.c_void_p))
+        if st not in (OK, ENOTCONV, ENONFINITE) or (raise_on_error and st == ENONFINITE):
+            _check(st, "hr_batch_relax")
+        self.status = st
+        return [RelaxResult(OK if reps[i].residual < tol or tol <= 0 else ENOTCONV,
+                            reps[i].steps_taken, reps[i].fp32_steps, reps[i].residual,
+                            reps[i].dt_used, hists[i][:min(reps[i].n_history, cap)].copy())
+                for i in range(n)]
+
+    def close(self) -> None:
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.hr_batch_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # Module-level functions named after the C ABI entry points.
@@ -320,6 +396,6 @@ def residual_l2(grid: Grid) -> float:
     return grid.residual_l2()
 
 
-__all__ = ["Grid", "GridParams", "RelaxResult", "HRError", "grid_create", "set_punctures",
+__all__ = ["Grid", "Batch", "GridParams", "RelaxResult", "HRError", "grid_create", "set_punctures",
            "relax", "get_u", "residual_l2", "load_library", "default_params",
            "SINHSYMTP", "SPHERICAL", "FP64", "FP32", "FP32_FP64FINISH"]

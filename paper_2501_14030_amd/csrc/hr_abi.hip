@@ -11,8 +11,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 
 #include "hr_internal.h"
 
@@ -21,6 +24,65 @@ namespace hr {
 static thread_local std::string g_err;
 
 void set_error(const std::string& msg) { g_err = msg; }
+
+namespace {
+hr_status kfail(hr_status s, const std::string& msg) {
+  set_error(msg);
+  return s;
+}
+}  // namespace
+
+#define HR_HIPK(call)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) return kfail(HR_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Kernel variant for this grid: explicit configuration, else by size (phi
+// columns when there are enough (x0, x1) tiles to fill the device).
+void resolve_variant(const hr_grid* g, int& variant, int& chunk) {
+  variant = g->variant;
+  chunk = g->chunk;
+  const long tiles = (long)((g->d.N0 + 63) / 64) * ((g->d.N1 + 7) / 8);
+  if (variant == 0) variant = (tiles * g->d.N2 >= 4096 && g->d.N2 >= 16) ? 2 : 1;
+  if (variant == 2 && chunk <= 0) {
+    // aim for about 2048 blocks, at least 4 planes per block
+    long c = (tiles * g->d.N2 + 2047) / 2048;
+    chunk = (int)std::max<long>(4, std::min<long>(c, g->d.N2));
+  }
+}
+
+
+// Uploads the wave-speed-dependent planes for scale kappa.
+hr_status load_kappa(hr_grid* g, double kappa) {
+  if (g->kappa_loaded == kappa) return HR_OK;
+  const Dims& d = g->d;
+  const int n2d = d.N0 * d.N1, o2d = d.NG * d.N1;
+  std::vector<double> fac(6 * (size_t)n2d), ofac(3 * (size_t)o2d);
+  std::memcpy(fac.data(), g->tab.alpha.data(), 5 * (size_t)n2d * sizeof(double));
+  for (int k = 0; k < n2d; ++k) {
+    const double c = kappa * g->tab.crat[k];
+    fac[5 * (size_t)n2d + k] = c * c;
+  }
+  for (int k = 0; k < o2d; ++k) {
+    ofac[k] = kappa * g->tab.ocrat[k];
+    ofac[o2d + k] = g->tab.orinv[k];
+    ofac[2 * (size_t)o2d + k] = g->tab.oq[k];
+  }
+  std::vector<float> fac32(fac.begin(), fac.end()), ofac32(ofac.begin(), ofac.end());
+  HR_HIPK(hipMemcpyAsync(g->f64.fac, fac.data(), fac.size() * sizeof(double),
+                        hipMemcpyHostToDevice, g->stream));
+  HR_HIPK(hipMemcpyAsync(g->f32.fac, fac32.data(), fac32.size() * sizeof(float),
+                        hipMemcpyHostToDevice, g->stream));
+  HR_HIPK(hipMemcpyAsync(g->f64.ofac, ofac.data(), ofac.size() * sizeof(double),
+                        hipMemcpyHostToDevice, g->stream));
+  HR_HIPK(hipMemcpyAsync(g->f32.ofac, ofac32.data(), ofac32.size() * sizeof(float),
+                        hipMemcpyHostToDevice, g->stream));
+  HR_HIPK(hipStreamSynchronize(g->stream));
+  g->kappa_loaded = kappa;
+  return HR_OK;
+}
+
 
 namespace {
 
@@ -57,7 +119,8 @@ size_t layout(hr_grid* g, char* base) {
                     &g->f64.vb, &g->f64.au, &g->f64.av, &g->f64.psi, &g->f64.ssrc};
   for (double** p : d64) *p = (double*)take(G * sizeof(double));
   float** d32[] = {&g->f32.un, &g->f32.vn, &g->f32.ua, &g->f32.va, &g->f32.ub,
-                   &g->f32.vb, &g->f32.au, &g->f32.av, &g->f32.psi, &g->f32.ssrc};
+                   &g->f32.vb, &g->f32.au, &g->f32.av, &g->f32.psi, &g->f32.ssrc,
+                   &g->f32.khu, &g->f32.khv, &g->f32.pb, &g->f32.sp7};
   for (float** p : d32) *p = (float*)take(G * sizeof(float));
   g->f64.fac = (double*)take(6 * (size_t)n2d * sizeof(double));
   g->f32.fac = (float*)take(6 * (size_t)n2d * sizeof(float));
@@ -72,93 +135,13 @@ size_t layout(hr_grid* g, char* base) {
   return off;
 }
 
-// Uploads the wave-speed-dependent planes for scale kappa.
-hr_status load_kappa(hr_grid* g, double kappa) {
-  if (g->kappa_loaded == kappa) return HR_OK;
-  const Dims& d = g->d;
-  const int n2d = d.N0 * d.N1, o2d = d.NG * d.N1;
-  std::vector<double> fac(6 * (size_t)n2d), ofac(3 * (size_t)o2d);
-  std::memcpy(fac.data(), g->tab.alpha.data(), 5 * (size_t)n2d * sizeof(double));
-  for (int k = 0; k < n2d; ++k) {
-    const double c = kappa * g->tab.crat[k];
-    fac[5 * (size_t)n2d + k] = c * c;
-  }
-  for (int k = 0; k < o2d; ++k) {
-    ofac[k] = kappa * g->tab.ocrat[k];
-    ofac[o2d + k] = g->tab.orinv[k];
-    ofac[2 * (size_t)o2d + k] = g->tab.oq[k];
-  }
-  std::vector<float> fac32(fac.begin(), fac.end()), ofac32(ofac.begin(), ofac.end());
-  HR_HIP(hipMemcpyAsync(g->f64.fac, fac.data(), fac.size() * sizeof(double),
-                        hipMemcpyHostToDevice, g->stream));
-  HR_HIP(hipMemcpyAsync(g->f32.fac, fac32.data(), fac32.size() * sizeof(float),
-                        hipMemcpyHostToDevice, g->stream));
-  HR_HIP(hipMemcpyAsync(g->f64.ofac, ofac.data(), ofac.size() * sizeof(double),
-                        hipMemcpyHostToDevice, g->stream));
-  HR_HIP(hipMemcpyAsync(g->f32.ofac, ofac32.data(), ofac32.size() * sizeof(float),
-                        hipMemcpyHostToDevice, g->stream));
-  HR_HIP(hipStreamSynchronize(g->stream));
-  g->kappa_loaded = kappa;
-  return HR_OK;
-}
-
-// Kernel variant for this grid: explicit configuration, else by size (phi
-// columns when there are enough (x0, x1) tiles to fill the device).
-void resolve_variant(const hr_grid* g, int& variant, int& chunk) {
-  variant = g->variant;
-  chunk = g->chunk;
-  const long tiles = (long)((g->d.N0 + 63) / 64) * ((g->d.N1 + 7) / 8);
-  if (variant == 0) variant = (tiles * g->d.N2 >= 4096 && g->d.N2 >= 16) ? 2 : 1;
-  if (variant == 2 && chunk <= 0) {
-    // aim for about 2048 blocks, at least 4 planes per block
-    long c = (tiles * g->d.N2 + 2047) / 2048;
-    chunk = (int)std::max<long>(4, std::min<long>(c, g->d.N2));
-  }
-}
-
 template <typename T>
-StageArgs<T> stage_args(const hr_grid* g, const Fields<T>& F, int stage, T eta, T dt) {
-  StageArgs<T> a{};
-  a.d = g->d;
-  a.psi = F.psi;
-  a.ssrc = F.ssrc;
-  a.fac = F.fac;
-  a.ofac = F.ofac;
-  a.eta = eta;
-  // non-temporal access measured no faster at any size: off unless asked for
-  a.streaming = g->streaming > 0 ? 1 : 0;
-  resolve_variant(g, a.variant, a.chunk);
-  a.un = F.un;
-  a.vn = F.vn;
-  a.au = F.au;
-  a.av = F.av;
-  switch (stage) {
-    case 1:  // Y1 = y_n -> A
-      a.uin = F.un; a.vin = F.vn; a.uout = F.ua; a.vout = F.va;
-      a.cy = dt / (T)2; a.ca = dt / (T)6;
-      break;
-    case 2:  // A -> B
-      a.uin = F.ua; a.vin = F.va; a.uout = F.ub; a.vout = F.vb;
-      a.cy = dt / (T)2; a.ca = dt / (T)3;
-      break;
-    case 3:  // B -> A
-      a.uin = F.ub; a.vin = F.vb; a.uout = F.ua; a.vout = F.va;
-      a.cy = dt; a.ca = dt / (T)3;
-      break;
-    default:  // A, acc -> y_{n+1}
-      a.uin = F.ua; a.vin = F.va; a.uout = F.un; a.vout = F.vn;
-      a.cy = dt; a.ca = dt / (T)6;
-      break;
-  }
-  return a;
-}
-
-template <typename T>
-hr_status launch_steps(hr_grid* g, const Fields<T>& F, T eta, T dt, long nsteps) {
-  const StageArgs<T> s1 = stage_args<T>(g, F, 1, eta, dt);
-  const StageArgs<T> s2 = stage_args<T>(g, F, 2, eta, dt);
-  const StageArgs<T> s3 = stage_args<T>(g, F, 3, eta, dt);
-  const StageArgs<T> s4 = stage_args<T>(g, F, 4, eta, dt);
+hr_status launch_steps(hr_grid* g, const Fields<T>& F, T eta, T dt, long nsteps,
+                       bool corr = false) {
+  const StageArgs<T> s1 = stage_args<T>(g, F, 1, eta, dt, corr);
+  const StageArgs<T> s2 = stage_args<T>(g, F, 2, eta, dt, corr);
+  const StageArgs<T> s3 = stage_args<T>(g, F, 3, eta, dt, corr);
+  const StageArgs<T> s4 = stage_args<T>(g, F, 4, eta, dt, corr);
   for (long n = 0; n < nsteps; ++n) {
     HR_HIP(launch_stage(g->fd_order, 1, s1, g->stream));
     HR_HIP(launch_stage(g->fd_order, 2, s2, g->stream));
@@ -301,6 +284,75 @@ hr_status run_phase(hr_grid* g, const Fields<T>& F, bool fp32, double eta, doubl
           break;
         }
       }
+    }
+  }
+  *done = s;
+  return HR_OK;
+}
+
+// Split-state single-precision phase: y = y_b (FP64) + e (FP32). Each cycle
+// evaluates the base slopes k(y_b) in FP64, integrates e with RK4 in FP32 for
+// K steps (slope k(y_b) + L e + source difference), adds e into y_b in FP64
+// and checks the FP64 residual of y_b. In exact arithmetic this is the same
+// RK4 trajectory as the FP64 form; single-precision rounding is relative to
+// the increment. Stops at tol, below the switch residual, on a stall, on a
+// non-finite residual or at the step cap (why as in run_phase).
+hr_status run_split_phase(hr_grid* g, double eta, double dt, long max_steps, double tol,
+                          int K, double sw_res, hr_relax_report* rep, long* done, int* why,
+                          double* last_res) {
+  BaseArgs b{};
+  b.d = g->d;
+  b.u = g->f64.un;
+  b.v = g->f64.vn;
+  b.psi = g->f64.psi;
+  b.ssrc = g->f64.ssrc;
+  b.fac = g->f64.fac;
+  b.ofac = g->f64.ofac;
+  b.eta = eta;
+  b.khu = g->f32.khu;
+  b.khv = g->f32.khv;
+  b.pb = g->f32.pb;
+  b.sp7 = g->f32.sp7;
+  b.eu = g->f32.un;
+  b.ev = g->f32.vn;
+  const int G = (int)g->G;
+  long s = 0;
+  int stall = 0;
+  double best = INFINITY;
+  *why = 0;
+  while (s < max_steps) {
+    const long chunk = std::min<long>(K, max_steps - s);
+    HR_HIP(launch_base(g->fd_order, b, g->stream));
+    hr_status st = launch_steps<float>(g, g->f32, (float)eta, (float)dt, chunk, true);
+    if (st != HR_OK) return st;
+    HR_HIP(launch_rebase(g->f64.un, g->f64.vn, g->f32.un, g->f32.vn, G, g->stream));
+    s += chunk;
+    if (chunk != K) break;
+    double res = 0.0;
+    st = residual_of(g, g->f64.un, false, &res);
+    if (st != HR_OK) return st;
+    *last_res = res;
+    if (rep) {
+      if (rep->history && rep->n_history < rep->history_cap) rep->history[rep->n_history] = res;
+      rep->n_history++;
+    }
+    if (!std::isfinite(res)) {
+      *why = 2;
+      break;
+    }
+    if (tol > 0 && res < tol) {
+      *why = 1;
+      break;
+    }
+    if (res < best) {
+      best = res;
+      stall = 0;
+    } else {
+      ++stall;
+    }
+    if (res < sw_res || stall >= g->sw_stall || (g->sw_max_steps > 0 && s >= g->sw_max_steps)) {
+      *why = 3;
+      break;
     }
   }
   *done = s;
@@ -505,20 +557,25 @@ hr_status hr_relax(hr_grid* g, double eta, double c, double dt, long n_steps, do
   long done = 0, total = 0, f32steps = 0;
   int why = 0;
   double last = NAN;
-  if (prec == HR_FP32 || prec == HR_FP32_FP64FINISH) {
+  if (prec == HR_FP32) {
     HR_HIP(launch_to_fp32(g->f64.un, g->f32.un, G, g->stream));
     HR_HIP(launch_to_fp32(g->f64.vn, g->f32.vn, G, g->stream));
-    const bool sw = prec == HR_FP32_FP64FINISH;
-    st = run_phase<float>(g, g->f32, true, eta, dt, n_steps, sw ? 0.0 : tol, check_every, sw,
-                          rep, &done, &why, &last);
+    st = run_phase<float>(g, g->f32, true, eta, dt, n_steps, tol, check_every, false, rep, &done,
+                          &why, &last);
     if (st != HR_OK) return st;
     total += done;
     f32steps = done;
     HR_HIP(launch_to_fp64(g->f32.un, g->f64.un, G, g->stream));
     HR_HIP(launch_to_fp64(g->f32.vn, g->f64.vn, G, g->stream));
     HR_HIP(hipStreamSynchronize(g->stream));
+  } else if (prec == HR_FP32_FP64FINISH) {
+    const double sw = g->sw_residual > 0 ? g->sw_residual : (tol > 0 ? 10.0 * tol : 0.0);
+    st = run_split_phase(g, eta, dt, n_steps, tol, check_every, sw, rep, &done, &why, &last);
+    if (st != HR_OK) return st;
+    total += done;
+    f32steps = done;
   }
-  if (prec == HR_FP64 || (prec == HR_FP32_FP64FINISH && why != 2 && total < n_steps)) {
+  if (prec == HR_FP64 || (prec == HR_FP32_FP64FINISH && why == 3 && total < n_steps)) {
     st = run_phase<double>(g, g->f64, false, eta, dt, n_steps - total, tol, check_every, false,
                            rep, &done, &why, &last);
     if (st != HR_OK) return st;
@@ -628,6 +685,92 @@ hr_status hr_get_kernel_config(const hr_grid* g, hr_kernel_config* cfg) {
   cfg->variant = g->variant;
   cfg->streaming = g->streaming;
   cfg->chunk = g->chunk;
+  return HR_OK;
+}
+
+namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int, int>, std::pair<hr_kernel_config, double>> g_tune;
+}  // namespace
+
+hr_status hr_autotune(hr_grid* g, hr_precision prec, int n_steps, hr_kernel_config* best,
+                      double* best_us) {
+  hr_status st = check_ready(g, false);
+  if (st != HR_OK) return st;
+  if (n_steps < 1) return fail(HR_EINVAL, "n_steps must be >= 1");
+  if (prec != HR_FP64 && prec != HR_FP32) return fail(HR_EINVAL, "prec must be FP64 or FP32");
+  const auto key = std::make_tuple(g->d.N0, g->d.N1, g->d.N2, g->fd_order, (int)prec);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      g->variant = it->second.first.variant;
+      g->streaming = it->second.first.streaming;
+      g->chunk = it->second.first.chunk;
+      if (best) *best = it->second.first;
+      if (best_us) *best_us = it->second.second;
+      return HR_OK;
+    }
+  }
+  HR_HIP(hipSetDevice(g->device));
+  std::vector<hr_kernel_config> cand;
+  cand.push_back(hr_kernel_config{1, 0, 0});
+  for (int c = 1; c <= g->d.N2; c *= 2) cand.push_back(hr_kernel_config{2, 0, c});
+  hipEvent_t e0, e1;
+  HR_HIP(hipEventCreate(&e0));
+  HR_HIP(hipEventCreate(&e1));
+  const double dt = g->prm.cfl * g->tab.ds_g;
+  const int sv = g->variant, ss = g->streaming, sc = g->chunk;
+  double best_t = INFINITY;
+  hr_kernel_config bc = cand[0];
+  hr_status rs = HR_OK;
+  for (const hr_kernel_config& k : cand) {
+    g->variant = k.variant;
+    g->streaming = k.streaming;
+    g->chunk = k.chunk;
+    double tot = 0.0;
+    for (int n = 0; n <= n_steps && rs == HR_OK; ++n)
+      for (int s = 1; s <= 3; ++s) {
+        hipError_t e;
+        if (prec == HR_FP64)
+          e = launch_stage(g->fd_order, s, stage_args<double>(g, g->f64, s, 1.0, dt), g->stream,
+                           e0, e1);
+        else
+          e = launch_stage(g->fd_order, s, stage_args<float>(g, g->f32, s, 1.0f, (float)dt),
+                           g->stream, e0, e1);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+          rs = hip_fail(e, "autotune timing");
+          break;
+        }
+        if (n > 0) tot += ms;  // the first round warms up
+      }
+    if (rs != HR_OK) break;
+    const double us = 1e3 * tot / (3.0 * n_steps);
+    if (us < best_t) {
+      best_t = us;
+      bc = k;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rs != HR_OK) {
+    g->variant = sv;
+    g->streaming = ss;
+    g->chunk = sc;
+    return rs;
+  }
+  g->variant = bc.variant;
+  g->streaming = bc.streaming;
+  g->chunk = bc.chunk;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = std::make_pair(bc, best_t);
+  }
+  if (best) *best = bc;
+  if (best_us) *best_us = best_t;
   return HR_OK;
 }
 

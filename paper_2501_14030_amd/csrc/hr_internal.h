@@ -38,6 +38,12 @@ struct Fields {
   T* ssrc;  // (1/8) A_ij A^ij
   T* fac;   // 6 planes of N0*N1: alpha0, alpha1, alpha2, beta0, beta1, c^2
   T* ofac;  // 3 planes of NG*N1: c, 1/r, 1/(2 dxx0 dr/dxx0)
+  // split-state single-precision form (FP32 set only): slopes of the FP64 base
+  // state, base p = psi_s + u_base and S_src p^-7
+  T* khu;
+  T* khv;
+  T* pb;
+  T* sp7;
 };
 
 // Geometry of one grid, shared by every kernel launch on it.
@@ -72,6 +78,30 @@ struct StageArgs {
   int streaming;  // 1: non-temporal access to fields touched once per stage
   int variant;    // 1: plane tiles, 2: phi-marching columns
   int chunk;      // phi planes per block (variant 2)
+  // split-state form: the state is an increment e on an FP64 base y_b and the
+  // slope is k(y_b) + L e + S_src [(p_b + e_u)^-7 - p_b^-7]; psi/ssrc then hold
+  // p_b and S_src p_b^-7
+  int corr;
+  const T* khu;
+  const T* khv;
+};
+
+// Base-state slopes for the split-state form (FP64 in, FP32 out).
+struct BaseArgs {
+  Dims d;
+  const double* u;
+  const double* v;
+  const double* psi;
+  const double* ssrc;
+  const double* fac;
+  const double* ofac;
+  double eta;
+  float* khu;
+  float* khv;
+  float* pb;
+  float* sp7;
+  float* eu;   // increment state, zeroed
+  float* ev;
 };
 
 struct ResidualArgs {
@@ -102,6 +132,36 @@ hipError_t launch_sources(const Dims& d, const double* rho, const double* zc,
                           float* psi32, float* ssrc32, hipStream_t s);
 hipError_t launch_to_fp32(const double* src, float* dst, int n, hipStream_t s);
 hipError_t launch_to_fp64(const float* src, double* dst, int n, hipStream_t s);
+struct RebaseArgs {
+  double* ub;
+  double* vb;
+  const float* eu;
+  const float* ev;
+  int n;
+};
+
+hipError_t launch_base(int order, const BaseArgs& a, hipStream_t s);
+
+// Batched launchers: persistent grids walking device work lists whose lengths
+// are read from device memory (*nitems). Stage items are (grid, x0 tile,
+// x1 tile, phi chunk); residual and base items (grid, x0 tile, x1 tile,
+// plane); rebase items (grid, element block). descs of the stage launcher
+// are StageArgs<float> (split form) or StageArgs<double>, four per grid.
+hipError_t launch_batch_stage(int order, int stage, bool fp32_split, const void* descs,
+                              const int4* items, const int* nitems, int nblocks_persistent,
+                              hipStream_t s);
+hipError_t launch_batch_residual(int order, const ResidualArgs* descs, const int4* items,
+                                 const int* nitems, double* partial, int nblocks_persistent,
+                                 hipStream_t s);
+hipError_t launch_batch_finalize(const int4* ranges, const double* partial, double* out,
+                                 int ngrids, hipStream_t s);
+hipError_t launch_batch_base(int order, const BaseArgs* descs, const int4* items,
+                             const int* nitems, int nblocks_persistent, hipStream_t s);
+hipError_t launch_batch_rebase(const RebaseArgs* descs, const int2* items, const int* nitems,
+                               int nblocks_persistent, hipStream_t s);
+// y_b += e over n stored elements (FP64 += FP32), both fields.
+hipError_t launch_rebase(double* ub, double* vb, const float* eu, const float* ev, int n,
+                         hipStream_t s);
 hipError_t launch_fill(double* dst, double value, int n, hipStream_t s);
 hipError_t launch_fill(float* dst, float value, int n, hipStream_t s);
 
@@ -159,8 +219,60 @@ struct hr_grid {
   int streaming = -1;           // non-temporal field access: -1 auto (by size), 0, 1
   int chunk = 0;                // phi planes per block of the column variant (0 auto)
 
-  // FP32 -> FP64 switch rule
-  double sw_residual = 1e-6;
-  int sw_stall = 2;
+  // FP32 -> FP64 switch rule (sw_residual 0: ten times the tolerance)
+  double sw_residual = 0.0;
+  int sw_stall = 8;
   long sw_max_steps = 0;
 };
+
+namespace hr {
+
+// Kernel variant and phi chunk of a grid (explicit configuration, else by size).
+void resolve_variant(const hr_grid* g, int& variant, int& chunk);
+
+// Uploads the wave-speed planes (c, c^2) for scale kappa if not loaded (synchronous).
+hr_status load_kappa(hr_grid* g, double kappa);
+
+// Stage-s arguments of grid g in precision T; corr selects the split-state form.
+template <typename T>
+StageArgs<T> stage_args(const hr_grid* g, const Fields<T>& F, int stage, T eta, T dt,
+                        bool corr = false) {
+  StageArgs<T> a{};
+  a.d = g->d;
+  a.psi = corr ? F.pb : F.psi;
+  a.ssrc = corr ? F.sp7 : F.ssrc;
+  a.corr = corr ? 1 : 0;
+  a.khu = F.khu;
+  a.khv = F.khv;
+  a.fac = F.fac;
+  a.ofac = F.ofac;
+  a.eta = eta;
+  // non-temporal access measured no faster at any size: off unless asked for
+  a.streaming = g->streaming > 0 ? 1 : 0;
+  resolve_variant(g, a.variant, a.chunk);
+  a.un = F.un;
+  a.vn = F.vn;
+  a.au = F.au;
+  a.av = F.av;
+  switch (stage) {
+    case 1:  // Y1 = y_n -> A
+      a.uin = F.un; a.vin = F.vn; a.uout = F.ua; a.vout = F.va;
+      a.cy = dt / (T)2; a.ca = dt / (T)6;
+      break;
+    case 2:  // A -> B
+      a.uin = F.ua; a.vin = F.va; a.uout = F.ub; a.vout = F.vb;
+      a.cy = dt / (T)2; a.ca = dt / (T)3;
+      break;
+    case 3:  // B -> A
+      a.uin = F.ub; a.vin = F.vb; a.uout = F.ua; a.vout = F.va;
+      a.cy = dt; a.ca = dt / (T)3;
+      break;
+    default:  // A, acc -> y_{n+1}
+      a.uin = F.ua; a.vin = F.va; a.uout = F.un; a.vout = F.vn;
+      a.cy = dt; a.ca = dt / (T)6;
+      break;
+  }
+  return a;
+}
+
+}  // namespace hr

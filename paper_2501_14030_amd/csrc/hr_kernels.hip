@@ -23,6 +23,8 @@
 
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 #include "hr_internal.h"
 
 namespace hr {
@@ -219,6 +221,12 @@ struct CombineIn {
   }
 };
 
+// Source difference of the split-state form: S p^-7 [(1 + x)^-7 - 1], x = e/p,
+// evaluated without cancellation for small increments.
+__device__ __forceinline__ float source_delta(float sp7, float pb, float e) {
+  return sp7 * expm1f(-7.0f * log1pf(e / pb));
+}
+
 // RK4 stage combine for one point, given the stage slopes. The next stage
 // input (uout) is re-read with stencils, so it is always a cached store.
 template <int STAGE, bool NT, typename T>
@@ -246,7 +254,7 @@ __device__ __forceinline__ void combine(const StageArgs<T>& a, unsigned idx,
 // threads with i0 in [N0-NG, N0) also update the outer point i0 + NG of their
 // row. Every global load of the interior point is issued before the tile
 // barrier so that the point waits for one memory round trip.
-template <typename T, int NG, int STAGE, bool NT>
+template <typename T, int NG, int STAGE, bool NT, bool CORR>
 __global__ void __launch_bounds__(kTileThreads) k_stage(StageArgs<T> a) {
   constexpr int W = TileShape<NG>::W, H = TileShape<NG>::H;
   __shared__ T tile[W * H];
@@ -260,12 +268,16 @@ __global__ void __launch_bounds__(kTileThreads) k_stage(StageArgs<T> a) {
   const unsigned idx = row + (unsigned)i0;
   PhiTaps<NG, T, T> ph;
   CombineIn<STAGE, NT, T> cin;
-  T v = 0, psi = 0, ssrc = 0, f[6];
+  T v = 0, psi = 0, ssrc = 0, f[6], khu = 0, khv = 0;
   if (active) {
     ph.load(a.uin, d, i0, i1, i2);
     v = ld<NT>(a.vin + idx);
     psi = ld<NT>(a.psi + idx);
     ssrc = ld<NT>(a.ssrc + idx);
+    if constexpr (CORR) {
+      khu = a.khu[idx];
+      khv = a.khv[idx];
+    }
 #pragma unroll
     for (int q = 0; q < 6; ++q) f[q] = a.fac[q * n2d + k2];
     cin.load(a, idx);
@@ -276,8 +288,14 @@ __global__ void __launch_bounds__(kTileThreads) k_stage(StageArgs<T> a) {
   const Sums<T> s = stencil<NG, T, T>(tile, ph);
   const T lap = f[0] * s.dd0 + f[1] * s.dd1 + f[2] * s.dd2 + f[3] * s.d0 + f[4] * s.d1;
   const T u = s.uc;
-  const T ku = v - a.eta * u;
-  const T kv = f[5] * (lap + source<T>(ssrc, psi, u));
+  T ku, kv;
+  if constexpr (CORR) {
+    ku = khu + (v - a.eta * u);
+    kv = khv + f[5] * (lap + source_delta(ssrc, psi, u));
+  } else {
+    ku = v - a.eta * u;
+    kv = f[5] * (lap + source<T>(ssrc, psi, u));
+  }
   combine<STAGE, NT, T>(a, idx, cin, u, v, ku, kv);
   if (i0 >= d.N0 - NG) {
     // outer point: radiation condition with a one-sided xx0 derivative
@@ -290,8 +308,12 @@ __global__ void __launch_bounds__(kTileThreads) k_stage(StageArgs<T> a) {
     const T v0 = a.vin[o], v1 = a.vin[o - 1], v2 = a.vin[o - 2];
     CombineIn<STAGE, NT, T> co;
     co.load(a, o);
-    const T kuo = -c * (u0 * rinv + ((T)3 * u0 - (T)4 * u1 + u2) * qd);
-    const T kvo = -c * (v0 * rinv + ((T)3 * v0 - (T)4 * v1 + v2) * qd);
+    T kuo = -c * (u0 * rinv + ((T)3 * u0 - (T)4 * u1 + u2) * qd);
+    T kvo = -c * (v0 * rinv + ((T)3 * v0 - (T)4 * v1 + v2) * qd);
+    if constexpr (CORR) {
+      kuo = a.khu[o] + kuo;
+      kvo = a.khv[o] + kvo;
+    }
     combine<STAGE, NT, T>(a, o, co, u0, v0, kuo, kvo);
   }
 }
@@ -353,13 +375,17 @@ struct TileRegs {
 };
 
 // Operands of one interior point that are read once per stage.
-template <int STAGE, typename T>
+template <int STAGE, bool CORR, typename T>
 struct PointIn {
-  T v, psi, ssrc, un, vn, au, av;
+  T v, psi, ssrc, un, vn, au, av, khu, khv;
   __device__ __forceinline__ void load(const StageArgs<T>& a, unsigned idx) {
     v = a.vin[idx];
     psi = a.psi[idx];
     ssrc = a.ssrc[idx];
+    if constexpr (CORR) {
+      khu = a.khu[idx];
+      khv = a.khv[idx];
+    }
     if constexpr (STAGE == 2 || STAGE == 3) {
       un = a.un[idx];
       vn = a.vn[idx];
@@ -371,9 +397,9 @@ struct PointIn {
   }
 };
 
-template <int STAGE, typename T>
+template <int STAGE, bool CORR, typename T>
 __device__ __forceinline__ void combine_pt(const StageArgs<T>& a, unsigned idx,
-                                           const PointIn<STAGE, T>& c, T uin, T ku, T kv) {
+                                           const PointIn<STAGE, CORR, T>& c, T uin, T ku, T kv) {
   if constexpr (STAGE == 1) {
     a.uout[idx] = uin + a.cy * ku;
     a.vout[idx] = c.v + a.cy * kv;
@@ -393,14 +419,15 @@ __device__ __forceinline__ void combine_pt(const StageArgs<T>& a, unsigned idx,
 template <int NG>
 __device__ __forceinline__ int step_up(int j, int N) { return j + 1 == N ? 0 : j + 1; }
 
-template <typename T, int NG, int STAGE>
-__global__ void __launch_bounds__(kTileThreads, 4) k_stage_col(StageArgs<T> a, int chunk) {
-  constexpr int W = TileShape<NG>::W, H = TileShape<NG>::H;
+template <typename T, int NG, int STAGE, bool CORR>
+__device__ __forceinline__ void stage_col_body(const StageArgs<T>& a, int bx, int by, int bz,
+                                               int chunk,
+                                               T (&tile)[2][TileShape<NG>::W * TileShape<NG>::H]) {
+  constexpr int W = TileShape<NG>::W;
   constexpr Weights<NG> Wt{};
-  __shared__ T tile[2][W * H];
   const Dims& d = a.d;
-  const int x0b = blockIdx.x * TX, x1b = blockIdx.y * TY;
-  const int z0 = blockIdx.z * chunk;
+  const int x0b = bx * TX, x1b = by * TY;
+  const int z0 = bz * chunk;
   const int z1 = min(z0 + chunk, d.N2);
   const int i0 = x0b + threadIdx.x, i1 = x1b + threadIdx.y;
   const bool active = i0 < d.N0 && i1 < d.N1;
@@ -416,7 +443,7 @@ __global__ void __launch_bounds__(kTileThreads, 4) k_stage_col(StageArgs<T> a, i
 #pragma unroll
   for (int k = 0; k < NG; ++k) jq = (jq == 0) ? d.N2 - 1 : jq - 1;
   T f[6];
-  PointIn<STAGE, T> cur;
+  PointIn<STAGE, CORR, T> cur;
   if (active) {
 #pragma unroll
     for (int j = 0; j <= 2 * NG; ++j) {
@@ -439,7 +466,7 @@ __global__ void __launch_bounds__(kTileThreads, 4) k_stage_col(StageArgs<T> a, i
     const bool more = z + 1 < z1;
     // prefetch plane z + 1
     TileRegs<NG, T> tn;
-    PointIn<STAGE, T> nxt;
+    PointIn<STAGE, CORR, T> nxt;
     T qn = (T)0;
     if (more) {
       tn.fetch(a.uin, d, x0b, x1b, z + 1);
@@ -465,10 +492,16 @@ __global__ void __launch_bounds__(kTileThreads, 4) k_stage_col(StageArgs<T> a, i
       const T w0 = (T)Wt.d2[0];
       const T lap = f[0] * (e0 + w0 * uc) + f[1] * (e1 + w0 * uc) + f[2] * (e2 + w0 * uc) +
                     f[3] * d0 + f[4] * d1;
-      const T ku = cur.v - a.eta * uc;
-      const T kv = f[5] * (lap + source<T>(cur.ssrc, cur.psi, uc));
+      T ku, kv;
+      if constexpr (CORR) {
+        ku = cur.khu + (cur.v - a.eta * uc);
+        kv = cur.khv + f[5] * (lap + source_delta(cur.ssrc, cur.psi, uc));
+      } else {
+        ku = cur.v - a.eta * uc;
+        kv = f[5] * (lap + source<T>(cur.ssrc, cur.psi, uc));
+      }
       const unsigned idx = col + plane * (unsigned)z;
-      combine_pt<STAGE, T>(a, idx, cur, uc, ku, kv);
+      combine_pt<STAGE, CORR, T>(a, idx, cur, uc, ku, kv);
       if (outer) {
         const int qo = i0 + NG - d.N0;
         const unsigned o = idx + (unsigned)NG;
@@ -479,8 +512,12 @@ __global__ void __launch_bounds__(kTileThreads, 4) k_stage_col(StageArgs<T> a, i
         const T v0 = a.vin[o], v1 = a.vin[o - 1], v2 = a.vin[o - 2];
         CombineIn<STAGE, false, T> co;
         co.load(a, o);
-        const T kuo = -c * (u0 * rinv + ((T)3 * u0 - (T)4 * u1 + u2) * qd);
-        const T kvo = -c * (v0 * rinv + ((T)3 * v0 - (T)4 * v1 + v2) * qd);
+        T kuo = -c * (u0 * rinv + ((T)3 * u0 - (T)4 * u1 + u2) * qd);
+        T kvo = -c * (v0 * rinv + ((T)3 * v0 - (T)4 * v1 + v2) * qd);
+        if constexpr (CORR) {
+          kuo = a.khu[o] + kuo;
+          kvo = a.khv[o] + kvo;
+        }
         combine<STAGE, false, T>(a, o, co, u0, v0, kuo, kvo);
       }
     }
@@ -493,6 +530,105 @@ __global__ void __launch_bounds__(kTileThreads, 4) k_stage_col(StageArgs<T> a, i
       jq = step_up<NG>(jq, d.N2);
     }
     __syncthreads();
+  }
+}
+
+template <typename T, int NG, int STAGE, bool CORR>
+__global__ void __launch_bounds__(kTileThreads, 4) k_stage_col(StageArgs<T> a, int chunk) {
+  __shared__ T tile[2][TileShape<NG>::W * TileShape<NG>::H];
+  stage_col_body<T, NG, STAGE, CORR>(a, blockIdx.x, blockIdx.y, blockIdx.z, chunk, tile);
+}
+
+// ---------------------------------------------------------------------------
+// Batched kernels: many grids (same order) relaxed by one launch per RK stage.
+// A persistent grid of blocks walks a device work list; each item is
+// (grid, x0 tile, x1 tile, phi chunk or plane). Per-grid stage arguments live
+// in device memory (four entries per grid, one per stage). The list lengths
+// are read from device memory, so a captured launch sequence stays valid when
+// converged grids are dropped from the lists.
+template <typename T, int NG, int STAGE, bool CORR>
+__global__ void __launch_bounds__(kTileThreads, 4)
+    k_batch_stage(const StageArgs<T>* __restrict__ descs, const int4* __restrict__ items,
+                  const int* __restrict__ nitems) {
+  __shared__ T tile[2][TileShape<NG>::W * TileShape<NG>::H];
+  const int n = *nitems;
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const int4 w = items[it];
+    const StageArgs<T> a = descs[4 * w.x + (STAGE - 1)];
+    stage_col_body<T, NG, STAGE, CORR>(a, w.y, w.z, w.w, a.chunk, tile);
+  }
+}
+
+
+// Slopes k(y_b) of the FP64 base state for the split-state single-precision
+// form, stored in FP32 with p_b = psi_s + u_b and S_src p_b^-7; the FP32
+// increment state is reset to zero. Same tiling as the plane stage kernel.
+template <int NG>
+__device__ __forceinline__ void base_body(const BaseArgs& a, int bx, int by, int i2,
+                                          double* __restrict__ tile) {
+  const Dims& d = a.d;
+  const int x0b = bx * TX, x1b = by * TY;
+  const int i0 = x0b + threadIdx.x, i1 = x1b + threadIdx.y;
+  const bool active = i0 < d.N0 && i1 < d.N1;
+  const unsigned n2d = (unsigned)d.N0 * (unsigned)d.N1;
+  const unsigned k2 = (unsigned)i0 + (unsigned)d.N0 * (unsigned)i1;
+  const unsigned row = (unsigned)d.P0 * ((unsigned)i1 + (unsigned)d.N1 * (unsigned)i2);
+  const unsigned idx = row + (unsigned)i0;
+  PhiTaps<NG, double, double> ph;
+  double v = 0, psi = 0, ssrc = 0, f[6];
+  if (active) {
+    ph.load(a.u, d, i0, i1, i2);
+    v = a.v[idx];
+    psi = a.psi[idx];
+    ssrc = a.ssrc[idx];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) f[q] = a.fac[q * n2d + k2];
+  }
+  load_tile<NG, double, double>(tile, a.u, d, x0b, x1b, i2);
+  __syncthreads();
+  if (!active) return;
+  const Sums<double> s = stencil<NG, double, double>(tile, ph);
+  const double lap = f[0] * s.dd0 + f[1] * s.dd1 + f[2] * s.dd2 + f[3] * s.d0 + f[4] * s.d1;
+  const double u = s.uc;
+  const double p = psi + u;
+  const double p2 = p * p, p4 = p2 * p2, p7 = p4 * p2 * p;
+  a.khu[idx] = (float)(v - a.eta * u);
+  a.khv[idx] = (float)(f[5] * (lap + ssrc / p7));
+  a.pb[idx] = (float)p;
+  a.sp7[idx] = (float)(ssrc / p7);
+  a.eu[idx] = 0.0f;
+  a.ev[idx] = 0.0f;
+  if (i0 >= d.N0 - NG) {
+    const int q = i0 + NG - d.N0;
+    const unsigned o = row + (unsigned)(i0 + NG);
+    const unsigned ko = (unsigned)q + (unsigned)NG * (unsigned)i1;
+    const unsigned o2d = (unsigned)NG * (unsigned)d.N1;
+    const double c = a.ofac[ko], rinv = a.ofac[o2d + ko], qd = a.ofac[2 * o2d + ko];
+    const double u0 = a.u[o], u1 = a.u[o - 1], u2 = a.u[o - 2];
+    const double v0 = a.v[o], v1 = a.v[o - 1], v2 = a.v[o - 2];
+    a.khu[o] = (float)(-c * (u0 * rinv + (3.0 * u0 - 4.0 * u1 + u2) * qd));
+    a.khv[o] = (float)(-c * (v0 * rinv + (3.0 * v0 - 4.0 * v1 + v2) * qd));
+    a.pb[o] = (float)(a.psi[o] + u0);
+    a.sp7[o] = 0.0f;
+    a.eu[o] = 0.0f;
+    a.ev[o] = 0.0f;
+  }
+}
+
+template <int NG>
+__global__ void __launch_bounds__(kTileThreads) k_base(BaseArgs a) {
+  __shared__ double tile[TileShape<NG>::W * TileShape<NG>::H];
+  base_body<NG>(a, blockIdx.x, blockIdx.y, blockIdx.z, tile);
+}
+
+__global__ void __launch_bounds__(kBlock) k_rebase(double* __restrict__ ub,
+                                                   double* __restrict__ vb,
+                                                   const float* __restrict__ eu,
+                                                   const float* __restrict__ ev, int n) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t < n) {
+    ub[t] = ub[t] + (double)eu[t];
+    vb[t] = vb[t] + (double)ev[t];
   }
 }
 
@@ -514,13 +650,13 @@ __device__ __forceinline__ double block_sum(double x) {
 }
 
 // Residual H (left-hand side of Eq. 4) in FP64 from a state of storage type S;
-// one partial sum of H^2 per block, same tiling as the stage kernel.
+// returns the block's sum of H^2 (valid in thread 0), same tiling as the plane
+// stage kernel.
 template <typename S, int NG>
-__global__ void __launch_bounds__(kTileThreads) k_residual(ResidualArgs a) {
-  constexpr int W = TileShape<NG>::W, H = TileShape<NG>::H;
-  __shared__ double tile[W * H];
+__device__ __forceinline__ double residual_body(const ResidualArgs& a, int bx, int by, int i2,
+                                               double* __restrict__ tile) {
   const Dims& d = a.d;
-  const int x0b = blockIdx.x * TX, x1b = blockIdx.y * TY, i2 = blockIdx.z;
+  const int x0b = bx * TX, x1b = by * TY;
   const S* U = static_cast<const S*>(a.u);
   const int i0 = x0b + threadIdx.x, i1 = x1b + threadIdx.y;
   const bool active = i0 < d.N0 && i1 < d.N1;
@@ -546,9 +682,74 @@ __global__ void __launch_bounds__(kTileThreads) k_residual(ResidualArgs a) {
     const double Hv = lap + source<double>(ssrc, psi, s.uc);
     h2 = Hv * Hv;
   }
-  const double tot = block_sum<kTileThreads>(h2);
+  return block_sum<kTileThreads>(h2);
+}
+
+template <typename S, int NG>
+__global__ void __launch_bounds__(kTileThreads) k_residual(ResidualArgs a) {
+  __shared__ double tile[TileShape<NG>::W * TileShape<NG>::H];
+  const double tot = residual_body<S, NG>(a, blockIdx.x, blockIdx.y, blockIdx.z, tile);
   if (threadIdx.x == 0 && threadIdx.y == 0)
     a.partial[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = tot;
+}
+
+// Batched residual: items (grid, x0 tile, x1 tile, plane); the block sum of
+// item `it` goes to partial[it]. FP64 states only.
+template <int NG>
+__global__ void __launch_bounds__(kTileThreads)
+    k_batch_residual(const ResidualArgs* __restrict__ descs, const int4* __restrict__ items,
+                     const int* __restrict__ nitems, double* __restrict__ partial) {
+  __shared__ double tile[TileShape<NG>::W * TileShape<NG>::H];
+  const int n = *nitems;
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const int4 w = items[it];
+    const ResidualArgs a = descs[w.x];
+    const double tot = residual_body<double, NG>(a, w.y, w.z, w.w, tile);
+    if (threadIdx.x == 0 && threadIdx.y == 0) partial[it] = tot;
+  }
+}
+
+// Per-grid L2 norms from the batched partials: block g adds partial[start_g ..
+// start_g + count_g) in a fixed order; ranges[g] = (start, count, N_interior).
+__global__ void __launch_bounds__(kBlock)
+    k_batch_finalize(const int4* __restrict__ ranges, const double* __restrict__ partial,
+                     double* __restrict__ out) {
+  const int4 r = ranges[blockIdx.x];
+  double s = 0.0;
+  for (int j = threadIdx.x; j < r.y; j += kBlock) s += partial[r.x + j];
+  const double tot = block_sum<kBlock>(s);
+  if (threadIdx.x == 0) out[blockIdx.x] = r.y > 0 ? sqrt(tot / (double)r.z) : 0.0;
+}
+
+// Batched base slopes of the split-state form.
+template <int NG>
+__global__ void __launch_bounds__(kTileThreads)
+    k_batch_base(const BaseArgs* __restrict__ descs, const int4* __restrict__ items,
+                 const int* __restrict__ nitems) {
+  __shared__ double tile[TileShape<NG>::W * TileShape<NG>::H];
+  const int n = *nitems;
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const int4 w = items[it];
+    const BaseArgs a = descs[w.x];
+    base_body<NG>(a, w.y, w.z, w.w, tile);
+    __syncthreads();
+  }
+}
+
+// Batched rebase y_b += e: items (grid, element block of 256).
+__global__ void __launch_bounds__(kBlock)
+    k_batch_rebase(const RebaseArgs* __restrict__ descs, const int2* __restrict__ items,
+                   const int* __restrict__ nitems) {
+  const int n = *nitems;
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const int2 w = items[it];
+    const RebaseArgs a = descs[w.x];
+    const int t = w.y * kBlock + threadIdx.x;
+    if (t < a.n) {
+      a.ub[t] = a.ub[t] + (double)a.eu[t];
+      a.vb[t] = a.vb[t] + (double)a.ev[t];
+    }
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ partial,
@@ -646,18 +847,6 @@ hipError_t tile_launch(K k, const A& args, const Dims& d, hipStream_t s, hipEven
   return hipGetLastError();
 }
 
-template <typename T, int NG, bool NT>
-hipError_t stage_dispatch_nt(int stage, const StageArgs<T>& a, hipStream_t s, hipEvent_t t0,
-                             hipEvent_t t1) {
-  switch (stage) {
-    case 1: return tile_launch(k_stage<T, NG, 1, NT>, a, a.d, s, t0, t1);
-    case 2: return tile_launch(k_stage<T, NG, 2, NT>, a, a.d, s, t0, t1);
-    case 3: return tile_launch(k_stage<T, NG, 3, NT>, a, a.d, s, t0, t1);
-    case 4: return tile_launch(k_stage<T, NG, 4, NT>, a, a.d, s, t0, t1);
-    default: return hipErrorInvalidValue;
-  }
-}
-
 template <typename K, typename A>
 hipError_t col_launch(K k, const A& args, int chunk, hipStream_t s, hipEvent_t t0,
                       hipEvent_t t1) {
@@ -671,21 +860,43 @@ hipError_t col_launch(K k, const A& args, int chunk, hipStream_t s, hipEvent_t t
   return hipGetLastError();
 }
 
+template <typename T, int NG, bool NT, bool CORR>
+hipError_t stage_dispatch_nt(int stage, const StageArgs<T>& a, hipStream_t s, hipEvent_t t0,
+                             hipEvent_t t1) {
+  switch (stage) {
+    case 1: return tile_launch(k_stage<T, NG, 1, NT, CORR>, a, a.d, s, t0, t1);
+    case 2: return tile_launch(k_stage<T, NG, 2, NT, CORR>, a, a.d, s, t0, t1);
+    case 3: return tile_launch(k_stage<T, NG, 3, NT, CORR>, a, a.d, s, t0, t1);
+    case 4: return tile_launch(k_stage<T, NG, 4, NT, CORR>, a, a.d, s, t0, t1);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int NG, bool CORR>
+hipError_t col_dispatch(int stage, const StageArgs<T>& a, int ch, hipStream_t s, hipEvent_t t0,
+                        hipEvent_t t1) {
+  switch (stage) {
+    case 1: return col_launch(k_stage_col<T, NG, 1, CORR>, a, ch, s, t0, t1);
+    case 2: return col_launch(k_stage_col<T, NG, 2, CORR>, a, ch, s, t0, t1);
+    case 3: return col_launch(k_stage_col<T, NG, 3, CORR>, a, ch, s, t0, t1);
+    case 4: return col_launch(k_stage_col<T, NG, 4, CORR>, a, ch, s, t0, t1);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+
 template <typename T, int NG>
 hipError_t stage_dispatch(int stage, const StageArgs<T>& a, hipStream_t s, hipEvent_t t0,
                           hipEvent_t t1) {
-  if (a.variant == 2) {
-    const int ch = a.chunk > 0 ? a.chunk : 1;
-    switch (stage) {
-      case 1: return col_launch(k_stage_col<T, NG, 1>, a, ch, s, t0, t1);
-      case 2: return col_launch(k_stage_col<T, NG, 2>, a, ch, s, t0, t1);
-      case 3: return col_launch(k_stage_col<T, NG, 3>, a, ch, s, t0, t1);
-      case 4: return col_launch(k_stage_col<T, NG, 4>, a, ch, s, t0, t1);
-      default: return hipErrorInvalidValue;
-    }
+  const int ch = a.chunk > 0 ? a.chunk : 1;
+  if constexpr (std::is_same<T, float>::value) {
+    if (a.corr)
+      return a.variant == 2 ? col_dispatch<T, NG, true>(stage, a, ch, s, t0, t1)
+                            : stage_dispatch_nt<T, NG, false, true>(stage, a, s, t0, t1);
   }
-  return a.streaming ? stage_dispatch_nt<T, NG, true>(stage, a, s, t0, t1)
-                     : stage_dispatch_nt<T, NG, false>(stage, a, s, t0, t1);
+  if (a.variant == 2) return col_dispatch<T, NG, false>(stage, a, ch, s, t0, t1);
+  return a.streaming ? stage_dispatch_nt<T, NG, true, false>(stage, a, s, t0, t1)
+                     : stage_dispatch_nt<T, NG, false, false>(stage, a, s, t0, t1);
 }
 
 template <typename T>
@@ -746,6 +957,103 @@ hipError_t launch_sources(const Dims& d, const double* rho, const double* zc,
   const int next = d.P0 * d.N1 * d.N2;
   k_sources<<<nblocks(next), kBlock, 0, s>>>(d, rho, zc, cphi, sphi, p, psi64, ssrc64, psi32,
                                              ssrc32);
+  return hipGetLastError();
+}
+
+hipError_t launch_base(int order, const BaseArgs& a, hipStream_t s) {
+  switch (order) {
+    case 2: return tile_launch(k_base<1>, a, a.d, s, nullptr, nullptr);
+    case 4: return tile_launch(k_base<2>, a, a.d, s, nullptr, nullptr);
+    case 6: return tile_launch(k_base<3>, a, a.d, s, nullptr, nullptr);
+    case 8: return tile_launch(k_base<4>, a, a.d, s, nullptr, nullptr);
+    case 10: return tile_launch(k_base<5>, a, a.d, s, nullptr, nullptr);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_rebase(double* ub, double* vb, const float* eu, const float* ev, int n,
+                         hipStream_t s) {
+  k_rebase<<<nblocks(n), kBlock, 0, s>>>(ub, vb, eu, ev, n);
+  return hipGetLastError();
+}
+
+template <int NG>
+hipError_t batch_stage_ng(int stage, bool fp32_split, const void* descs, const int4* items,
+                          const int* nitems, int nblocks_persistent, hipStream_t s) {
+  const dim3 block(TX, TY, 1), grid(nblocks_persistent);
+  if (fp32_split) {
+    const StageArgs<float>* d = static_cast<const StageArgs<float>*>(descs);
+    switch (stage) {
+      case 1: k_batch_stage<float, NG, 1, true><<<grid, block, 0, s>>>(d, items, nitems); break;
+      case 2: k_batch_stage<float, NG, 2, true><<<grid, block, 0, s>>>(d, items, nitems); break;
+      case 3: k_batch_stage<float, NG, 3, true><<<grid, block, 0, s>>>(d, items, nitems); break;
+      case 4: k_batch_stage<float, NG, 4, true><<<grid, block, 0, s>>>(d, items, nitems); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    const StageArgs<double>* d = static_cast<const StageArgs<double>*>(descs);
+    switch (stage) {
+      case 1: k_batch_stage<double, NG, 1, false><<<grid, block, 0, s>>>(d, items, nitems); break;
+      case 2: k_batch_stage<double, NG, 2, false><<<grid, block, 0, s>>>(d, items, nitems); break;
+      case 3: k_batch_stage<double, NG, 3, false><<<grid, block, 0, s>>>(d, items, nitems); break;
+      case 4: k_batch_stage<double, NG, 4, false><<<grid, block, 0, s>>>(d, items, nitems); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_stage(int order, int stage, bool fp32_split, const void* descs,
+                              const int4* items, const int* nitems, int nblocks_persistent,
+                              hipStream_t s) {
+  switch (order) {
+    case 2: return batch_stage_ng<1>(stage, fp32_split, descs, items, nitems, nblocks_persistent, s);
+    case 4: return batch_stage_ng<2>(stage, fp32_split, descs, items, nitems, nblocks_persistent, s);
+    case 6: return batch_stage_ng<3>(stage, fp32_split, descs, items, nitems, nblocks_persistent, s);
+    case 8: return batch_stage_ng<4>(stage, fp32_split, descs, items, nitems, nblocks_persistent, s);
+    case 10: return batch_stage_ng<5>(stage, fp32_split, descs, items, nitems, nblocks_persistent, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_batch_residual(int order, const ResidualArgs* descs, const int4* items,
+                                 const int* nitems, double* partial, int nblocks_persistent,
+                                 hipStream_t s) {
+  const dim3 block(TX, TY, 1), grid(nblocks_persistent);
+  switch (order) {
+    case 2: k_batch_residual<1><<<grid, block, 0, s>>>(descs, items, nitems, partial); break;
+    case 4: k_batch_residual<2><<<grid, block, 0, s>>>(descs, items, nitems, partial); break;
+    case 6: k_batch_residual<3><<<grid, block, 0, s>>>(descs, items, nitems, partial); break;
+    case 8: k_batch_residual<4><<<grid, block, 0, s>>>(descs, items, nitems, partial); break;
+    case 10: k_batch_residual<5><<<grid, block, 0, s>>>(descs, items, nitems, partial); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_finalize(const int4* ranges, const double* partial, double* out,
+                                 int ngrids, hipStream_t s) {
+  k_batch_finalize<<<ngrids, kBlock, 0, s>>>(ranges, partial, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_base(int order, const BaseArgs* descs, const int4* items,
+                             const int* nitems, int nblocks_persistent, hipStream_t s) {
+  const dim3 block(TX, TY, 1), grid(nblocks_persistent);
+  switch (order) {
+    case 2: k_batch_base<1><<<grid, block, 0, s>>>(descs, items, nitems); break;
+    case 4: k_batch_base<2><<<grid, block, 0, s>>>(descs, items, nitems); break;
+    case 6: k_batch_base<3><<<grid, block, 0, s>>>(descs, items, nitems); break;
+    case 8: k_batch_base<4><<<grid, block, 0, s>>>(descs, items, nitems); break;
+    case 10: k_batch_base<5><<<grid, block, 0, s>>>(descs, items, nitems); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_rebase(const RebaseArgs* descs, const int2* items, const int* nitems,
+                               int nblocks_persistent, hipStream_t s) {
+  k_batch_rebase<<<nblocks_persistent, kBlock, 0, s>>>(descs, items, nitems);
   return hipGetLastError();
 }
 

@@ -1,0 +1,191 @@
+"""Learned warm start: data from the relaxation's own solves, training with the
+library's MLP kernels, and evaluation against the zero initial guess.
+
+The relaxation stays the judge: a warm-started grid is relaxed to the same
+residual tolerance as a cold one, and only the steps and time differ.
+
+Run the catalog experiment with ``python -m paper_2501_14030_amd.warmstart``.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import FP64, Batch, default_params, grid_create
+from . import workloads
+from .mlp import MLP, config_features
+
+
+def config_of(w: workloads.Workload) -> np.ndarray:
+    e = w.extra
+    P = float(np.linalg.norm(w.punctures.P[0]))
+    return config_features(e["q"], e["chi1"], e["chi2"], P, e["D"])
+
+
+def make_grids(ws, shape):
+    grids = []
+    for w in ws:
+        spec = w.grid
+        g = grid_create(spec.coords, shape[0], shape[1], shape[2], spec.fd_order,
+                        params=default_params(amax=spec.amax, sinhwaa=spec.sinhwaa,
+                                              bscale=spec.bscale, rmax=spec.rmax))
+        g.set_punctures(*w.punctures.as_tuple())
+        grids.append(g)
+    return grids
+
+
+def relax_all(grids, tol: float, n_steps: int = 60000, check_every: int = 100,
+              precision: int = FP64):
+    """Relaxes the grids together (one batched launch per RK stage); eta per grid
+    from its time step. A grid that does not converge within n_steps is
+    reported with its last residual (the caller decides what to do with it)."""
+    etas = [workloads.eta_for_dt(g.suggest_dt(0.5)) for g in grids]
+    b = Batch(grids)
+    res = b.relax(etas, 1.0, n_steps=n_steps, tol=tol, check_every=check_every,
+                  precision=precision, raise_on_error=False)
+    b.close()
+    return res
+
+
+def dataset(ws, shape, points_per_solve: int, seed: int, mlp: MLP, tol: float = 1e-9,
+            batch: int = 64, log=print):
+    """Solves every configuration at `shape` and samples points_per_solve stored
+    points of each: features (device, float32) and targets log u (device)."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    xs, ts = [], []
+    t0 = time.perf_counter()
+    for i in range(0, len(ws), batch):
+        chunk = ws[i:i + batch]
+        grids = make_grids(chunk, shape)
+        res = relax_all(grids, tol)
+        for w, g, r in zip(chunk, grids, res):
+            if not (r.residual < tol):
+                log(f"[warmstart] skipping {w.label}: residual {r.residual:.2e} after "
+                    f"{r.steps_taken} steps")
+                g.close()
+                continue
+            X = mlp.grid_features(g, config_of(w))
+            u = g.get_u(extended=True).reshape(-1)
+            idx = rng.choice(len(u), size=min(points_per_solve, len(u)), replace=False)
+            xs.append(X[torch.as_tensor(idx, device=X.device)])
+            ts.append(torch.as_tensor(np.log(np.maximum(u[idx], 1e-30)), dtype=torch.float32,
+                                      device=X.device))
+            g.close()
+        log(f"[warmstart] solved {min(i + batch, len(ws))}/{len(ws)} configs at {shape} "
+            f"({time.perf_counter() - t0:.1f} s)")
+    return torch.cat(xs), torch.cat(ts)
+
+
+def train(mlp: MLP, X, T, epochs: int, batch: int, lr: float, seed: int, log=print):
+    """Normalises the targets (output map) and runs Adam steps over shuffled batches."""
+    import torch
+
+    shift = float(T.mean().item())
+    scale = float(T.std().item()) or 1.0
+    mlp.set_output_map(scale, shift)
+    Tn = ((T - shift) / scale).contiguous()
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    n = X.shape[0]
+    losses = []
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=g).to(X.device)
+        tot, cnt = 0.0, 0
+        lr_ep = lr * 0.5 * (1 + np.cos(np.pi * ep / max(1, epochs)))
+        for s in range(0, n - batch + 1, batch):
+            idx = perm[s:s + batch]
+            xb = X[idx].contiguous()
+            tb = Tn[idx].contiguous()
+            tot += mlp.train_step(xb, tb, lr_ep)
+            cnt += 1
+        losses.append(tot / max(cnt, 1))
+        log(f"[warmstart] epoch {ep}: loss {losses[-1]:.4e} (lr {lr_ep:.2e})")
+    return losses
+
+
+def evaluate(mlp: MLP, ws, shape, tol: float = 1e-10, batch: int = 32, log=print):
+    """Relaxes every configuration from u = v = 0 and from the network's
+    prediction (v = eta u), to the same tolerance; returns per-config steps and
+    the wall time of each batched pass."""
+    import torch
+
+    out = {"cold_steps": [], "warm_steps": [], "cold_s": 0.0, "warm_s": 0.0,
+           "initial_residual_cold": [], "initial_residual_warm": []}
+    for i in range(0, len(ws), batch):
+        chunk = ws[i:i + batch]
+        grids = make_grids(chunk, shape)
+        out["initial_residual_cold"] += [g.residual_l2() for g in grids]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = relax_all(grids, tol)
+        torch.cuda.synchronize()
+        out["cold_s"] += time.perf_counter() - t0
+        out["cold_steps"] += [r.steps_taken for r in res]
+        for w, g in zip(chunk, grids):
+            g.set_punctures(*w.punctures.as_tuple())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for w, g in zip(chunk, grids):
+            mlp.warm_start(g, config_of(w), workloads.eta_for_dt(g.suggest_dt(0.5)))
+        out["initial_residual_warm"] += [g.residual_l2() for g in grids]
+        res = relax_all(grids, tol)
+        torch.cuda.synchronize()
+        out["warm_s"] += time.perf_counter() - t0
+        out["warm_steps"] += [r.steps_taken for r in res]
+        for g in grids:
+            g.close()
+        log(f"[warmstart] evaluated {min(i + batch, len(ws))}/{len(ws)}")
+    return out
+
+
+def main(argv=None) -> int:
+    import torch
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=4096)
+    ap.add_argument("--test", type=int, default=512)
+    ap.add_argument("--train-shape", default="64x64x8")
+    ap.add_argument("--test-shape", default="128x128x16")
+    ap.add_argument("--points", type=int, default=512)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=8192)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--width", type=int, default=256)
+    args = ap.parse_args(argv)
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    torch.cuda.set_device(0)
+    tr_shape = tuple(int(x) for x in args.train_shape.split("x"))
+    te_shape = tuple(int(x) for x in args.test_shape.split("x"))
+    train_ws = workloads.catalog(args.train, seed=14031, shapes=(tr_shape,))
+    test_ws = workloads.catalog(args.test, seed=14032, shapes=(te_shape,))
+    mlp = MLP(width=args.width, seed=1, max_batch=max(args.batch, 65536))
+    t0 = time.perf_counter()
+    X, T = dataset(train_ws, tr_shape, args.points, 7, mlp, log=log)
+    t_data = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    losses = train(mlp, X, T, args.epochs, args.batch, args.lr, 3, log=log)
+    t_train = time.perf_counter() - t0
+    ev = evaluate(mlp, test_ws, te_shape, log=log)
+    cold = np.array(ev["cold_steps"])
+    warm = np.array(ev["warm_steps"])
+    res = {"train_configs": args.train, "train_shape": tr_shape, "test_configs": args.test,
+           "test_shape": te_shape, "points_per_solve": args.points, "epochs": args.epochs,
+           "final_loss": losses[-1], "data_s": t_data, "train_s": t_train,
+           "mean_steps_cold": float(cold.mean()), "mean_steps_warm": float(warm.mean()),
+           "steps_ratio": float(warm.mean() / cold.mean()),
+           "time_cold_s": ev["cold_s"], "time_warm_s": ev["warm_s"],
+           "time_ratio": ev["warm_s"] / ev["cold_s"],
+           "median_initial_residual_cold": float(np.median(ev["initial_residual_cold"])),
+           "median_initial_residual_warm": float(np.median(ev["initial_residual_warm"])),
+           "frac_configs_fewer_steps": float(np.mean(warm < cold))}
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -103,6 +103,13 @@ def brill_lindquist(grid: GridSpec | None = None) -> Workload:
 ETA_PAPER_SCALE = 80.0
 
 
+def eta_for_dt(dt: float) -> float:
+    """Damping for a grid with time step dt: a power law through the sweep optima
+    (eta = 16 at dt = 1.35e-3 on 64x64x8, eta = 80 at dt = 1.68e-4 on 128x128x16):
+    eta = 0.115 dt^-3/4."""
+    return 0.115 * dt ** -0.75
+
+
 def paper_scale(coords: int = SINHSYMTP, fd_order: int = 10) -> Workload:
     """q = 1, D = 10 (z = +-5), |P| = 0.095 along +-y, S1 = S2 = (0, 0, 0.2); relax to
     residual 1e-10. SinhSymTP 128x128x16 (bscale 5) or Spherical 128x64x8 (rmax 100)."""

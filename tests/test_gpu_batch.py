@@ -1,0 +1,96 @@
+"""Batched relaxation (one persistent launch per RK stage over many grids,
+graph-captured per check interval) against the same grids relaxed one at a
+time with the eager single-grid path.
+
+Every check interval replays the captured graph; the per-grid residual
+histories compared below check every replay against the eager result, and the
+final states are compared point by point. The batch uses the phi-column
+kernel body for every grid, the eager path may use plane tiles: both evaluate
+the same arithmetic in the same order, so results agree to a few roundoff
+units. FP64 results are also compared with the CPU oracle.
+"""
+import numpy as np
+import pytest
+
+import paper_2501_14030_amd as hr
+from paper_2501_14030_amd import workloads
+
+from gpu_common import banner, gpu_grid, oracle_extended, oracle_grid, rel_maxdiff
+
+pytestmark = pytest.mark.gpu
+
+SPECS = [
+    workloads.GridSpec(0, 37, 19, 6, 10, bscale=3.0),
+    workloads.GridSpec(0, 64, 64, 8, 10, bscale=4.0),
+    workloads.GridSpec(1, 40, 24, 4, 10, rmax=60.0),
+    workloads.GridSpec(0, 20, 12, 2, 10, amax=100.0, sinhwaa=0.2, bscale=2.0),
+]
+
+
+def _punctures(spec, k):
+    D = 2 * spec.bscale if spec.coords == 0 else 10.0
+    return workloads.quasi_circular(1.0 + 0.7 * k, D, [0.1 * k, 0.0, 0.2], [0.0, -0.1, 0.1 * k])
+
+
+def _grids():
+    gs = []
+    for k, spec in enumerate(SPECS):
+        g = gpu_grid(spec)
+        g.set_punctures(*_punctures(spec, k).as_tuple())
+        gs.append(g)
+    return gs
+
+
+def test_batch_fixed_steps_matches_eager_and_oracle():
+    banner("batch fixed steps")
+    etas = [4.0, 8.0, 6.0, 5.0]
+    gs = _grids()
+    b = hr.Batch(gs)
+    res = b.relax(etas, 1.0, n_steps=300, tol=0.0, check_every=100)
+    assert b.status == hr.OK
+    for k, spec in enumerate(SPECS):
+        e = gpu_grid(spec)
+        e.set_punctures(*_punctures(spec, k).as_tuple())
+        r = e.relax(etas[k], 1.0, 0.0, 300, 0.0, check_every=100)
+        d = rel_maxdiff(gs[k].get_u(extended=True), e.get_u(extended=True))
+        banner(f"{spec.name()}: batch vs eager {d:.2e}")
+        assert d <= 1e-13
+        np.testing.assert_allclose(res[k].history, r.history, rtol=1e-10, atol=1e-16)
+        assert res[k].steps_taken == 300
+    # one grid against the oracle as well
+    spec = SPECS[0]
+    og = oracle_grid(spec)
+    og.set_punctures(*_punctures(spec, 0).as_tuple())
+    og.relax(etas[0], 1.0, og.suggest_dt(0.5), 300, 0.0, 100)
+    ou, _ = og.state()
+    assert rel_maxdiff(gs[0].get_u(extended=True), oracle_extended(og, ou)) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", [hr.FP64, hr.FP32_FP64FINISH])
+def test_batch_to_tolerance_each_grid_stops_on_its_own(prec):
+    banner(f"batch to tolerance prec {prec}")
+    etas = [4.0, 8.0, 6.0, 5.0]
+    gs = _grids()
+    b = hr.Batch(gs)
+    res = b.relax(etas, 1.0, n_steps=60000, tol=1e-10, check_every=100, precision=prec)
+    assert b.status == hr.OK
+    for k, spec in enumerate(SPECS):
+        e = gpu_grid(spec)
+        e.set_punctures(*_punctures(spec, k).as_tuple())
+        r = e.relax(etas[k], 1.0, 0.0, 60000, 1e-10, check_every=100, precision=prec)
+        assert r.status == hr.OK
+        banner(f"{spec.name()}: batch steps {res[k].steps_taken} (fp32 {res[k].fp32_steps}), "
+               f"eager {r.steps_taken} (fp32 {r.fp32_steps})")
+        assert res[k].steps_taken == r.steps_taken
+        assert res[k].fp32_steps == r.fp32_steps
+        assert gs[k].residual_l2() < 1e-10
+        assert rel_maxdiff(gs[k].get_u(extended=True), e.get_u(extended=True)) <= 1e-11
+
+
+def test_batch_rejects_mixed_orders_and_unbound():
+    a = gpu_grid(workloads.GridSpec(0, 16, 8, 2, 8, bscale=1.0))
+    c = gpu_grid(workloads.GridSpec(0, 16, 8, 2, 10, bscale=1.0))
+    with pytest.raises(hr.HRError):
+        hr.Batch([a, c])
+    with pytest.raises(hr.HRError):
+        hr.Batch([a, a])

@@ -1,0 +1,75 @@
+"""Warm-start network on the GPU: MFMA GEMM layers and their gradients against
+the FP64 numpy oracle, training reduces the loss, and a trained network lets
+the relaxation reach the same tolerance in fewer steps than the zero initial
+guess (the relaxation judges the result in both cases)."""
+import numpy as np
+import pytest
+
+import paper_2501_14030_amd as hr
+from paper_2501_14030_amd import warmstart, workloads
+from paper_2501_14030_amd.mlp import MLP
+
+from gpu_common import banner
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("width,B", [(16, 5), (64, 70), (256, 300)])
+def test_forward_and_gradients_match_oracle(width, B):
+    from oracle import mlp as omlp
+
+    banner(f"mlp width {width} batch {B}")
+    rng = np.random.default_rng(width + B)
+    net = MLP(width=width, seed=5, max_batch=512)
+    p = net.get_params().astype(np.float64)
+    # non-zero biases so that every term is exercised
+    p = p + rng.normal(scale=0.1, size=p.size)
+    net.set_params(p.astype(np.float32))
+    p32 = net.get_params().astype(np.float64)
+    x = rng.normal(size=(B, omlp.N_FEAT)).astype(np.float32)
+    t = rng.normal(size=B).astype(np.float32)
+    y = net.forward(x)
+    yo, _ = omlp.forward(p32, width, x.astype(np.float64))
+    np.testing.assert_allclose(y, yo, rtol=2e-4, atol=2e-4 * np.abs(yo).max())
+    loss, g = net.gradients(x, t)
+    lo, go = omlp.loss_and_grad(p32, width, x.astype(np.float64), t.astype(np.float64))
+    assert abs(loss - lo) <= 1e-4 * abs(lo)
+    err = np.linalg.norm(g - go) / np.linalg.norm(go)
+    banner(f"relative gradient error {err:.2e}")
+    assert err <= 1e-4
+
+
+def test_training_reduces_loss():
+    import torch
+
+    banner("mlp training")
+    rng = np.random.default_rng(1)
+    net = MLP(width=64, seed=2, max_batch=4096)
+    net.set_output_map(1.0, 0.0)
+    x = rng.uniform(-1, 1, size=(4096, 13)).astype(np.float32)
+    t = (np.sin(2 * x[:, 9]) + x[:, 0] * x[:, 10] + 0.5 * x[:, 11] ** 2).astype(np.float32)
+    xd = torch.as_tensor(x, device="cuda")
+    td = torch.as_tensor(t, device="cuda")
+    first = None
+    for it in range(300):
+        l = net.train_step(xd[:1024 * (it % 4 + 1)].contiguous(), td[:1024 * (it % 4 + 1)].contiguous(), 3e-3)
+        first = l if first is None else first
+    banner(f"loss {first:.3e} -> {l:.3e}")
+    assert l < 0.05 * first
+
+
+def test_warm_start_needs_fewer_steps():
+    banner("warm start end to end (small catalog)")
+    train_ws = workloads.catalog(96, seed=14031, shapes=((32, 32, 8),))
+    test_ws = workloads.catalog(6, seed=14032, shapes=((64, 64, 8),))
+    net = MLP(width=128, seed=1, max_batch=16384)
+    X, T = warmstart.dataset(train_ws, (32, 32, 8), 1024, 7, net, batch=48, log=banner)
+    warmstart.train(net, X, T, epochs=40, batch=4096, lr=3e-3, seed=3, log=lambda m: None)
+    ev = warmstart.evaluate(net, test_ws, (64, 64, 8), tol=1e-10, batch=6, log=banner)
+    cold = np.array(ev["cold_steps"])
+    warm = np.array(ev["warm_steps"])
+    banner(f"steps cold {cold.tolist()} warm {warm.tolist()}; initial residual median "
+           f"{np.median(ev['initial_residual_cold']):.2e} -> {np.median(ev['initial_residual_warm']):.2e}")
+    assert np.median(ev["initial_residual_warm"]) < 0.1 * np.median(ev["initial_residual_cold"])
+    assert warm.mean() < cold.mean()
+    assert np.mean(warm <= cold) >= 0.8

@@ -75,3 +75,32 @@ def test_invalid_kernel_config_rejected():
         g.set_kernel_config(variant=5)
     with pytest.raises(hr.HRError):
         g.set_kernel_config(variant=2, chunk=-1)
+
+
+def test_autotune_keeps_state_and_caches():
+    banner("autotune")
+    w = workloads.paper_scale()
+    spec = workloads.GridSpec(0, 64, 64, 16, 10, bscale=5.0)
+    g = gpu_grid(spec)
+    g.set_punctures(*w.punctures.as_tuple())
+    g.relax(16.0, 1.0, 0.0, 100, 0.0, check_every=100)
+    u0 = g.get_u(extended=True)
+    v0 = g.get_v(extended=True)
+    cfg, us = g.autotune(hr.FP64, 3)
+    assert cfg["variant"] in (1, 2) and us > 0
+    if cfg["variant"] == 2:
+        assert 1 <= cfg["chunk"] <= spec.N2
+    assert np.array_equal(g.get_u(extended=True), u0)
+    assert np.array_equal(g.get_v(extended=True), v0)
+    assert g.kernel_config() == cfg
+    # a second grid of the same shape takes the cached choice
+    h = gpu_grid(spec)
+    h.set_punctures(*w.punctures.as_tuple())
+    cfg2, us2 = h.autotune(hr.FP64, 3)
+    assert cfg2 == cfg and us2 == us
+    # the tuned configuration relaxes to the same state as the default one
+    g.relax(16.0, 1.0, 0.0, 200, 0.0, check_every=100)
+    h.set_kernel_config(variant=1)
+    h.set_punctures(*w.punctures.as_tuple())
+    h.relax(16.0, 1.0, 0.0, 300, 0.0, check_every=100)
+    assert rel_maxdiff(g.get_u(extended=True), h.get_u(extended=True)) <= 1e-14
