@@ -214,12 +214,17 @@ hr_status hr_suggest_dt(const hr_grid* g, double cfl, double* dt);
  *   streaming  -1 = automatic (by grid size), 0 = cached, 1 = non-temporal
  *              loads/stores for fields touched once per stage
  *   chunk      phi planes per block for variant 2 (0 = automatic)
+ *   graph      -1 = automatic (on), 0 = off, 1 = on: hr_relax captures the
+ *              launches of one check interval (RK stages, residual) in a HIP
+ *              graph once per (precision form, check_every, eta, dt, c,
+ *              configuration) and replays it
  * Errors: HR_EINVAL.
  */
 typedef struct {
   int variant;
   int streaming;
   int chunk;
+  int graph;
 } hr_kernel_config;
 
 hr_status hr_set_kernel_config(hr_grid* g, const hr_kernel_config* cfg);
@@ -283,16 +288,18 @@ hr_status hr_batch_relax(hr_batch* b, const double* eta, const double* c, long n
 void hr_batch_destroy(hr_batch* b);
 
 /*
- * Learned warm start. An MLP (FP32) maps 13 features -- 9 configuration
+ * Learned warm start. An MLP (FP32) maps 15 features -- 9 configuration
  * values (caller-normalised: mass ratio, spins chi1 and chi2, momentum
- * magnitude, separation) and 4 coordinate values of a grid point
- * (2 xx0/xx0_max - 1, cos xx1, sin xx1 cos xx2, sin xx1 sin xx2) -- through
+ * magnitude, separation), 4 coordinate values of a grid point
+ * (2 xx0/xx0_max - 1, cos xx1, sin xx1 cos xx2, sin xx1 sin xx2) and
+ * 0.1 log(r_n^2) for the distance r_n to each of the first two punctures --
+ * through
  * two hidden layers of `width` GELU units to y, with log u = scale y + shift.
  * Trained on the relaxation's own solves; its prediction is only an initial
  * state, which the relaxation then drives to the residual tolerance.
  *   hr_mlp_create          width (multiple of 8, 8..1024); He-normal
  *                          weights from seed, zero biases (host side).
- *   hr_mlp_param_count     parameters, laid out W1[width x 13], b1, W2[width x
+ *   hr_mlp_param_count     parameters, laid out W1[width x 15], b1, W2[width x
  *                          width], b2, W3[1 x width], b3 (row-major, FP32).
  *   hr_mlp_workspace_bytes / hr_mlp_bind
  *                          caller-owned device memory for parameters, Adam
@@ -300,12 +307,13 @@ void hr_batch_destroy(hr_batch* b);
  *                          (1..262144); 256-byte aligned; stream NULL = own.
  *   hr_mlp_get/set_params  host copies (count = hr_mlp_param_count).
  *   hr_mlp_set_output_map  scale (non-zero) and shift of log u.
- *   hr_mlp_forward         host x[B x 13] -> host y[B] (network output y).
+ *   hr_mlp_forward         host x[B x 15] -> host y[B] (network output y).
  *   hr_mlp_gradients       host x, host targets t[B] -> loss = mean (y-t)^2
  *                          and its gradient w.r.t. every parameter (host).
- *   hr_mlp_train_step      device x[B x 13], device t[B]: loss, gradient and
+ *   hr_mlp_train_step      device x[B x 15], device t[B]: loss, gradient and
  *                          one Adam step (beta1 0.9, beta2 0.999, eps 1e-8).
- *   hr_mlp_grid_features   device out[n_extended x 13] for a bound grid.
+ *   hr_mlp_grid_features   device out[n_extended x 15] for a bound grid with
+ *                          punctures set.
  *   hr_warm_start          sets u = exp(scale y + shift) and v = eta u at every
  *                          stored point of the grid (punctures must be set).
  * Errors: HR_EINVAL, HR_ESTATE, HR_ENOMEM, HR_EDEVICE.

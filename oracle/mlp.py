@@ -4,9 +4,9 @@ backward) in numpy.
 TEST INFRASTRUCTURE ONLY: used by tests to check the HIP network's outputs and
 gradients; the product never imports it.
 
-Network: x (13) -> W1 x + b1 -> GELU -> W2 . + b2 -> GELU -> W3 . + b3 -> y;
+Network: x (15) -> W1 x + b1 -> GELU -> W2 . + b2 -> GELU -> W3 . + b3 -> y;
 GELU(z) = z Phi(z) with Phi the standard normal CDF; loss = mean (y - t)^2.
-Parameters are one flat vector laid out W1[w x 13], b1[w], W2[w x w], b2[w],
+Parameters are one flat vector laid out W1[w x 15], b1[w], W2[w x w], b2[w],
 W3[1 x w], b3[1] (row-major).
 """
 from __future__ import annotations
@@ -15,7 +15,7 @@ import math
 
 import numpy as np
 
-N_FEAT = 13
+N_FEAT = 15
 
 _erf = np.vectorize(math.erf, otypes=[np.float64])
 

@@ -52,7 +52,8 @@ class GridParams(ctypes.Structure):
 
 
 class KernelConfig(ctypes.Structure):
-    _fields_ = [("variant", ctypes.c_int), ("streaming", ctypes.c_int), ("chunk", ctypes.c_int)]
+    _fields_ = [("variant", ctypes.c_int), ("streaming", ctypes.c_int), ("chunk", ctypes.c_int),
+                ("graph", ctypes.c_int)]
 
 
 class RelaxReport(ctypes.Structure):
@@ -289,8 +290,9 @@ class Grid:
                "hr_time_stage_kernels")
         return out
 
-    def set_kernel_config(self, variant: int = 0, streaming: int = -1, chunk: int = 0) -> None:
-        cfg = KernelConfig(int(variant), int(streaming), int(chunk))
+    def set_kernel_config(self, variant: int = 0, streaming: int = -1, chunk: int = 0,
+                          graph: int = -1) -> None:
+        cfg = KernelConfig(int(variant), int(streaming), int(chunk), int(graph))
         _check(load_library().hr_set_kernel_config(self._h, ctypes.byref(cfg)),
                "hr_set_kernel_config")
 
@@ -301,13 +303,15 @@ class Grid:
         us = ctypes.c_double()
         _check(load_library().hr_autotune(self._h, int(precision), int(n_steps), ctypes.byref(cfg),
                                           ctypes.byref(us)), "hr_autotune")
-        return {"variant": cfg.variant, "streaming": cfg.streaming, "chunk": cfg.chunk}, us.value
+        return {"variant": cfg.variant, "streaming": cfg.streaming, "chunk": cfg.chunk,
+                "graph": cfg.graph}, us.value
 
     def kernel_config(self) -> dict:
         cfg = KernelConfig()
         _check(load_library().hr_get_kernel_config(self._h, ctypes.byref(cfg)),
                "hr_get_kernel_config")
-        return {"variant": cfg.variant, "streaming": cfg.streaming, "chunk": cfg.chunk}
+        return {"variant": cfg.variant, "streaming": cfg.streaming, "chunk": cfg.chunk,
+                "graph": cfg.graph}
 
     def suggest_dt(self, cfl: float = 0.5) -> float:
         out = ctypes.c_double()

@@ -236,6 +236,112 @@ hr_status set_field(hr_grid* g, double* dev, const double* host, size_t n) {
   return HR_OK;
 }
 
+// Enqueues the residual kernels of the given state (no readback).
+hr_status enqueue_residual(hr_grid* g, const void* u, bool fp32) {
+  ResidualArgs r{};
+  r.d = g->d;
+  r.u = u;
+  r.psi = g->f64.psi;
+  r.ssrc = g->f64.ssrc;
+  r.fac = g->f64.fac;
+  r.partial = g->partial;
+  HR_HIP(launch_residual(g->fd_order, fp32, r, g->stream));
+  HR_HIP(launch_finalize(g->partial, g->nblk_res, g->d.nint, g->result, g->stream));
+  return HR_OK;
+}
+
+BaseArgs base_args(const hr_grid* g, double eta) {
+  BaseArgs b{};
+  b.d = g->d;
+  b.u = g->f64.un;
+  b.v = g->f64.vn;
+  b.psi = g->f64.psi;
+  b.ssrc = g->f64.ssrc;
+  b.fac = g->f64.fac;
+  b.ofac = g->f64.ofac;
+  b.eta = eta;
+  b.khu = g->f32.khu;
+  b.khv = g->f32.khv;
+  b.pb = g->f32.pb;
+  b.sp7 = g->f32.sp7;
+  b.eu = g->f32.un;
+  b.ev = g->f32.vn;
+  return b;
+}
+
+// The launches of one check interval of kind 0 (FP64), 1 (FP32 state) or 2
+// (split-state FP32 increment on the FP64 base): K RK4 steps, then the
+// residual of the resulting state into g->result.
+hr_status enqueue_interval(hr_grid* g, int kind, int K, double eta, double dt) {
+  hr_status st;
+  if (kind == 0) {
+    st = launch_steps<double>(g, g->f64, eta, dt, K);
+    if (st != HR_OK) return st;
+    return enqueue_residual(g, g->f64.un, false);
+  }
+  if (kind == 1) {
+    st = launch_steps<float>(g, g->f32, (float)eta, (float)dt, K);
+    if (st != HR_OK) return st;
+    return enqueue_residual(g, g->f32.un, true);
+  }
+  HR_HIP(launch_base(g->fd_order, base_args(g, eta), g->stream));
+  st = launch_steps<float>(g, g->f32, (float)eta, (float)dt, K, true);
+  if (st != HR_OK) return st;
+  HR_HIP(launch_rebase(g->f64.un, g->f64.vn, g->f32.un, g->f32.vn, (int)g->G, g->stream));
+  return enqueue_residual(g, g->f64.un, false);
+}
+
+// Runs one check interval (graph-captured once per key when enabled) and
+// reads the residual back.
+hr_status run_interval(hr_grid* g, int kind, int K, double eta, double dt, double* res) {
+  int variant = 0, chunk = 0;
+  resolve_variant(g, variant, chunk);
+  const int streaming = g->streaming > 0 ? 1 : 0;
+  if (g->graph != 0) {
+    const bool same = g->gexec && g->g_kind == kind && g->g_K == K && g->g_eta == eta &&
+                      g->g_dt == dt && g->g_kappa == g->kappa_loaded && g->g_variant == variant &&
+                      g->g_chunk == chunk && g->g_streaming == streaming;
+    if (!same) {
+      if (g->gexec) {
+        (void)hipGraphExecDestroy(g->gexec);
+        g->gexec = nullptr;
+      }
+      HR_HIP(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
+      hr_status st = enqueue_interval(g, kind, K, eta, dt);
+      hipGraph_t graph = nullptr;
+      const hipError_t ee = hipStreamEndCapture(g->stream, &graph);
+      if (st != HR_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+      }
+      if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
+      const hipError_t ei = hipGraphInstantiate(&g->gexec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) {
+        g->gexec = nullptr;
+        return hip_fail(ei, "hipGraphInstantiate");
+      }
+      g->g_kind = kind;
+      g->g_K = K;
+      g->g_eta = eta;
+      g->g_dt = dt;
+      g->g_kappa = g->kappa_loaded;
+      g->g_variant = variant;
+      g->g_chunk = chunk;
+      g->g_streaming = streaming;
+    }
+    HR_HIP(hipGraphLaunch(g->gexec, g->stream));
+  } else {
+    hr_status st = enqueue_interval(g, kind, K, eta, dt);
+    if (st != HR_OK) return st;
+  }
+  HR_HIP(hipMemcpyAsync(g->host_res, g->result, sizeof(double), hipMemcpyDeviceToHost,
+                        g->stream));
+  HR_HIP(hipStreamSynchronize(g->stream));
+  *res = g->host_res[0];
+  return HR_OK;
+}
+
 // One precision phase of the relaxation: runs until the stop rule fires.
 // Returns the number of steps done in *done; *why: 0 = step cap, 1 = tol,
 // 2 = non-finite, 3 = FP32 switch rule.
@@ -249,15 +355,19 @@ hr_status run_phase(hr_grid* g, const Fields<T>& F, bool fp32, double eta, doubl
   *why = 0;
   while (s < max_steps) {
     const long chunk = std::min<long>(K, max_steps - s);
-    hr_status st = launch_steps<T>(g, F, (T)eta, (T)dt, chunk);
-    if (st != HR_OK) return st;
-    s += chunk;
-    if (chunk == K) {
-      // a check after every K steps of this phase; a shorter tail is unchecked
-      double res = 0.0;
-      st = residual_of(g, F.un, fp32, &res);
+    if (chunk != K) {
+      // a shorter tail is run without a check
+      hr_status st = launch_steps<T>(g, F, (T)eta, (T)dt, chunk);
       if (st != HR_OK) return st;
-      *last_res = res;
+      s += chunk;
+      break;
+    }
+    s += chunk;
+    {
+      // a check after every K steps of this phase
+      double res = 0.0;
+      hr_status st = run_interval(g, fp32 ? 1 : 0, K, eta, dt, &res);
+      if (st != HR_OK) return st;      *last_res = res;
       if (rep) {
         if (rep->history && rep->n_history < rep->history_cap)
           rep->history[rep->n_history] = res;
@@ -300,21 +410,7 @@ hr_status run_phase(hr_grid* g, const Fields<T>& F, bool fp32, double eta, doubl
 hr_status run_split_phase(hr_grid* g, double eta, double dt, long max_steps, double tol,
                           int K, double sw_res, hr_relax_report* rep, long* done, int* why,
                           double* last_res) {
-  BaseArgs b{};
-  b.d = g->d;
-  b.u = g->f64.un;
-  b.v = g->f64.vn;
-  b.psi = g->f64.psi;
-  b.ssrc = g->f64.ssrc;
-  b.fac = g->f64.fac;
-  b.ofac = g->f64.ofac;
-  b.eta = eta;
-  b.khu = g->f32.khu;
-  b.khv = g->f32.khv;
-  b.pb = g->f32.pb;
-  b.sp7 = g->f32.sp7;
-  b.eu = g->f32.un;
-  b.ev = g->f32.vn;
+  const BaseArgs b = base_args(g, eta);
   const int G = (int)g->G;
   long s = 0;
   int stall = 0;
@@ -322,15 +418,19 @@ hr_status run_split_phase(hr_grid* g, double eta, double dt, long max_steps, dou
   *why = 0;
   while (s < max_steps) {
     const long chunk = std::min<long>(K, max_steps - s);
-    HR_HIP(launch_base(g->fd_order, b, g->stream));
-    hr_status st = launch_steps<float>(g, g->f32, (float)eta, (float)dt, chunk, true);
-    if (st != HR_OK) return st;
-    HR_HIP(launch_rebase(g->f64.un, g->f64.vn, g->f32.un, g->f32.vn, G, g->stream));
-    s += chunk;
-    if (chunk != K) break;
+    if (chunk != K) {
+      // a shorter tail is run without a check
+      HR_HIP(launch_base(g->fd_order, b, g->stream));
+      hr_status st = launch_steps<float>(g, g->f32, (float)eta, (float)dt, chunk, true);
+      if (st != HR_OK) return st;
+      HR_HIP(launch_rebase(g->f64.un, g->f64.vn, g->f32.un, g->f32.vn, G, g->stream));
+      s += chunk;
+      break;
+    }
     double res = 0.0;
-    st = residual_of(g, g->f64.un, false, &res);
+    hr_status st = run_interval(g, 2, K, eta, dt, &res);
     if (st != HR_OK) return st;
+    s += chunk;
     *last_res = res;
     if (rep) {
       if (rep->history && rep->n_history < rep->history_cap) rep->history[rep->n_history] = res;
@@ -424,6 +524,7 @@ void hr_grid_destroy(hr_grid* g) {
   if (g->bound) {
     (void)hipSetDevice(g->device);
     (void)hipStreamSynchronize(g->stream);
+    if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
     if (g->host_res) (void)hipHostFree(g->host_res);
     if (g->own_stream) (void)hipStreamDestroy(g->stream);
   }
@@ -518,6 +619,7 @@ hr_status hr_set_punctures(hr_grid* g, int n, const double* m, const double* x,
   HR_HIP(launch_fill(g->f64.vn, 0.0, G, g->stream));
   HR_HIP(hipStreamSynchronize(g->stream));
   g->have_sources = true;
+  g->pz = pz;
   return HR_OK;
 }
 
@@ -672,11 +774,12 @@ hr_status hr_time_stage_kernels(hr_grid* g, double eta, double c, double dt, lon
 hr_status hr_set_kernel_config(hr_grid* g, const hr_kernel_config* cfg) {
   if (!g || !cfg) return fail(HR_EINVAL, "null argument");
   if (cfg->variant < 0 || cfg->variant > 2 || cfg->streaming < -1 || cfg->streaming > 1 ||
-      cfg->chunk < 0)
+      cfg->chunk < 0 || cfg->graph < -1 || cfg->graph > 1)
     return fail(HR_EINVAL, "invalid kernel configuration");
   g->variant = cfg->variant;
   g->streaming = cfg->streaming;
   g->chunk = cfg->chunk;
+  g->graph = cfg->graph;
   return HR_OK;
 }
 
@@ -685,6 +788,7 @@ hr_status hr_get_kernel_config(const hr_grid* g, hr_kernel_config* cfg) {
   cfg->variant = g->variant;
   cfg->streaming = g->streaming;
   cfg->chunk = g->chunk;
+  cfg->graph = g->graph;
   return HR_OK;
 }
 
@@ -714,8 +818,8 @@ hr_status hr_autotune(hr_grid* g, hr_precision prec, int n_steps, hr_kernel_conf
   }
   HR_HIP(hipSetDevice(g->device));
   std::vector<hr_kernel_config> cand;
-  cand.push_back(hr_kernel_config{1, 0, 0});
-  for (int c = 1; c <= g->d.N2; c *= 2) cand.push_back(hr_kernel_config{2, 0, c});
+  cand.push_back(hr_kernel_config{1, 0, 0, g->graph});
+  for (int c = 1; c <= g->d.N2; c *= 2) cand.push_back(hr_kernel_config{2, 0, c, g->graph});
   hipEvent_t e0, e1;
   HR_HIP(hipEventCreate(&e0));
   HR_HIP(hipEventCreate(&e1));

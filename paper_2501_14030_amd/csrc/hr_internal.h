@@ -213,11 +213,16 @@ struct hr_grid {
   double* result = nullptr;
   double* host_res = nullptr;   // pinned readback slot
   bool have_sources = false;
+  hr::Punctures pz{};           // punctures of the last hr_set_punctures
   double kappa_loaded = -1.0;   // wave-speed scale currently in fac/ofac
 
   int variant = 0;              // kernel variant: 0 auto, 1 plane tiles, 2 phi columns
   int streaming = -1;           // non-temporal field access: -1 auto (by size), 0, 1
   int chunk = 0;                // phi planes per block of the column variant (0 auto)
+  int graph = -1;               // graph capture of check intervals: -1 auto (on), 0, 1
+  hipGraphExec_t gexec = nullptr;  // captured check interval and its key
+  int g_kind = -1, g_K = 0, g_variant = 0, g_chunk = 0, g_streaming = 0;
+  double g_eta = 0, g_dt = 0, g_kappa = 0;
 
   // FP32 -> FP64 switch rule (sw_residual 0: ten times the tolerance)
   double sw_residual = 0.0;

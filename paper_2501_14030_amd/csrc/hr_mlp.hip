@@ -22,7 +22,7 @@ using namespace hr;
 
 namespace {
 
-constexpr int kFeat = 13;   // 9 configuration + 4 coordinate features
+constexpr int kFeat = 15;   // 9 configuration + 4 coordinate + 2 puncture-distance features
 
 // ---------------------------------------------------------------------------
 // GEMM C[M x N] = A[M x K] B[K x N] (+ bias[n]) with optional GELU, FP32, on
@@ -166,12 +166,18 @@ __global__ void __launch_bounds__(256) k_adam(float* __restrict__ p, const float
 }
 
 // Input features of every stored point of a grid (extended layout order):
-// 9 normalised configuration values and 4 coordinate values
-// (2 xx0 - 1, cos xx1, sin xx1 cos xx2, sin xx1 sin xx2).
+// 9 normalised configuration values, 4 coordinate values (2 xx0/xx0_max - 1,
+// cos xx1, sin xx1 cos xx2, sin xx1 sin xx2) and the logarithm of the distance
+// to each of the first two punctures, divided by 5.
 struct FeatArgs {
   Dims d;
   double x0max;
   float cfg[9];
+  const double* rho;   // cylindrical radius and z over the (i0, i1) plane
+  const double* zc;
+  const double* cphi;
+  const double* sphi;
+  double px[2][3];     // puncture positions (the second repeats the first if n = 1)
   int row0;    // first stored point (extended-layout index) of this launch
   int nrows;   // points in this launch; row t of X is point row0 + t
   float* X;
@@ -196,6 +202,13 @@ __global__ void __launch_bounds__(256) k_features(FeatArgs a) {
   x[10] = (float)cos(xx1);
   x[11] = (float)(sin(xx1) * cos(xx2));
   x[12] = (float)(sin(xx1) * sin(xx2));
+  const int e = i0 + a.d.P0 * i1;
+  const double X0 = a.rho[e] * a.cphi[i2], Y0 = a.rho[e] * a.sphi[i2], Z0 = a.zc[e];
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const double dx = X0 - a.px[p][0], dy = Y0 - a.px[p][1], dz = Z0 - a.px[p][2];
+    x[13 + p] = (float)(0.1 * log(dx * dx + dy * dy + dz * dz));
+  }
 }
 
 // u = exp(scale y + shift) into the FP64 state, v = eta u.
@@ -510,10 +523,17 @@ hr_status hr_mlp_grid_features(hr_mlp* n, const hr_grid* g, const double* cfg9, 
   if (!n || !g || !cfg9 || !dev_out) return mfail(HR_EINVAL, "null argument");
   (void)n;
   if (!g->bound) return mfail(HR_ESTATE, "grid not bound");
+  if (!g->have_sources) return mfail(HR_ESTATE, "punctures not set");
   FeatArgs a{};
   a.d = g->d;
   a.x0max = g->coords == HR_SINHSYMTP ? 1.0 : g->prm.rmax;
   for (int k = 0; k < 9; ++k) a.cfg[k] = (float)cfg9[k];
+  a.rho = g->rho;
+  a.zc = g->zc;
+  a.cphi = g->cphi;
+  a.sphi = g->sphi;
+  for (int p = 0; p < 2; ++p)
+    for (int k = 0; k < 3; ++k) a.px[p][k] = g->pz.x[p < g->pz.n ? p : 0][k];
   a.X = dev_out;
   a.row0 = 0;
   a.nrows = g->d.P0 * g->d.N1 * g->d.N2;
@@ -534,6 +554,12 @@ hr_status hr_warm_start(hr_grid* g, hr_mlp* n, const double* cfg9, double eta) {
   a.d = g->d;
   a.x0max = g->coords == HR_SINHSYMTP ? 1.0 : g->prm.rmax;
   for (int k = 0; k < 9; ++k) a.cfg[k] = (float)cfg9[k];
+  a.rho = g->rho;
+  a.zc = g->zc;
+  a.cphi = g->cphi;
+  a.sphi = g->sphi;
+  for (int p = 0; p < 2; ++p)
+    for (int k = 0; k < 3; ++k) a.px[p][k] = g->pz.x[p < g->pz.n ? p : 0][k];
   const int next = g->d.P0 * g->d.N1 * g->d.N2;
   // the grid's stored points go through the network in max_batch chunks
   for (int start = 0; start < next; start += n->max_batch) {

@@ -11,7 +11,7 @@ from . import _check, _dp, load_library
 
 _fp = ctypes.POINTER(ctypes.c_float)
 
-N_FEAT = 13
+N_FEAT = 15
 
 _SIG = {
     "hr_mlp_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_ulonglong, ctypes.POINTER(ctypes.c_void_p)]),
@@ -114,7 +114,7 @@ class MLP:
         return float(loss.value), g
 
     def train_step(self, x_dev, t_dev, lr: float) -> float:
-        """x_dev (B x 13) and t_dev (B) are contiguous float32 torch tensors on the device."""
+        """x_dev (B x 15) and t_dev (B) are contiguous float32 torch tensors on the device."""
         loss = ctypes.c_float()
         _check(_lib().hr_mlp_train_step(self._h, ctypes.c_void_p(x_dev.data_ptr()),
                                         ctypes.c_void_p(t_dev.data_ptr()), int(x_dev.shape[0]),

@@ -46,7 +46,7 @@ def test_training_reduces_loss():
     rng = np.random.default_rng(1)
     net = MLP(width=64, seed=2, max_batch=4096)
     net.set_output_map(1.0, 0.0)
-    x = rng.uniform(-1, 1, size=(4096, 13)).astype(np.float32)
+    x = rng.uniform(-1, 1, size=(4096, 15)).astype(np.float32)
     t = (np.sin(2 * x[:, 9]) + x[:, 0] * x[:, 10] + 0.5 * x[:, 11] ** 2).astype(np.float32)
     xd = torch.as_tensor(x, device="cuda")
     td = torch.as_tensor(t, device="cuda")

@@ -104,3 +104,27 @@ def test_autotune_keeps_state_and_caches():
     h.set_punctures(*w.punctures.as_tuple())
     h.relax(16.0, 1.0, 0.0, 300, 0.0, check_every=100)
     assert rel_maxdiff(g.get_u(extended=True), h.get_u(extended=True)) <= 1e-14
+
+
+@pytest.mark.parametrize("prec", [hr.FP64, hr.FP32_FP64FINISH, hr.FP32])
+def test_graph_replays_match_eager_launches(prec):
+    """Each check interval is one replay of the captured graph; the residual read
+    back after every replay and the final state must equal the eager launches'
+    bitwise (same kernels, same arguments)."""
+    banner(f"graph vs eager, precision {prec}")
+    w = workloads.equal_mass_small()
+    out = []
+    for graph in (0, 1):
+        g = gpu_grid(w.grid)
+        g.set_kernel_config(graph=graph)
+        g.set_fp32_switch(0.0, 1000000, 0)
+        g.set_punctures(*w.punctures.as_tuple())
+        r1 = g.relax(8.0, 1.0, 0.0, 700, 0.0, check_every=100, precision=prec)
+        # eager host work between replays, then a second call reusing the graph
+        _ = g.get_u()
+        r2 = g.relax(8.0, 1.0, 0.0, 350, 0.0, check_every=100, precision=prec)
+        out.append((np.concatenate([r1.history, r2.history]), g.get_u(extended=True),
+                    g.get_v(extended=True)))
+    assert len(out[0][0]) == 10
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1]) and np.array_equal(out[0][2], out[1][2])
