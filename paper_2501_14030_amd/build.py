@@ -17,7 +17,8 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhrelax.so")
 
-SOURCES = ["hr_geometry.cpp", "hr_kernels.hip", "hr_abi.hip", "hr_batch.hip", "hr_mlp.hip"]
+SOURCES = ["hr_geometry.cpp", "hr_kernels.hip", "hr_resident.hip", "hr_abi.hip", "hr_batch.hip",
+           "hr_mlp.hip"]
 ARCH = "gfx950"
 
 # -packed-fp32-ops: no packed FP32 VALU instructions are generated.

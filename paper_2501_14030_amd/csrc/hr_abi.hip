@@ -17,6 +17,8 @@
 #include <string>
 #include <tuple>
 
+#include <type_traits>
+
 #include "hr_internal.h"
 
 namespace hr {
@@ -40,6 +42,11 @@ hr_status kfail(hr_status s, const std::string& msg) {
 
 // Kernel variant for this grid: explicit configuration, else by size (phi
 // columns when there are enough (x0, x1) tiles to fill the device).
+bool resident_ok(const hr_grid* g) {
+  return g->bound && g->res_nbx > 0 && g->res_nbx * g->res_nby <= g->res_capacity &&
+         (g->fd_order == 8 || g->fd_order == 10);
+}
+
 void resolve_variant(const hr_grid* g, int& variant, int& chunk) {
   variant = g->variant;
   chunk = g->chunk;
@@ -132,12 +139,73 @@ size_t layout(hr_grid* g, char* base) {
   g->sphi = (double*)take(g->d.N2 * sizeof(double));
   g->partial = (double*)take((size_t)g->nblk_res * sizeof(double));
   g->result = (double*)take(4 * sizeof(double));
+  const int nres = g->res_nbx * g->res_nby;
+  if (nres > 0) {
+    g->res_flags = (unsigned*)take((size_t)nres * kResFlagStride * sizeof(unsigned));
+    g->res_waits = (int*)take(g->res_plan.size() * sizeof(int));
+    g->res_err = (unsigned*)take(sizeof(unsigned));
+  }
   return off;
+}
+
+ResidentArgs resident_args(hr_grid* g, double eta, double dt, int nsteps) {
+  ResidentArgs r{};
+  r.d = g->d;
+  r.u = g->f64.un;
+  r.v = g->f64.vn;
+  r.psi = g->f64.psi;
+  r.ssrc = g->f64.ssrc;
+  r.fac = g->f64.fac;
+  r.ofac = g->f64.ofac;
+  r.x0 = g->f64.ua;
+  r.x1 = g->f64.ub;
+  r.flags = g->res_flags;
+  r.waits = g->res_waits;
+  r.err = g->res_err;
+  r.eta = eta;
+  // the stage coefficients of the stage kernels (classic RK4)
+  r.cy[0] = dt / 2.0; r.cy[1] = dt / 2.0; r.cy[2] = dt; r.cy[3] = dt;
+  r.ca[0] = dt / 6.0; r.ca[1] = dt / 3.0; r.ca[2] = dt / 3.0; r.ca[3] = dt / 6.0;
+  r.nbx = g->res_nbx;
+  r.nby = g->res_nby;
+  r.nsteps = nsteps;
+  r.spin_limit = 1u << 19;
+  return r;
+}
+
+// Reads the resident kernel's error word (synchronous); a timed-out exchange
+// wait leaves the state unchanged from the launch's start and is reported.
+hr_status check_resident(hr_grid* g) {
+  unsigned e = 0;
+  HR_HIP(hipMemcpyAsync(&e, g->res_err, sizeof(unsigned), hipMemcpyDeviceToHost, g->stream));
+  HR_HIP(hipStreamSynchronize(g->stream));
+  if (e) {
+    HR_HIP(hipMemsetAsync(g->res_err, 0, sizeof(unsigned), g->stream));
+    HR_HIP(hipStreamSynchronize(g->stream));
+    return fail(HR_EDEVICE, "resident kernel: an exchange wait timed out");
+  }
+  return HR_OK;
+}
+
+bool use_resident(const hr_grid* g) {
+  int variant = 0, chunk = 0;
+  resolve_variant(g, variant, chunk);
+  return variant == 3;
 }
 
 template <typename T>
 hr_status launch_steps(hr_grid* g, const Fields<T>& F, T eta, T dt, long nsteps,
                        bool corr = false) {
+  if constexpr (std::is_same<T, double>::value) {
+    if (!corr && use_resident(g)) {
+      // whole RK4 steps in cooperative launches of at most 1000 steps
+      for (long n = 0; n < nsteps; n += 1000) {
+        const int k = (int)std::min<long>(1000, nsteps - n);
+        HR_HIP(launch_resident(g->fd_order, resident_args(g, eta, dt, k), g->stream));
+      }
+      return HR_OK;
+    }
+  }
   const StageArgs<T> s1 = stage_args<T>(g, F, 1, eta, dt, corr);
   const StageArgs<T> s2 = stage_args<T>(g, F, 2, eta, dt, corr);
   const StageArgs<T> s3 = stage_args<T>(g, F, 3, eta, dt, corr);
@@ -297,7 +365,8 @@ hr_status run_interval(hr_grid* g, int kind, int K, double eta, double dt, doubl
   int variant = 0, chunk = 0;
   resolve_variant(g, variant, chunk);
   const int streaming = g->streaming > 0 ? 1 : 0;
-  if (g->graph != 0) {
+  const bool resident = kind == 0 && variant == 3;
+  if (g->graph != 0 && !resident) {
     const bool same = g->gexec && g->g_kind == kind && g->g_K == K && g->g_eta == eta &&
                       g->g_dt == dt && g->g_kappa == g->kappa_loaded && g->g_variant == variant &&
                       g->g_chunk == chunk && g->g_streaming == streaming;
@@ -339,6 +408,7 @@ hr_status run_interval(hr_grid* g, int kind, int K, double eta, double dt, doubl
                         g->stream));
   HR_HIP(hipStreamSynchronize(g->stream));
   *res = g->host_res[0];
+  if (resident) return check_resident(g);
   return HR_OK;
 }
 
@@ -359,6 +429,10 @@ hr_status run_phase(hr_grid* g, const Fields<T>& F, bool fp32, double eta, doubl
       // a shorter tail is run without a check
       hr_status st = launch_steps<T>(g, F, (T)eta, (T)dt, chunk);
       if (st != HR_OK) return st;
+      if (!fp32 && use_resident(g)) {
+        st = check_resident(g);
+        if (st != HR_OK) return st;
+      }
       s += chunk;
       break;
     }
@@ -510,6 +584,10 @@ hr_status hr_grid_create(hr_coords coords, int N0, int N1, int N2, int fd_order,
   g->d.sph = coords == HR_SPHERICAL ? 1 : 0;
   g->G = align_up((size_t)next, 64);
   g->nblk_res = residual_blocks(g->d);
+  if (fd_order >= 8 && !resident_plan(g->d, g->res_plan, g->res_nbx, g->res_nby)) {
+    g->res_plan.clear();
+    g->res_nbx = g->res_nby = 0;
+  }
   std::string err;
   if (!build_tables(coords, g->d, prm, g->tab, err)) {
     delete g;
@@ -585,6 +663,12 @@ hr_status hr_grid_bind(hr_grid* g, void* dev_ptr, size_t bytes, void* hip_stream
   float* z32[] = {g->f32.un, g->f32.vn, g->f32.ua, g->f32.va, g->f32.ub,
                   g->f32.vb, g->f32.au, g->f32.av, g->f32.psi, g->f32.ssrc};
   for (float* p : z32) HR_HIP(launch_fill(p, 0.0f, G, g->stream));
+  if (g->res_nbx > 0) {
+    HR_HIP(hipMemcpyAsync(g->res_waits, g->res_plan.data(), g->res_plan.size() * sizeof(int),
+                          hipMemcpyHostToDevice, g->stream));
+    HR_HIP(hipMemsetAsync(g->res_err, 0, sizeof(unsigned), g->stream));
+    g->res_capacity = resident_capacity(g->fd_order, g->d);
+  }
   g->kappa_loaded = -1.0;
   hr_status st = load_kappa(g, 1.0);
   if (st != HR_OK) return st;
@@ -737,6 +821,20 @@ hr_status hr_time_stage_kernels(hr_grid* g, double eta, double c, double dt, lon
   HR_HIP(hipEventCreate(&e1));
   double sum[4] = {0, 0, 0, 0};
   const int G = (int)g->G;
+  if (prec == HR_FP64 && use_resident(g)) {
+    // one launch runs every stage: its duration is shared evenly
+    const int nrun = (int)std::min<long>(n_steps, 100000);
+    HR_HIP(launch_resident(g->fd_order, resident_args(g, eta, dt, nrun), g->stream, e0, e1));
+    HR_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HR_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    st = check_resident(g);
+    if (st != HR_OK) return st;
+    for (int s = 0; s < 5; ++s) avg_us[s] = 1e3 * ms / (4.0 * nrun);
+    return HR_OK;
+  }
   if (prec == HR_FP32) {
     HR_HIP(launch_to_fp32(g->f64.un, g->f32.un, G, g->stream));
     HR_HIP(launch_to_fp32(g->f64.vn, g->f32.vn, G, g->stream));
@@ -773,9 +871,12 @@ hr_status hr_time_stage_kernels(hr_grid* g, double eta, double c, double dt, lon
 
 hr_status hr_set_kernel_config(hr_grid* g, const hr_kernel_config* cfg) {
   if (!g || !cfg) return fail(HR_EINVAL, "null argument");
-  if (cfg->variant < 0 || cfg->variant > 2 || cfg->streaming < -1 || cfg->streaming > 1 ||
+  if (cfg->variant < 0 || cfg->variant > 3 || cfg->streaming < -1 || cfg->streaming > 1 ||
       cfg->chunk < 0 || cfg->graph < -1 || cfg->graph > 1)
     return fail(HR_EINVAL, "invalid kernel configuration");
+  if (cfg->variant == 3 && !resident_ok(g))
+    return fail(HR_EINVAL, "resident variant needs a bound grid of whole 8x8 (x0, x1) patches, "
+                           "N2 <= 32, order 8 or 10, and one compute unit per patch");
   g->variant = cfg->variant;
   g->streaming = cfg->streaming;
   g->chunk = cfg->chunk;
@@ -820,6 +921,7 @@ hr_status hr_autotune(hr_grid* g, hr_precision prec, int n_steps, hr_kernel_conf
   std::vector<hr_kernel_config> cand;
   cand.push_back(hr_kernel_config{1, 0, 0, g->graph});
   for (int c = 1; c <= g->d.N2; c *= 2) cand.push_back(hr_kernel_config{2, 0, c, g->graph});
+  if (prec == HR_FP64 && resident_ok(g)) cand.push_back(hr_kernel_config{3, 0, 0, g->graph});
   hipEvent_t e0, e1;
   HR_HIP(hipEventCreate(&e0));
   HR_HIP(hipEventCreate(&e1));
@@ -832,6 +934,35 @@ hr_status hr_autotune(hr_grid* g, hr_precision prec, int n_steps, hr_kernel_conf
     g->variant = k.variant;
     g->streaming = k.streaming;
     g->chunk = k.chunk;
+    if (k.variant == 3) {
+      // whole steps change the state: run them on a copy kept in the accumulator
+      const size_t bytes = g->G * sizeof(double);
+      hipError_t e = hipMemcpyAsync(g->f64.au, g->f64.un, bytes, hipMemcpyDeviceToDevice, g->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(g->f64.av, g->f64.vn, bytes, hipMemcpyDeviceToDevice, g->stream);
+      if (e == hipSuccess) e = launch_resident(g->fd_order, resident_args(g, 1.0, dt, 1), g->stream);
+      if (e == hipSuccess)
+        e = launch_resident(g->fd_order, resident_args(g, 1.0, dt, n_steps), g->stream, e0, e1);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(g->f64.un, g->f64.au, bytes, hipMemcpyDeviceToDevice, g->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(g->f64.vn, g->f64.av, bytes, hipMemcpyDeviceToDevice, g->stream);
+      if (e != hipSuccess) {
+        rs = hip_fail(e, "autotune timing");
+        break;
+      }
+      rs = check_resident(g);
+      if (rs != HR_OK) break;
+      const double us = 1e3 * ms / (4.0 * n_steps);
+      if (us < best_t) {
+        best_t = us;
+        bc = k;
+      }
+      continue;
+    }
     double tot = 0.0;
     for (int n = 0; n <= n_steps && rs == HR_OK; ++n)
       for (int s = 1; s <= 3; ++s) {

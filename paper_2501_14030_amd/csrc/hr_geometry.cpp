@@ -18,7 +18,9 @@
 // the local Courant number is the same everywhere (end of the "Basic
 // equations" section: wave speed proportional to the local grid spacing).
 
+#include <algorithm>
 #include <cmath>
+#include <set>
 
 #include "hr_internal.h"
 
@@ -158,6 +160,59 @@ bool build_tables(hr_coords coords, const Dims& d, const hr_grid_params& p,
       err = "non-finite Laplacian coefficient (check coordinate parameters)";
       return false;
     }
+  return true;
+}
+
+// Partition of a grid into the resident kernel's 8 x 8 (x0, x1) patches and
+// the exchange partners of each patch: the owners of the stored points its
+// rim taps read (inner-boundary images resolved as in the stage kernels), and
+// the patches whose rims read it, so that every reader of a patch's exchange
+// slot is one of its partners (the double-buffered exchange relies on it).
+bool resident_plan(const Dims& d, std::vector<int>& waits, int& nbx, int& nby) {
+  constexpr int RB = kResPatch;
+  nbx = nby = 0;
+  if (d.N0 % RB || d.N1 % RB || d.NG > RB || d.N2 > 32 || d.N2 < 2) return false;
+  const int bx_n = d.N0 / RB, by_n = d.N1 / RB, nb = bx_n * by_n;
+  if (nb > kResMaxBlocks) return false;
+  const int NG = d.NG;
+  // owner patch of a stored (s0, s1); outer points belong to the last x0 patch
+  auto owner = [&](int s0, int s1) { return std::min(s0 / RB, bx_n - 1) + bx_n * (s1 / RB); };
+  std::vector<std::set<int>> rel(nb);
+  for (int b = 0; b < nb; ++b) {
+    const int x0b = (b % bx_n) * RB, x1b = (b / bx_n) * RB;
+    auto tap = [&](int j0, int j1) {
+      int s0 = j0, s1 = j1;
+      if (j0 < 0) {
+        s0 = -1 - j0;
+        s1 = d.sph ? d.N1 - 1 - j1 : j1;
+      } else if (j1 < 0) {
+        s1 = -1 - j1;
+      } else if (j1 >= d.N1) {
+        s1 = 2 * d.N1 - 1 - j1;
+      }
+      const int o = owner(s0, s1);
+      if (o != b) {
+        rel[b].insert(o);
+        rel[o].insert(b);
+      }
+    };
+    for (int r = 0; r < RB; ++r)
+      for (int k = 1; k <= NG; ++k) {
+        tap(x0b - k, x1b + r);
+        tap(x0b + RB - 1 + k, x1b + r);
+        tap(x0b + r, x1b - k);
+        tap(x0b + r, x1b + RB - 1 + k);
+      }
+  }
+  waits.assign((size_t)nb * (kResMaxWait + 1), 0);
+  for (int b = 0; b < nb; ++b) {
+    if ((int)rel[b].size() > kResMaxWait) return false;
+    waits[(size_t)b * (kResMaxWait + 1)] = (int)rel[b].size();
+    int k = 1;
+    for (int o : rel[b]) waits[(size_t)b * (kResMaxWait + 1) + k++] = o;
+  }
+  nbx = bx_n;
+  nby = by_n;
   return true;
 }
 

@@ -165,6 +165,55 @@ hipError_t launch_rebase(double* ub, double* vb, const float* eu, const float* e
 hipError_t launch_fill(double* dst, double value, int n, hipStream_t s);
 hipError_t launch_fill(float* dst, float value, int n, hipStream_t s);
 
+// Resident RK4 kernel (hr_resident.hip): one cooperative launch runs nsteps
+// whole RK4 steps of a small grid with the state held on chip. Every block owns
+// an 8 x 8 patch of (x0, x1) columns over all phi planes (the last x0 patch also
+// the outer points), keeps y_n, the stage input and the accumulator of its
+// points in registers, and exchanges the stage input u with the blocks whose
+// points its stencils reach through a double-buffered global array, ordered by
+// per-block stage counters.
+constexpr int kResPatch = 8;          // patch width along x0 and x1
+constexpr int kResMaxWait = 16;       // blocks one block exchanges with, at most
+constexpr int kResFlagStride = 32;    // one 128-byte line per block counter
+constexpr int kResMaxBlocks = 1024;
+
+struct ResidentArgs {
+  Dims d;
+  double* u;            // state y_n (extended layout), read at start, written at the end
+  double* v;
+  const double* psi;
+  const double* ssrc;
+  const double* fac;    // 6 planes of N0*N1
+  const double* ofac;   // 3 planes of NG*N1
+  double* x0;           // exchange buffers (extended layout), by stage parity
+  double* x1;
+  unsigned* flags;      // per-block stage counters, zero at launch
+  const int* waits;     // per block: count, then up to kResMaxWait block ids
+  unsigned* err;        // bit 0: a wait timed out
+  double eta;
+  double cy[4];         // Y_{s+1} = y_n + cy[s] k (stage 4: y_{n+1} = acc + ca[3] k)
+  double ca[4];         // accumulator weights
+  int nbx, nby;         // patches along x0 and x1
+  int nsteps;
+  unsigned spin_limit;  // polls of one counter before a wait gives up
+};
+
+// Exchange partners of every patch (count, then ids; kResMaxWait + 1 ints per
+// block) for dims d: the owners of every stencil tap outside the patch,
+// including inner-boundary images, and every patch whose taps reach this one.
+// False if the grid is not made of whole 8 x 8 patches or has too many blocks.
+bool resident_plan(const Dims& d, std::vector<int>& waits, int& nbx, int& nby);
+// Dynamic LDS bytes of the resident kernel for these dims (at least enough to
+// keep one block per compute unit).
+size_t resident_lds_bytes(const Dims& d);
+// Largest number of co-resident blocks of the resident kernel on the current
+// device for these dims (0 if the order or N2 is not supported).
+int resident_capacity(int order, const Dims& d);
+// Resets the counters and launches the resident kernel cooperatively; events
+// (optional) bracket the launch.
+hipError_t launch_resident(int order, const ResidentArgs& a, hipStream_t s,
+                           hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+
 // Host geometry (hr_geometry.cpp).
 struct HostTables {
   double ds_g;                 // smallest proper cell width over the interior
@@ -216,7 +265,14 @@ struct hr_grid {
   hr::Punctures pz{};           // punctures of the last hr_set_punctures
   double kappa_loaded = -1.0;   // wave-speed scale currently in fac/ofac
 
-  int variant = 0;              // kernel variant: 0 auto, 1 plane tiles, 2 phi columns
+  int variant = 0;              // kernel variant: 0 auto, 1 plane tiles, 2 phi columns,
+                                // 3 resident (FP64 steps in one cooperative launch)
+  int res_nbx = 0, res_nby = 0; // resident patches (0: grid not eligible)
+  int res_capacity = 0;         // co-resident blocks the device allows for it
+  std::vector<int> res_plan;    // exchange partners (host copy, uploaded at bind)
+  unsigned* res_flags = nullptr;
+  int* res_waits = nullptr;
+  unsigned* res_err = nullptr;
   int streaming = -1;           // non-temporal field access: -1 auto (by size), 0, 1
   int chunk = 0;                // phi planes per block of the column variant (0 auto)
   int graph = -1;               // graph capture of check intervals: -1 auto (on), 0, 1
@@ -233,7 +289,11 @@ struct hr_grid {
 namespace hr {
 
 // Kernel variant and phi chunk of a grid (explicit configuration, else by size).
+// Variant 3 (resident) applies to FP64 steps only; stage launches of the
+// single-precision forms use plane tiles in its place.
 void resolve_variant(const hr_grid* g, int& variant, int& chunk);
+// The grid can run the resident kernel on its device.
+bool resident_ok(const hr_grid* g);
 
 // Uploads the wave-speed planes (c, c^2) for scale kappa if not loaded (synchronous).
 hr_status load_kappa(hr_grid* g, double kappa);
@@ -255,6 +315,7 @@ StageArgs<T> stage_args(const hr_grid* g, const Fields<T>& F, int stage, T eta, 
   // non-temporal access measured no faster at any size: off unless asked for
   a.streaming = g->streaming > 0 ? 1 : 0;
   resolve_variant(g, a.variant, a.chunk);
+  if (a.variant == 3) a.variant = 1;
   a.un = F.un;
   a.vn = F.vn;
   a.au = F.au;

@@ -1,0 +1,403 @@
+// Resident RK4 kernel for small grids (gfx950).
+//
+// At the paper's grid sizes (128 x 128 x 16) one RK4 stage moves ~22 MB and a
+// stage kernel is bound by launch and memory latency, not bandwidth. Here one
+// cooperative launch runs many whole RK4 steps (Algorithm 1, inner loop; RHS
+// of Eq. 5 with the radiation condition at the outer points) and the state
+// never leaves the chip:
+//   * block b owns an 8 x 8 patch of (x0, x1) columns through all N2 phi planes
+//     (the last x0 patch also the NG outer points of its rows); its 256
+//     threads are 64 (x0, x1) positions x 4 plane groups;
+//   * y_n, the stage input v, the accumulator, psi_s and S_src of the block's
+//     points sit in registers; the stage input u of the whole patch plus its
+//     NG-deep rim (all planes) sits in LDS, so every stencil tap, phi included,
+//     is an LDS read;
+//   * after each stage the block writes its new stage input u to a global
+//     exchange array (one per stage parity) and raises its stage counter; the
+//     next stage waits only for the counters of its exchange partners (the
+//     owners of its rim taps and the blocks whose rims reach it), then loads
+//     its rim from the exchange array.
+// Exchange data and counters are written and read with agent-scope atomics,
+// which are coherent across the XCDs' L2 caches without cache-wide
+// write-back or invalidate; a full s_waitcnt before the block barrier orders
+// the data stores before the counter store. Every wait is bounded: a poll
+// count past spin_limit sets err, and the blocks leave their loops.
+//
+// The arithmetic per point is that of the stage kernels (same stencil
+// summation order and stage combine), so results match them to rounding.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "hr_internal.h"
+#include "hr_stencil.h"
+
+namespace hr {
+namespace {
+
+constexpr int RB = kResPatch;
+constexpr int RT = 256;   // threads per block
+
+__device__ __forceinline__ void xstore(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double xload(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void k_zero_u32(unsigned* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// NPT: phi planes per thread (plane group g holds planes g, g + 4, ...).
+template <int NG, int NPT>
+__global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
+  constexpr int RW = RB + 2 * NG;                // LDS tile row (x0) length
+  constexpr int TP = RW * RW;                    // tile cells per plane (corners unused)
+  constexpr int VW = RB + NG;                    // v tile row: patch columns + outer
+  constexpr int NRIM = 4 * NG * RB;              // rim cells per plane
+  constexpr int NR = (NRIM * 4 * NPT + RT - 1) / RT;
+  constexpr int NQ = (NG * RB * 4 * NPT + RT - 1) / RT;
+  constexpr Weights<NG> Wt{};
+  extern __shared__ double smem[];
+  __shared__ int bad;
+
+  const Dims& d = a.d;
+  const int N2 = d.N2;
+  double* ut = smem;                 // [N2][RW][RW]
+  double* vt = smem + N2 * TP;       // [N2][RB][VW]
+  const int t = threadIdx.x, pos = t & 63, x0l = pos & 7, x1l = pos >> 3, grp = t >> 6;
+  const int b = blockIdx.x, bx = b % a.nbx, by = b / a.nbx;
+  const int x0b = bx * RB, x1b = by * RB;
+  const int i0 = x0b + x0l, i1 = x1b + x1l;
+  const bool last = bx == a.nbx - 1;
+  const unsigned P0 = (unsigned)d.P0, N1 = (unsigned)d.N1;
+  const unsigned n2d = (unsigned)d.N0 * N1;
+  const unsigned o2d = (unsigned)NG * N1;
+
+  // --- own points --------------------------------------------------------
+  double f[6];
+  {
+    const unsigned k2 = (unsigned)i0 + (unsigned)d.N0 * (unsigned)i1;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) f[q] = a.fac[q * n2d + k2];
+  }
+  double yu[NPT], yv[NPT], su[NPT], sv[NPT], au[NPT], av[NPT], ps[NPT], ss[NPT];
+  unsigned gidx[NPT];
+  int lidx[NPT], vidx[NPT];
+  int php[NPT][NG], phm[NPT][NG];   // LDS offsets of the phi taps
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int i2 = grp + 4 * j;
+    const bool ok = i2 < N2;
+    const int i2c = ok ? i2 : 0;
+    gidx[j] = P0 * ((unsigned)i1 + N1 * (unsigned)i2c) + (unsigned)i0;
+    lidx[j] = i2c * TP + (x1l + NG) * RW + (x0l + NG);
+    vidx[j] = (i2c * RB + x1l) * VW + x0l;
+    int jp = i2c, jm = i2c;
+#pragma unroll
+    for (int k = 1; k <= NG; ++k) {
+      jp = (jp + 1 == N2) ? 0 : jp + 1;
+      jm = (jm == 0) ? N2 - 1 : jm - 1;
+      php[j][k - 1] = (jp - i2c) * TP;
+      phm[j][k - 1] = (jm - i2c) * TP;
+    }
+    yu[j] = ok ? a.u[gidx[j]] : 0.0;
+    yv[j] = ok ? a.v[gidx[j]] : 0.0;
+    ps[j] = ok ? a.psi[gidx[j]] : 0.0;
+    ss[j] = ok ? a.ssrc[gidx[j]] : 0.0;
+    su[j] = yu[j];
+    sv[j] = yv[j];
+    au[j] = 0.0;
+    av[j] = 0.0;
+  }
+
+  // --- outer points (last x0 patch only) ---------------------------------
+  double oyu[NQ], oyv[NQ], osu[NQ], osv[NQ], oau[NQ], oav[NQ], oc[NQ], ori[NQ], oqd[NQ];
+  unsigned oidx[NQ];
+  int otl[NQ], ovl[NQ];
+  bool oval[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int o = t + RT * q;
+    const int col = o % NG, rest = o / NG;
+    const int r = rest % RB, pl = rest / RB;
+    oval[q] = last && pl < N2;
+    const int plc = oval[q] ? pl : 0;
+    oidx[q] = P0 * ((unsigned)(x1b + r) + N1 * (unsigned)plc) + (unsigned)(d.N0 + col);
+    otl[q] = plc * TP + (NG + r) * RW + (NG + RB + col);
+    ovl[q] = (plc * RB + r) * VW + RB + col;
+    const unsigned ko = (unsigned)col + (unsigned)NG * (unsigned)(x1b + r);
+    oc[q] = oval[q] ? a.ofac[ko] : 0.0;
+    ori[q] = oval[q] ? a.ofac[o2d + ko] : 0.0;
+    oqd[q] = oval[q] ? a.ofac[2 * o2d + ko] : 0.0;
+    oyu[q] = oval[q] ? a.u[oidx[q]] : 0.0;
+    oyv[q] = oval[q] ? a.v[oidx[q]] : 0.0;
+    osu[q] = oyu[q];
+    osv[q] = oyv[q];
+    oau[q] = 0.0;
+    oav[q] = 0.0;
+  }
+
+  // --- rim cells: LDS slot and stored source (images resolved) ------------
+  unsigned rg[NR];
+  int rl[NR];
+  bool rval[NR];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    const int c = t + RT * q;
+    const int pl = c / NRIM, w = c - pl * NRIM;
+    rval[q] = pl < N2;
+    const int plc = rval[q] ? pl : 0;
+    const int side = w / (NG * RB), w2 = w - side * (NG * RB);
+    int l0, l1;
+    if (side == 0) { l0 = w2 % NG; l1 = NG + w2 / NG; }
+    else if (side == 1) { l0 = NG + RB + w2 % NG; l1 = NG + w2 / NG; }
+    else if (side == 2) { l0 = NG + w2 % RB; l1 = w2 / RB; }
+    else { l0 = NG + w2 % RB; l1 = NG + RB + w2 / RB; }
+    const int j0 = x0b + l0 - NG, j1 = x1b + l1 - NG;
+    int s0 = j0, s1 = j1;
+    bool flip = false;
+    if (j0 < 0) {            // reflection through xx0 = 0
+      s0 = -1 - j0;
+      s1 = d.sph ? d.N1 - 1 - j1 : j1;
+      flip = true;
+    } else if (j1 < 0) {     // reflection through theta = 0
+      s1 = -1 - j1;
+      flip = true;
+    } else if (j1 >= d.N1) { // reflection through theta = pi
+      s1 = 2 * d.N1 - 1 - j1;
+      flip = true;
+    }
+    const int sp = flip ? half_turn(plc, N2) : plc;
+    rg[q] = P0 * ((unsigned)s1 + N1 * (unsigned)sp) + (unsigned)s0;
+    rl[q] = plc * TP + l1 * RW + l0;
+  }
+
+  // --- exchange partners --------------------------------------------------
+  const int nw = a.waits[b * (kResMaxWait + 1)];
+  const int wt = t < nw ? a.waits[b * (kResMaxWait + 1) + 1 + t] : 0;
+
+  if (t == 0) bad = 0;
+  __syncthreads();
+
+  const int nst = 4 * a.nsteps;
+  for (int e = 1; e <= nst; ++e) {
+    const int stage = (e - 1) & 3;
+    if (e > 1) {
+      if (t < nw) {
+        const unsigned* fl = a.flags + wt * kResFlagStride;
+        unsigned spin = 0;
+        while (__hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+               (unsigned)(e - 1)) {
+          if (++spin > a.spin_limit) {
+            atomicOr(a.err, 1u);
+            bad = 1;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      __syncthreads();
+      if (bad) break;
+    }
+    // stage input u: rim from the exchange array (the state itself at the first
+    // stage), own points from registers; v of the patch and outer points
+    if (e == 1) {
+#pragma unroll
+      for (int q = 0; q < NR; ++q)
+        if (rval[q]) ut[rl[q]] = a.u[rg[q]];
+    } else {
+      const double* src = ((e - 1) & 1) ? a.x1 : a.x0;
+#pragma unroll
+      for (int q = 0; q < NR; ++q)
+        if (rval[q]) ut[rl[q]] = xload(src + rg[q]);
+    }
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+      if (grp + 4 * j < N2) {
+        ut[lidx[j]] = su[j];
+        vt[vidx[j]] = sv[j];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      if (oval[q]) vt[ovl[q]] = osv[q];
+    __syncthreads();
+
+    const double cy = a.cy[stage], ca = a.ca[stage];
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+      if (grp + 4 * j >= N2) continue;
+      const double* r = ut + lidx[j];
+      const double uc = r[0];
+      double d0 = 0, d1 = 0, e0 = 0, e1 = 0, e2 = 0;
+#pragma unroll
+      for (int k = 1; k <= NG; ++k) {
+        const double p0 = r[k], m0 = r[-k];
+        const double p1 = r[k * RW], m1 = r[-k * RW];
+        d0 += Wt.d1[k] * (p0 - m0);
+        d1 += Wt.d1[k] * (p1 - m1);
+        e0 += Wt.d2[k] * (p0 + m0);
+        e1 += Wt.d2[k] * (p1 + m1);
+        e2 += Wt.d2[k] * (r[php[j][k - 1]] + r[phm[j][k - 1]]);
+      }
+      const double w0 = Wt.d2[0];
+      const double dd0 = e0 + w0 * uc, dd1 = e1 + w0 * uc, dd2 = e2 + w0 * uc;
+      const double lap = f[0] * dd0 + f[1] * dd1 + f[2] * dd2 + f[3] * d0 + f[4] * d1;
+      const double p = ps[j] + uc;
+      const double p2 = p * p;
+      const double p4 = p2 * p2;
+      const double ku = sv[j] - a.eta * uc;
+      const double kv = f[5] * (lap + ss[j] / (p4 * p2 * p));
+      if (stage == 0) {
+        au[j] = uc + ca * ku;
+        av[j] = sv[j] + ca * kv;
+        su[j] = uc + cy * ku;
+        sv[j] = sv[j] + cy * kv;
+      } else if (stage == 3) {
+        su[j] = au[j] + ca * ku;
+        sv[j] = av[j] + ca * kv;
+        yu[j] = su[j];
+        yv[j] = sv[j];
+      } else {
+        su[j] = yu[j] + cy * ku;
+        sv[j] = yv[j] + cy * kv;
+        au[j] = au[j] + ca * ku;
+        av[j] = av[j] + ca * kv;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      if (!oval[q]) continue;
+      // radiation condition with a one-sided xx0 derivative
+      const double u0 = ut[otl[q]], u1 = ut[otl[q] - 1], u2 = ut[otl[q] - 2];
+      const double v0 = osv[q], v1 = vt[ovl[q] - 1], v2 = vt[ovl[q] - 2];
+      const double kuo = -oc[q] * (u0 * ori[q] + (3.0 * u0 - 4.0 * u1 + u2) * oqd[q]);
+      const double kvo = -oc[q] * (v0 * ori[q] + (3.0 * v0 - 4.0 * v1 + v2) * oqd[q]);
+      if (stage == 0) {
+        oau[q] = u0 + ca * kuo;
+        oav[q] = v0 + ca * kvo;
+        osu[q] = u0 + cy * kuo;
+        osv[q] = v0 + cy * kvo;
+      } else if (stage == 3) {
+        osu[q] = oau[q] + ca * kuo;
+        osv[q] = oav[q] + ca * kvo;
+        oyu[q] = osu[q];
+        oyv[q] = osv[q];
+      } else {
+        osu[q] = oyu[q] + cy * kuo;
+        osv[q] = oyv[q] + cy * kvo;
+        oau[q] = oau[q] + ca * kuo;
+        oav[q] = oav[q] + ca * kvo;
+      }
+    }
+
+    if (e < nst) {
+      // publish the next stage input u, then raise this block's counter
+      double* dst = (e & 1) ? a.x1 : a.x0;
+#pragma unroll
+      for (int j = 0; j < NPT; ++j)
+        if (grp + 4 * j < N2) xstore(dst + gidx[j], su[j]);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        if (oval[q]) xstore(dst + oidx[q], osu[q]);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (t == 0)
+        __hip_atomic_store(a.flags + b * kResFlagStride, (unsigned)e, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+#pragma unroll
+      for (int j = 0; j < NPT; ++j)
+        if (grp + 4 * j < N2) {
+          a.u[gidx[j]] = yu[j];
+          a.v[gidx[j]] = yv[j];
+        }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        if (oval[q]) {
+          a.u[oidx[q]] = oyu[q];
+          a.v[oidx[q]] = oyv[q];
+        }
+    }
+  }
+}
+
+// NPT choices: planes per thread rounded up to a power of two (N2 <= 32).
+int npt_of(int N2) {
+  const int n = (N2 + 3) / 4;
+  return n <= 1 ? 1 : n <= 2 ? 2 : n <= 4 ? 4 : n <= 8 ? 8 : 0;
+}
+
+template <int NG>
+const void* kernel_for_npt(int npt) {
+  switch (npt) {
+    case 1: return (const void*)k_resident<NG, 1>;
+    case 2: return (const void*)k_resident<NG, 2>;
+    case 4: return (const void*)k_resident<NG, 4>;
+    case 8: return (const void*)k_resident<NG, 8>;
+    default: return nullptr;
+  }
+}
+
+const void* resident_kernel(int order, int N2) {
+  const int npt = npt_of(N2);
+  switch (order) {
+    case 8: return kernel_for_npt<4>(npt);
+    case 10: return kernel_for_npt<5>(npt);
+    default: return nullptr;
+  }
+}
+
+}  // namespace
+
+size_t resident_lds_bytes(const Dims& d) {
+  const int RW = RB + 2 * d.NG, VW = RB + d.NG;
+  const size_t need = (size_t)d.N2 * (RW * RW + RB * VW) * sizeof(double);
+  // more than half of the 160 KiB of LDS per compute unit: one block per CU
+  return std::max<size_t>(need, 82 * 1024);
+}
+
+int resident_capacity(int order, const Dims& d) {
+  const void* k = resident_kernel(order, d.N2);
+  if (!k) return 0;
+  const size_t lds = resident_lds_bytes(d);
+  if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return 0;
+  int per = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, RT, lds) != hipSuccess) return 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return per * cus;
+}
+
+hipError_t launch_resident(int order, const ResidentArgs& a, hipStream_t s, hipEvent_t t0,
+                           hipEvent_t t1) {
+  const void* k = resident_kernel(order, a.d.N2);
+  if (!k) return hipErrorInvalidValue;
+  const int nb = a.nbx * a.nby;
+  if (nb <= 0 || nb > kResMaxBlocks || a.nsteps <= 0) return hipErrorInvalidValue;
+  const int nflags = nb * kResFlagStride;
+  k_zero_u32<<<(nflags + 255) / 256, 256, 0, s>>>(a.flags, nflags);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t lds = resident_lds_bytes(a.d);
+  e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  ResidentArgs arg = a;
+  void* args[] = {&arg};
+  if (t0) {
+    e = hipEventRecord(t0, s);
+    if (e != hipSuccess) return e;
+  }
+  e = hipLaunchCooperativeKernel(k, dim3(nb), dim3(RT), args, (unsigned)lds, s);
+  if (e != hipSuccess) return e;
+  if (t1) e = hipEventRecord(t1, s);
+  return e;
+}
+
+}  // namespace hr

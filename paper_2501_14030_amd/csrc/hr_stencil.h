@@ -1,0 +1,55 @@
+// Device helpers shared by the stage kernels: centred finite-difference
+// weights and the phi + pi plane map of the inner-boundary images.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace hr {
+
+// Centred finite-difference weights of order 2*NG, from the closed forms for
+// equispaced centred stencils (m = NG):
+//   first derivative   w_k = (-1)^(k+1) (m!)^2 / ( k (m-k)! (m+k)! )
+//   second derivative  w_k = 2 (-1)^(k+1) (m!)^2 / ( k^2 (m-k)! (m+k)! ),
+//                      w_0 = -2 sum_{k=1..m} 1/k^2
+// evaluated at compile time as one rounding of an exact integer ratio.
+constexpr double fact(int n) { return n <= 1 ? 1.0 : n * fact(n - 1); }
+constexpr long long gcdll(long long a, long long b) { return b == 0 ? a : gcdll(b, a % b); }
+constexpr long long lcm_upto(int m) {
+  long long l = 1;
+  for (int k = 2; k <= m; ++k) l = l / gcdll(l, k) * k;
+  return l;
+}
+constexpr double w1(int m, int k) {
+  return ((k % 2) ? 1.0 : -1.0) * fact(m) * fact(m) / (k * fact(m - k) * fact(m + k));
+}
+constexpr double w2(int m, int k) {
+  if (k == 0) {
+    const long long L = lcm_upto(m), D = L * L;
+    long long num = 0;
+    for (int j = 1; j <= m; ++j) num += D / ((long long)j * j);
+    return -2.0 * (double)num / (double)D;
+  }
+  return ((k % 2) ? 2.0 : -2.0) * fact(m) * fact(m) / ((double)k * k * fact(m - k) * fact(m + k));
+}
+static_assert(w2(4, 0) == -205.0 / 72.0, "8th-order centre weight");
+static_assert(w2(5, 0) == -5269.0 / 1800.0, "10th-order centre weight");
+
+template <int NG>
+struct Weights {
+  double d1[NG + 1];
+  double d2[NG + 1];
+  constexpr Weights() : d1(), d2() {
+    for (int k = 0; k <= NG; ++k) {
+      d1[k] = k == 0 ? 0.0 : w1(NG, k);
+      d2[k] = w2(NG, k);
+    }
+  }
+};
+
+// Plane index of phi + pi (N2 even).
+__device__ __forceinline__ int half_turn(int i2, int N2) {
+  const int h = i2 + (N2 >> 1);
+  return h >= N2 ? h - N2 : h;
+}
+
+}  // namespace hr

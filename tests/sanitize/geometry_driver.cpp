@@ -1,11 +1,15 @@
-// Host-only driver for the library's geometry tables, built with
-// AddressSanitizer and UndefinedBehaviorSanitizer by tests/test_sanitize_host.py.
-// Builds the tables for many shapes, orders and coordinate parameters and
-// checks basic invariants; any out-of-bounds access or undefined behaviour
-// aborts the run.
+// Host-only driver for the library's geometry tables and the resident
+// kernel's patch partition, built with AddressSanitizer and
+// UndefinedBehaviorSanitizer by tests/test_sanitize_host.py. Builds the tables
+// for many shapes, orders and coordinate parameters and checks basic
+// invariants; checks the partition against the rim cells the resident kernel
+// enumerates (walked here independently, in the kernel's order); any
+// out-of-bounds access or undefined behaviour aborts the run.
 #include <cmath>
 #include <cstdio>
+#include <set>
 #include <string>
+#include <vector>
 
 #include "../../paper_2501_14030_amd/csrc/hr_internal.h"
 
@@ -13,7 +17,83 @@ namespace hr {
 void set_error(const std::string&) {}
 }
 
+// Owner patch of every rim cell of patch b, as the kernel walks them: per
+// plane, 4 sides of NG x 8 cells (x0 low, x0 high, x1 low, x1 high).
+static std::set<int> rim_owners(const hr::Dims& d, int nbx, int b) {
+  const int RB = hr::kResPatch, NG = d.NG;
+  const int x0b = (b % nbx) * RB, x1b = (b / nbx) * RB;
+  std::set<int> out;
+  for (int w = 0; w < 4 * NG * RB; ++w) {
+    const int side = w / (NG * RB), w2 = w % (NG * RB);
+    int l0, l1;
+    if (side == 0) { l0 = w2 % NG; l1 = NG + w2 / NG; }
+    else if (side == 1) { l0 = NG + RB + w2 % NG; l1 = NG + w2 / NG; }
+    else if (side == 2) { l0 = NG + w2 % RB; l1 = w2 / RB; }
+    else { l0 = NG + w2 % RB; l1 = NG + RB + w2 / RB; }
+    int s0 = x0b + l0 - NG, s1 = x1b + l1 - NG;
+    if (s0 < 0) {
+      s0 = -1 - s0;
+      if (d.sph) s1 = d.N1 - 1 - s1;
+    } else if (s1 < 0) {
+      s1 = -1 - s1;
+    } else if (s1 >= d.N1) {
+      s1 = 2 * d.N1 - 1 - s1;
+    }
+    if (s0 < 0 || s0 >= d.P0 || s1 < 0 || s1 >= d.N1) return {-1};
+    const int bx = s0 >= d.N0 ? nbx - 1 : s0 / RB;
+    out.insert(bx + nbx * (s1 / RB));
+  }
+  out.erase(b);
+  return out;
+}
+
+static int check_plans() {
+  int checked = 0;
+  const int shapes[][3] = {{8, 8, 2}, {16, 8, 2}, {64, 32, 8}, {64, 64, 8}, {128, 128, 16},
+                           {24, 40, 32}, {256, 256, 8}};
+  for (int sph = 0; sph < 2; ++sph)
+    for (const auto& sh : shapes)
+      for (int NG : {4, 5}) {
+        hr::Dims d{};
+        d.N0 = sh[0]; d.N1 = sh[1]; d.N2 = sh[2]; d.NG = NG; d.P0 = sh[0] + NG; d.sph = sph;
+        std::vector<int> w;
+        int nbx = 0, nby = 0;
+        if (!hr::resident_plan(d, w, nbx, nby)) return 10;
+        if (nbx != d.N0 / 8 || nby != d.N1 / 8) return 11;
+        const int W = hr::kResMaxWait + 1;
+        for (int b = 0; b < nbx * nby; ++b) {
+          const int n = w[(size_t)b * W];
+          std::set<int> part(w.begin() + (size_t)b * W + 1, w.begin() + (size_t)b * W + 1 + n);
+          if ((int)part.size() != n || part.count(b)) return 12;
+          for (int o : rim_owners(d, nbx, b))
+            if (o < 0 || !part.count(o)) return 13;       // a rim owner is a partner
+          for (int o : part) {                            // the relation is symmetric
+            const int m = w[(size_t)o * W];
+            bool back = false;
+            for (int k = 1; k <= m; ++k) back = back || w[(size_t)o * W + k] == b;
+            if (!back) return 14;
+          }
+        }
+        ++checked;
+      }
+  // shapes the partition refuses
+  const int bad[][4] = {{37, 19, 6, 5}, {32, 16, 34, 4}, {12, 8, 4, 4}, {16, 16, 4, 9}};
+  for (const auto& sh : bad) {
+    hr::Dims d{};
+    d.N0 = sh[0]; d.N1 = sh[1]; d.N2 = sh[2]; d.NG = sh[3]; d.P0 = sh[0] + sh[3];
+    std::vector<int> w;
+    int nbx = 1, nby = 1;
+    if (hr::resident_plan(d, w, nbx, nby) || nbx || nby) return 15;
+  }
+  std::printf("resident partitions checked: %d\n", checked);
+  return 0;
+}
+
 int main() {
+  if (int rc = check_plans()) {
+    std::printf("partition check failed: %d\n", rc);
+    return rc;
+  }
   int checked = 0;
   const int shapes[][3] = {{5, 5, 2}, {8, 4, 2}, {32, 16, 4}, {37, 19, 6}, {64, 64, 8}, {128, 64, 8}};
   const int orders[] = {2, 4, 6, 8, 10};

@@ -1,0 +1,110 @@
+"""Resident RK4 kernel (kernel variant 3): whole RK4 steps in one cooperative
+launch, the state of every 8 x 8 (x0, x1) patch held on chip and the stage
+input exchanged between patches through global memory.
+
+It evaluates the stage kernels' arithmetic in the same order, so its
+trajectories must agree with the plane-tile kernels to a few roundoff units
+and with the oracle to the parity tolerance. The cases cover the paper-scale
+grid (256 patches, one per compute unit), 8th and 10th order, Spherical
+coordinates (the xx0 reflection pairs patches across the theta range), a
+single patch, N2 = 2 (phi taps wrapping several times) and N2 = 32."""
+import numpy as np
+import pytest
+
+import paper_2501_14030_amd as hr
+from paper_2501_14030_amd import workloads
+
+from gpu_common import banner, gpu_grid, oracle_extended, oracle_grid, rel_maxdiff
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    (workloads.GridSpec(0, 128, 128, 16, 10, bscale=5.0), True),
+    (workloads.GridSpec(0, 64, 64, 8, 8, bscale=3.0), True),
+    (workloads.GridSpec(1, 64, 32, 8, 10, rmax=60.0), True),
+    (workloads.GridSpec(0, 16, 8, 2, 10, amax=100.0, sinhwaa=0.2, bscale=1.0), True),
+    (workloads.GridSpec(0, 8, 8, 6, 10, amax=100.0, sinhwaa=0.2, bscale=1.0), False),
+    (workloads.GridSpec(0, 24, 40, 32, 8, bscale=2.0), False),
+]
+
+
+def _punctures(spec):
+    D = 2 * spec.bscale if spec.coords == 0 else 10.0
+    return workloads.quasi_circular(1.7, D, [0.1, 0.2, 0.3], [0.0, -0.2, 0.1])
+
+
+def _run(spec, variant, n_steps, dt, eta=6.0, tol=0.0):
+    g = gpu_grid(spec)
+    g.set_kernel_config(variant=variant)
+    g.set_punctures(*_punctures(spec).as_tuple())
+    r = g.relax(eta, 1.0, dt, n_steps, tol, check_every=100)
+    return g, r
+
+
+@pytest.mark.parametrize("spec,with_oracle", CASES)
+def test_resident_matches_plane_kernels_and_oracle(spec, with_oracle):
+    banner(f"resident {spec.name()}")
+    og = oracle_grid(spec)
+    dt = og.suggest_dt(0.5)
+    # 250 steps: two checked intervals and an unchecked tail of 50
+    gr, rr = _run(spec, 3, 250, dt)
+    gp, rp = _run(spec, 1, 250, dt)
+    assert rr.status == hr.OK and rr.steps_taken == 250
+    du = rel_maxdiff(gr.get_u(extended=True), gp.get_u(extended=True))
+    dv = rel_maxdiff(gr.get_v(extended=True), gp.get_v(extended=True))
+    banner(f"resident vs plane: u {du:.2e}, v {dv:.2e}")
+    assert du <= 1e-13 and dv <= 1e-13
+    np.testing.assert_allclose(rr.history, rp.history, rtol=1e-12, atol=1e-16)
+    if with_oracle:
+        og.set_punctures(*_punctures(spec).as_tuple())
+        og.relax(6.0, 1.0, dt, 250, 0.0, 100)
+        ou, ov = og.state()
+        d_or = rel_maxdiff(gr.get_u(extended=True), oracle_extended(og, ou))
+        banner(f"resident vs oracle: {d_or:.2e}")
+        assert d_or <= 1e-12
+
+
+def test_resident_relaxes_paper_scale_to_tolerance():
+    w = workloads.paper_scale()
+    banner("resident paper-scale solve to 1e-10")
+    g = gpu_grid(w.grid)
+    g.set_kernel_config(variant=3)
+    g.set_punctures(*w.punctures.as_tuple())
+    r = g.relax(w.eta, 1.0, 0.0, 20000, 1e-10, check_every=100)
+    h = gpu_grid(w.grid)
+    h.set_kernel_config(variant=1)
+    h.set_punctures(*w.punctures.as_tuple())
+    rp = h.relax(w.eta, 1.0, 0.0, 20000, 1e-10, check_every=100)
+    banner(f"resident {r.steps_taken} steps, plane {rp.steps_taken} steps, "
+           f"residual {r.residual:.2e}")
+    assert r.status == hr.OK and r.steps_taken == rp.steps_taken
+    assert g.residual_l2() < 1e-10
+    assert rel_maxdiff(g.get_u(extended=True), h.get_u(extended=True)) <= 1e-12
+
+
+def test_resident_rejected_where_not_applicable():
+    for spec in (workloads.GridSpec(0, 37, 19, 6, 10, bscale=1.0),   # not whole patches
+                 workloads.GridSpec(0, 32, 16, 4, 6, bscale=1.0),    # order 6
+                 workloads.GridSpec(0, 32, 16, 34, 8, bscale=1.0)):  # N2 > 32
+        g = gpu_grid(spec)
+        with pytest.raises(hr.HRError):
+            g.set_kernel_config(variant=3)
+    # more patches than compute units
+    g = gpu_grid(workloads.GridSpec(0, 256, 256, 8, 10, bscale=1.0))
+    with pytest.raises(hr.HRError):
+        g.set_kernel_config(variant=3)
+
+
+def test_resident_stage_timing_keeps_trajectory():
+    w = workloads.paper_scale()
+    g = gpu_grid(w.grid)
+    g.set_kernel_config(variant=3)
+    g.set_punctures(*w.punctures.as_tuple())
+    t = g.time_stage_kernels(w.eta, 1.0, 0.0, 100, hr.FP64)
+    banner(f"resident per-stage time {t[4]:.2f} us")
+    assert all(x > 0 for x in t)
+    h = gpu_grid(w.grid)
+    h.set_kernel_config(variant=1)
+    h.set_punctures(*w.punctures.as_tuple())
+    h.relax(w.eta, 1.0, 0.0, 100, 0.0, check_every=100)
+    assert rel_maxdiff(g.get_u(extended=True), h.get_u(extended=True)) <= 1e-13

@@ -87,7 +87,7 @@ def test_autotune_keeps_state_and_caches():
     u0 = g.get_u(extended=True)
     v0 = g.get_v(extended=True)
     cfg, us = g.autotune(hr.FP64, 3)
-    assert cfg["variant"] in (1, 2) and us > 0
+    assert cfg["variant"] in (1, 2, 3) and us > 0
     if cfg["variant"] == 2:
         assert 1 <= cfg["chunk"] <= spec.N2
     assert np.array_equal(g.get_u(extended=True), u0)

@@ -1,6 +1,7 @@
-"""Host code under sanitizers: the library's geometry tables (host C++) built
-with g++ -fsanitize=address,undefined and exercised over many shapes, orders
-and both coordinate systems (no device code is involved)."""
+"""Host code under sanitizers: the library's geometry tables and the resident
+kernel's patch partition (host C++) built with g++ -fsanitize=address,undefined
+and exercised over many shapes, orders and both coordinate systems (no device
+code is involved)."""
 import os
 import shutil
 import subprocess
@@ -26,3 +27,4 @@ def test_geometry_tables_clean_under_asan_ubsan(tmp_path):
                        env=dict(os.environ, ASAN_OPTIONS="detect_leaks=1"))
     assert r.returncode == 0, (r.stdout + r.stderr)[-2000:]
     assert "geometry tables checked" in r.stdout
+    assert "resident partitions checked: 28" in r.stdout
