@@ -209,8 +209,19 @@ hr_status hr_suggest_dt(const hr_grid* g, double cfl, double* dt);
  * Kernel configuration of a grid (performance only; results are identical up
  * to floating-point rounding order, and bitwise identical for the streaming
  * switch, which changes cache policy only).
- *   variant    0 = automatic, 1 = plane tiles (one phi plane per block),
- *              2 = phi-marching columns (a block walks `chunk` phi planes)
+ *   variant    0 = automatic (3 where it applies, else 1 or 2 by size),
+ *              1 = plane tiles (one phi plane per block),
+ *              2 = phi-marching columns (a block walks `chunk` phi planes),
+ *              3 = resident (FP64 only): one kernel launch runs up to
+ *              1000 whole RK4 steps with the state of every 8 x 8 (x0, x1)
+ *              patch (all phi planes) on one compute unit; the patches
+ *              exchange their stage input through the grid's stage buffers.
+ *              Needs a bound grid with N0 and N1 multiples of 8, N2 <= 32,
+ *              fd_order 8 or 10 and no more patches than the device holds at
+ *              once (256 on MI355X: up to 128 x 128 (x0, x1)), else
+ *              HR_EINVAL. Single-precision stages run plane tiles instead.
+ *              A timed-out exchange wait (not expected) is reported as
+ *              HR_EDEVICE by the relaxing call.
  *   streaming  -1 = automatic (by grid size), 0 = cached, 1 = non-temporal
  *              loads/stores for fields touched once per stage
  *   chunk      phi planes per block for variant 2 (0 = automatic)
@@ -231,10 +242,20 @@ hr_status hr_set_kernel_config(hr_grid* g, const hr_kernel_config* cfg);
 hr_status hr_get_kernel_config(const hr_grid* g, hr_kernel_config* cfg);
 
 /*
+ * The configuration the relaxation actually runs for precision prec, with the
+ * automatic choices resolved (variant 0 becomes 3 where the resident kernel
+ * applies and prec is HR_FP64, else 2 or 1 by size; graph 0 for the resident
+ * kernel, whose check interval is a single launch). Errors: HR_EINVAL.
+ */
+hr_status hr_resolved_kernel(const hr_grid* g, hr_precision prec, hr_kernel_config* cfg);
+
+/*
  * Autotuner: times the stage kernels of this grid in precision prec (HR_FP64
- * or HR_FP32) for every candidate configuration -- plane tiles, and phi
- * columns with chunk 1, 2, 4, ... up to N2 -- over n_steps (>= 1) rounds of
- * stages 1-3 (which never write the state y_n, so the state is unchanged),
+ * or HR_FP32) for every candidate configuration -- plane tiles, phi columns
+ * with chunk 1, 2, 4, ... up to N2, and (FP64, where it applies) the resident
+ * kernel -- over n_steps (>= 1) rounds of stages 1-3 (which never write the
+ * state y_n; the resident kernel runs whole steps on a copy of the state that
+ * is put back afterwards, so the state is unchanged),
  * keeps the fastest in the grid (as hr_set_kernel_config would) and in a
  * process-wide cache keyed by (N0, N1, N2, fd_order, prec); a cached shape is
  * not timed again. best and best_us (optional) receive the choice and its mean
@@ -248,6 +269,8 @@ hr_status hr_autotune(hr_grid* g, hr_precision prec, int n_steps, hr_kernel_conf
  * (HR_FP64 or HR_FP32), bracketing every stage-kernel launch with hipEvents
  * recorded on the grid's stream, and returns in avg_us[0..3] the mean duration
  * of the stage-1..4 kernels in microseconds (avg_us[4]: mean over all four).
+ * With the resident variant (FP64) the n_steps (at most 100000) run in one
+ * launch and every entry is its duration / (4 n_steps).
  * The state advances by n_steps. Errors: HR_EINVAL, HR_ESTATE, HR_EDEVICE.
  */
 hr_status hr_time_stage_kernels(hr_grid* g, double eta, double c, double dt, long n_steps,

@@ -94,6 +94,8 @@ _SIGNATURES = {
                                              ctypes.c_double, ctypes.c_long, ctypes.c_int, _dp]),
     "hr_set_kernel_config": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KernelConfig)]),
     "hr_get_kernel_config": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KernelConfig)]),
+    "hr_resolved_kernel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
+                                          ctypes.POINTER(KernelConfig)]),
     "hr_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                    ctypes.POINTER(KernelConfig), _dp]),
     "hr_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
@@ -305,6 +307,15 @@ class Grid:
                                           ctypes.byref(us)), "hr_autotune")
         return {"variant": cfg.variant, "streaming": cfg.streaming, "chunk": cfg.chunk,
                 "graph": cfg.graph}, us.value
+
+    def resolved_kernel(self, precision: int = FP64) -> dict:
+        """The configuration the relaxation runs in this precision, automatic
+        choices resolved (variant 3 = resident kernel)."""
+        cfg = KernelConfig()
+        _check(load_library().hr_resolved_kernel(self._h, int(precision), ctypes.byref(cfg)),
+               "hr_resolved_kernel")
+        return {"variant": cfg.variant, "streaming": cfg.streaming, "chunk": cfg.chunk,
+                "graph": cfg.graph}
 
     def kernel_config(self) -> dict:
         cfg = KernelConfig()

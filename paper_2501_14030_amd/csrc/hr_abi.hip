@@ -40,8 +40,9 @@ hr_status kfail(hr_status s, const std::string& msg) {
     if (e_ != hipSuccess) return kfail(HR_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-// Kernel variant for this grid: explicit configuration, else by size (phi
-// columns when there are enough (x0, x1) tiles to fill the device).
+// Kernel variant for this grid: explicit configuration, else the resident
+// kernel where it applies (whole steps on chip), else by size (phi columns
+// when there are enough (x0, x1) tiles to fill the device).
 bool resident_ok(const hr_grid* g) {
   return g->bound && g->res_nbx > 0 && g->res_nbx * g->res_nby <= g->res_capacity &&
          (g->fd_order == 8 || g->fd_order == 10);
@@ -51,7 +52,12 @@ void resolve_variant(const hr_grid* g, int& variant, int& chunk) {
   variant = g->variant;
   chunk = g->chunk;
   const long tiles = (long)((g->d.N0 + 63) / 64) * ((g->d.N1 + 7) / 8);
-  if (variant == 0) variant = (tiles * g->d.N2 >= 4096 && g->d.N2 >= 16) ? 2 : 1;
+  if (variant == 0) {
+    if (resident_ok(g))
+      variant = 3;
+    else
+      variant = (tiles * g->d.N2 >= 4096 && g->d.N2 >= 16) ? 2 : 1;
+  }
   if (variant == 2 && chunk <= 0) {
     // aim for about 2048 blocks, at least 4 planes per block
     long c = (tiles * g->d.N2 + 2047) / 2048;
@@ -198,7 +204,7 @@ hr_status launch_steps(hr_grid* g, const Fields<T>& F, T eta, T dt, long nsteps,
                        bool corr = false) {
   if constexpr (std::is_same<T, double>::value) {
     if (!corr && use_resident(g)) {
-      // whole RK4 steps in cooperative launches of at most 1000 steps
+      // whole RK4 steps in resident launches of at most 1000 steps
       for (long n = 0; n < nsteps; n += 1000) {
         const int k = (int)std::min<long>(1000, nsteps - n);
         HR_HIP(launch_resident(g->fd_order, resident_args(g, eta, dt, k), g->stream));
@@ -881,6 +887,20 @@ hr_status hr_set_kernel_config(hr_grid* g, const hr_kernel_config* cfg) {
   g->streaming = cfg->streaming;
   g->chunk = cfg->chunk;
   g->graph = cfg->graph;
+  return HR_OK;
+}
+
+hr_status hr_resolved_kernel(const hr_grid* g, hr_precision prec, hr_kernel_config* cfg) {
+  if (!g || !cfg) return fail(HR_EINVAL, "null argument");
+  if (prec != HR_FP64 && prec != HR_FP32 && prec != HR_FP32_FP64FINISH)
+    return fail(HR_EINVAL, "unknown precision");
+  int variant = 0, chunk = 0;
+  resolve_variant(g, variant, chunk);
+  if (variant == 3 && prec != HR_FP64) variant = 1;
+  cfg->variant = variant;
+  cfg->chunk = variant == 2 ? chunk : 0;
+  cfg->streaming = g->streaming > 0 ? 1 : 0;
+  cfg->graph = (variant == 3 || g->graph == 0) ? 0 : 1;
   return HR_OK;
 }
 

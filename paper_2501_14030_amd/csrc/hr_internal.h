@@ -165,7 +165,7 @@ hipError_t launch_rebase(double* ub, double* vb, const float* eu, const float* e
 hipError_t launch_fill(double* dst, double value, int n, hipStream_t s);
 hipError_t launch_fill(float* dst, float value, int n, hipStream_t s);
 
-// Resident RK4 kernel (hr_resident.hip): one cooperative launch runs nsteps
+// Resident RK4 kernel (hr_resident.hip): one launch runs nsteps
 // whole RK4 steps of a small grid with the state held on chip. Every block owns
 // an 8 x 8 patch of (x0, x1) columns over all phi planes (the last x0 patch also
 // the outer points), keeps y_n, the stage input and the accumulator of its
@@ -209,8 +209,8 @@ size_t resident_lds_bytes(const Dims& d);
 // Largest number of co-resident blocks of the resident kernel on the current
 // device for these dims (0 if the order or N2 is not supported).
 int resident_capacity(int order, const Dims& d);
-// Resets the counters and launches the resident kernel cooperatively; events
-// (optional) bracket the launch.
+// Resets the counters and launches the resident kernel (one block per
+// compute unit, all resident at once); events (optional) bracket the kernel.
 hipError_t launch_resident(int order, const ResidentArgs& a, hipStream_t s,
                            hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
@@ -266,7 +266,7 @@ struct hr_grid {
   double kappa_loaded = -1.0;   // wave-speed scale currently in fac/ofac
 
   int variant = 0;              // kernel variant: 0 auto, 1 plane tiles, 2 phi columns,
-                                // 3 resident (FP64 steps in one cooperative launch)
+                                // 3 resident (FP64 steps in one launch, state on chip)
   int res_nbx = 0, res_nby = 0; // resident patches (0: grid not eligible)
   int res_capacity = 0;         // co-resident blocks the device allows for it
   std::vector<int> res_plan;    // exchange partners (host copy, uploaded at bind)

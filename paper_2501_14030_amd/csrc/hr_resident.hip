@@ -2,12 +2,12 @@
 //
 // At the paper's grid sizes (128 x 128 x 16) one RK4 stage moves ~22 MB and a
 // stage kernel is bound by launch and memory latency, not bandwidth. Here one
-// cooperative launch runs many whole RK4 steps (Algorithm 1, inner loop; RHS
+// launch runs many whole RK4 steps (Algorithm 1, inner loop; RHS
 // of Eq. 5 with the radiation condition at the outer points) and the state
 // never leaves the chip:
 //   * block b owns an 8 x 8 patch of (x0, x1) columns through all N2 phi planes
-//     (the last x0 patch also the NG outer points of its rows); its 256
-//     threads are 64 (x0, x1) positions x 4 plane groups;
+//     (the last x0 patch also the NG outer points of its rows); its threads
+//     are 64 (x0, x1) positions x up to 16 plane groups;
 //   * y_n, the stage input v, the accumulator, psi_s and S_src of the block's
 //     points sit in registers; the stage input u of the whole patch plus its
 //     NG-deep rim (all planes) sits in LDS, so every stencil tap, phi included,
@@ -17,6 +17,9 @@
 //     next stage waits only for the counters of its exchange partners (the
 //     owners of its rim taps and the blocks whose rims reach it), then loads
 //     its rim from the exchange array.
+// All blocks are resident at once: each takes more than half of a compute
+// unit's LDS, and the grid has at most as many blocks as the device has
+// compute units (checked by occupancy before use).
 // Exchange data and counters are written and read with agent-scope atomics,
 // which are coherent across the XCDs' L2 caches without cache-wide
 // write-back or invalidate; a full s_waitcnt before the block barrier orders
@@ -26,6 +29,7 @@
 // The arithmetic per point is that of the stage kernels (same stencil
 // summation order and stage combine), so results match them to rounding.
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,7 +41,6 @@ namespace hr {
 namespace {
 
 constexpr int RB = kResPatch;
-constexpr int RT = 256;   // threads per block
 
 __device__ __forceinline__ void xstore(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -51,15 +54,17 @@ __global__ void k_zero_u32(unsigned* p, int n) {
   if (i < n) p[i] = 0u;
 }
 
-// NPT: phi planes per thread (plane group g holds planes g, g + 4, ...).
-template <int NG, int NPT>
+// RT threads = 64 (x0, x1) positions x PG plane groups; plane group g holds
+// planes g, g + PG, ... (NPT of them).
+template <int NG, int NPT, int RT>
 __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
+  constexpr int PG = RT / 64;
   constexpr int RW = RB + 2 * NG;                // LDS tile row (x0) length
   constexpr int TP = RW * RW;                    // tile cells per plane (corners unused)
   constexpr int VW = RB + NG;                    // v tile row: patch columns + outer
   constexpr int NRIM = 4 * NG * RB;              // rim cells per plane
-  constexpr int NR = (NRIM * 4 * NPT + RT - 1) / RT;
-  constexpr int NQ = (NG * RB * 4 * NPT + RT - 1) / RT;
+  constexpr int NR = (NRIM * PG * NPT + RT - 1) / RT;
+  constexpr int NQ = (NG * RB * PG * NPT + RT - 1) / RT;
   constexpr Weights<NG> Wt{};
   extern __shared__ double smem[];
   __shared__ int bad;
@@ -87,23 +92,14 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
   double yu[NPT], yv[NPT], su[NPT], sv[NPT], au[NPT], av[NPT], ps[NPT], ss[NPT];
   unsigned gidx[NPT];
   int lidx[NPT], vidx[NPT];
-  int php[NPT][NG], phm[NPT][NG];   // LDS offsets of the phi taps
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
-    const int i2 = grp + 4 * j;
+    const int i2 = grp + PG * j;
     const bool ok = i2 < N2;
     const int i2c = ok ? i2 : 0;
     gidx[j] = P0 * ((unsigned)i1 + N1 * (unsigned)i2c) + (unsigned)i0;
     lidx[j] = i2c * TP + (x1l + NG) * RW + (x0l + NG);
     vidx[j] = (i2c * RB + x1l) * VW + x0l;
-    int jp = i2c, jm = i2c;
-#pragma unroll
-    for (int k = 1; k <= NG; ++k) {
-      jp = (jp + 1 == N2) ? 0 : jp + 1;
-      jm = (jm == 0) ? N2 - 1 : jm - 1;
-      php[j][k - 1] = (jp - i2c) * TP;
-      phm[j][k - 1] = (jm - i2c) * TP;
-    }
     yu[j] = ok ? a.u[gidx[j]] : 0.0;
     yv[j] = ok ? a.v[gidx[j]] : 0.0;
     ps[j] = ok ? a.psi[gidx[j]] : 0.0;
@@ -217,7 +213,7 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
     }
 #pragma unroll
     for (int j = 0; j < NPT; ++j) {
-      if (grp + 4 * j < N2) {
+      if (grp + PG * j < N2) {
         ut[lidx[j]] = su[j];
         vt[vidx[j]] = sv[j];
       }
@@ -230,19 +226,24 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
     const double cy = a.cy[stage], ca = a.ca[stage];
 #pragma unroll
     for (int j = 0; j < NPT; ++j) {
-      if (grp + 4 * j >= N2) continue;
+      if (grp + PG * j >= N2) continue;
       const double* r = ut + lidx[j];
       const double uc = r[0];
       double d0 = 0, d1 = 0, e0 = 0, e1 = 0, e2 = 0;
+      // phi taps: planes i2 +- k (mod N2), stepped one at a time (wave-uniform)
+      const int i2 = grp + PG * j;
+      int jp = i2, jm = i2;
 #pragma unroll
       for (int k = 1; k <= NG; ++k) {
+        jp = (jp + 1 == N2) ? 0 : jp + 1;
+        jm = (jm == 0) ? N2 - 1 : jm - 1;
         const double p0 = r[k], m0 = r[-k];
         const double p1 = r[k * RW], m1 = r[-k * RW];
         d0 += Wt.d1[k] * (p0 - m0);
         d1 += Wt.d1[k] * (p1 - m1);
         e0 += Wt.d2[k] * (p0 + m0);
         e1 += Wt.d2[k] * (p1 + m1);
-        e2 += Wt.d2[k] * (r[php[j][k - 1]] + r[phm[j][k - 1]]);
+        e2 += Wt.d2[k] * (r[(jp - i2) * TP] + r[(jm - i2) * TP]);
       }
       const double w0 = Wt.d2[0];
       const double dd0 = e0 + w0 * uc, dd1 = e1 + w0 * uc, dd2 = e2 + w0 * uc;
@@ -300,7 +301,7 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
       double* dst = (e & 1) ? a.x1 : a.x0;
 #pragma unroll
       for (int j = 0; j < NPT; ++j)
-        if (grp + 4 * j < N2) xstore(dst + gidx[j], su[j]);
+        if (grp + PG * j < N2) xstore(dst + gidx[j], su[j]);
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
         if (oval[q]) xstore(dst + oidx[q], osu[q]);
@@ -312,7 +313,7 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
     } else {
 #pragma unroll
       for (int j = 0; j < NPT; ++j)
-        if (grp + 4 * j < N2) {
+        if (grp + PG * j < N2) {
           a.u[gidx[j]] = yu[j];
           a.v[gidx[j]] = yv[j];
         }
@@ -326,29 +327,27 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
   }
 }
 
-// NPT choices: planes per thread rounded up to a power of two (N2 <= 32).
-int npt_of(int N2) {
-  const int n = (N2 + 3) / 4;
-  return n <= 1 ? 1 : n <= 2 ? 2 : n <= 4 ? 4 : n <= 8 ? 8 : 0;
-}
+// Threads and planes per thread by N2: enough plane groups to give every
+// thread one or two planes (1024 threads: four waves per SIMD for latency).
+struct ResShape {
+  const void* kernel;
+  int threads;
+};
 
 template <int NG>
-const void* kernel_for_npt(int npt) {
-  switch (npt) {
-    case 1: return (const void*)k_resident<NG, 1>;
-    case 2: return (const void*)k_resident<NG, 2>;
-    case 4: return (const void*)k_resident<NG, 4>;
-    case 8: return (const void*)k_resident<NG, 8>;
-    default: return nullptr;
-  }
+ResShape shape_for(int N2) {
+  if (N2 <= 4) return {(const void*)k_resident<NG, 1, 256>, 256};
+  if (N2 <= 8) return {(const void*)k_resident<NG, 1, 512>, 512};
+  if (N2 <= 16) return {(const void*)k_resident<NG, 1, 1024>, 1024};
+  if (N2 <= 32) return {(const void*)k_resident<NG, 4, 512>, 512};
+  return {nullptr, 0};
 }
 
-const void* resident_kernel(int order, int N2) {
-  const int npt = npt_of(N2);
+ResShape resident_kernel(int order, int N2) {
   switch (order) {
-    case 8: return kernel_for_npt<4>(npt);
-    case 10: return kernel_for_npt<5>(npt);
-    default: return nullptr;
+    case 8: return shape_for<4>(N2);
+    case 10: return shape_for<5>(N2);
+    default: return {nullptr, 0};
   }
 }
 
@@ -362,13 +361,15 @@ size_t resident_lds_bytes(const Dims& d) {
 }
 
 int resident_capacity(int order, const Dims& d) {
-  const void* k = resident_kernel(order, d.N2);
+  const ResShape rs = resident_kernel(order, d.N2);
+  const void* k = rs.kernel;
   if (!k) return 0;
   const size_t lds = resident_lds_bytes(d);
   if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return 0;
   int per = 0, dev = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, RT, lds) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, rs.threads, lds) != hipSuccess)
+    return 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
@@ -377,7 +378,8 @@ int resident_capacity(int order, const Dims& d) {
 
 hipError_t launch_resident(int order, const ResidentArgs& a, hipStream_t s, hipEvent_t t0,
                            hipEvent_t t1) {
-  const void* k = resident_kernel(order, a.d.N2);
+  const ResShape rs = resident_kernel(order, a.d.N2);
+  const void* k = rs.kernel;
   if (!k) return hipErrorInvalidValue;
   const int nb = a.nbx * a.nby;
   if (nb <= 0 || nb > kResMaxBlocks || a.nsteps <= 0) return hipErrorInvalidValue;
@@ -390,14 +392,12 @@ hipError_t launch_resident(int order, const ResidentArgs& a, hipStream_t s, hipE
   if (e != hipSuccess) return e;
   ResidentArgs arg = a;
   void* args[] = {&arg};
-  if (t0) {
-    e = hipEventRecord(t0, s);
-    if (e != hipSuccess) return e;
-  }
-  e = hipLaunchCooperativeKernel(k, dim3(nb), dim3(RT), args, (unsigned)lds, s);
-  if (e != hipSuccess) return e;
-  if (t1) e = hipEventRecord(t1, s);
-  return e;
+  // The caller has checked that every block fits at once (one per compute unit,
+  // resident_capacity); the blocks synchronise only through their bounded
+  // counter waits, so a plain launch suffices. If the device were shared and a
+  // block could not start, its partners' waits would time out (err) instead
+  // of hanging.
+  return hipExtLaunchKernel(k, dim3(nb), dim3(rs.threads), args, lds, s, t0, t1, 0);
 }
 
 }  // namespace hr

@@ -55,7 +55,10 @@ def test_batch_fixed_steps_matches_eager_and_oracle():
         d = rel_maxdiff(gs[k].get_u(extended=True), e.get_u(extended=True))
         banner(f"{spec.name()}: batch vs eager {d:.2e}")
         assert d <= 1e-13
-        np.testing.assert_allclose(res[k].history, r.history, rtol=1e-10, atol=1e-16)
+        # the residual is a small difference of much larger terms: roundoff-level
+        # differences of u (column kernels here, the resident kernel eagerly) move
+        # it by up to ~1e-10 relative
+        np.testing.assert_allclose(res[k].history, r.history, rtol=1e-9, atol=1e-16)
         assert res[k].steps_taken == 300
     # one grid against the oracle as well
     spec = SPECS[0]

@@ -57,6 +57,9 @@ def test_automatic_variant_choice_on_paper_scale():
     g = gpu_grid(w.grid)
     cfg = g.kernel_config()
     assert cfg["variant"] == 0 and cfg["streaming"] == -1
+    # automatic: the resident kernel for FP64 at this size, plane tiles for FP32
+    assert g.resolved_kernel(hr.FP64)["variant"] == 3
+    assert g.resolved_kernel(hr.FP32)["variant"] == 1
     g.set_kernel_config(variant=2, streaming=0, chunk=0)
     g.set_punctures(*w.punctures.as_tuple())
     r = g.relax(w.eta, 1.0, 0.0, 100, 0.0, check_every=100)
@@ -103,7 +106,7 @@ def test_autotune_keeps_state_and_caches():
     h.set_kernel_config(variant=1)
     h.set_punctures(*w.punctures.as_tuple())
     h.relax(16.0, 1.0, 0.0, 300, 0.0, check_every=100)
-    assert rel_maxdiff(g.get_u(extended=True), h.get_u(extended=True)) <= 1e-14
+    assert rel_maxdiff(g.get_u(extended=True), h.get_u(extended=True)) <= 1e-13
 
 
 @pytest.mark.parametrize("prec", [hr.FP64, hr.FP32_FP64FINISH, hr.FP32])
@@ -116,7 +119,9 @@ def test_graph_replays_match_eager_launches(prec):
     out = []
     for graph in (0, 1):
         g = gpu_grid(w.grid)
-        g.set_kernel_config(graph=graph)
+        # plane tiles: the resident kernel (automatic for FP64 here) runs a
+        # check interval as one launch and is never captured
+        g.set_kernel_config(variant=1, graph=graph)
         g.set_fp32_switch(0.0, 1000000, 0)
         g.set_punctures(*w.punctures.as_tuple())
         r1 = g.relax(8.0, 1.0, 0.0, 700, 0.0, check_every=100, precision=prec)
