@@ -216,7 +216,7 @@ hr_status hr_suggest_dt(const hr_grid* g, double cfl, double* dt);
  *              1000 whole RK4 steps with the state of every 8 x 8 (x0, x1)
  *              patch (all phi planes) on one compute unit; the patches
  *              exchange their stage input through the grid's stage buffers.
- *              Needs a bound grid with N0 and N1 multiples of 8, N2 <= 32,
+ *              Needs a bound grid with N0 and N1 multiples of 8, N2 <= 16,
  *              fd_order 8 or 10 and no more patches than the device holds at
  *              once (256 on MI355X: up to 128 x 128 (x0, x1)), else
  *              HR_EINVAL. Single-precision stages run plane tiles instead.

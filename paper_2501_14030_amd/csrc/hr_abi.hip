@@ -882,7 +882,7 @@ hr_status hr_set_kernel_config(hr_grid* g, const hr_kernel_config* cfg) {
     return fail(HR_EINVAL, "invalid kernel configuration");
   if (cfg->variant == 3 && !resident_ok(g))
     return fail(HR_EINVAL, "resident variant needs a bound grid of whole 8x8 (x0, x1) patches, "
-                           "N2 <= 32, order 8 or 10, and one compute unit per patch");
+                           "N2 <= 16, order 8 or 10, and one compute unit per patch");
   g->variant = cfg->variant;
   g->streaming = cfg->streaming;
   g->chunk = cfg->chunk;

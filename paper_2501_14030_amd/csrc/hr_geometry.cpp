@@ -171,7 +171,7 @@ bool build_tables(hr_coords coords, const Dims& d, const hr_grid_params& p,
 bool resident_plan(const Dims& d, std::vector<int>& waits, int& nbx, int& nby) {
   constexpr int RB = kResPatch;
   nbx = nby = 0;
-  if (d.N0 % RB || d.N1 % RB || d.NG > RB || d.N2 > 32 || d.N2 < 2) return false;
+  if (d.N0 % RB || d.N1 % RB || d.NG > RB || d.N2 > 16 || d.N2 < 2) return false;
   const int bx_n = d.N0 / RB, by_n = d.N1 / RB, nb = bx_n * by_n;
   if (nb > kResMaxBlocks) return false;
   const int NG = d.NG;

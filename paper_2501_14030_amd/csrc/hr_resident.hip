@@ -15,8 +15,12 @@
 //   * after each stage the block writes its new stage input u to a global
 //     exchange array (one per stage parity) and raises its stage counter; the
 //     next stage waits only for the counters of its exchange partners (the
-//     owners of its rim taps and the blocks whose rims reach it), then loads
-//     its rim from the exchange array.
+//     owners of its rim taps; the relation is symmetric), then loads its rim
+//     from the exchange array. Rim cells that are images of the patch's own
+//     points (inner-boundary reflections onto itself) are copied within LDS,
+//     and the outer points, read only by their own patch, stay in LDS;
+//   * the phi sums and the source term need only the patch's own planes and
+//     are computed before the wait, while the partners finish.
 // All blocks are resident at once: each takes more than half of a compute
 // unit's LDS, and the grid has at most as many blocks as the device has
 // compute units (checked by occupancy before use).
@@ -138,15 +142,17 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
   }
 
   // --- rim cells: LDS slot and stored source (images resolved) ------------
-  unsigned rg[NR];
-  int rl[NR];
-  bool rval[NR];
+  // kind 0: no cell (plane >= N2); 1: owned by another patch, read from the
+  // exchange array; 2: an image of one of this patch's own points, copied
+  // within LDS; 3: one of this patch's own outer points, stored into LDS by its
+  // thread. Packed: LDS slot (15 bits), LDS source of a kind-2 cell (15 bits),
+  // kind (2 bits); LDS indices stay below 16 planes x 20 x 20 < 2^15.
+  unsigned rg[NR], rmeta[NR];
 #pragma unroll
   for (int q = 0; q < NR; ++q) {
     const int c = t + RT * q;
     const int pl = c / NRIM, w = c - pl * NRIM;
-    rval[q] = pl < N2;
-    const int plc = rval[q] ? pl : 0;
+    const int plc = pl < N2 ? pl : 0;
     const int side = w / (NG * RB), w2 = w - side * (NG * RB);
     int l0, l1;
     if (side == 0) { l0 = w2 % NG; l1 = NG + w2 / NG; }
@@ -169,7 +175,12 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
     }
     const int sp = flip ? half_turn(plc, N2) : plc;
     rg[q] = P0 * ((unsigned)s1 + N1 * (unsigned)sp) + (unsigned)s0;
-    rl[q] = plc * TP + l1 * RW + l0;
+    const bool self = min(s0 / RB, a.nbx - 1) == bx && s1 / RB == by;
+    const unsigned kind = pl >= N2 ? 0u : !self ? 1u : flip ? 2u : 3u;
+    const unsigned rl = (unsigned)(plc * TP + l1 * RW + l0);
+    const unsigned rs =
+        kind == 2u ? (unsigned)(sp * TP + (s1 - x1b + NG) * RW + (s0 - x0b + NG)) : 0u;
+    rmeta[q] = rl | (rs << 15) | (kind << 30);
   }
 
   // --- exchange partners --------------------------------------------------
@@ -182,6 +193,45 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
   const int nst = 4 * a.nsteps;
   for (int e = 1; e <= nst; ++e) {
     const int stage = (e - 1) & 3;
+    // (1) stage input of the patch into LDS: own points and own outer points
+    // from registers, with v
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+      if (grp + PG * j < N2) {
+        ut[lidx[j]] = su[j];
+        vt[vidx[j]] = sv[j];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      if (oval[q]) {
+        ut[otl[q]] = osu[q];
+        vt[ovl[q]] = osv[q];
+      }
+    __syncthreads();
+    // (2) the phi sums and the source term need only the patch's own planes:
+    // computed while the partners finish the previous stage
+    double e2[NPT], src[NPT];
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+      e2[j] = 0.0;
+      src[j] = 0.0;
+      if (grp + PG * j >= N2) continue;
+      const double* r = ut + lidx[j];
+      const int i2 = grp + PG * j;
+      int jp = i2, jm = i2;
+#pragma unroll
+      for (int k = 1; k <= NG; ++k) {
+        jp = (jp + 1 == N2) ? 0 : jp + 1;
+        jm = (jm == 0) ? N2 - 1 : jm - 1;
+        e2[j] += Wt.d2[k] * (r[(jp - i2) * TP] + r[(jm - i2) * TP]);
+      }
+      const double p = ps[j] + r[0];
+      const double p2 = p * p;
+      const double p4 = p2 * p2;
+      src[j] = ss[j] / (p4 * p2 * p);
+    }
+    // (3) wait until every exchange partner has published the previous stage
     if (e > 1) {
       if (t < nw) {
         const unsigned* fl = a.flags + wt * kResFlagStride;
@@ -199,28 +249,23 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
       __syncthreads();
       if (bad) break;
     }
-    // stage input u: rim from the exchange array (the state itself at the first
-    // stage), own points from registers; v of the patch and outer points
-    if (e == 1) {
+    // (4) the rim: cells of other patches from the exchange array (the state
+    // itself at the first stage), images of own points within LDS
+    {
+      const double* src_x = ((e - 1) & 1) ? a.x1 : a.x0;
+      double rv[NR];
 #pragma unroll
-      for (int q = 0; q < NR; ++q)
-        if (rval[q]) ut[rl[q]] = a.u[rg[q]];
-    } else {
-      const double* src = ((e - 1) & 1) ? a.x1 : a.x0;
+      for (int q = 0; q < NR; ++q) {
+        rv[q] = 0.0;
+        if ((rmeta[q] >> 30) == 1u) rv[q] = e == 1 ? a.u[rg[q]] : xload(src_x + rg[q]);
+      }
 #pragma unroll
-      for (int q = 0; q < NR; ++q)
-        if (rval[q]) ut[rl[q]] = xload(src + rg[q]);
-    }
-#pragma unroll
-    for (int j = 0; j < NPT; ++j) {
-      if (grp + PG * j < N2) {
-        ut[lidx[j]] = su[j];
-        vt[vidx[j]] = sv[j];
+      for (int q = 0; q < NR; ++q) {
+        const unsigned kind = rmeta[q] >> 30, rl = rmeta[q] & 0x7fffu;
+        if (kind == 1u) ut[rl] = rv[q];
+        else if (kind == 2u) ut[rl] = ut[(rmeta[q] >> 15) & 0x7fffu];
       }
     }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-      if (oval[q]) vt[ovl[q]] = osv[q];
     __syncthreads();
 
     const double cy = a.cy[stage], ca = a.ca[stage];
@@ -229,30 +274,21 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
       if (grp + PG * j >= N2) continue;
       const double* r = ut + lidx[j];
       const double uc = r[0];
-      double d0 = 0, d1 = 0, e0 = 0, e1 = 0, e2 = 0;
-      // phi taps: planes i2 +- k (mod N2), stepped one at a time (wave-uniform)
-      const int i2 = grp + PG * j;
-      int jp = i2, jm = i2;
+      double d0 = 0, d1 = 0, e0 = 0, e1 = 0;
 #pragma unroll
       for (int k = 1; k <= NG; ++k) {
-        jp = (jp + 1 == N2) ? 0 : jp + 1;
-        jm = (jm == 0) ? N2 - 1 : jm - 1;
         const double p0 = r[k], m0 = r[-k];
         const double p1 = r[k * RW], m1 = r[-k * RW];
         d0 += Wt.d1[k] * (p0 - m0);
         d1 += Wt.d1[k] * (p1 - m1);
         e0 += Wt.d2[k] * (p0 + m0);
         e1 += Wt.d2[k] * (p1 + m1);
-        e2 += Wt.d2[k] * (r[(jp - i2) * TP] + r[(jm - i2) * TP]);
       }
       const double w0 = Wt.d2[0];
-      const double dd0 = e0 + w0 * uc, dd1 = e1 + w0 * uc, dd2 = e2 + w0 * uc;
+      const double dd0 = e0 + w0 * uc, dd1 = e1 + w0 * uc, dd2 = e2[j] + w0 * uc;
       const double lap = f[0] * dd0 + f[1] * dd1 + f[2] * dd2 + f[3] * d0 + f[4] * d1;
-      const double p = ps[j] + uc;
-      const double p2 = p * p;
-      const double p4 = p2 * p2;
       const double ku = sv[j] - a.eta * uc;
-      const double kv = f[5] * (lap + ss[j] / (p4 * p2 * p));
+      const double kv = f[5] * (lap + src[j]);
       if (stage == 0) {
         au[j] = uc + ca * ku;
         av[j] = sv[j] + ca * kv;
@@ -302,9 +338,7 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
 #pragma unroll
       for (int j = 0; j < NPT; ++j)
         if (grp + PG * j < N2) xstore(dst + gidx[j], su[j]);
-#pragma unroll
-      for (int q = 0; q < NQ; ++q)
-        if (oval[q]) xstore(dst + oidx[q], osu[q]);
+      // (outer points are read only by their own patch, through LDS)
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
       if (t == 0)
@@ -327,8 +361,9 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
   }
 }
 
-// Threads and planes per thread by N2: enough plane groups to give every
-// thread one or two planes (1024 threads: four waves per SIMD for latency).
+// Threads by N2: one plane per thread (1024 threads for N2 > 8: four waves per
+// SIMD to hide LDS and exchange latency). Deeper grids would need several
+// planes per thread and more registers than a 1024-thread block has.
 struct ResShape {
   const void* kernel;
   int threads;
@@ -339,7 +374,6 @@ ResShape shape_for(int N2) {
   if (N2 <= 4) return {(const void*)k_resident<NG, 1, 256>, 256};
   if (N2 <= 8) return {(const void*)k_resident<NG, 1, 512>, 512};
   if (N2 <= 16) return {(const void*)k_resident<NG, 1, 1024>, 1024};
-  if (N2 <= 32) return {(const void*)k_resident<NG, 4, 512>, 512};
   return {nullptr, 0};
 }
 

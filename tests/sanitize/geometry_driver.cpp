@@ -50,7 +50,7 @@ static std::set<int> rim_owners(const hr::Dims& d, int nbx, int b) {
 static int check_plans() {
   int checked = 0;
   const int shapes[][3] = {{8, 8, 2}, {16, 8, 2}, {64, 32, 8}, {64, 64, 8}, {128, 128, 16},
-                           {24, 40, 32}, {256, 256, 8}};
+                           {24, 40, 14}, {256, 256, 8}};
   for (int sph = 0; sph < 2; ++sph)
     for (const auto& sh : shapes)
       for (int NG : {4, 5}) {
@@ -77,7 +77,7 @@ static int check_plans() {
         ++checked;
       }
   // shapes the partition refuses
-  const int bad[][4] = {{37, 19, 6, 5}, {32, 16, 34, 4}, {12, 8, 4, 4}, {16, 16, 4, 9}};
+  const int bad[][4] = {{37, 19, 6, 5}, {32, 16, 18, 4}, {12, 8, 4, 4}, {16, 16, 4, 9}};
   for (const auto& sh : bad) {
     hr::Dims d{};
     d.N0 = sh[0]; d.N1 = sh[1]; d.N2 = sh[2]; d.NG = sh[3]; d.P0 = sh[0] + sh[3];

@@ -7,7 +7,8 @@ trajectories must agree with the plane-tile kernels to a few roundoff units
 and with the oracle to the parity tolerance. The cases cover the paper-scale
 grid (256 patches, one per compute unit), 8th and 10th order, Spherical
 coordinates (the xx0 reflection pairs patches across the theta range), a
-single patch, N2 = 2 (phi taps wrapping several times) and N2 = 32."""
+single patch, N2 = 2 (phi taps wrapping several times) and N2 = 14 (idle
+plane groups)."""
 import numpy as np
 import pytest
 
@@ -24,7 +25,7 @@ CASES = [
     (workloads.GridSpec(1, 64, 32, 8, 10, rmax=60.0), True),
     (workloads.GridSpec(0, 16, 8, 2, 10, amax=100.0, sinhwaa=0.2, bscale=1.0), True),
     (workloads.GridSpec(0, 8, 8, 6, 10, amax=100.0, sinhwaa=0.2, bscale=1.0), False),
-    (workloads.GridSpec(0, 24, 40, 32, 8, bscale=2.0), False),
+    (workloads.GridSpec(0, 24, 40, 14, 8, bscale=2.0), False),
 ]
 
 
@@ -90,7 +91,7 @@ def test_resident_relaxes_paper_scale_to_tolerance():
 def test_resident_rejected_where_not_applicable():
     for spec in (workloads.GridSpec(0, 37, 19, 6, 10, bscale=1.0),   # not whole patches
                  workloads.GridSpec(0, 32, 16, 4, 6, bscale=1.0),    # order 6
-                 workloads.GridSpec(0, 32, 16, 34, 8, bscale=1.0)):  # N2 > 32
+                 workloads.GridSpec(0, 32, 16, 18, 8, bscale=1.0)):  # N2 > 16
         g = gpu_grid(spec)
         with pytest.raises(hr.HRError):
             g.set_kernel_config(variant=3)
