@@ -46,6 +46,13 @@ namespace {
 
 constexpr int RB = kResPatch;
 
+// Row stride (in doubles) of an LDS tile of rows of n doubles: the smallest
+// w >= n with w = 8 (mod 16), so that two consecutive rows of 8 doubles, read
+// by one 16-lane group of a 64-bit LDS access, fall on disjoint halves of the
+// 32 banks.
+constexpr int tile_row(int n) { return n + ((8 - n % 16) + 16) % 16; }
+static_assert(tile_row(18) == 24 && tile_row(16) == 24 && tile_row(13) == 24, "tile rows");
+
 __device__ __forceinline__ void xstore(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -63,9 +70,9 @@ __global__ void k_zero_u32(unsigned* p, int n) {
 template <int NG, int NPT, int RT>
 __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
   constexpr int PG = RT / 64;
-  constexpr int RW = RB + 2 * NG;                // LDS tile row (x0) length
-  constexpr int TP = RW * RW;                    // tile cells per plane (corners unused)
-  constexpr int VW = RB + NG;                    // v tile row: patch columns + outer
+  constexpr int RW = tile_row(RB + 2 * NG);      // LDS tile row (x0) stride, padded
+  constexpr int TP = RW * (RB + 2 * NG);         // tile cells per plane (corners unused)
+  constexpr int VW = tile_row(RB + NG);          // v tile row: patch columns + outer
   constexpr int NRIM = 4 * NG * RB;              // rim cells per plane
   constexpr int NR = (NRIM * PG * NPT + RT - 1) / RT;
   constexpr int NQ = (NG * RB * PG * NPT + RT - 1) / RT;
@@ -75,7 +82,7 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
 
   const Dims& d = a.d;
   const int N2 = d.N2;
-  double* ut = smem;                 // [N2][RW][RW]
+  double* ut = smem;                 // [N2][RB + 2 NG][RW]
   double* vt = smem + N2 * TP;       // [N2][RB][VW]
   const int t = threadIdx.x, pos = t & 63, x0l = pos & 7, x1l = pos >> 3, grp = t >> 6;
   const int b = blockIdx.x, bx = b % a.nbx, by = b / a.nbx;
@@ -146,7 +153,7 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
   // exchange array; 2: an image of one of this patch's own points, copied
   // within LDS; 3: one of this patch's own outer points, stored into LDS by its
   // thread. Packed: LDS slot (15 bits), LDS source of a kind-2 cell (15 bits),
-  // kind (2 bits); LDS indices stay below 16 planes x 20 x 20 < 2^15.
+  // kind (2 bits); LDS indices stay below 16 planes x 18 rows x 24 < 2^15.
   unsigned rg[NR], rmeta[NR];
 #pragma unroll
   for (int q = 0; q < NR; ++q) {
@@ -388,8 +395,8 @@ ResShape resident_kernel(int order, int N2) {
 }  // namespace
 
 size_t resident_lds_bytes(const Dims& d) {
-  const int RW = RB + 2 * d.NG, VW = RB + d.NG;
-  const size_t need = (size_t)d.N2 * (RW * RW + RB * VW) * sizeof(double);
+  const int RH = RB + 2 * d.NG, RW = tile_row(RH), VW = tile_row(RB + d.NG);
+  const size_t need = (size_t)d.N2 * (RW * RH + RB * VW) * sizeof(double);
   // more than half of the 160 KiB of LDS per compute unit: one block per CU
   return std::max<size_t>(need, 82 * 1024);
 }
