@@ -115,7 +115,7 @@ def evaluate(mlp: MLP, ws, shape, tol: float = 1e-10, batch: int = 32, log=print
     import torch
 
     out = {"cold_steps": [], "warm_steps": [], "cold_s": 0.0, "warm_s": 0.0,
-           "initial_residual_cold": [], "initial_residual_warm": []}
+           "initial_residual_cold": [], "initial_residual_warm": [], "pred_rel_err": []}
     for i in range(0, len(ws), batch):
         chunk = ws[i:i + batch]
         grids = make_grids(chunk, shape)
@@ -126,13 +126,21 @@ def evaluate(mlp: MLP, ws, shape, tol: float = 1e-10, batch: int = 32, log=print
         torch.cuda.synchronize()
         out["cold_s"] += time.perf_counter() - t0
         out["cold_steps"] += [r.steps_taken for r in res]
+        solved = [g.get_u(extended=True) for g in grids]
         for w, g in zip(chunk, grids):
             g.set_punctures(*w.punctures.as_tuple())
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for w, g in zip(chunk, grids):
             mlp.warm_start(g, config_of(w), workloads.eta_for_dt(g.suggest_dt(0.5)))
+        torch.cuda.synchronize()
+        pause = time.perf_counter()
+        # median relative error of the prediction against the relaxed solution
+        for g, us in zip(grids, solved):
+            out["pred_rel_err"].append(float(np.median(np.abs(g.get_u(extended=True) - us) /
+                                                       np.abs(us))))
         out["initial_residual_warm"] += [g.residual_l2() for g in grids]
+        t0 += time.perf_counter() - pause
         res = relax_all(grids, tol)
         torch.cuda.synchronize()
         out["warm_s"] += time.perf_counter() - t0
@@ -182,6 +190,8 @@ def main(argv=None) -> int:
            "time_ratio": ev["warm_s"] / ev["cold_s"],
            "median_initial_residual_cold": float(np.median(ev["initial_residual_cold"])),
            "median_initial_residual_warm": float(np.median(ev["initial_residual_warm"])),
+           "pred_rel_err_median": float(np.median(ev["pred_rel_err"])),
+           "pred_rel_err_p90": float(np.percentile(ev["pred_rel_err"], 90)),
            "frac_configs_fewer_steps": float(np.mean(warm < cold))}
     print(json.dumps(res), flush=True)
     return 0
