@@ -212,14 +212,15 @@ hr_status hr_suggest_dt(const hr_grid* g, double cfl, double* dt);
  *   variant    0 = automatic (3 where it applies, else 1 or 2 by size),
  *              1 = plane tiles (one phi plane per block),
  *              2 = phi-marching columns (a block walks `chunk` phi planes),
- *              3 = resident (FP64 only): one kernel launch runs up to
+ *              3 = resident (FP64 steps, and the FP32 increment steps of
+ *              HR_FP32_FP64FINISH): one kernel launch runs up to
  *              1000 whole RK4 steps with the state of every 8 x 8 (x0, x1)
  *              patch (all phi planes) on one compute unit; the patches
  *              exchange their stage input through the grid's stage buffers.
  *              Needs a bound grid with N0 and N1 multiples of 8, N2 <= 16,
  *              fd_order 8 or 10 and no more patches than the device holds at
  *              once (256 on MI355X: up to 128 x 128 (x0, x1)), else
- *              HR_EINVAL. Single-precision stages run plane tiles instead.
+ *              HR_EINVAL. Plain HR_FP32 stages run plane tiles instead.
  *              A timed-out exchange wait (not expected) is reported as
  *              HR_EDEVICE by the relaxing call.
  *   streaming  -1 = automatic (by grid size), 0 = cached, 1 = non-temporal
@@ -244,8 +245,9 @@ hr_status hr_get_kernel_config(const hr_grid* g, hr_kernel_config* cfg);
 /*
  * The configuration the relaxation actually runs for precision prec, with the
  * automatic choices resolved (variant 0 becomes 3 where the resident kernel
- * applies and prec is HR_FP64, else 2 or 1 by size; graph 0 for the resident
- * kernel, whose check interval is a single launch). Errors: HR_EINVAL.
+ * applies and prec is HR_FP64 or HR_FP32_FP64FINISH, else 2 or 1 by size;
+ * graph 0 for the resident kernel, whose check interval is a single launch).
+ * Errors: HR_EINVAL.
  */
 hr_status hr_resolved_kernel(const hr_grid* g, hr_precision prec, hr_kernel_config* cfg);
 

@@ -48,6 +48,10 @@ bool resident_ok(const hr_grid* g) {
          (g->fd_order == 8 || g->fd_order == 10);
 }
 
+bool resident_split_ok(const hr_grid* g) {
+  return resident_ok(g) && g->res_nbx * g->res_nby <= g->res_capacity32;
+}
+
 void resolve_variant(const hr_grid* g, int& variant, int& chunk) {
   variant = g->variant;
   chunk = g->chunk;
@@ -179,6 +183,35 @@ ResidentArgs resident_args(hr_grid* g, double eta, double dt, int nsteps) {
   return r;
 }
 
+// Resident arguments of the split-state form: the FP32 increment, the base
+// quantities (p_b, S_src p_b^-7, k(y_b)) of the last base evaluation.
+ResidentArgsT<float> resident_args_split(hr_grid* g, float eta, float dt, int nsteps) {
+  ResidentArgsT<float> r{};
+  r.d = g->d;
+  r.u = g->f32.un;
+  r.v = g->f32.vn;
+  r.psi = g->f32.pb;
+  r.ssrc = g->f32.sp7;
+  r.khu = g->f32.khu;
+  r.khv = g->f32.khv;
+  r.fac = g->f32.fac;
+  r.ofac = g->f32.ofac;
+  r.x0 = g->f32.ua;
+  r.x1 = g->f32.ub;
+  r.flags = g->res_flags;
+  r.waits = g->res_waits;
+  r.err = g->res_err;
+  r.eta = eta;
+  // the stage coefficients of the stage kernels (classic RK4, in FP32)
+  r.cy[0] = dt / 2.0f; r.cy[1] = dt / 2.0f; r.cy[2] = dt; r.cy[3] = dt;
+  r.ca[0] = dt / 6.0f; r.ca[1] = dt / 3.0f; r.ca[2] = dt / 3.0f; r.ca[3] = dt / 6.0f;
+  r.nbx = g->res_nbx;
+  r.nby = g->res_nby;
+  r.nsteps = nsteps;
+  r.spin_limit = 1u << 19;
+  return r;
+}
+
 // Reads the resident kernel's error word (synchronous); a timed-out exchange
 // wait leaves the state unchanged from the launch's start and is reported.
 hr_status check_resident(hr_grid* g) {
@@ -199,6 +232,8 @@ bool use_resident(const hr_grid* g) {
   return variant == 3;
 }
 
+bool use_resident_split(const hr_grid* g) { return use_resident(g) && resident_split_ok(g); }
+
 template <typename T>
 hr_status launch_steps(hr_grid* g, const Fields<T>& F, T eta, T dt, long nsteps,
                        bool corr = false) {
@@ -208,6 +243,14 @@ hr_status launch_steps(hr_grid* g, const Fields<T>& F, T eta, T dt, long nsteps,
       for (long n = 0; n < nsteps; n += 1000) {
         const int k = (int)std::min<long>(1000, nsteps - n);
         HR_HIP(launch_resident(g->fd_order, resident_args(g, eta, dt, k), g->stream));
+      }
+      return HR_OK;
+    }
+  } else {
+    if (corr && use_resident_split(g)) {
+      for (long n = 0; n < nsteps; n += 1000) {
+        const int k = (int)std::min<long>(1000, nsteps - n);
+        HR_HIP(launch_resident(g->fd_order, resident_args_split(g, eta, dt, k), g->stream));
       }
       return HR_OK;
     }
@@ -371,7 +414,7 @@ hr_status run_interval(hr_grid* g, int kind, int K, double eta, double dt, doubl
   int variant = 0, chunk = 0;
   resolve_variant(g, variant, chunk);
   const int streaming = g->streaming > 0 ? 1 : 0;
-  const bool resident = kind == 0 && variant == 3;
+  const bool resident = variant == 3 && (kind == 0 || (kind == 2 && resident_split_ok(g)));
   if (g->graph != 0 && !resident) {
     const bool same = g->gexec && g->g_kind == kind && g->g_K == K && g->g_eta == eta &&
                       g->g_dt == dt && g->g_kappa == g->kappa_loaded && g->g_variant == variant &&
@@ -504,6 +547,10 @@ hr_status run_split_phase(hr_grid* g, double eta, double dt, long max_steps, dou
       hr_status st = launch_steps<float>(g, g->f32, (float)eta, (float)dt, chunk, true);
       if (st != HR_OK) return st;
       HR_HIP(launch_rebase(g->f64.un, g->f64.vn, g->f32.un, g->f32.vn, G, g->stream));
+      if (use_resident_split(g)) {
+        st = check_resident(g);
+        if (st != HR_OK) return st;
+      }
       s += chunk;
       break;
     }
@@ -674,6 +721,7 @@ hr_status hr_grid_bind(hr_grid* g, void* dev_ptr, size_t bytes, void* hip_stream
                           hipMemcpyHostToDevice, g->stream));
     HR_HIP(hipMemsetAsync(g->res_err, 0, sizeof(unsigned), g->stream));
     g->res_capacity = resident_capacity(g->fd_order, g->d);
+    g->res_capacity32 = resident_capacity(g->fd_order, g->d, true);
   }
   g->kappa_loaded = -1.0;
   hr_status st = load_kappa(g, 1.0);
@@ -896,7 +944,8 @@ hr_status hr_resolved_kernel(const hr_grid* g, hr_precision prec, hr_kernel_conf
     return fail(HR_EINVAL, "unknown precision");
   int variant = 0, chunk = 0;
   resolve_variant(g, variant, chunk);
-  if (variant == 3 && prec != HR_FP64) variant = 1;
+  if (variant == 3 && !(prec == HR_FP64 || (prec == HR_FP32_FP64FINISH && resident_split_ok(g))))
+    variant = 1;
   cfg->variant = variant;
   cfg->chunk = variant == 2 ? chunk : 0;
   cfg->streaming = g->streaming > 0 ? 1 : 0;

@@ -177,41 +177,52 @@ constexpr int kResMaxWait = 16;       // blocks one block exchanges with, at mos
 constexpr int kResFlagStride = 32;    // one 128-byte line per block counter
 constexpr int kResMaxBlocks = 1024;
 
-struct ResidentArgs {
+// T = double: the FP64 state. T = float: the split-state form's FP32
+// increment e on the FP64 base (psi/ssrc then hold p_b and S_src p_b^-7, and
+// khu/khv the base slopes k(y_b); the slope is k(y_b) + L e + source
+// difference, as in the stage kernels).
+template <typename T>
+struct ResidentArgsT {
   Dims d;
-  double* u;            // state y_n (extended layout), read at start, written at the end
-  double* v;
-  const double* psi;
-  const double* ssrc;
-  const double* fac;    // 6 planes of N0*N1
-  const double* ofac;   // 3 planes of NG*N1
-  double* x0;           // exchange buffers (extended layout), by stage parity
-  double* x1;
+  T* u;                 // state (extended layout), read at start, written at the end
+  T* v;
+  const T* psi;
+  const T* ssrc;
+  const T* khu;         // split form only
+  const T* khv;
+  const T* fac;         // 6 planes of N0*N1
+  const T* ofac;        // 3 planes of NG*N1
+  T* x0;                // exchange buffers (extended layout), by stage parity
+  T* x1;
   unsigned* flags;      // per-block stage counters, zero at launch
   const int* waits;     // per block: count, then up to kResMaxWait block ids
   unsigned* err;        // bit 0: a wait timed out
-  double eta;
-  double cy[4];         // Y_{s+1} = y_n + cy[s] k (stage 4: y_{n+1} = acc + ca[3] k)
-  double ca[4];         // accumulator weights
+  T eta;
+  T cy[4];              // Y_{s+1} = y_n + cy[s] k (stage 4: y_{n+1} = acc + ca[3] k)
+  T ca[4];              // accumulator weights
   int nbx, nby;         // patches along x0 and x1
   int nsteps;
   unsigned spin_limit;  // polls of one counter before a wait gives up
 };
+using ResidentArgs = ResidentArgsT<double>;
 
 // Exchange partners of every patch (count, then ids; kResMaxWait + 1 ints per
 // block) for dims d: the owners of every stencil tap outside the patch,
 // including inner-boundary images, and every patch whose taps reach this one.
 // False if the grid is not made of whole 8 x 8 patches or has too many blocks.
 bool resident_plan(const Dims& d, std::vector<int>& waits, int& nbx, int& nby);
-// Dynamic LDS bytes of the resident kernel for these dims (at least enough to
-// keep one block per compute unit).
-size_t resident_lds_bytes(const Dims& d);
-// Largest number of co-resident blocks of the resident kernel on the current
-// device for these dims (0 if the order or N2 is not supported).
-int resident_capacity(int order, const Dims& d);
+// Dynamic LDS bytes of the resident kernel for these dims and element size (at
+// least enough to keep one block per compute unit).
+size_t resident_lds_bytes(const Dims& d, size_t elem);
+// Largest number of co-resident blocks of the resident kernel (FP64 form, or
+// the split form with split = true) on the current device for these dims (0 if
+// the order or N2 is not supported).
+int resident_capacity(int order, const Dims& d, bool split = false);
 // Resets the counters and launches the resident kernel (one block per
 // compute unit, all resident at once); events (optional) bracket the kernel.
-hipError_t launch_resident(int order, const ResidentArgs& a, hipStream_t s,
+hipError_t launch_resident(int order, const ResidentArgsT<double>& a, hipStream_t s,
+                           hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+hipError_t launch_resident(int order, const ResidentArgsT<float>& a, hipStream_t s,
                            hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
 // Host geometry (hr_geometry.cpp).
@@ -268,7 +279,8 @@ struct hr_grid {
   int variant = 0;              // kernel variant: 0 auto, 1 plane tiles, 2 phi columns,
                                 // 3 resident (FP64 steps in one launch, state on chip)
   int res_nbx = 0, res_nby = 0; // resident patches (0: grid not eligible)
-  int res_capacity = 0;         // co-resident blocks the device allows for it
+  int res_capacity = 0;         // co-resident blocks the device allows for it (FP64)
+  int res_capacity32 = 0;       // the same for the split-state FP32 form
   std::vector<int> res_plan;    // exchange partners (host copy, uploaded at bind)
   unsigned* res_flags = nullptr;
   int* res_waits = nullptr;

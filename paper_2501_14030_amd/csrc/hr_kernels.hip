@@ -176,11 +176,6 @@ struct CombineIn {
   }
 };
 
-// Source difference of the split-state form: S p^-7 [(1 + x)^-7 - 1], x = e/p,
-// evaluated without cancellation for small increments.
-__device__ __forceinline__ float source_delta(float sp7, float pb, float e) {
-  return sp7 * expm1f(-7.0f * log1pf(e / pb));
-}
 
 // RK4 stage combine for one point, given the stage slopes. The next stage
 // input (uout) is re-read with stencils, so it is always a cached store.

@@ -46,17 +46,20 @@ namespace {
 
 constexpr int RB = kResPatch;
 
-// Row stride (in doubles) of an LDS tile of rows of n doubles: the smallest
-// w >= n with w = 8 (mod 16), so that two consecutive rows of 8 doubles, read
-// by one 16-lane group of a 64-bit LDS access, fall on disjoint halves of the
-// 32 banks.
+// Row stride (in elements) of an LDS tile of rows of n elements: the smallest
+// w >= n with w = 8 (mod 16). For doubles, the two rows of 8 that one 16-lane
+// group of a 64-bit LDS access reads fall on disjoint halves of the 32 banks;
+// for floats, the four rows of 8 that one 32-lane group reads fall on four
+// disjoint quarters.
 constexpr int tile_row(int n) { return n + ((8 - n % 16) + 16) % 16; }
 static_assert(tile_row(18) == 24 && tile_row(16) == 24 && tile_row(13) == 24, "tile rows");
 
-__device__ __forceinline__ void xstore(double* p, double v) {
+template <typename T>
+__device__ __forceinline__ void xstore(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ double xload(const double* p) {
+template <typename T>
+__device__ __forceinline__ T xload(const T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -66,9 +69,10 @@ __global__ void k_zero_u32(unsigned* p, int n) {
 }
 
 // RT threads = 64 (x0, x1) positions x PG plane groups; plane group g holds
-// planes g, g + PG, ... (NPT of them).
-template <int NG, int NPT, int RT>
-__global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
+// planes g, g + PG, ... (NPT of them). T = double: the FP64 state; T = float
+// with CORR: the split-state form's increment (slopes as in the stage kernels).
+template <typename T, int NG, int NPT, int RT, bool CORR>
+__global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
   constexpr int PG = RT / 64;
   constexpr int RW = tile_row(RB + 2 * NG);      // LDS tile row (x0) stride, padded
   constexpr int TP = RW * (RB + 2 * NG);         // tile cells per plane (corners unused)
@@ -77,13 +81,14 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
   constexpr int NR = (NRIM * PG * NPT + RT - 1) / RT;
   constexpr int NQ = (NG * RB * PG * NPT + RT - 1) / RT;
   constexpr Weights<NG> Wt{};
-  extern __shared__ double smem[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
   __shared__ int bad;
 
   const Dims& d = a.d;
   const int N2 = d.N2;
-  double* ut = smem;                 // [N2][RB + 2 NG][RW]
-  double* vt = smem + N2 * TP;       // [N2][RB][VW]
+  T* ut = smem;                      // [N2][RB + 2 NG][RW]
+  T* vt = smem + N2 * TP;            // [N2][RB][VW]
   const int t = threadIdx.x, pos = t & 63, x0l = pos & 7, x1l = pos >> 3, grp = t >> 6;
   const int b = blockIdx.x, bx = b % a.nbx, by = b / a.nbx;
   const int x0b = bx * RB, x1b = by * RB;
@@ -94,13 +99,14 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
   const unsigned o2d = (unsigned)NG * N1;
 
   // --- own points --------------------------------------------------------
-  double f[6];
+  T f[6];
   {
     const unsigned k2 = (unsigned)i0 + (unsigned)d.N0 * (unsigned)i1;
 #pragma unroll
     for (int q = 0; q < 6; ++q) f[q] = a.fac[q * n2d + k2];
   }
-  double yu[NPT], yv[NPT], su[NPT], sv[NPT], au[NPT], av[NPT], ps[NPT], ss[NPT];
+  T yu[NPT], yv[NPT], su[NPT], sv[NPT], au[NPT], av[NPT], ps[NPT], ss[NPT];
+  T hu[NPT], hv[NPT];   // split form: base slopes
   unsigned gidx[NPT];
   int lidx[NPT], vidx[NPT];
 #pragma unroll
@@ -111,18 +117,21 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
     gidx[j] = P0 * ((unsigned)i1 + N1 * (unsigned)i2c) + (unsigned)i0;
     lidx[j] = i2c * TP + (x1l + NG) * RW + (x0l + NG);
     vidx[j] = (i2c * RB + x1l) * VW + x0l;
-    yu[j] = ok ? a.u[gidx[j]] : 0.0;
-    yv[j] = ok ? a.v[gidx[j]] : 0.0;
-    ps[j] = ok ? a.psi[gidx[j]] : 0.0;
-    ss[j] = ok ? a.ssrc[gidx[j]] : 0.0;
+    yu[j] = ok ? a.u[gidx[j]] : (T)0;
+    yv[j] = ok ? a.v[gidx[j]] : (T)0;
+    ps[j] = ok ? a.psi[gidx[j]] : (T)0;
+    ss[j] = ok ? a.ssrc[gidx[j]] : (T)0;
+    hu[j] = CORR && ok ? a.khu[gidx[j]] : (T)0;
+    hv[j] = CORR && ok ? a.khv[gidx[j]] : (T)0;
     su[j] = yu[j];
     sv[j] = yv[j];
-    au[j] = 0.0;
-    av[j] = 0.0;
+    au[j] = (T)0;
+    av[j] = (T)0;
   }
 
   // --- outer points (last x0 patch only) ---------------------------------
-  double oyu[NQ], oyv[NQ], osu[NQ], osv[NQ], oau[NQ], oav[NQ], oc[NQ], ori[NQ], oqd[NQ];
+  T oyu[NQ], oyv[NQ], osu[NQ], osv[NQ], oau[NQ], oav[NQ], oc[NQ], ori[NQ], oqd[NQ];
+  T ohu[NQ], ohv[NQ];   // split form: base slopes of the outer points
   unsigned oidx[NQ];
   int otl[NQ], ovl[NQ];
   bool oval[NQ];
@@ -137,15 +146,17 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
     otl[q] = plc * TP + (NG + r) * RW + (NG + RB + col);
     ovl[q] = (plc * RB + r) * VW + RB + col;
     const unsigned ko = (unsigned)col + (unsigned)NG * (unsigned)(x1b + r);
-    oc[q] = oval[q] ? a.ofac[ko] : 0.0;
-    ori[q] = oval[q] ? a.ofac[o2d + ko] : 0.0;
-    oqd[q] = oval[q] ? a.ofac[2 * o2d + ko] : 0.0;
-    oyu[q] = oval[q] ? a.u[oidx[q]] : 0.0;
-    oyv[q] = oval[q] ? a.v[oidx[q]] : 0.0;
+    oc[q] = oval[q] ? a.ofac[ko] : (T)0;
+    ori[q] = oval[q] ? a.ofac[o2d + ko] : (T)0;
+    oqd[q] = oval[q] ? a.ofac[2 * o2d + ko] : (T)0;
+    oyu[q] = oval[q] ? a.u[oidx[q]] : (T)0;
+    oyv[q] = oval[q] ? a.v[oidx[q]] : (T)0;
+    ohu[q] = CORR && oval[q] ? a.khu[oidx[q]] : (T)0;
+    ohv[q] = CORR && oval[q] ? a.khv[oidx[q]] : (T)0;
     osu[q] = oyu[q];
     osv[q] = oyv[q];
-    oau[q] = 0.0;
-    oav[q] = 0.0;
+    oau[q] = (T)0;
+    oav[q] = (T)0;
   }
 
   // --- rim cells: LDS slot and stored source (images resolved) ------------
@@ -218,25 +229,29 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
     __syncthreads();
     // (2) the phi sums and the source term need only the patch's own planes:
     // computed while the partners finish the previous stage
-    double e2[NPT], src[NPT];
+    T e2[NPT], src[NPT];
 #pragma unroll
     for (int j = 0; j < NPT; ++j) {
-      e2[j] = 0.0;
-      src[j] = 0.0;
+      e2[j] = (T)0;
+      src[j] = (T)0;
       if (grp + PG * j >= N2) continue;
-      const double* r = ut + lidx[j];
+      const T* r = ut + lidx[j];
       const int i2 = grp + PG * j;
       int jp = i2, jm = i2;
 #pragma unroll
       for (int k = 1; k <= NG; ++k) {
         jp = (jp + 1 == N2) ? 0 : jp + 1;
         jm = (jm == 0) ? N2 - 1 : jm - 1;
-        e2[j] += Wt.d2[k] * (r[(jp - i2) * TP] + r[(jm - i2) * TP]);
+        e2[j] += (T)Wt.d2[k] * (r[(jp - i2) * TP] + r[(jm - i2) * TP]);
       }
-      const double p = ps[j] + r[0];
-      const double p2 = p * p;
-      const double p4 = p2 * p2;
-      src[j] = ss[j] / (p4 * p2 * p);
+      if constexpr (CORR) {
+        src[j] = source_delta(ss[j], ps[j], r[0]);
+      } else {
+        const T p = ps[j] + r[0];
+        const T p2 = p * p;
+        const T p4 = p2 * p2;
+        src[j] = ss[j] / (p4 * p2 * p);
+      }
     }
     // (3) wait until every exchange partner has published the previous stage
     if (e > 1) {
@@ -259,11 +274,11 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
     // (4) the rim: cells of other patches from the exchange array (the state
     // itself at the first stage), images of own points within LDS
     {
-      const double* src_x = ((e - 1) & 1) ? a.x1 : a.x0;
-      double rv[NR];
+      const T* src_x = ((e - 1) & 1) ? a.x1 : a.x0;
+      T rv[NR];
 #pragma unroll
       for (int q = 0; q < NR; ++q) {
-        rv[q] = 0.0;
+        rv[q] = (T)0;
         if ((rmeta[q] >> 30) == 1u) rv[q] = e == 1 ? a.u[rg[q]] : xload(src_x + rg[q]);
       }
 #pragma unroll
@@ -275,27 +290,33 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
     }
     __syncthreads();
 
-    const double cy = a.cy[stage], ca = a.ca[stage];
+    const T cy = a.cy[stage], ca = a.ca[stage];
 #pragma unroll
     for (int j = 0; j < NPT; ++j) {
       if (grp + PG * j >= N2) continue;
-      const double* r = ut + lidx[j];
-      const double uc = r[0];
-      double d0 = 0, d1 = 0, e0 = 0, e1 = 0;
+      const T* r = ut + lidx[j];
+      const T uc = r[0];
+      T d0 = 0, d1 = 0, e0 = 0, e1 = 0;
 #pragma unroll
       for (int k = 1; k <= NG; ++k) {
-        const double p0 = r[k], m0 = r[-k];
-        const double p1 = r[k * RW], m1 = r[-k * RW];
-        d0 += Wt.d1[k] * (p0 - m0);
-        d1 += Wt.d1[k] * (p1 - m1);
-        e0 += Wt.d2[k] * (p0 + m0);
-        e1 += Wt.d2[k] * (p1 + m1);
+        const T p0 = r[k], m0 = r[-k];
+        const T p1 = r[k * RW], m1 = r[-k * RW];
+        d0 += (T)Wt.d1[k] * (p0 - m0);
+        d1 += (T)Wt.d1[k] * (p1 - m1);
+        e0 += (T)Wt.d2[k] * (p0 + m0);
+        e1 += (T)Wt.d2[k] * (p1 + m1);
       }
-      const double w0 = Wt.d2[0];
-      const double dd0 = e0 + w0 * uc, dd1 = e1 + w0 * uc, dd2 = e2[j] + w0 * uc;
-      const double lap = f[0] * dd0 + f[1] * dd1 + f[2] * dd2 + f[3] * d0 + f[4] * d1;
-      const double ku = sv[j] - a.eta * uc;
-      const double kv = f[5] * (lap + src[j]);
+      const T w0 = (T)Wt.d2[0];
+      const T dd0 = e0 + w0 * uc, dd1 = e1 + w0 * uc, dd2 = e2[j] + w0 * uc;
+      const T lap = f[0] * dd0 + f[1] * dd1 + f[2] * dd2 + f[3] * d0 + f[4] * d1;
+      T ku, kv;
+      if constexpr (CORR) {
+        ku = hu[j] + (sv[j] - a.eta * uc);
+        kv = hv[j] + f[5] * (lap + src[j]);
+      } else {
+        ku = sv[j] - a.eta * uc;
+        kv = f[5] * (lap + src[j]);
+      }
       if (stage == 0) {
         au[j] = uc + ca * ku;
         av[j] = sv[j] + ca * kv;
@@ -317,10 +338,14 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
     for (int q = 0; q < NQ; ++q) {
       if (!oval[q]) continue;
       // radiation condition with a one-sided xx0 derivative
-      const double u0 = ut[otl[q]], u1 = ut[otl[q] - 1], u2 = ut[otl[q] - 2];
-      const double v0 = osv[q], v1 = vt[ovl[q] - 1], v2 = vt[ovl[q] - 2];
-      const double kuo = -oc[q] * (u0 * ori[q] + (3.0 * u0 - 4.0 * u1 + u2) * oqd[q]);
-      const double kvo = -oc[q] * (v0 * ori[q] + (3.0 * v0 - 4.0 * v1 + v2) * oqd[q]);
+      const T u0 = ut[otl[q]], u1 = ut[otl[q] - 1], u2 = ut[otl[q] - 2];
+      const T v0 = osv[q], v1 = vt[ovl[q] - 1], v2 = vt[ovl[q] - 2];
+      T kuo = -oc[q] * (u0 * ori[q] + ((T)3 * u0 - (T)4 * u1 + u2) * oqd[q]);
+      T kvo = -oc[q] * (v0 * ori[q] + ((T)3 * v0 - (T)4 * v1 + v2) * oqd[q]);
+      if constexpr (CORR) {
+        kuo = ohu[q] + kuo;
+        kvo = ohv[q] + kvo;
+      }
       if (stage == 0) {
         oau[q] = u0 + ca * kuo;
         oav[q] = v0 + ca * kvo;
@@ -341,7 +366,7 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgs a) {
 
     if (e < nst) {
       // publish the next stage input u, then raise this block's counter
-      double* dst = (e & 1) ? a.x1 : a.x0;
+      T* dst = (e & 1) ? a.x1 : a.x0;
 #pragma unroll
       for (int j = 0; j < NPT; ++j)
         if (grp + PG * j < N2) xstore(dst + gidx[j], su[j]);
@@ -376,36 +401,63 @@ struct ResShape {
   int threads;
 };
 
-template <int NG>
+template <typename T, int NG, bool CORR>
 ResShape shape_for(int N2) {
-  if (N2 <= 4) return {(const void*)k_resident<NG, 1, 256>, 256};
-  if (N2 <= 8) return {(const void*)k_resident<NG, 1, 512>, 512};
-  if (N2 <= 16) return {(const void*)k_resident<NG, 1, 1024>, 1024};
+  if (N2 <= 4) return {(const void*)k_resident<T, NG, 1, 256, CORR>, 256};
+  if (N2 <= 8) return {(const void*)k_resident<T, NG, 1, 512, CORR>, 512};
+  if (N2 <= 16) return {(const void*)k_resident<T, NG, 1, 1024, CORR>, 1024};
   return {nullptr, 0};
 }
 
+template <typename T, bool CORR>
 ResShape resident_kernel(int order, int N2) {
   switch (order) {
-    case 8: return shape_for<4>(N2);
-    case 10: return shape_for<5>(N2);
+    case 8: return shape_for<T, 4, CORR>(N2);
+    case 10: return shape_for<T, 5, CORR>(N2);
     default: return {nullptr, 0};
   }
 }
 
+template <typename T, bool CORR>
+hipError_t launch_resident_t(int order, const ResidentArgsT<T>& a, hipStream_t s, hipEvent_t t0,
+                             hipEvent_t t1) {
+  const ResShape rs = resident_kernel<T, CORR>(order, a.d.N2);
+  const void* k = rs.kernel;
+  if (!k) return hipErrorInvalidValue;
+  const int nb = a.nbx * a.nby;
+  if (nb <= 0 || nb > kResMaxBlocks || a.nsteps <= 0) return hipErrorInvalidValue;
+  const int nflags = nb * kResFlagStride;
+  k_zero_u32<<<(nflags + 255) / 256, 256, 0, s>>>(a.flags, nflags);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t lds = resident_lds_bytes(a.d, sizeof(T));
+  e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  ResidentArgsT<T> arg = a;
+  void* args[] = {&arg};
+  // The caller has checked that every block fits at once (one per compute unit,
+  // resident_capacity); the blocks synchronise only through their bounded
+  // counter waits, so a plain launch suffices. If the device were shared and a
+  // block could not start, its partners' waits would time out (err) instead
+  // of hanging.
+  return hipExtLaunchKernel(k, dim3(nb), dim3(rs.threads), args, lds, s, t0, t1, 0);
+}
+
 }  // namespace
 
-size_t resident_lds_bytes(const Dims& d) {
+size_t resident_lds_bytes(const Dims& d, size_t elem) {
   const int RH = RB + 2 * d.NG, RW = tile_row(RH), VW = tile_row(RB + d.NG);
-  const size_t need = (size_t)d.N2 * (RW * RH + RB * VW) * sizeof(double);
+  const size_t need = (size_t)d.N2 * (RW * RH + RB * VW) * elem;
   // more than half of the 160 KiB of LDS per compute unit: one block per CU
   return std::max<size_t>(need, 82 * 1024);
 }
 
-int resident_capacity(int order, const Dims& d) {
-  const ResShape rs = resident_kernel(order, d.N2);
+int resident_capacity(int order, const Dims& d, bool split) {
+  const ResShape rs = split ? resident_kernel<float, true>(order, d.N2)
+                            : resident_kernel<double, false>(order, d.N2);
   const void* k = rs.kernel;
   if (!k) return 0;
-  const size_t lds = resident_lds_bytes(d);
+  const size_t lds = resident_lds_bytes(d, split ? sizeof(float) : sizeof(double));
   if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return 0;
   int per = 0, dev = 0, cus = 0;
@@ -417,28 +469,14 @@ int resident_capacity(int order, const Dims& d) {
   return per * cus;
 }
 
-hipError_t launch_resident(int order, const ResidentArgs& a, hipStream_t s, hipEvent_t t0,
-                           hipEvent_t t1) {
-  const ResShape rs = resident_kernel(order, a.d.N2);
-  const void* k = rs.kernel;
-  if (!k) return hipErrorInvalidValue;
-  const int nb = a.nbx * a.nby;
-  if (nb <= 0 || nb > kResMaxBlocks || a.nsteps <= 0) return hipErrorInvalidValue;
-  const int nflags = nb * kResFlagStride;
-  k_zero_u32<<<(nflags + 255) / 256, 256, 0, s>>>(a.flags, nflags);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const size_t lds = resident_lds_bytes(a.d);
-  e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  ResidentArgs arg = a;
-  void* args[] = {&arg};
-  // The caller has checked that every block fits at once (one per compute unit,
-  // resident_capacity); the blocks synchronise only through their bounded
-  // counter waits, so a plain launch suffices. If the device were shared and a
-  // block could not start, its partners' waits would time out (err) instead
-  // of hanging.
-  return hipExtLaunchKernel(k, dim3(nb), dim3(rs.threads), args, lds, s, t0, t1, 0);
+hipError_t launch_resident(int order, const ResidentArgsT<double>& a, hipStream_t s,
+                           hipEvent_t t0, hipEvent_t t1) {
+  return launch_resident_t<double, false>(order, a, s, t0, t1);
+}
+
+hipError_t launch_resident(int order, const ResidentArgsT<float>& a, hipStream_t s,
+                           hipEvent_t t0, hipEvent_t t1) {
+  return launch_resident_t<float, true>(order, a, s, t0, t1);
 }
 
 }  // namespace hr

@@ -1,5 +1,6 @@
 // Device helpers shared by the stage kernels: centred finite-difference
-// weights and the phi + pi plane map of the inner-boundary images.
+// weights, the split-state source difference and the phi + pi plane map of
+// the inner-boundary images.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -45,6 +46,12 @@ struct Weights {
     }
   }
 };
+
+// Source difference of the split-state form: S p^-7 [(1 + x)^-7 - 1], x = e/p,
+// evaluated without cancellation for small increments.
+__device__ __forceinline__ float source_delta(float sp7, float pb, float e) {
+  return sp7 * expm1f(-7.0f * log1pf(e / pb));
+}
 
 // Plane index of phi + pi (N2 even).
 __device__ __forceinline__ int half_turn(int i2, int N2) {

@@ -114,3 +114,41 @@ def test_resident_stage_timing_keeps_trajectory():
     h.set_punctures(*w.punctures.as_tuple())
     h.relax(w.eta, 1.0, 0.0, 100, 0.0, check_every=100)
     assert rel_maxdiff(g.get_u(extended=True), h.get_u(extended=True)) <= 1e-13
+
+
+@pytest.mark.parametrize("spec", [CASES[0][0], CASES[2][0], CASES[3][0]])
+def test_resident_split_form_matches_plane_split_form(spec):
+    """The split-state single-precision form (FP32 increment on the FP64 base)
+    on the resident kernel against the same form on plane tiles, 300 steps from
+    rest with the FP32 phase held: the same FP32 arithmetic per point, rounded
+    in a different order, so the two may differ by single-precision rounding of
+    the increments (large here: from rest an interval's increment is most of u),
+    but the resident form is no further from the FP64 oracle than the plane
+    form (within a factor 2) and the two differ by at most twice that
+    distance. Near convergence, where the increments are small, the split form
+    meets the FP64 solution to 1e-8 (test_gpu_precision)."""
+    banner(f"resident split form {spec.name()}")
+    og = oracle_grid(spec)
+    dt = og.suggest_dt(0.5)
+    out = []
+    for variant in (3, 1):
+        g = gpu_grid(spec)
+        g.set_kernel_config(variant=variant)
+        g.set_fp32_switch(0.0, 1000000, 0)   # stay in the FP32 phase
+        g.set_punctures(*_punctures(spec).as_tuple())
+        r = g.relax(6.0, 1.0, dt, 300, 0.0, check_every=100, precision=hr.FP32_FP64FINISH)
+        assert r.status == hr.OK and r.fp32_steps == 300
+        out.append((g.get_u(extended=True), r.history))
+    if spec.N0 == 128:
+        assert gpu_grid(spec).resolved_kernel(hr.FP32_FP64FINISH)["variant"] == 3
+    og.set_punctures(*_punctures(spec).as_tuple())
+    og.relax(6.0, 1.0, dt, 300, 0.0, 100)
+    ou, _ = og.state()
+    oe = oracle_extended(og, ou)
+    d = rel_maxdiff(out[0][0], out[1][0])
+    d_res = rel_maxdiff(out[0][0], oe)
+    d_pl = rel_maxdiff(out[1][0], oe)
+    banner(f"split resident vs split plane {d:.2e}; vs oracle: resident {d_res:.2e}, "
+           f"plane {d_pl:.2e}")
+    assert d_res <= 2 * d_pl + 1e-12
+    assert d <= 2 * d_pl + 1e-12
