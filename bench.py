@@ -264,31 +264,39 @@ def catalog_run(n: int, precision_s: str, autotune: bool, max_steps: int) -> int
     return 0
 
 
-def run_solve(hr, g, w, precision):
+def run_solve(hr, torch, g, w, precision, times=None):
+    """One solve: sources on the device (u = v = 0), then relaxation to tol.
+    With `times`, appends (sources seconds, relaxation seconds)."""
+    t0 = time.perf_counter()
     g.set_punctures(*w.punctures.as_tuple())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
     res = g.relax(w.eta, w.kappa, 0.0, w.n_steps, w.tol, check_every=w.check_every,
                   precision=precision)
+    torch.cuda.synchronize()
+    if times is not None:
+        times.append((t1 - t0, time.perf_counter() - t1))
     return res
 
 
 def timed_solves(hr, torch, g, w, precision, steps, warmup, label):
     for i in range(warmup):
-        r = run_solve(hr, g, w, precision)
+        r = run_solve(hr, torch, g, w, precision)
         log(f"{label} warmup {i}: status {r.status} steps {r.steps_taken} residual {r.residual:.3e}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    results = []
+    results, times = [], []
     for i in range(steps):
-        r = run_solve(hr, g, w, precision)
+        r = run_solve(hr, torch, g, w, precision, times)
         results.append(r)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for i, r in enumerate(results):
         log(f"{label} solve {i}: status {r.status} rk4 steps {r.steps_taken} "
-            f"(fp32 {r.fp32_steps}) residual {r.residual:.3e}")
+            f"(fp32 {r.fp32_steps}) residual {r.residual:.3e} ({times[i][1] * 1e3:.2f} ms)")
         if r.status != hr.OK:
             raise RuntimeError(f"{label} solve did not converge: status {r.status}")
-    return results, t1 - t0
+    return results, t1 - t0, times
 
 
 def cpu_baseline(w, budget_s: float):
@@ -311,11 +319,21 @@ def cpu_baseline(w, budget_s: float):
     og.rk4_steps(w.eta, w.kappa, dt, n)
     el = time.perf_counter() - t0
     upd = spec.n_interior * 4 * n / el
-    return {"value": upd, "unit": "grid-pt RHS updates/s", "cores": oracle.num_threads(),
+    cores = oracle.num_threads()
+    # the same on one thread (fewer steps: about a third of the budget)
+    oracle.set_num_threads(1)
+    n1 = max(1, int(budget_s / 3 / max(per_step * cores, 1e-6)))
+    t0 = time.perf_counter()
+    og.rk4_steps(w.eta, w.kappa, dt, n1)
+    el1 = time.perf_counter() - t0
+    oracle.set_num_threads(cores)
+    return {"value": upd, "unit": "grid-pt RHS updates/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{n} RK4 steps of {spec.name()} from rest ({el:.1f} s); "
                       f"time to residual 1e-10 extrapolates as steps_to_tol / "
-                      f"{n / el:.2f} steps/s"}
+                      f"{n / el:.2f} steps/s",
+            "value_1_thread": spec.n_interior * 4 * n1 / el1,
+            "sample_1_thread": f"{n1} RK4 steps, same grid, 1 thread ({el1:.1f} s)"}
 
 
 def main() -> int:
@@ -363,12 +381,17 @@ def main() -> int:
     w = workloads.paper_scale(workloads.SINHSYMTP, 10)
     spec = w.grid
     log(f"workload {w.label}: eta {w.eta} cfl {w.cfl} tol {w.tol} check every {w.check_every}")
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter()
     g = hr.grid_create(spec.coords, spec.N0, spec.N1, spec.N2, spec.fd_order,
                        params=hr.default_params(amax=spec.amax, sinhwaa=spec.sinhwaa,
                                                 bscale=spec.bscale, rmax=spec.rmax))
+    g.set_punctures(*w.punctures.as_tuple())
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_setup   # host tables, device workspace, sources
     if args.variant:
         g.set_kernel_config(variant=args.variant)
-    res64, t64 = timed_solves(hr, torch, g, w, hr.FP64, args.steps, args.warmup, "fp64")
+    res64, t64, tm64 = timed_solves(hr, torch, g, w, hr.FP64, args.steps, args.warmup, "fp64")
     steps64 = res64[-1].steps_taken
     upd64 = sum(spec.n_interior * 4 * r.steps_taken for r in res64) / t64
     u64 = g.get_u()
@@ -393,18 +416,29 @@ def main() -> int:
             "tol": w.tol, "check_every": w.check_every,
         },
         "time_to_residual_s": t64 / args.steps,
+        "time_to_residual": {
+            "relax_median_s": float(np.median([t[1] for t in tm64])),
+            "relax_per_solve_s": [t[1] for t in tm64],
+            "sources_median_s": float(np.median([t[0] for t in tm64])),
+            "first_setup_s": setup_s,
+            "note": "relax = setup excluded; + sources = the timed step; first_setup = grid "
+                    "creation, host tables, workspace allocation and binding, sources (once)",
+        },
         "rk4_steps_to_tol": steps64,
         "final_residual": res64[-1].residual,
+        "kernel": g.resolved_kernel(hr.FP64),
     }
     if not args.no_mixed:
         g.set_fp32_switch(0.0, 8, 0)  # FP64 finish below 10 x tol
-        res32, t32 = timed_solves(hr, torch, g, w, hr.FP32_FP64FINISH, args.steps, 0, "fp32+fp64")
+        res32, t32, tm32 = timed_solves(hr, torch, g, w, hr.FP32_FP64FINISH, args.steps, 0,
+                                        "fp32+fp64")
         u32 = g.get_u()
         out["mixed"] = {
             "precision": "FP32 bulk (split state: FP64 base + FP32 increment, FP64 slopes, "
                          "rebase and residual every check) + plain FP64 finish below 10 x tol",
             "value": sum(spec.n_interior * 4 * r.steps_taken for r in res32) / t32,
             "time_to_residual_s": t32 / args.steps,
+            "relax_median_s": float(np.median([t[1] for t in tm32])),
             "rk4_steps_to_tol": res32[-1].steps_taken,
             "fp32_steps": res32[-1].fp32_steps,
             "final_residual": res32[-1].residual,

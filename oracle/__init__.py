@@ -100,6 +100,8 @@ def lib():
                                ctypes.c_long, ctypes.c_double, ctypes.c_long, _dp, ctypes.c_long,
                                _lp, _lp]
         L.or_num_threads.restype = ctypes.c_int
+        L.or_set_num_threads.argtypes = [ctypes.c_int]
+        L.or_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -303,3 +305,8 @@ class OracleGrid:
 
 def num_threads() -> int:
     return lib().or_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Thread count of the oracle's OpenMP loops (for timing it on one core)."""
+    lib().or_set_num_threads(int(n))

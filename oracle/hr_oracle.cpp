@@ -732,5 +732,6 @@ int or_relax(void* h, double eta, double kappa, double dt, long n_steps,
 }
 
 int or_num_threads(void) { return omp_get_max_threads(); }
+void or_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 
 }  // extern "C"
