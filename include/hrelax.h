@@ -243,6 +243,17 @@ hr_status hr_set_kernel_config(hr_grid* g, const hr_kernel_config* cfg);
 hr_status hr_get_kernel_config(const hr_grid* g, hr_kernel_config* cfg);
 
 /*
+ * Bound on the resident kernel's exchange waits: a block gives up after this
+ * many polls of one partner's stage counter (each poll is one memory round
+ * trip, ~1-2 us), sets an error word, and every block leaves its loop; the
+ * relaxing call then returns HR_EDEVICE and the grid's state is unspecified
+ * until it is set again (hr_set_punctures, hr_set_u/v). polls = 0 restores the
+ * default, 2^19 (about a second). Small values force the timeout path.
+ * Errors: HR_EINVAL.
+ */
+hr_status hr_set_wait_limit(hr_grid* g, unsigned polls);
+
+/*
  * The configuration the relaxation actually runs for precision prec, with the
  * automatic choices resolved (variant 0 becomes 3 where the resident kernel
  * applies and prec is HR_FP64 or HR_FP32_FP64FINISH, else 2 or 1 by size;

@@ -96,6 +96,7 @@ _SIGNATURES = {
     "hr_get_kernel_config": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KernelConfig)]),
     "hr_resolved_kernel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
                                           ctypes.POINTER(KernelConfig)]),
+    "hr_set_wait_limit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint]),
     "hr_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                    ctypes.POINTER(KernelConfig), _dp]),
     "hr_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
@@ -307,6 +308,11 @@ class Grid:
                                           ctypes.byref(us)), "hr_autotune")
         return {"variant": cfg.variant, "streaming": cfg.streaming, "chunk": cfg.chunk,
                 "graph": cfg.graph}, us.value
+
+    def set_wait_limit(self, polls: int = 0) -> None:
+        """Polls of one partner's counter before a resident-kernel wait gives up
+        (0: the default, about a second); small values force the timeout path."""
+        _check(load_library().hr_set_wait_limit(self._h, int(polls)), "hr_set_wait_limit")
 
     def resolved_kernel(self, precision: int = FP64) -> dict:
         """The configuration the relaxation runs in this precision, automatic

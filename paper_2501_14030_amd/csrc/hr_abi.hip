@@ -179,7 +179,7 @@ ResidentArgs resident_args(hr_grid* g, double eta, double dt, int nsteps) {
   r.nbx = g->res_nbx;
   r.nby = g->res_nby;
   r.nsteps = nsteps;
-  r.spin_limit = 1u << 19;
+  r.spin_limit = g->res_wait_limit;
   return r;
 }
 
@@ -208,7 +208,7 @@ ResidentArgsT<float> resident_args_split(hr_grid* g, float eta, float dt, int ns
   r.nbx = g->res_nbx;
   r.nby = g->res_nby;
   r.nsteps = nsteps;
-  r.spin_limit = 1u << 19;
+  r.spin_limit = g->res_wait_limit;
   return r;
 }
 
@@ -950,6 +950,12 @@ hr_status hr_resolved_kernel(const hr_grid* g, hr_precision prec, hr_kernel_conf
   cfg->chunk = variant == 2 ? chunk : 0;
   cfg->streaming = g->streaming > 0 ? 1 : 0;
   cfg->graph = (variant == 3 || g->graph == 0) ? 0 : 1;
+  return HR_OK;
+}
+
+hr_status hr_set_wait_limit(hr_grid* g, unsigned polls) {
+  if (!g) return fail(HR_EINVAL, "null grid handle");
+  g->res_wait_limit = polls ? polls : (1u << 19);
   return HR_OK;
 }
 

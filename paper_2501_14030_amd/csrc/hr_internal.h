@@ -281,6 +281,7 @@ struct hr_grid {
   int res_nbx = 0, res_nby = 0; // resident patches (0: grid not eligible)
   int res_capacity = 0;         // co-resident blocks the device allows for it (FP64)
   int res_capacity32 = 0;       // the same for the split-state FP32 form
+  unsigned res_wait_limit = 1u << 19;  // polls of one partner counter before giving up
   std::vector<int> res_plan;    // exchange partners (host copy, uploaded at bind)
   unsigned* res_flags = nullptr;
   int* res_waits = nullptr;

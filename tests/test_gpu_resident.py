@@ -152,3 +152,28 @@ def test_resident_split_form_matches_plane_split_form(spec):
            f"plane {d_pl:.2e}")
     assert d_res <= 2 * d_pl + 1e-12
     assert d <= 2 * d_pl + 1e-12
+
+
+def test_resident_wait_timeout_is_reported_and_recoverable():
+    """A wait bound of one poll makes the exchange waits give up (a partner is
+    rarely done at the first poll); the kernel's blocks all leave their loops,
+    the call reports HR_EDEVICE instead of hanging, and the grid relaxes
+    normally once the bound is restored and the state is set again."""
+    w = workloads.paper_scale()
+    g = gpu_grid(w.grid)
+    g.set_kernel_config(variant=3)
+    g.set_punctures(*w.punctures.as_tuple())
+    g.set_wait_limit(1)
+    with pytest.raises(hr.HRError) as ei:
+        g.relax(w.eta, 1.0, 0.0, 200, 0.0, check_every=100)
+    assert ei.value.status == hr.EDEVICE
+    banner(f"forced wait timeout reported: {ei.value}")
+    g.set_wait_limit(0)
+    g.set_punctures(*w.punctures.as_tuple())
+    r = g.relax(w.eta, 1.0, 0.0, 200, 0.0, check_every=100)
+    h = gpu_grid(w.grid)
+    h.set_kernel_config(variant=1)
+    h.set_punctures(*w.punctures.as_tuple())
+    h.relax(w.eta, 1.0, 0.0, 200, 0.0, check_every=100)
+    assert r.status == hr.OK
+    assert rel_maxdiff(g.get_u(extended=True), h.get_u(extended=True)) <= 1e-13
