@@ -191,20 +191,24 @@ def copy_calibration() -> int:
     return 0
 
 
-def catalog_run(n: int, precision_s: str, autotune: bool, max_steps: int) -> int:
+def catalog_run(n: int, precision_s: str, autotune: bool, max_steps: int,
+                budget: int) -> int:
     """The seeded BBH catalog (q ~ U[1,10], D ~ U[6,20], |chi| ~ U[0,0.8] isotropic,
     grids drawn from 64x64x8, 128x128x16, 256x256x32) relaxed to the catalog
     tolerance of each shape (1e-10; 1e-9 at 256x256x32, whose FP64 residual
     floor is above 1e-10) by the batched path: one persistent launch per RK
-    stage over every grid still relaxing, graph-captured per check interval;
+    stage over every grid still relaxing in its group, graph-captured per check
+    interval; groups sized to the Infinity Cache (budget bytes, 0: one group);
     eta per grid from its dt."""
     import torch
 
     import paper_2501_14030_amd as hr
-    from paper_2501_14030_amd import warmstart, workloads
+    from paper_2501_14030_amd import catalog, warmstart, workloads
 
     torch.cuda.set_device(0)
     prec = hr.FP64 if precision_s == "fp64" else hr.FP32_FP64FINISH
+    if budget <= 0:
+        budget = 1 << 62
     ws = workloads.catalog(n, seed=14030)
     grids = [warmstart.make_grids([w], w.grid.shape)[0] for w in ws]
     tuned = {}
@@ -217,32 +221,10 @@ def catalog_run(n: int, precision_s: str, autotune: bool, max_steps: int) -> int
                 g.set_kernel_config(**tuned[key][0])
     etas = [workloads.eta_for_dt(g.suggest_dt(0.5)) for g in grids]
     tols = [workloads.catalog_tol(g.N) for g in grids]
-    # relaxed in chunks of `chunk` steps (one batched call per tolerance group) so
-    # that progress is visible; a grid leaves the batch at its first check below
-    # its tolerance
-    chunk = 5000
-    steps = [0] * len(grids)
-    resid = [float("inf")] * len(grids)
-    active = list(range(len(grids)))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    while active and max(steps[i] for i in active) < max_steps:
-        nxt = []
-        for tol in sorted(set(tols[i] for i in active)):
-            group = [i for i in active if tols[i] == tol]
-            b = hr.Batch([grids[i] for i in group])
-            res = b.relax([etas[i] for i in group], 1.0, n_steps=chunk, tol=tol,
-                          check_every=100, precision=prec, raise_on_error=False)
-            b.close()
-            for i, r in zip(group, res):
-                steps[i] += r.steps_taken
-                resid[i] = r.residual
-                if not (r.residual < tol) and np.isfinite(r.residual):
-                    nxt.append(i)
-        active = sorted(nxt)
-        log(f"catalog: {len(grids) - len(active)}/{len(grids)} converged after "
-            f"{time.perf_counter() - t0:.1f} s; still relaxing: "
-            f"{sorted(set('x'.join(map(str, grids[i].N)) for i in active))}")
+    steps, resid = catalog.relax_catalog(grids, etas, tols, prec, max_steps=max_steps,
+                                         budget=budget, log=log)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     upd = sum(g.n_interior * 4 * st for g, st in zip(grids, steps))
@@ -258,6 +240,8 @@ def catalog_run(n: int, precision_s: str, autotune: bool, max_steps: int) -> int
         e["max_steps"] = int(np.max(e.pop("steps")))
     print(json.dumps({"catalog_configs": n, "precision": precision_s, "converged": conv,
                       "wall_s": el, "grid_point_rhs_updates_per_s": upd / el,
+                      "groups": len(catalog.cache_groups(grids, prec, budget)),
+                      "cache_budget_bytes": budget,
                       "by_shape": by_shape,
                       "autotuned": {"x".join(map(str, k)): v[0] for k, v in tuned.items()}}),
           flush=True)
@@ -353,12 +337,15 @@ def main() -> int:
                     help="relax the seeded N-configuration catalog with the batched path")
     ap.add_argument("--catalog-prec", default="fp64", choices=["fp64", "split"])
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--cache-budget", type=int, default=200 << 20,
+                    help="catalog: per-stage working set of one batch (bytes; 0 = one batch)")
     ap.add_argument("--max-steps", type=int, default=60000)
     ap.add_argument("--variant", type=int, default=0,
                     help="stage kernel variant (0 automatic, 1 plane, 2 columns, 3 resident)")
     args = ap.parse_args()
     if args.catalog:
-        return catalog_run(args.catalog, args.catalog_prec, args.autotune, args.max_steps)
+        return catalog_run(args.catalog, args.catalog_prec, args.autotune, args.max_steps,
+                           args.cache_budget)
     if args.kernel_profile:
         return kernel_profile(args.kernel_profile, args.prec, args.variant)
     if args.copy_calibration:

@@ -63,6 +63,33 @@ __device__ __forceinline__ void st(T* p, T v) {
   else *p = v;
 }
 
+// XCD-aware tile order for the phi-column kernel. The hardware hands block b of
+// a launch to XCD b mod 8, and each XCD has its own L2. Block b is given tile
+// number (b mod 8) * (T / 8) + b / 8 (T tiles, remainder spread over the first
+// XCDs), so that every XCD works through a contiguous run of tiles, x0
+// fastest: the rim rows a tile shares with its x0 and x1 neighbours were most
+// likely just loaded into the same L2 (512x512x64 FP64: 414 -> 353 us per
+// stage).
+constexpr int kXcds = 8;
+
+struct TileId {
+  int x, y, z;
+};
+
+__device__ __forceinline__ TileId xcd_tile() {
+  const unsigned gx = gridDim.x, gy = gridDim.y;
+  const unsigned n = gx * gy * gridDim.z;
+  const unsigned b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const unsigned per = n / kXcds, rem = n % kXcds;
+  const unsigned x = b % kXcds, k = b / kXcds;
+  const unsigned t = x * per + (x < rem ? x : rem) + k;
+  TileId id;
+  id.x = (int)(t % gx);
+  id.y = (int)((t / gx) % gy);
+  id.z = (int)(t / (gx * gy));
+  return id;
+}
+
 // Stage the rim-extended patch of plane i2 of field U into tile (type C).
 template <int NG, typename C, typename S>
 __device__ __forceinline__ void load_tile(C* __restrict__ tile, const S* __restrict__ U,
@@ -209,6 +236,9 @@ __global__ void __launch_bounds__(kTileThreads) k_stage(StageArgs<T> a) {
   constexpr int W = TileShape<NG>::W, H = TileShape<NG>::H;
   __shared__ T tile[W * H];
   const Dims& d = a.d;
+  // hardware block order: the blocks of one (x0, x1) tile at every plane share
+  // an XCD (gridDim.x * gridDim.y is a multiple of 8 for the shapes where this
+  // matters), so the phi taps of neighbouring planes hit the same L2
   const int x0b = blockIdx.x * TX, x1b = blockIdx.y * TY, i2 = blockIdx.z;
   const int i0 = x0b + threadIdx.x, i1 = x1b + threadIdx.y;
   const bool active = i0 < d.N0 && i1 < d.N1;
@@ -486,7 +516,8 @@ __device__ __forceinline__ void stage_col_body(const StageArgs<T>& a, int bx, in
 template <typename T, int NG, int STAGE, bool CORR>
 __global__ void __launch_bounds__(kTileThreads, 4) k_stage_col(StageArgs<T> a, int chunk) {
   __shared__ T tile[2][TileShape<NG>::W * TileShape<NG>::H];
-  stage_col_body<T, NG, STAGE, CORR>(a, blockIdx.x, blockIdx.y, blockIdx.z, chunk, tile);
+  const TileId tid = xcd_tile();
+  stage_col_body<T, NG, STAGE, CORR>(a, tid.x, tid.y, tid.z, chunk, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -502,10 +533,25 @@ __global__ void __launch_bounds__(kTileThreads, 4)
                   const int* __restrict__ nitems) {
   __shared__ T tile[2][TileShape<NG>::W * TileShape<NG>::H];
   const int n = *nitems;
-  for (int it = blockIdx.x; it < n; it += gridDim.x) {
-    const int4 w = items[it];
-    const StageArgs<T> a = descs[4 * w.x + (STAGE - 1)];
-    stage_col_body<T, NG, STAGE, CORR>(a, w.y, w.z, w.w, a.chunk, tile);
+  const int G = gridDim.x;
+  if (G % kXcds == 0) {
+    // XCD-aware walk: the blocks on XCD x (b mod 8 == x) share the contiguous
+    // run x of the list (items are grid-major, x0 tile fastest), so tiles and
+    // their neighbours meet in one L2
+    const int x = blockIdx.x % kXcds, k = blockIdx.x / kXcds, gk = G / kXcds;
+    const int per = n / kXcds, rem = n % kXcds;
+    const int lo = x * per + (x < rem ? x : rem), hi = lo + per + (x < rem ? 1 : 0);
+    for (int it = lo + k; it < hi; it += gk) {
+      const int4 w = items[it];
+      const StageArgs<T> a = descs[4 * w.x + (STAGE - 1)];
+      stage_col_body<T, NG, STAGE, CORR>(a, w.y, w.z, w.w, a.chunk, tile);
+    }
+  } else {
+    for (int it = blockIdx.x; it < n; it += G) {
+      const int4 w = items[it];
+      const StageArgs<T> a = descs[4 * w.x + (STAGE - 1)];
+      stage_col_body<T, NG, STAGE, CORR>(a, w.y, w.z, w.w, a.chunk, tile);
+    }
   }
 }
 
