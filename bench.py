@@ -68,27 +68,30 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def stage_bytes_per_point(itemsize: int):
+def stage_bytes_per_point(itemsize: int, split: bool = False):
     """Algorithmic bytes per point of the four fused stage kernels.
 
     interior point: stage 1 reads u, v, psi, S_src and writes Y2(u,v), acc(u,v);
     stages 2, 3 read Y(u,v), y_n(u,v), acc(u,v), psi, S_src and write Y(u,v),
     acc(u,v); stage 4 reads Y4(u,v), acc(u,v), psi, S_src and writes y_{n+1}(u,v).
-    outer point: the same without psi and S_src.
+    outer point: the same without psi and S_src. The split-state form's
+    increment stages also read the base slopes k(y_b) (two values; p_b and
+    S_src p_b^-7 take the places of psi and S_src).
     """
-    interior = [8, 12, 12, 8]
-    outer = [6, 10, 10, 6]
+    extra = 2 if split else 0
+    interior = [8 + extra, 12 + extra, 12 + extra, 8 + extra]
+    outer = [6 + extra, 10 + extra, 10 + extra, 6 + extra]
     return [itemsize * n for n in interior], [itemsize * n for n in outer]
 
 
-def stage_algorithmic_bytes(spec, itemsize: int):
+def stage_algorithmic_bytes(spec, itemsize: int, split: bool = False):
     """Per-launch algorithmic bytes of each stage kernel (grid functions plus the
     2D coefficient tables, each read once)."""
     N0, N1, N2 = spec.shape
     ng = spec.fd_order // 2
     nint = N0 * N1 * N2
     nout = ng * N1 * N2
-    bi, bo = stage_bytes_per_point(itemsize)
+    bi, bo = stage_bytes_per_point(itemsize, split)
     tables = itemsize * (6 * N0 * N1 + 3 * ng * N1)
     return [nint * bi[s] + nout * bo[s] + tables for s in range(4)]
 
@@ -107,17 +110,20 @@ def roofline_entry(g, hr, spec, w, prec, nsteps=20):
     must move when the state lives in HBM (the resident kernel keeps it on chip,
     so its rate may exceed what HBM alone would allow)."""
     item = 8 if prec == hr.FP64 else 4
+    split = prec == hr.FP32_FP64FINISH
     cfg = g.resolved_kernel(prec)
     if cfg["variant"] == 3:
         nsteps = w.check_every   # the launch length the relaxation itself uses
     us = g.time_stage_kernels(w.eta, w.kappa, 0.0, nsteps, prec)
-    byts = stage_algorithmic_bytes(spec, item)
+    byts = stage_algorithmic_bytes(spec, item, split)
     agg = sum(byts) / (sum(us[:4]) * 1e-6) / 1e9
-    tr = measured_traffic(spec.shape, "fp64" if prec == hr.FP64 else "fp32", cfg["variant"])
+    pname = "FP64" if prec == hr.FP64 else ("FP32 split-state increment" if split else "FP32")
+    tr = None if split else measured_traffic(spec.shape, "fp64" if prec == hr.FP64 else "fp32",
+                                             cfg["variant"])
     out = {
         "bound": "hbm", "achieved": agg, "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": agg / HBM_PEAK_GBS, "traffic": tr,
-        "kernel": f"{VARIANT_NAMES[cfg['variant']]} ({'FP64' if prec == hr.FP64 else 'FP32'}, "
+        "kernel": f"{VARIANT_NAMES[cfg['variant']]} ({pname}, "
                   f"order {spec.fd_order}, {spec.N0}x{spec.N1}x{spec.N2}, config {cfg}), "
                   f"mean over stages 1-4",
         "avg_stage_us": [float(x) for x in us[:4]],
@@ -437,7 +443,8 @@ def main() -> int:
     copy = copy_bandwidth(torch)
     out["roofline"] = roofline_entry(g, hr, spec, w, hr.FP64)
     out["roofline_fp32"] = roofline_entry(g, hr, spec, w, hr.FP32)
-    for k in ("roofline", "roofline_fp32"):
+    out["roofline_split"] = roofline_entry(g, hr, spec, w, hr.FP32_FP64FINISH)
+    for k in ("roofline", "roofline_fp32", "roofline_split"):
         out[k]["copy_gbs"] = copy
         out[k]["frac_of_copy"] = out[k]["achieved"] / copy
     if not args.no_large:

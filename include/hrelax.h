@@ -279,7 +279,9 @@ hr_status hr_autotune(hr_grid* g, hr_precision prec, int n_steps, hr_kernel_conf
 
 /*
  * Measurement: runs n_steps RK4 steps of the current state in precision prec
- * (HR_FP64 or HR_FP32), bracketing every stage-kernel launch with hipEvents
+ * (HR_FP64, HR_FP32, or HR_FP32_FP64FINISH: the split form's FP32 increment
+ * steps after one FP64 base evaluation, added into the base at the end),
+ * bracketing every stage-kernel launch with hipEvents
  * recorded on the grid's stream, and returns in avg_us[0..3] the mean duration
  * of the stage-1..4 kernels in microseconds (avg_us[4]: mean over all four).
  * With the resident variant (FP64) the n_steps (at most 100000) run in one

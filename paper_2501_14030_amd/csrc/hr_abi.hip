@@ -865,7 +865,8 @@ hr_status hr_time_stage_kernels(hr_grid* g, double eta, double c, double dt, lon
   if (st != HR_OK) return st;
   if (!avg_us || n_steps <= 0 || !(eta > 0) || !(c > 0))
     return fail(HR_EINVAL, "need avg_us, n_steps > 0, eta > 0, c > 0");
-  if (prec != HR_FP64 && prec != HR_FP32) return fail(HR_EINVAL, "prec must be FP64 or FP32");
+  if (prec != HR_FP64 && prec != HR_FP32 && prec != HR_FP32_FP64FINISH)
+    return fail(HR_EINVAL, "unknown precision");
   if (dt <= 0) dt = g->prm.cfl * g->tab.ds_g;
   HR_HIP(hipSetDevice(g->device));
   st = load_kappa(g, c);
@@ -875,6 +876,43 @@ hr_status hr_time_stage_kernels(hr_grid* g, double eta, double c, double dt, lon
   HR_HIP(hipEventCreate(&e1));
   double sum[4] = {0, 0, 0, 0};
   const int G = (int)g->G;
+  if (prec == HR_FP32_FP64FINISH) {
+    // the split form's increment steps: base slopes, timed FP32 steps, rebase
+    HR_HIP(launch_base(g->fd_order, base_args(g, eta), g->stream));
+    const float fe = (float)eta, fd = (float)dt;
+    if (use_resident_split(g)) {
+      const int nrun = (int)std::min<long>(n_steps, 100000);
+      HR_HIP(launch_resident(g->fd_order, resident_args_split(g, fe, fd, nrun), g->stream, e0,
+                             e1));
+      HR_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HR_HIP(hipEventElapsedTime(&ms, e0, e1));
+      for (int s = 0; s < 4; ++s) sum[s] = ms * (double)n_steps / (4.0 * nrun);
+      st = check_resident(g);
+      if (st != HR_OK) return st;
+    } else {
+      for (long n = 0; n < n_steps; ++n)
+        for (int s = 1; s <= 4; ++s) {
+          HR_HIP(launch_stage(g->fd_order, s, stage_args<float>(g, g->f32, s, fe, fd, true),
+                              g->stream, e0, e1));
+          HR_HIP(hipEventSynchronize(e1));
+          float ms = 0.f;
+          HR_HIP(hipEventElapsedTime(&ms, e0, e1));
+          sum[s - 1] += ms;
+        }
+    }
+    HR_HIP(launch_rebase(g->f64.un, g->f64.vn, g->f32.un, g->f32.vn, G, g->stream));
+    HR_HIP(hipStreamSynchronize(g->stream));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    double tot = 0;
+    for (int s = 0; s < 4; ++s) {
+      avg_us[s] = 1e3 * sum[s] / n_steps;
+      tot += avg_us[s];
+    }
+    avg_us[4] = tot / 4;
+    return HR_OK;
+  }
   if (prec == HR_FP64 && use_resident(g)) {
     // one launch runs every stage: its duration is shared evenly
     const int nrun = (int)std::min<long>(n_steps, 100000);
