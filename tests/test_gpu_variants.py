@@ -1,7 +1,9 @@
-"""The two stage-kernel variants (plane tiles; phi-marching columns with a
+"""The stage-kernel variants (plane tiles; phi-marching columns with a
 register queue) and the cache-policy switch compute the same arithmetic in
 the same order: their trajectories must agree with each other (to a few
-roundoff units) and with the oracle, including ragged phi chunks."""
+roundoff units) and with the oracle, including ragged phi chunks. The
+automatic choice, the autotuner (which may pick the resident kernel, tested
+on its own in test_gpu_resident) and graph capture are checked here too."""
 import numpy as np
 import pytest
 
