@@ -455,9 +455,18 @@ hr_status run_interval(hr_grid* g, int kind, int K, double eta, double dt, doubl
   }
   HR_HIP(hipMemcpyAsync(g->host_res, g->result, sizeof(double), hipMemcpyDeviceToHost,
                         g->stream));
+  unsigned* err_word = reinterpret_cast<unsigned*>(g->host_res + 1);
+  if (resident)  // the error word rides along with the residual readback
+    HR_HIP(hipMemcpyAsync(err_word, g->res_err, sizeof(unsigned), hipMemcpyDeviceToHost,
+                          g->stream));
   HR_HIP(hipStreamSynchronize(g->stream));
   *res = g->host_res[0];
-  if (resident) return check_resident(g);
+  if (resident && *err_word) {
+    *err_word = 0;
+    HR_HIP(hipMemsetAsync(g->res_err, 0, sizeof(unsigned), g->stream));
+    HR_HIP(hipStreamSynchronize(g->stream));
+    return fail(HR_EDEVICE, "resident kernel: an exchange wait timed out");
+  }
   return HR_OK;
 }
 

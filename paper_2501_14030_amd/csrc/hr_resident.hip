@@ -212,12 +212,13 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
   for (int e = 1; e <= nst; ++e) {
     const int stage = (e - 1) & 3;
     // (1) stage input of the patch into LDS: own points and own outer points
-    // from registers, with v
+    // from registers; v only where the outer points' radiation condition
+    // reads it (the last two interior columns and the outer points)
 #pragma unroll
     for (int j = 0; j < NPT; ++j) {
       if (grp + PG * j < N2) {
         ut[lidx[j]] = su[j];
-        vt[vidx[j]] = sv[j];
+        if (last && x0l >= RB - 2) vt[vidx[j]] = sv[j];
       }
     }
 #pragma unroll
@@ -254,6 +255,7 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
       }
     }
     // (3) wait until every exchange partner has published the previous stage
+    // (one lane per partner; polling by every wave was measured slower)
     if (e > 1) {
       if (t < nw) {
         const unsigned* fl = a.flags + wt * kResFlagStride;
