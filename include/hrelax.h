@@ -52,8 +52,9 @@ typedef enum {
 } hr_status;
 
 typedef enum {
-  HR_SINHSYMTP = 0, /* prolate-spheroidal, sinh-stretched radial coordinate */
-  HR_SPHERICAL = 1  /* uniform r in [0, rmax], theta, phi */
+  HR_SINHSYMTP = 0,    /* prolate-spheroidal, sinh-stretched radial coordinate */
+  HR_SPHERICAL = 1,    /* uniform r in [0, rmax], theta, phi */
+  HR_SINHSPHERICAL = 2 /* r = amax sinh(xx0/w)/sinh(1/w), xx0 in [0,1], theta, phi */
 } hr_coords;
 
 typedef enum {
@@ -88,7 +89,7 @@ void hr_default_params(hr_grid_params* p);
 
 /*
  * Creates a grid (host side only; no device memory yet).
- *   coords   HR_SINHSYMTP or HR_SPHERICAL
+ *   coords   HR_SINHSYMTP, HR_SPHERICAL or HR_SINHSPHERICAL
  *   N0,N1,N2 interior points along xx0, xx1 (theta), xx2 (phi);
  *            N0 >= NG, N1 >= NG, N2 even and >= 2 (phi + pi parity images),
  *            total stored points below 2^31.

@@ -32,6 +32,9 @@
 //     z = sqrt(A^2+b^2) cos(xx1), A = AMAX sinh(xx0/w)/sinh(1/w), xx0 in [0,1];
 //     the two foci (0,0,+-b) carry the punctures;
 //   * Spherical: uniform r in [0,RMAX], theta in [0,pi], phi in [-pi,pi];
+//   * SinhSpherical (one of the further coordinate families the paper's
+//     conclusions list): r = A(xx0) with the same sinh stretching, xx0 in
+//     [0,1], theta, phi as for Spherical;
 //   * psi_singular = 1 + sum_n m_n / (2 r_n);
 //   * A^ij = sum_n 3/(2 r^2) [P^i n^j + P^j n^i - (delta^ij - n^i n^j) P.n]
 //              + 3/r^3 [(S x n)^i n^j + (S x n)^j n^i];
@@ -60,7 +63,7 @@ namespace {
 
 const double kPi = 3.14159265358979323846;
 
-enum { OR_SINHSYMTP = 0, OR_SPHERICAL = 1 };
+enum { OR_SINHSYMTP = 0, OR_SPHERICAL = 1, OR_SINHSPHERICAL = 2 };
 
 // Fornberg's algorithm (B. Fornberg, "Generation of finite difference formulas
 // on arbitrarily spaced grids", Math. Comp. 51 (1988) 699): weights c[j][k] of
@@ -140,7 +143,8 @@ struct Grid {
   }
 };
 
-// Radial map of SinhSymTP and its first two derivatives.
+// Sinh-stretched radial map A(xx0) (SinhSymTP's A, SinhSpherical's r) and its
+// first two derivatives.
 void sinh_radial(const Grid& g, double x0, double& A, double& Ap, double& App) {
   const double s1 = std::sinh(1.0 / g.w);
   A = g.amax * std::sinh(x0 / g.w) / s1;
@@ -159,14 +163,20 @@ void to_cart(const Grid& g, double x0, double x1, double x2, double& x,
     y = A * std::sin(x1) * std::sin(x2);
     z = R * std::cos(x1);
   } else {
-    x = x0 * std::sin(x1) * std::cos(x2);
-    y = x0 * std::sin(x1) * std::sin(x2);
-    z = x0 * std::cos(x1);
+    // spherical: r = xx0 (Spherical) or the sinh-stretched A(xx0) (SinhSpherical)
+    double r = x0;
+    if (g.coords == OR_SINHSPHERICAL) {
+      double Ap, App;
+      sinh_radial(g, x0, r, Ap, App);
+    }
+    x = r * std::sin(x1) * std::cos(x2);
+    y = r * std::sin(x1) * std::sin(x2);
+    z = r * std::cos(x1);
   }
 }
 
 // Scale factors h_i (proper length per unit coordinate) and Laplacian factors
-// at (x0, x1). The flat metric is diagonal in both coordinate systems, so
+// at (x0, x1). The flat metric is diagonal in all three coordinate systems, so
 // lap f = sum_i [ f,ii / h_i^2 + (1/J) d_i(J/h_i^2) f,i ],  J = h0 h1 h2.
 void metric_at(const Grid& g, double x0, double x1, double h[3], double* a,
                double* bb) {
@@ -187,6 +197,23 @@ void metric_at(const Grid& g, double x0, double x1, double h[3], double* a,
       bb[0] = (2.0 * A * A + g.b * g.b - A * R2 * App / (Ap * Ap)) / (A * Ap * S);
       // (1/J) d_1 (J/h1^2) with J/h1^2 = A A' sin(x1)/R
       bb[1] = c / (s * S);
+    }
+  } else if (g.coords == OR_SINHSPHERICAL) {
+    // r = A(xx0): h = (A', A, A sin x1), J = A' A^2 sin x1
+    double A, Ap, App;
+    sinh_radial(g, x0, A, Ap, App);
+    h[0] = Ap;
+    h[1] = A;
+    h[2] = A * s;
+    if (a) {
+      a[0] = 1.0 / (Ap * Ap);
+      a[1] = 1.0 / (A * A);
+      a[2] = 1.0 / (A * A * s * s);
+      // (1/J) d_0 (J/h0^2) with J/h0^2 = A^2 sin(x1)/A':
+      //   d_0 (A^2/A') = (2 A A'^2 - A^2 A'')/A'^2, divided by A' A^2
+      bb[0] = (2.0 * A * Ap * Ap - A * A * App) / (Ap * Ap * Ap * A * A);
+      // (1/J) d_1 (J/h1^2), J/h1^2 = A' sin(x1)
+      bb[1] = c / (s * A * A);
     }
   } else {
     const double r = x0;
@@ -210,7 +237,7 @@ long image_of(const Grid& g, int i0, int i1, int i2) {
   const int NG = g.NG, N1 = g.N[1], N2 = g.N[2];
   for (int guard = 0; guard < 8; ++guard) {
     if (i0 < NG) {
-      if (g.coords == OR_SPHERICAL) i1 = N1 + 2 * NG - 1 - i1;
+      if (g.coords != OR_SINHSYMTP) i1 = N1 + 2 * NG - 1 - i1;  // spherical: theta mirrors
       i0 = 2 * NG - 1 - i0;
       i2 += N2 / 2;
     } else if (i1 < NG) {
@@ -232,7 +259,7 @@ void build_grid(Grid& g) {
   g.NG = g.fd_order / 2;
   for (int d = 0; d < 3; ++d) g.Nx[d] = g.N[d] + 2 * g.NG;
   g.xxmin[0] = 0.0;
-  g.xxmax[0] = (g.coords == OR_SINHSYMTP) ? 1.0 : g.rmax;
+  g.xxmax[0] = (g.coords == OR_SPHERICAL) ? g.rmax : 1.0;
   g.xxmin[1] = 0.0;
   g.xxmax[1] = kPi;
   g.xxmin[2] = -kPi;
@@ -291,6 +318,10 @@ void build_grid(Grid& g) {
         double A, Ap, App;
         sinh_radial(g, g.xx[0][i0], A, Ap, App);
         g.drdxx0[k] = A * Ap / r;
+      } else if (g.coords == OR_SINHSPHERICAL) {
+        double A, Ap, App;
+        sinh_radial(g, g.xx[0][i0], A, Ap, App);
+        g.drdxx0[k] = Ap;
       } else {
         g.drdxx0[k] = 1.0;
       }
@@ -494,7 +525,8 @@ extern "C" {
 // Returns NULL on invalid arguments.
 void* or_create(int coords, int N0, int N1, int N2, int fd_order, double amax,
                 double sinhwaa, double bscale, double rmax) {
-  if (coords != OR_SINHSYMTP && coords != OR_SPHERICAL) return nullptr;
+  if (coords != OR_SINHSYMTP && coords != OR_SPHERICAL && coords != OR_SINHSPHERICAL)
+    return nullptr;
   if (fd_order < 2 || fd_order % 2 || fd_order > 12) return nullptr;
   const int NG = fd_order / 2;
   if (N0 < NG || N1 < NG || N2 < 2 || N2 % 2) return nullptr;

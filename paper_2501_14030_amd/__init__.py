@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_PKG, "libhrelax.so")
 
 SINHSYMTP = 0
 SPHERICAL = 1
+SINHSPHERICAL = 2
 
 FP64 = 0
 FP32 = 1
@@ -419,4 +420,4 @@ def residual_l2(grid: Grid) -> float:
 
 __all__ = ["Grid", "Batch", "GridParams", "RelaxResult", "HRError", "grid_create", "set_punctures",
            "relax", "get_u", "residual_l2", "load_library", "default_params",
-           "SINHSYMTP", "SPHERICAL", "FP64", "FP32", "FP32_FP64FINISH"]
+           "SINHSYMTP", "SPHERICAL", "SINHSPHERICAL", "FP64", "FP32", "FP32_FP64FINISH"]

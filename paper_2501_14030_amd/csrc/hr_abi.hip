@@ -615,7 +615,7 @@ hr_status hr_grid_create(hr_coords coords, int N0, int N1, int N2, int fd_order,
                          const hr_grid_params* p, hr_grid** out) {
   if (!out) return fail(HR_EINVAL, "null output handle pointer");
   *out = nullptr;
-  if (coords != HR_SINHSYMTP && coords != HR_SPHERICAL)
+  if (coords != HR_SINHSYMTP && coords != HR_SPHERICAL && coords != HR_SINHSPHERICAL)
     return fail(HR_EINVAL, "unknown coordinate system");
   if (fd_order != 2 && fd_order != 4 && fd_order != 6 && fd_order != 8 && fd_order != 10)
     return fail(HR_EINVAL, "fd_order must be 2, 4, 6, 8 or 10");
@@ -630,6 +630,8 @@ hr_status hr_grid_create(hr_coords coords, int N0, int N1, int N2, int fd_order,
   if (coords == HR_SINHSYMTP && !(prm.amax > 0 && prm.sinhwaa > 0 && prm.bscale > 0))
     return fail(HR_EINVAL, "SinhSymTP needs amax, sinhwaa, bscale > 0");
   if (coords == HR_SPHERICAL && !(prm.rmax > 0)) return fail(HR_EINVAL, "rmax must be > 0");
+  if (coords == HR_SINHSPHERICAL && !(prm.amax > 0 && prm.sinhwaa > 0))
+    return fail(HR_EINVAL, "SinhSpherical needs amax, sinhwaa > 0");
   if (!(prm.cfl > 0)) return fail(HR_EINVAL, "cfl must be > 0");
   hr_grid* g = new (std::nothrow) hr_grid();
   if (!g) return fail(HR_ENOMEM, "host allocation failed");
@@ -643,7 +645,7 @@ hr_status hr_grid_create(hr_coords coords, int N0, int N1, int N2, int fd_order,
   g->d.P0 = N0 + NG;
   g->d.nint = N0 * N1 * N2;
   g->d.nout = NG * N1 * N2;
-  g->d.sph = coords == HR_SPHERICAL ? 1 : 0;
+  g->d.sph = coords == HR_SINHSYMTP ? 0 : 1;  // spherical families: xx0 image mirrors theta
   g->G = align_up((size_t)next, 64);
   g->nblk_res = residual_blocks(g->d);
   if (fd_order >= 8 && !resident_plan(g->d, g->res_plan, g->res_nbx, g->res_nby)) {

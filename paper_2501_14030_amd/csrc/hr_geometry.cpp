@@ -9,6 +9,8 @@
 //              rho = A(xx0) sin xx1, z = sqrt(A^2 + b^2) cos xx1,
 //              A(xx0) = amax sinh(xx0/w) / sinh(1/w), xx0 in [0,1];
 //   Spherical  rho = r sin xx1, z = r cos xx1, r = xx0 in [0, rmax];
+//   SinhSpherical  the same with r = A(xx0), xx0 in [0,1] (one of the further
+//              coordinate families the paper's conclusions name);
 // with xx1 in [0,pi] and xx2 = phi in [-pi,pi], cell-centred.
 //
 // Both metrics are diagonal, so with scale factors h_i and J = h0 h1 h2
@@ -64,6 +66,31 @@ Local local_sinhsymtp(const hr_grid_params& p, double x0, double x1) {
   return L;
 }
 
+// SinhSpherical: r = A(xx0) with SinhSymTP's sinh stretching, spherical angles.
+// Scale factors (A', A, A sin xx1); with J = A' A^2 sin xx1,
+//   (1/J) d_0 (J / A'^2) = (1/J) d_0 (A^2 sin xx1 / A') = 2/(A A') - A''/A'^3.
+Local local_sinhspherical(const hr_grid_params& p, double x0, double x1) {
+  const double w = p.sinhwaa;
+  const double norm = std::sinh(1.0 / w);
+  const double A = p.amax * std::sinh(x0 / w) / norm;
+  const double dA = p.amax * std::cosh(x0 / w) / (w * norm);
+  const double d2A = A / (w * w);
+  const double sn = std::sin(x1), cs = std::cos(x1);
+  Local L;
+  L.h0 = dA;
+  L.h1 = A;
+  L.h2 = A * sn;
+  L.a0 = 1.0 / (dA * dA);
+  L.a1 = 1.0 / (A * A);
+  L.a2 = 1.0 / (A * A * sn * sn);
+  L.b0 = 2.0 / (A * dA) - d2A / (dA * dA * dA);
+  L.b1 = cs / (sn * A * A);
+  L.rho = A * sn;
+  L.z = A * cs;
+  L.drdx0 = dA;
+  return L;
+}
+
 Local local_spherical(double x0, double x1) {
   const double r = x0, sn = std::sin(x1), cs = std::cos(x1);
   Local L;
@@ -85,15 +112,16 @@ Local local_spherical(double x0, double x1) {
 
 bool build_tables(hr_coords coords, const Dims& d, const hr_grid_params& p,
                   HostTables& t, std::string& err) {
-  const double x0max = (coords == HR_SINHSYMTP) ? 1.0 : p.rmax;
+  const double x0max = (coords == HR_SPHERICAL) ? p.rmax : 1.0;
   const double dx[3] = {x0max / d.N0, kPi / d.N1, 2.0 * kPi / d.N2};
   auto coord = [&](int dir, int j) {  // j = stored index (0 = first interior)
     const double lo = (dir == 2) ? -kPi : 0.0;
     return lo + (j + 0.5) * dx[dir];
   };
   auto local = [&](int i0, int i1) {
-    return coords == HR_SINHSYMTP ? local_sinhsymtp(p, coord(0, i0), coord(1, i1))
-                                  : local_spherical(coord(0, i0), coord(1, i1));
+    if (coords == HR_SINHSYMTP) return local_sinhsymtp(p, coord(0, i0), coord(1, i1));
+    if (coords == HR_SINHSPHERICAL) return local_sinhspherical(p, coord(0, i0), coord(1, i1));
+    return local_spherical(coord(0, i0), coord(1, i1));
   };
   auto dsmin = [&](const Local& L) {
     double s = std::fabs(L.h0) * dx[0];

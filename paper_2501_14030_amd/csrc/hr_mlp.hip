@@ -526,7 +526,7 @@ hr_status hr_mlp_grid_features(hr_mlp* n, const hr_grid* g, const double* cfg9, 
   if (!g->have_sources) return mfail(HR_ESTATE, "punctures not set");
   FeatArgs a{};
   a.d = g->d;
-  a.x0max = g->coords == HR_SINHSYMTP ? 1.0 : g->prm.rmax;
+  a.x0max = g->coords == HR_SPHERICAL ? g->prm.rmax : 1.0;
   for (int k = 0; k < 9; ++k) a.cfg[k] = (float)cfg9[k];
   a.rho = g->rho;
   a.zc = g->zc;
@@ -552,7 +552,7 @@ hr_status hr_warm_start(hr_grid* g, hr_mlp* n, const double* cfg9, double eta) {
   HR_HIPM(hipStreamSynchronize(g->stream));
   FeatArgs a{};
   a.d = g->d;
-  a.x0max = g->coords == HR_SINHSYMTP ? 1.0 : g->prm.rmax;
+  a.x0max = g->coords == HR_SPHERICAL ? g->prm.rmax : 1.0;
   for (int k = 0; k < 9; ++k) a.cfg[k] = (float)cfg9[k];
   a.rho = g->rho;
   a.zc = g->zc;

@@ -21,6 +21,7 @@ import numpy as np
 
 SINHSYMTP = 0
 SPHERICAL = 1
+SINHSPHERICAL = 2
 
 
 @dataclass
@@ -55,7 +56,8 @@ class GridSpec:
         return self.N0 * self.N1 * self.N2
 
     def name(self) -> str:
-        c = "SinhSymTP" if self.coords == SINHSYMTP else "Spherical"
+        c = {SINHSYMTP: "SinhSymTP", SPHERICAL: "Spherical",
+             SINHSPHERICAL: "SinhSpherical"}[self.coords]
         return f"{c} {self.N0}x{self.N1}x{self.N2} order {self.fd_order}"
 
 

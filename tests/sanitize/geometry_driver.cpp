@@ -97,7 +97,7 @@ int main() {
   int checked = 0;
   const int shapes[][3] = {{5, 5, 2}, {8, 4, 2}, {32, 16, 4}, {37, 19, 6}, {64, 64, 8}, {128, 64, 8}};
   const int orders[] = {2, 4, 6, 8, 10};
-  for (int coords = 0; coords < 2; ++coords)
+  for (int coords = 0; coords < 3; ++coords)
     for (const auto& sh : shapes)
       for (int order : orders) {
         const int NG = order / 2;
@@ -110,7 +110,7 @@ int main() {
         d.P0 = sh[0] + NG;
         d.nint = sh[0] * sh[1] * sh[2];
         d.nout = NG * sh[1] * sh[2];
-        d.sph = coords;
+        d.sph = coords == 0 ? 0 : 1;
         hr_grid_params p{1.0e6, 0.07, 1.5, 100.0, 0.5};
         hr::HostTables t;
         std::string err;

@@ -57,6 +57,8 @@ def test_config0_trajectory_parity():
     # the smallest legal grid; a milder stretch keeps RK4 stable at CFL 0.5 on it
     (workloads.GridSpec(0, 5, 5, 2, 10, amax=100.0, sinhwaa=0.2, bscale=1.0),
      "minimal grid N0=N1=NG"),
+    (workloads.GridSpec(2, 37, 19, 6, 10), "ragged SinhSpherical order 10"),
+    (workloads.GridSpec(2, 64, 32, 8, 8), "SinhSpherical order 8 (resident kernel)"),
 ])
 def test_parity_shapes_orders_coords(spec, label):
     banner(f"parity {label}: {spec.name()}")

@@ -118,7 +118,8 @@ def _lap_errors(oracle_lib, coords, N, order, fn, kw, region):
     return e[mask].max()
 
 
-@pytest.mark.parametrize("coords,kw", [(0, SINH_MILD), (1, dict(rmax=3.0))])
+@pytest.mark.parametrize("coords,kw", [(0, SINH_MILD), (1, dict(rmax=3.0)),
+                                       (2, dict(amax=3.0, sinhwaa=0.4))])
 @pytest.mark.parametrize("order", [4, 8, 10])
 @pytest.mark.parametrize("fn", [_gauss, _inv_dist])
 def test_laplacian_converges_at_stencil_order(oracle_lib, coords, kw, order, fn):

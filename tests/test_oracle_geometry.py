@@ -16,6 +16,8 @@ import pytest
 
 SINH = dict(amax=1.0e6, sinhwaa=0.07, bscale=1.0)
 SINH_MILD = dict(amax=3.0, sinhwaa=0.4, bscale=0.5)
+SSPH = dict(amax=1.0e6, sinhwaa=0.07)          # SinhSpherical
+SSPH_MILD = dict(amax=3.0, sinhwaa=0.4)
 
 
 def _grid(oracle_lib, coords, kw, N=(16, 12, 8), order=8):
@@ -34,11 +36,14 @@ def _jac(g, x0, x1, x2, eps):
     return J
 
 
-@pytest.mark.parametrize("coords,kw", [(0, SINH_MILD), (0, SINH), (1, dict(rmax=100.0))])
+COORDS = [(0, SINH_MILD), (0, SINH), (1, dict(rmax=100.0)), (2, SSPH_MILD), (2, SSPH)]
+
+
+@pytest.mark.parametrize("coords,kw", COORDS)
 def test_scale_factors_match_jacobian_and_orthogonality(oracle_lib, coords, kw):
     g = _grid(oracle_lib, coords, kw)
     rng = np.random.default_rng(1)
-    x0max = 1.0 if coords == 0 else kw["rmax"]
+    x0max = kw["rmax"] if coords == 1 else 1.0
     for _ in range(25):
         x0 = rng.uniform(0.05, 0.95) * x0max
         x1 = rng.uniform(0.1, np.pi - 0.1)
@@ -53,7 +58,7 @@ def test_scale_factors_match_jacobian_and_orthogonality(oracle_lib, coords, kw):
         assert off < 2e-6 * np.abs(np.diag(G)).max()
 
 
-@pytest.mark.parametrize("coords,kw", [(0, SINH_MILD), (0, SINH), (1, dict(rmax=100.0))])
+@pytest.mark.parametrize("coords,kw", COORDS)
 def test_laplacian_coefficients_from_scale_factors(oracle_lib, coords, kw):
     g = _grid(oracle_lib, coords, kw, N=(16, 12, 4))
     met = g.metric()
@@ -92,7 +97,8 @@ def test_sinhsymtp_foci_and_compactification(oracle_lib):
 
 
 @pytest.mark.parametrize("coords,kw,N", [(0, SINH, (8, 6, 4)), (1, dict(rmax=10.0), (8, 6, 4)),
-                                         (0, SINH_MILD, (5, 5, 6)), (1, dict(rmax=3.0), (5, 5, 2))])
+                                         (0, SINH_MILD, (5, 5, 6)), (1, dict(rmax=3.0), (5, 5, 2)),
+                                         (2, SSPH, (8, 6, 4)), (2, SSPH_MILD, (5, 5, 6))])
 def test_ghost_images_share_cartesian_position(oracle_lib, coords, kw, N):
     g = oracle_lib.OracleGrid(coords, *N, 8, **kw)
     img = g.bc_images()
@@ -112,6 +118,19 @@ def test_ghost_images_share_cartesian_position(oracle_lib, coords, kw, N):
     ng = g.NG
     assert nint == N[0] * N[1] * N[2]
     assert nout == ng * N[1] * N[2]
+
+
+def test_sinhspherical_radius_and_origin(oracle_lib):
+    g = _grid(oracle_lib, 2, SSPH)
+    # r = A(xx0): xx0 = 1 is the outer sphere r = amax, xx0 = 0 the origin
+    for x1, x2 in ((0.3, 1.0), (2.0, -2.5)):
+        np.testing.assert_allclose(np.linalg.norm(g.to_cart(1.0, x1, x2)), 1.0e6, rtol=1e-12)
+        assert np.linalg.norm(g.to_cart(0.0, x1, x2)) == 0.0
+    # the same sinh stretching as SinhSymTP's A (b = 0 there gives the same map)
+    h = _grid(oracle_lib, 0, dict(amax=1.0e6, sinhwaa=0.07, bscale=1e-300))
+    for x0 in (0.1, 0.5, 0.9):
+        np.testing.assert_allclose(np.linalg.norm(g.to_cart(x0, 0.7, 0.1)),
+                                   np.linalg.norm(h.to_cart(x0, 0.7, 0.1)), rtol=1e-12)
 
 
 def test_wave_speed_gives_uniform_courant_number(oracle_lib):
