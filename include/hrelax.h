@@ -199,9 +199,29 @@ hr_status hr_get_v(const hr_grid* g, double* host_out, size_t n);
 hr_status hr_set_u(hr_grid* g, const double* host_in, size_t n);
 hr_status hr_set_v(hr_grid* g, const double* host_in, size_t n);
 
-/* Grid L2 norm of the Hamiltonian-constraint residual of the current state,
- * sqrt(sum_interior H^2 / N_interior), in FP64. */
+/* L2 norm of the Hamiltonian-constraint residual of the current state, in
+ * FP64: by default the grid norm over points, sqrt(sum_interior H^2 /
+ * N_interior) (the grid L2 norm of the constraint violations that the paper's
+ * stop test uses, Data Transfer Optimization subsection); with
+ * hr_set_residual_norm(g, HR_NORM_VOLUME) the volume-weighted norm
+ * sqrt(sum H^2 dV / sum dV), dV = |h0 h1 h2| dxx0 dxx1 dxx2 the proper cell
+ * volume. */
 hr_status hr_residual_l2(hr_grid* g, double* out);
+
+typedef enum {
+  HR_NORM_POINTS = 0,  /* mean of H^2 over interior points (default) */
+  HR_NORM_VOLUME = 1   /* H^2 weighted by the proper cell volume */
+} hr_norm;
+
+/*
+ * Selects the residual norm for hr_residual_l2 and for the stop test of
+ * hr_relax (the tolerance is then compared with the volume-weighted norm).
+ * The volume norm takes every interior cell at its proper volume, so the fine
+ * cells near the punctures count less and the large outer cells more than in
+ * the point norm. Grids in a batch must use HR_NORM_POINTS (hr_batch_relax
+ * returns HR_EINVAL otherwise). Errors: HR_EINVAL (null grid, unknown norm).
+ */
+hr_status hr_set_residual_norm(hr_grid* g, hr_norm norm);
 
 /* cfl * ds_g. */
 hr_status hr_suggest_dt(const hr_grid* g, double cfl, double* dt);

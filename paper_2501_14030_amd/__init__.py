@@ -28,6 +28,9 @@ FP64 = 0
 FP32 = 1
 FP32_FP64FINISH = 2
 
+NORM_POINTS = 0
+NORM_VOLUME = 1
+
 OK = 0
 EINVAL = -1
 ENOMEM = -2
@@ -98,6 +101,7 @@ _SIGNATURES = {
     "hr_resolved_kernel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
                                           ctypes.POINTER(KernelConfig)]),
     "hr_set_wait_limit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint]),
+    "hr_set_residual_norm": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "hr_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                    ctypes.POINTER(KernelConfig), _dp]),
     "hr_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
@@ -309,6 +313,12 @@ class Grid:
                                           ctypes.byref(us)), "hr_autotune")
         return {"variant": cfg.variant, "streaming": cfg.streaming, "chunk": cfg.chunk,
                 "graph": cfg.graph}, us.value
+
+    def set_residual_norm(self, norm: int = NORM_POINTS) -> None:
+        """Norm of residual_l2 and of relax's stop test: NORM_POINTS (mean of H^2
+        over interior points) or NORM_VOLUME (H^2 weighted by the proper cell
+        volume)."""
+        _check(load_library().hr_set_residual_norm(self._h, int(norm)), "hr_set_residual_norm")
 
     def set_wait_limit(self, polls: int = 0) -> None:
         """Polls of one partner's counter before a resident-kernel wait gives up

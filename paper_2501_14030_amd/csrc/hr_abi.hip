@@ -147,6 +147,7 @@ size_t layout(hr_grid* g, char* base) {
   g->zc = (double*)take(e2d * sizeof(double));
   g->cphi = (double*)take(g->d.N2 * sizeof(double));
   g->sphi = (double*)take(g->d.N2 * sizeof(double));
+  g->vol = (double*)take((size_t)n2d * sizeof(double));
   g->partial = (double*)take((size_t)g->nblk_res * sizeof(double));
   g->result = (double*)take(4 * sizeof(double));
   const int nres = g->res_nbx * g->res_nby;
@@ -156,6 +157,12 @@ size_t layout(hr_grid* g, char* base) {
     g->res_err = (unsigned*)take(sizeof(unsigned));
   }
   return off;
+}
+
+// Divisor of the residual norm: the interior point count, or the total cell
+// volume for the volume-weighted norm.
+double norm_divisor(const hr_grid* g) {
+  return g->norm ? g->tab.vol_total : (double)g->d.nint;
 }
 
 ResidentArgs resident_args(hr_grid* g, double eta, double dt, int nsteps) {
@@ -276,9 +283,10 @@ hr_status residual_of(hr_grid* g, const void* u, bool fp32, double* out) {
   r.psi = g->f64.psi;
   r.ssrc = g->f64.ssrc;
   r.fac = g->f64.fac;
+  r.wt = g->norm ? g->vol : nullptr;
   r.partial = g->partial;
   HR_HIP(launch_residual(g->fd_order, fp32, r, g->stream));
-  HR_HIP(launch_finalize(g->partial, g->nblk_res, g->d.nint, g->result, g->stream));
+  HR_HIP(launch_finalize(g->partial, g->nblk_res, norm_divisor(g), g->result, g->stream));
   HR_HIP(hipMemcpyAsync(g->host_res, g->result, sizeof(double), hipMemcpyDeviceToHost,
                         g->stream));
   HR_HIP(hipStreamSynchronize(g->stream));
@@ -361,9 +369,10 @@ hr_status enqueue_residual(hr_grid* g, const void* u, bool fp32) {
   r.psi = g->f64.psi;
   r.ssrc = g->f64.ssrc;
   r.fac = g->f64.fac;
+  r.wt = g->norm ? g->vol : nullptr;
   r.partial = g->partial;
   HR_HIP(launch_residual(g->fd_order, fp32, r, g->stream));
-  HR_HIP(launch_finalize(g->partial, g->nblk_res, g->d.nint, g->result, g->stream));
+  HR_HIP(launch_finalize(g->partial, g->nblk_res, norm_divisor(g), g->result, g->stream));
   return HR_OK;
 }
 
@@ -418,7 +427,7 @@ hr_status run_interval(hr_grid* g, int kind, int K, double eta, double dt, doubl
   if (g->graph != 0 && !resident) {
     const bool same = g->gexec && g->g_kind == kind && g->g_K == K && g->g_eta == eta &&
                       g->g_dt == dt && g->g_kappa == g->kappa_loaded && g->g_variant == variant &&
-                      g->g_chunk == chunk && g->g_streaming == streaming;
+                      g->g_chunk == chunk && g->g_streaming == streaming && g->g_norm == g->norm;
     if (!same) {
       if (g->gexec) {
         (void)hipGraphExecDestroy(g->gexec);
@@ -447,6 +456,7 @@ hr_status run_interval(hr_grid* g, int kind, int K, double eta, double dt, doubl
       g->g_variant = variant;
       g->g_chunk = chunk;
       g->g_streaming = streaming;
+      g->g_norm = g->norm;
     }
     HR_HIP(hipGraphLaunch(g->gexec, g->stream));
   } else {
@@ -719,6 +729,8 @@ hr_status hr_grid_bind(hr_grid* g, void* dev_ptr, size_t bytes, void* hip_stream
   HR_HIP(hipMemcpyAsync(g->cphi, g->tab.cphi.data(), d.N2 * sizeof(double),
                         hipMemcpyHostToDevice, g->stream));
   HR_HIP(hipMemcpyAsync(g->sphi, g->tab.sphi.data(), d.N2 * sizeof(double),
+                        hipMemcpyHostToDevice, g->stream));
+  HR_HIP(hipMemcpyAsync(g->vol, g->tab.vol.data(), g->tab.vol.size() * sizeof(double),
                         hipMemcpyHostToDevice, g->stream));
   const int G = (int)g->G;
   double* z64[] = {g->f64.un, g->f64.vn, g->f64.ua, g->f64.va, g->f64.ub,
@@ -999,6 +1011,13 @@ hr_status hr_resolved_kernel(const hr_grid* g, hr_precision prec, hr_kernel_conf
   cfg->chunk = variant == 2 ? chunk : 0;
   cfg->streaming = g->streaming > 0 ? 1 : 0;
   cfg->graph = (variant == 3 || g->graph == 0) ? 0 : 1;
+  return HR_OK;
+}
+
+hr_status hr_set_residual_norm(hr_grid* g, hr_norm norm) {
+  if (!g) return fail(HR_EINVAL, "null grid handle");
+  if (norm != HR_NORM_POINTS && norm != HR_NORM_VOLUME) return fail(HR_EINVAL, "unknown norm");
+  g->norm = norm == HR_NORM_VOLUME ? 1 : 0;
   return HR_OK;
 }
 

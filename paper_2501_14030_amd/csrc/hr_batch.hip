@@ -290,6 +290,8 @@ hr_status hr_batch_relax(hr_batch* b, const double* eta, const double* c, long n
     return bfail(HR_EINVAL, "batched precision must be HR_FP64 or HR_FP32_FP64FINISH");
   for (int i = 0; i < b->n; ++i) {
     if (!b->g[i]->have_sources) return bfail(HR_ESTATE, "punctures not set on a batched grid");
+    if (b->g[i]->norm != 0)
+      return bfail(HR_EINVAL, "batched relaxation uses the point norm (hr_set_residual_norm)");
     if (!(eta[i] > 0) || !(c[i] > 0) || !std::isfinite(eta[i]) || !std::isfinite(c[i]))
       return bfail(HR_EINVAL, "eta and c must be finite and > 0");
   }
@@ -323,7 +325,7 @@ hr_status hr_batch_relax(hr_batch* b, const double* eta, const double* c, long n
       f.chunk = chunk;
       h32[4 * i + s - 1] = f;
     }
-    hra[i] = ResidualArgs{g->d, g->f64.un, g->f64.psi, g->f64.ssrc, g->f64.fac, nullptr};
+    hra[i] = ResidualArgs{g->d, g->f64.un, g->f64.psi, g->f64.ssrc, g->f64.fac, nullptr, nullptr};
     BaseArgs ba{};
     ba.d = g->d;
     ba.u = g->f64.un;

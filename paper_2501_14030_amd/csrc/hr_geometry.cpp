@@ -140,6 +140,8 @@ bool build_tables(hr_coords coords, const Dims& d, const hr_grid_params& p,
   t.rcart.assign(e2d, 0.0);
   t.cphi.assign(d.N2, 0.0);
   t.sphi.assign(d.N2, 0.0);
+  t.vol.assign(n2d, 0.0);
+  t.vol_total = 0.0;
 
   std::vector<double> ds(e2d);
   double dsg = INFINITY;
@@ -158,6 +160,8 @@ bool build_tables(hr_coords coords, const Dims& d, const hr_grid_params& p,
         t.alpha[2 * (size_t)n2d + k] = L.a2 / (dx[2] * dx[2]);
         t.alpha[3 * (size_t)n2d + k] = L.b0 / dx[0];
         t.alpha[4 * (size_t)n2d + k] = L.b1 / dx[1];
+        t.vol[k] = std::fabs(L.h0 * L.h1 * L.h2) * dx[0] * dx[1] * dx[2];
+        t.vol_total += t.vol[k] * d.N2;
         dsg = std::fmin(dsg, ds[e]);
       } else {
         const int k = (i0 - d.N0) + d.NG * i1;

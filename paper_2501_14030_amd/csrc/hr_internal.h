@@ -110,6 +110,7 @@ struct ResidualArgs {
   const double* psi;
   const double* ssrc;
   const double* fac;    // FP64 table (alpha/beta planes used)
+  const double* wt;     // N0*N1 cell volumes (volume-weighted norm) or null
   double* partial;      // one per block
 };
 
@@ -124,7 +125,8 @@ hipError_t launch_stage(int order, int stage, const StageArgs<float>& a,
 int residual_blocks(const Dims& d);
 hipError_t launch_residual(int order, bool fp32_state, const ResidualArgs& a,
                            hipStream_t s);
-hipError_t launch_finalize(const double* partial, int nparts, int nint,
+// out[0] = sqrt(sum(partial) / divisor), out[1] = sum(partial).
+hipError_t launch_finalize(const double* partial, int nparts, double divisor,
                            double* out, hipStream_t s);
 hipError_t launch_sources(const Dims& d, const double* rho, const double* zc,
                           const double* cphi, const double* sphi,
@@ -238,6 +240,8 @@ struct HostTables {
   std::vector<double> rcart;   // P0*N1: Cartesian radius
   std::vector<double> cphi;    // N2
   std::vector<double> sphi;    // N2
+  std::vector<double> vol;     // N0*N1: cell volume |h0 h1 h2| dxx0 dxx1 dxx2 (any plane)
+  double vol_total = 0.0;      // sum of the cell volumes over the interior
 };
 
 bool build_tables(hr_coords coords, const Dims& d, const hr_grid_params& p,
@@ -269,6 +273,7 @@ struct hr_grid {
   double* zc = nullptr;
   double* cphi = nullptr;
   double* sphi = nullptr;
+  double* vol = nullptr;        // device copy of the cell volumes (N0*N1)
   double* partial = nullptr;
   double* result = nullptr;
   double* host_res = nullptr;   // pinned readback slot
@@ -276,6 +281,7 @@ struct hr_grid {
   hr::Punctures pz{};           // punctures of the last hr_set_punctures
   double kappa_loaded = -1.0;   // wave-speed scale currently in fac/ofac
 
+  int norm = 0;                 // residual norm: 0 over points, 1 volume-weighted
   int variant = 0;              // kernel variant: 0 auto, 1 plane tiles, 2 phi columns,
                                 // 3 resident (FP64 steps in one launch, state on chip)
   int res_nbx = 0, res_nby = 0; // resident patches (0: grid not eligible)
@@ -290,7 +296,7 @@ struct hr_grid {
   int chunk = 0;                // phi planes per block of the column variant (0 auto)
   int graph = -1;               // graph capture of check intervals: -1 auto (on), 0, 1
   hipGraphExec_t gexec = nullptr;  // captured check interval and its key
-  int g_kind = -1, g_K = 0, g_variant = 0, g_chunk = 0, g_streaming = 0;
+  int g_kind = -1, g_K = 0, g_variant = 0, g_chunk = 0, g_streaming = 0, g_norm = 0;
   double g_eta = 0, g_dt = 0, g_kappa = 0;
 
   // FP32 -> FP64 switch rule (sw_residual 0: ten times the tolerance)

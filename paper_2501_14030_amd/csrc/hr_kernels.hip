@@ -677,6 +677,7 @@ __device__ __forceinline__ double residual_body(const ResidualArgs& a, int bx, i
     const double lap = f[0] * s.dd0 + f[1] * s.dd1 + f[2] * s.dd2 + f[3] * s.d0 + f[4] * s.d1;
     const double Hv = lap + source<double>(ssrc, psi, s.uc);
     h2 = Hv * Hv;
+    if (a.wt) h2 *= a.wt[k2];  // volume-weighted norm: H^2 times the cell volume
   }
   return block_sum<kTileThreads>(h2);
 }
@@ -749,13 +750,13 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 __global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ partial,
-                                                     int nparts, int nint,
+                                                     int nparts, double divisor,
                                                      double* __restrict__ out) {
   double s = 0.0;
   for (int j = threadIdx.x; j < nparts; j += kBlock) s += partial[j];
   const double tot = block_sum<kBlock>(s);
   if (threadIdx.x == 0) {
-    out[0] = sqrt(tot / (double)nint);
+    out[0] = sqrt(tot / divisor);
     out[1] = tot;
   }
 }
@@ -940,9 +941,9 @@ hipError_t launch_residual(int order, bool fp32_state, const ResidualArgs& a, hi
   return fp32_state ? residual_order<float>(order, a, s) : residual_order<double>(order, a, s);
 }
 
-hipError_t launch_finalize(const double* partial, int nparts, int nint, double* out,
+hipError_t launch_finalize(const double* partial, int nparts, double divisor, double* out,
                            hipStream_t s) {
-  k_finalize<<<1, kBlock, 0, s>>>(partial, nparts, nint, out);
+  k_finalize<<<1, kBlock, 0, s>>>(partial, nparts, divisor, out);
   return hipGetLastError();
 }
 
