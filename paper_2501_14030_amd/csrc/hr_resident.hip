@@ -16,11 +16,16 @@
 //     exchange array (one per stage parity) and raises its stage counter; the
 //     next stage waits only for the counters of its exchange partners (the
 //     owners of its rim taps; the relation is symmetric), then loads its rim
-//     from the exchange array. Rim cells that are images of the patch's own
-//     points (inner-boundary reflections onto itself) are copied within LDS,
-//     and the outer points, read only by their own patch, stay in LDS;
+//     from the exchange array. The exchange array is packed by patch
+//     ([patch][plane][x1][x0], 512 contiguous bytes per patch plane in FP64),
+//     so a block's publish is whole cache lines and each rim strip spans a few
+//     lines of one patch plane instead of one line per grid row; the initial
+//     state is published the same way before the first stage. Rim cells that
+//     are images of the patch's own points (inner-boundary reflections onto
+//     itself) are copied within LDS, and the outer points, read only by their
+//     own patch, stay in LDS;
 //   * the phi sums and the source term need only the patch's own planes and
-//     are computed before the wait, while the partners finish.
+//     are computed while the rim loads are in flight.
 // All blocks are resident at once: each takes more than half of a compute
 // unit's LDS, and the grid has at most as many blocks as the device has
 // compute units (checked by occupancy before use).
@@ -192,7 +197,11 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
       flip = true;
     }
     const int sp = flip ? half_turn(plc, N2) : plc;
-    rg[q] = P0 * ((unsigned)s1 + N1 * (unsigned)sp) + (unsigned)s0;
+    // packed exchange slot of (s0, s1, sp); only read for cells of other
+    // patches, which are interior points (outer points stay with their patch)
+    const int ox = s0 / RB, oy = s1 / RB;
+    rg[q] = ((unsigned)(ox + a.nbx * oy) * (unsigned)N2 + (unsigned)sp) * 64u +
+            (unsigned)((s1 - oy * RB) * RB + (s0 - ox * RB));
     const bool self = min(s0 / RB, a.nbx - 1) == bx && s1 / RB == by;
     const unsigned kind = pl >= N2 ? 0u : !self ? 1u : flip ? 2u : 3u;
     const unsigned rl = (unsigned)(plc * TP + l1 * RW + l0);
@@ -205,8 +214,20 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
   const int nw = a.waits[b * (kResMaxWait + 1)];
   const int wt = t < nw ? a.waits[b * (kResMaxWait + 1) + 1 + t] : 0;
 
+  // packed exchange slot of this thread's point in plane 0
+  const unsigned pslot = (unsigned)b * (unsigned)N2 * 64u + (unsigned)pos;
+
+  // publish the initial stage input (counter 1); stage e waits for counters
+  // >= e and publishes its result with counter e + 1
+#pragma unroll
+  for (int j = 0; j < NPT; ++j)
+    if (grp + PG * j < N2) xstore(a.x0 + pslot + 64u * (unsigned)(grp + PG * j), su[j]);
+  __builtin_amdgcn_s_waitcnt(0);
   if (t == 0) bad = 0;
   __syncthreads();
+  if (t == 0)
+    __hip_atomic_store(a.flags + b * kResFlagStride, 1u, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
 
   const int nst = 4 * a.nsteps;
   for (int e = 1; e <= nst; ++e) {
@@ -227,9 +248,34 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
         ut[otl[q]] = osu[q];
         vt[ovl[q]] = osv[q];
       }
+    // (2) wait until every exchange partner has published the previous stage
+    // (one lane per partner; polling by every wave was measured slower); the
+    // barrier also completes step 1
+    if (t < nw) {
+      const unsigned* fl = a.flags + wt * kResFlagStride;
+      unsigned spin = 0;
+      while (__hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)e) {
+        if (++spin > a.spin_limit) {
+          atomicOr(a.err, 1u);
+          bad = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
     __syncthreads();
-    // (2) the phi sums and the source term need only the patch's own planes:
-    // computed while the partners finish the previous stage
+    if (bad) break;
+    // (3) the rim: loads of the cells of other patches from the exchange array
+    // are issued here and stored to LDS after step 4
+    const T* src_x = ((e - 1) & 1) ? a.x1 : a.x0;
+    T rv[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      rv[q] = (T)0;
+      if ((rmeta[q] >> 30) == 1u) rv[q] = xload(src_x + rg[q]);
+    }
+    // (4) the phi sums and the source term need only the patch's own planes:
+    // computed while the rim loads are in flight
     T e2[NPT], src[NPT];
 #pragma unroll
     for (int j = 0; j < NPT; ++j) {
@@ -254,41 +300,13 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
         src[j] = ss[j] / (p4 * p2 * p);
       }
     }
-    // (3) wait until every exchange partner has published the previous stage
-    // (one lane per partner; polling by every wave was measured slower)
-    if (e > 1) {
-      if (t < nw) {
-        const unsigned* fl = a.flags + wt * kResFlagStride;
-        unsigned spin = 0;
-        while (__hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-               (unsigned)(e - 1)) {
-          if (++spin > a.spin_limit) {
-            atomicOr(a.err, 1u);
-            bad = 1;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
-      }
-      __syncthreads();
-      if (bad) break;
-    }
-    // (4) the rim: cells of other patches from the exchange array (the state
-    // itself at the first stage), images of own points within LDS
-    {
-      const T* src_x = ((e - 1) & 1) ? a.x1 : a.x0;
-      T rv[NR];
+    // (5) rim cells into LDS: loaded values, and images of own points copied
+    // within LDS
 #pragma unroll
-      for (int q = 0; q < NR; ++q) {
-        rv[q] = (T)0;
-        if ((rmeta[q] >> 30) == 1u) rv[q] = e == 1 ? a.u[rg[q]] : xload(src_x + rg[q]);
-      }
-#pragma unroll
-      for (int q = 0; q < NR; ++q) {
-        const unsigned kind = rmeta[q] >> 30, rl = rmeta[q] & 0x7fffu;
-        if (kind == 1u) ut[rl] = rv[q];
-        else if (kind == 2u) ut[rl] = ut[(rmeta[q] >> 15) & 0x7fffu];
-      }
+    for (int q = 0; q < NR; ++q) {
+      const unsigned kind = rmeta[q] >> 30, rl = rmeta[q] & 0x7fffu;
+      if (kind == 1u) ut[rl] = rv[q];
+      else if (kind == 2u) ut[rl] = ut[(rmeta[q] >> 15) & 0x7fffu];
     }
     __syncthreads();
 
@@ -371,12 +389,12 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
       T* dst = (e & 1) ? a.x1 : a.x0;
 #pragma unroll
       for (int j = 0; j < NPT; ++j)
-        if (grp + PG * j < N2) xstore(dst + gidx[j], su[j]);
+        if (grp + PG * j < N2) xstore(dst + pslot + 64u * (unsigned)(grp + PG * j), su[j]);
       // (outer points are read only by their own patch, through LDS)
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
       if (t == 0)
-        __hip_atomic_store(a.flags + b * kResFlagStride, (unsigned)e, __ATOMIC_RELAXED,
+        __hip_atomic_store(a.flags + b * kResFlagStride, (unsigned)(e + 1), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     } else {
 #pragma unroll
