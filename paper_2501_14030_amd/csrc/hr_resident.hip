@@ -266,7 +266,7 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
     __syncthreads();
     if (bad) break;
     // (3) the rim: loads of the cells of other patches from the exchange array
-    // are issued here and stored to LDS after step 4
+    // are issued here and stored to LDS in step 6
     const T* src_x = ((e - 1) & 1) ? a.x1 : a.x0;
     T rv[NR];
 #pragma unroll
@@ -274,6 +274,11 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
       rv[q] = (T)0;
       if ((rmeta[q] >> 30) == 1u) rv[q] = xload(src_x + rg[q]);
     }
+    // rim cells that are images of the patch's own points: copied within LDS
+    // while the loads are in flight
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+      if ((rmeta[q] >> 30) == 2u) ut[rmeta[q] & 0x7fffu] = ut[(rmeta[q] >> 15) & 0x7fffu];
     // (4) the phi sums and the source term need only the patch's own planes:
     // computed while the rim loads are in flight
     T e2[NPT], src[NPT];
@@ -300,17 +305,46 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
         src[j] = ss[j] / (p4 * p2 * p);
       }
     }
-    // (5) rim cells into LDS: loaded values, and images of own points copied
-    // within LDS
+    // (5) the outer points' radiation condition needs only the patch's own
+    // cells: also computed while the rim loads are in flight
+    const T cy = a.cy[stage], ca = a.ca[stage];
 #pragma unroll
-    for (int q = 0; q < NR; ++q) {
-      const unsigned kind = rmeta[q] >> 30, rl = rmeta[q] & 0x7fffu;
-      if (kind == 1u) ut[rl] = rv[q];
-      else if (kind == 2u) ut[rl] = ut[(rmeta[q] >> 15) & 0x7fffu];
+    for (int q = 0; q < NQ; ++q) {
+      if (!oval[q]) continue;
+      // radiation condition with a one-sided xx0 derivative
+      const T u0 = ut[otl[q]], u1 = ut[otl[q] - 1], u2 = ut[otl[q] - 2];
+      const T v0 = osv[q], v1 = vt[ovl[q] - 1], v2 = vt[ovl[q] - 2];
+      T kuo = -oc[q] * (u0 * ori[q] + ((T)3 * u0 - (T)4 * u1 + u2) * oqd[q]);
+      T kvo = -oc[q] * (v0 * ori[q] + ((T)3 * v0 - (T)4 * v1 + v2) * oqd[q]);
+      if constexpr (CORR) {
+        kuo = ohu[q] + kuo;
+        kvo = ohv[q] + kvo;
+      }
+      if (stage == 0) {
+        oau[q] = u0 + ca * kuo;
+        oav[q] = v0 + ca * kvo;
+        osu[q] = u0 + cy * kuo;
+        osv[q] = v0 + cy * kvo;
+      } else if (stage == 3) {
+        osu[q] = oau[q] + ca * kuo;
+        osv[q] = oav[q] + ca * kvo;
+        oyu[q] = osu[q];
+        oyv[q] = osv[q];
+      } else {
+        osu[q] = oyu[q] + cy * kuo;
+        osv[q] = oyv[q] + cy * kvo;
+        oau[q] = oau[q] + ca * kuo;
+        oav[q] = oav[q] + ca * kvo;
+      }
     }
+
+    // (6) loaded rim cells into LDS
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+      if ((rmeta[q] >> 30) == 1u) ut[rmeta[q] & 0x7fffu] = rv[q];
     __syncthreads();
 
-    const T cy = a.cy[stage], ca = a.ca[stage];
+    // (7) x0/x1 sums, right-hand side and stage combine at the own points
 #pragma unroll
     for (int j = 0; j < NPT; ++j) {
       if (grp + PG * j >= N2) continue;
@@ -354,36 +388,6 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
         av[j] = av[j] + ca * kv;
       }
     }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      if (!oval[q]) continue;
-      // radiation condition with a one-sided xx0 derivative
-      const T u0 = ut[otl[q]], u1 = ut[otl[q] - 1], u2 = ut[otl[q] - 2];
-      const T v0 = osv[q], v1 = vt[ovl[q] - 1], v2 = vt[ovl[q] - 2];
-      T kuo = -oc[q] * (u0 * ori[q] + ((T)3 * u0 - (T)4 * u1 + u2) * oqd[q]);
-      T kvo = -oc[q] * (v0 * ori[q] + ((T)3 * v0 - (T)4 * v1 + v2) * oqd[q]);
-      if constexpr (CORR) {
-        kuo = ohu[q] + kuo;
-        kvo = ohv[q] + kvo;
-      }
-      if (stage == 0) {
-        oau[q] = u0 + ca * kuo;
-        oav[q] = v0 + ca * kvo;
-        osu[q] = u0 + cy * kuo;
-        osv[q] = v0 + cy * kvo;
-      } else if (stage == 3) {
-        osu[q] = oau[q] + ca * kuo;
-        osv[q] = oav[q] + ca * kvo;
-        oyu[q] = osu[q];
-        oyv[q] = osv[q];
-      } else {
-        osu[q] = oyu[q] + cy * kuo;
-        osv[q] = oyv[q] + cy * kvo;
-        oau[q] = oau[q] + ca * kuo;
-        oav[q] = oav[q] + ca * kvo;
-      }
-    }
-
     if (e < nst) {
       // publish the next stage input u, then raise this block's counter
       T* dst = (e & 1) ? a.x1 : a.x0;
