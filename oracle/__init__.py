@@ -101,9 +101,9 @@ def lib():
                                ctypes.c_long, ctypes.c_double, ctypes.c_long, _dp, ctypes.c_long,
                                _lp, _lp]
         L.or_num_threads.restype = ctypes.c_int
-        L.or_volume_mean.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.or_volume_mean.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double, _dp]
         L.or_volume_mean.restype = ctypes.c_double
-        L.or_residual_volume.argtypes = [ctypes.c_void_p]
+        L.or_residual_volume.argtypes = [ctypes.c_void_p, ctypes.c_double]
         L.or_residual_volume.restype = ctypes.c_double
         L.or_set_num_threads.argtypes = [ctypes.c_int]
         L.or_set_num_threads.restype = None
@@ -292,18 +292,20 @@ class OracleGrid:
             r = lib().or_residual_of(self._h, _p(uu), Hp)
         return (r, H.reshape(self.shape)) if want_H else r
 
-    def volume_mean(self, f: np.ndarray):
-        """(sum f J dV / sum J dV over the interior, total volume sum J dV) for a
-        padded field f."""
+    def volume_mean(self, f: np.ndarray, radius: float = 0.0):
+        """(sum f J dV / sum J dV, total volume sum J dV) over the interior cells
+        whose centre lies within `radius` of the origin (all if radius <= 0),
+        for a padded field f."""
         f = _f64(f).reshape(-1)
         assert f.size == self.npad
         vol = ctypes.c_double()
-        m = lib().or_volume_mean(self._h, _p(f), ctypes.byref(vol))
+        m = lib().or_volume_mean(self._h, _p(f), float(radius), ctypes.byref(vol))
         return m, vol.value
 
-    def residual_volume(self) -> float:
-        """Volume-weighted residual norm sqrt(sum H^2 J dV / sum J dV) of the state."""
-        return lib().or_residual_volume(self._h)
+    def residual_volume(self, radius: float = 0.0) -> float:
+        """Volume-weighted residual norm sqrt(sum H^2 J dV / sum J dV) of the
+        state, over the cells within `radius` (all if radius <= 0)."""
+        return lib().or_residual_volume(self._h, float(radius))
 
     def rk4_steps(self, eta: float, kappa: float, dt: float, nsteps: int) -> None:
         lib().or_rk4_steps(self._h, eta, kappa, dt, int(nsteps))

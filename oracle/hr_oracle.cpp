@@ -496,14 +496,21 @@ void rk4_step(Grid& g, double eta, double kappa, double dt) {
 // Volume-weighted mean of f over the interior cells: sum f J dV / sum J dV
 // with J = |h0 h1 h2| at the cell centre and dV = dxx0 dxx1 dxx2 (the
 // midpoint rule for the integral of f over the domain, divided by its volume).
-// With vol_out, also returns the total volume sum J dV.
-double volume_mean(const Grid& g, const double* f, double* vol_out) {
+// radius > 0 keeps only the cells whose centre lies at a Cartesian distance
+// below radius (an integration sphere). With vol_out, also returns the total
+// volume sum J dV of the cells taken.
+double volume_mean(const Grid& g, const double* f, double radius, double* vol_out) {
   const int NG = g.NG;
   double num = 0.0, den = 0.0;
   const double dV = g.dxx[0] * g.dxx[1] * g.dxx[2];
   for (int i2 = NG; i2 < NG + g.N[2]; ++i2)
     for (int i1 = NG; i1 < NG + g.N[1]; ++i1)
       for (int i0 = NG; i0 < NG + g.N[0]; ++i0) {
+        if (radius > 0.0) {
+          double x, y, z;
+          to_cart(g, g.xx[0][i0], g.xx[1][i1], g.xx[2][i2], x, y, z);
+          if (!(std::sqrt(x * x + y * y + z * z) < radius)) continue;
+        }
         double h[3];
         metric_at(g, g.xx[0][i0], g.xx[1][i1], h, nullptr, nullptr);
         const double w = std::fabs(h[0] * h[1] * h[2]) * dV;
@@ -739,18 +746,20 @@ double or_residual(void* h, double* Hout) {
   return residual(*g, g->u.data(), Hout);
 }
 
-// sum f J dV / sum J dV over the interior (f padded); *vol = sum J dV.
-double or_volume_mean(void* h, const double* f, double* vol) {
-  return volume_mean(*static_cast<Grid*>(h), f, vol);
+// sum f J dV / sum J dV over the interior cells within radius (all if
+// radius <= 0; f padded); *vol = sum J dV.
+double or_volume_mean(void* h, const double* f, double radius, double* vol) {
+  return volume_mean(*static_cast<Grid*>(h), f, radius, vol);
 }
 
-// Volume-weighted residual norm sqrt(sum H^2 J dV / sum J dV) of the state.
-double or_residual_volume(void* h) {
+// Volume-weighted residual norm sqrt(sum H^2 J dV / sum J dV) of the state,
+// over the cells within radius (all if radius <= 0).
+double or_residual_volume(void* h, double radius) {
   Grid& g = *static_cast<Grid*>(h);
   std::vector<double> H(g.npad(), 0.0);
   residual(g, g.u.data(), H.data());
   for (double& x : H) x = x * x;
-  return std::sqrt(volume_mean(g, H.data(), nullptr));
+  return std::sqrt(volume_mean(g, H.data(), radius, nullptr));
 }
 
 double or_residual_of(void* h, const double* u, double* Hout) {

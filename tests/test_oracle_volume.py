@@ -112,3 +112,39 @@ def test_residual_volume_is_root_volume_mean_of_H2(oracle_lib, coords, kw):
     assert abs(r_vol - np.sqrt(m)) <= 1e-14 * r_vol
     # the two norms weight the cells differently: they must not coincide
     assert abs(r_vol - r_pts) > 1e-3 * r_pts
+
+
+def test_integration_radius_on_cell_faces_is_exact(oracle_lib):
+    """Spherical with the integration radius on a cell face (r = 10 dr): the
+    cells kept are exactly those of the smaller ball, so the total volume is the
+    same closed-form midpoint sum taken over [0, R]."""
+    rmax, N0, N1, N2 = 2.0, 20, 14, 6
+    g = oracle_lib.OracleGrid(1, N0, N1, N2, 8, rmax=rmax)
+    dr, dth = rmax / N0, np.pi / N1
+    R = 10 * dr
+    exact = (R ** 3 / 3.0 - R * dr * dr / 12.0) * 2.0 * (dth / 2.0) / np.sin(dth / 2.0) * 2.0 * np.pi
+    m, vol = g.volume_mean(np.full(g.shape, 1.0), radius=R)
+    assert abs(vol / exact - 1.0) < 1e-13 and abs(m - 1.0) < 1e-14
+    # a radius beyond the domain keeps every cell
+    _, vall = g.volume_mean(np.full(g.shape, 1.0))
+    _, vbig = g.volume_mean(np.full(g.shape, 1.0), radius=10 * rmax)
+    assert vbig == vall
+
+
+@pytest.mark.parametrize("coords,kw", [(0, SINH_MILD), (2, SSPH_MILD)])
+def test_integration_sphere_volume_and_moment_converge(oracle_lib, coords, kw):
+    """A sphere of radius 1.5 inside the stretched domains (outer radius 3):
+    its volume 4 pi R^3/3 and the mean of r^2 over it, 3 R^2/5, are approached
+    as the grid is refined (the cells are cut at the sphere by their centres,
+    so the error falls at first order or better)."""
+    R = 1.5
+    V, M2 = 4.0 * np.pi * R ** 3 / 3.0, 3.0 * R * R / 5.0
+    ev, em = [], []
+    for n in (16, 32, 64):
+        g = oracle_lib.OracleGrid(coords, n, n, 16, 8, **kw)
+        X, Y, Z = g.cart()
+        m, vol = g.volume_mean(X * X + Y * Y + Z * Z, radius=R)
+        ev.append(abs(vol / V - 1.0))
+        em.append(abs(m / M2 - 1.0))
+    assert ev[-1] < 0.05 and em[-1] < 0.05, (ev, em)
+    assert ev[-1] < ev[0] / 2.0 and em[-1] < em[0] / 2.0, (ev, em)
