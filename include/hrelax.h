@@ -203,9 +203,9 @@ hr_status hr_set_v(hr_grid* g, const double* host_in, size_t n);
  * FP64: by default the grid norm over points, sqrt(sum_interior H^2 /
  * N_interior) (the grid L2 norm of the constraint violations that the paper's
  * stop test uses, Data Transfer Optimization subsection); with
- * hr_set_residual_norm(g, HR_NORM_VOLUME) the volume-weighted norm
+ * hr_set_residual_norm(g, HR_NORM_VOLUME, radius) the volume-weighted norm
  * sqrt(sum H^2 dV / sum dV), dV = |h0 h1 h2| dxx0 dxx1 dxx2 the proper cell
- * volume. */
+ * volume, optionally over the cells within an integration radius. */
 hr_status hr_residual_l2(hr_grid* g, double* out);
 
 typedef enum {
@@ -218,10 +218,16 @@ typedef enum {
  * hr_relax (the tolerance is then compared with the volume-weighted norm).
  * The volume norm takes every interior cell at its proper volume, so the fine
  * cells near the punctures count less and the large outer cells more than in
- * the point norm. Grids in a batch must use HR_NORM_POINTS (hr_batch_relax
- * returns HR_EINVAL otherwise). Errors: HR_EINVAL (null grid, unknown norm).
+ * the point norm. radius > 0 restricts the volume norm to the cells whose
+ * centre lies at a Cartesian distance below radius from the origin (both sums,
+ * H^2 dV and dV, run over those cells); radius <= 0 takes the whole grid.
+ * Called on a bound grid, it waits for the grid's stream before updating the
+ * weights on the device. Grids in a batch must use HR_NORM_POINTS
+ * (hr_batch_relax returns HR_EINVAL otherwise). Errors: HR_EINVAL (null grid,
+ * unknown norm, non-finite radius, radius > 0 with HR_NORM_POINTS, no cell
+ * centre within the radius), HR_EDEVICE.
  */
-hr_status hr_set_residual_norm(hr_grid* g, hr_norm norm);
+hr_status hr_set_residual_norm(hr_grid* g, hr_norm norm, double radius);
 
 /* cfl * ds_g. */
 hr_status hr_suggest_dt(const hr_grid* g, double cfl, double* dt);

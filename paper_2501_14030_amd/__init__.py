@@ -101,7 +101,7 @@ _SIGNATURES = {
     "hr_resolved_kernel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
                                           ctypes.POINTER(KernelConfig)]),
     "hr_set_wait_limit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint]),
-    "hr_set_residual_norm": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "hr_set_residual_norm": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_double]),
     "hr_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                    ctypes.POINTER(KernelConfig), _dp]),
     "hr_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
@@ -314,11 +314,13 @@ class Grid:
         return {"variant": cfg.variant, "streaming": cfg.streaming, "chunk": cfg.chunk,
                 "graph": cfg.graph}, us.value
 
-    def set_residual_norm(self, norm: int = NORM_POINTS) -> None:
+    def set_residual_norm(self, norm: int = NORM_POINTS, radius: float = 0.0) -> None:
         """Norm of residual_l2 and of relax's stop test: NORM_POINTS (mean of H^2
         over interior points) or NORM_VOLUME (H^2 weighted by the proper cell
-        volume)."""
-        _check(load_library().hr_set_residual_norm(self._h, int(norm)), "hr_set_residual_norm")
+        volume; radius > 0 keeps the cells whose centre lies within that
+        Cartesian radius)."""
+        _check(load_library().hr_set_residual_norm(self._h, int(norm), float(radius)),
+               "hr_set_residual_norm")
 
     def set_wait_limit(self, polls: int = 0) -> None:
         """Polls of one partner's counter before a resident-kernel wait gives up

@@ -159,10 +159,10 @@ size_t layout(hr_grid* g, char* base) {
   return off;
 }
 
-// Divisor of the residual norm: the interior point count, or the total cell
-// volume for the volume-weighted norm.
+// Divisor of the residual norm: the interior point count, or the total
+// volume of the cells the volume-weighted norm takes.
 double norm_divisor(const hr_grid* g) {
-  return g->norm ? g->tab.vol_total : (double)g->d.nint;
+  return g->norm ? g->tab.volw_total : (double)g->d.nint;
 }
 
 ResidentArgs resident_args(hr_grid* g, double eta, double dt, int nsteps) {
@@ -427,7 +427,8 @@ hr_status run_interval(hr_grid* g, int kind, int K, double eta, double dt, doubl
   if (g->graph != 0 && !resident) {
     const bool same = g->gexec && g->g_kind == kind && g->g_K == K && g->g_eta == eta &&
                       g->g_dt == dt && g->g_kappa == g->kappa_loaded && g->g_variant == variant &&
-                      g->g_chunk == chunk && g->g_streaming == streaming && g->g_norm == g->norm;
+                      g->g_chunk == chunk && g->g_streaming == streaming && g->g_norm == g->norm &&
+                      g->g_norm_radius == g->norm_radius;
     if (!same) {
       if (g->gexec) {
         (void)hipGraphExecDestroy(g->gexec);
@@ -457,6 +458,7 @@ hr_status run_interval(hr_grid* g, int kind, int K, double eta, double dt, doubl
       g->g_chunk = chunk;
       g->g_streaming = streaming;
       g->g_norm = g->norm;
+      g->g_norm_radius = g->norm_radius;
     }
     HR_HIP(hipGraphLaunch(g->gexec, g->stream));
   } else {
@@ -730,7 +732,7 @@ hr_status hr_grid_bind(hr_grid* g, void* dev_ptr, size_t bytes, void* hip_stream
                         hipMemcpyHostToDevice, g->stream));
   HR_HIP(hipMemcpyAsync(g->sphi, g->tab.sphi.data(), d.N2 * sizeof(double),
                         hipMemcpyHostToDevice, g->stream));
-  HR_HIP(hipMemcpyAsync(g->vol, g->tab.vol.data(), g->tab.vol.size() * sizeof(double),
+  HR_HIP(hipMemcpyAsync(g->vol, g->tab.volw.data(), g->tab.volw.size() * sizeof(double),
                         hipMemcpyHostToDevice, g->stream));
   const int G = (int)g->G;
   double* z64[] = {g->f64.un, g->f64.vn, g->f64.ua, g->f64.va, g->f64.ub,
@@ -1014,10 +1016,34 @@ hr_status hr_resolved_kernel(const hr_grid* g, hr_precision prec, hr_kernel_conf
   return HR_OK;
 }
 
-hr_status hr_set_residual_norm(hr_grid* g, hr_norm norm) {
+hr_status hr_set_residual_norm(hr_grid* g, hr_norm norm, double radius) {
   if (!g) return fail(HR_EINVAL, "null grid handle");
   if (norm != HR_NORM_POINTS && norm != HR_NORM_VOLUME) return fail(HR_EINVAL, "unknown norm");
+  if (!std::isfinite(radius)) return fail(HR_EINVAL, "radius must be finite");
+  if (norm == HR_NORM_POINTS && radius > 0.0)
+    return fail(HR_EINVAL, "an integration radius applies to HR_NORM_VOLUME only");
+  const Dims& d = g->d;
+  std::vector<double> w(g->tab.vol);
+  double tot = g->tab.vol_total;
+  if (radius > 0.0) {
+    tot = 0.0;
+    for (int i1 = 0; i1 < d.N1; ++i1)
+      for (int i0 = 0; i0 < d.N0; ++i0) {
+        const int k = i0 + d.N0 * i1;
+        if (!(g->tab.rcart[i0 + d.P0 * i1] < radius)) w[k] = 0.0;
+        tot += w[k] * d.N2;
+      }
+    if (!(tot > 0.0)) return fail(HR_EINVAL, "no interior cell centre lies within the radius");
+  }
+  if (g->bound) {
+    // the grid's stream may still run a relaxation that reads the weights
+    HR_HIP(hipStreamSynchronize(g->stream));
+    HR_HIP(hipMemcpy(g->vol, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  g->tab.volw.swap(w);
+  g->tab.volw_total = tot;
   g->norm = norm == HR_NORM_VOLUME ? 1 : 0;
+  g->norm_radius = radius > 0.0 ? radius : 0.0;
   return HR_OK;
 }
 

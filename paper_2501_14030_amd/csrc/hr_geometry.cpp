@@ -174,6 +174,8 @@ bool build_tables(hr_coords coords, const Dims& d, const hr_grid_params& p,
     return false;
   }
   t.ds_g = dsg;
+  t.volw = t.vol;
+  t.volw_total = t.vol_total;
   for (int i1 = 0; i1 < d.N1; ++i1)
     for (int i0 = 0; i0 < d.P0; ++i0) {
       const int e = i0 + d.P0 * i1;

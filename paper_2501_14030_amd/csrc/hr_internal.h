@@ -242,6 +242,9 @@ struct HostTables {
   std::vector<double> sphi;    // N2
   std::vector<double> vol;     // N0*N1: cell volume |h0 h1 h2| dxx0 dxx1 dxx2 (any plane)
   double vol_total = 0.0;      // sum of the cell volumes over the interior
+  std::vector<double> volw;    // N0*N1: weights of the volume norm (vol, zero for cells
+                               // whose centre lies beyond the integration radius)
+  double volw_total = 0.0;     // sum of the weights over the interior
 };
 
 bool build_tables(hr_coords coords, const Dims& d, const hr_grid_params& p,
@@ -282,6 +285,7 @@ struct hr_grid {
   double kappa_loaded = -1.0;   // wave-speed scale currently in fac/ofac
 
   int norm = 0;                 // residual norm: 0 over points, 1 volume-weighted
+  double norm_radius = 0.0;     // integration radius of the volume norm (<= 0: whole grid)
   int variant = 0;              // kernel variant: 0 auto, 1 plane tiles, 2 phi columns,
                                 // 3 resident (FP64 steps in one launch, state on chip)
   int res_nbx = 0, res_nby = 0; // resident patches (0: grid not eligible)
@@ -297,7 +301,7 @@ struct hr_grid {
   int graph = -1;               // graph capture of check intervals: -1 auto (on), 0, 1
   hipGraphExec_t gexec = nullptr;  // captured check interval and its key
   int g_kind = -1, g_K = 0, g_variant = 0, g_chunk = 0, g_streaming = 0, g_norm = 0;
-  double g_eta = 0, g_dt = 0, g_kappa = 0;
+  double g_eta = 0, g_dt = 0, g_kappa = 0, g_norm_radius = 0;
 
   // FP32 -> FP64 switch rule (sw_residual 0: ten times the tolerance)
   double sw_residual = 0.0;

@@ -102,3 +102,21 @@ def test_suggested_dt_matches_oracle(lib, oracle_lib, spec):
                                rmax=spec.rmax)
     np.testing.assert_allclose(dt.value, og.suggest_dt(0.5), rtol=1e-15)
     lib.hr_grid_destroy(h)
+
+
+def test_residual_norm_arguments_on_an_unbound_grid(lib):
+    """hr_set_residual_norm validates its arguments on the host (no device
+    call on a grid that is not bound)."""
+    p = hr.default_params(rmax=2.0)
+    st, h = _create(lib, 1, 20, 14, 6, 8, p)
+    assert st == hr.OK
+    f = lib.hr_set_residual_norm
+    assert f(h, hr.NORM_VOLUME, 0.0) == hr.OK
+    assert f(h, hr.NORM_VOLUME, 1.0) == hr.OK            # cells with r < 1 kept
+    assert f(h, hr.NORM_VOLUME, 1e-6) == hr.EINVAL       # no cell centre inside
+    assert f(h, hr.NORM_POINTS, 1.0) == hr.EINVAL        # radius needs the volume norm
+    assert f(h, hr.NORM_VOLUME, float("inf")) == hr.EINVAL
+    assert f(h, 7, 0.0) == hr.EINVAL
+    assert f(None, hr.NORM_POINTS, 0.0) == hr.EINVAL
+    assert f(h, hr.NORM_POINTS, 0.0) == hr.OK
+    lib.hr_grid_destroy(h)

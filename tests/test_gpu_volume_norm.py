@@ -82,12 +82,49 @@ def test_volume_norm_stop_test(spec, label):
                                atol=1e-10 * hist[0])
 
 
+@pytest.mark.parametrize("spec,label", [SPECS[0], SPECS[2]])
+def test_volume_norm_integration_radius(spec, label):
+    banner(f"volume norm with integration radius {label}")
+    og, gg, dt = _pair(spec)
+    X, Y, Z = og.cart()
+    ri = np.sqrt(X ** 2 + Y ** 2 + Z ** 2)[og.NG, og.NG:-og.NG, og.NG:-og.NG]
+    # about half of the cells inside; the radius sits halfway between two cell
+    # centre distances so that no cell is a rounding-dependent tie
+    # (distances equal up to rounding, e.g. one Spherical shell, are merged)
+    scale = float(ri.max())
+    rs = np.unique(np.round(ri / scale, 9)) * scale
+    k = len(rs) // 2
+    R = 0.5 * float(rs[k] + rs[k + 1])
+    gg.set_residual_norm(hr.NORM_VOLUME, R)
+    np.testing.assert_allclose(gg.residual_l2(), og.residual_volume(R), rtol=1e-13)
+    og.relax(8.0, 1.0, dt, 300, 0.0, 100)
+    res = gg.relax(8.0, 1.0, dt, 300, 0.0, check_every=100)
+    assert res.status == hr.OK
+    rv = gg.residual_l2()
+    banner(f"radius {R:.6g}: gpu {rv:.12e} oracle {og.residual_volume(R):.12e}")
+    np.testing.assert_allclose(rv, og.residual_volume(R), rtol=RTOL)
+    np.testing.assert_allclose(res.history[-1], rv, rtol=1e-14)
+    # another radius on the same state, then the whole grid again
+    R2 = 0.5 * float(rs[-2] + rs[-1])  # all but the outermost cells
+    gg.set_residual_norm(hr.NORM_VOLUME, R2)
+    banner(f"radius {R2:.6g}: gpu {gg.residual_l2():.12e} oracle {og.residual_volume(R2):.12e}")
+    np.testing.assert_allclose(gg.residual_l2(), og.residual_volume(R2), rtol=RTOL)
+    gg.set_residual_norm(hr.NORM_VOLUME)
+    np.testing.assert_allclose(gg.residual_l2(), og.residual_volume(), rtol=RTOL)
+
+
 def test_volume_norm_errors():
     banner("volume norm errors")
     spec = SPECS[0][0]
     _, gg, _ = _pair(spec)
     with pytest.raises(hr.HRError):
         gg.set_residual_norm(2)
+    with pytest.raises(hr.HRError):
+        gg.set_residual_norm(hr.NORM_POINTS, 1.0)     # a radius needs the volume norm
+    with pytest.raises(hr.HRError):
+        gg.set_residual_norm(hr.NORM_VOLUME, 1e-9)    # no cell centre inside
+    with pytest.raises(hr.HRError):
+        gg.set_residual_norm(hr.NORM_VOLUME, float("nan"))
     gg.set_residual_norm(hr.NORM_VOLUME)
     b = hr.Batch([gg])
     try:
