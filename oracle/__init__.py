@@ -105,6 +105,8 @@ def lib():
         L.or_volume_mean.restype = ctypes.c_double
         L.or_residual_volume.argtypes = [ctypes.c_void_p, ctypes.c_double]
         L.or_residual_volume.restype = ctypes.c_double
+        L.or_set_bc_order.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.or_set_bc_order.restype = ctypes.c_int
         L.or_set_num_threads.argtypes = [ctypes.c_int]
         L.or_set_num_threads.restype = None
         _lib = L
@@ -306,6 +308,12 @@ class OracleGrid:
         """Volume-weighted residual norm sqrt(sum H^2 J dV / sum J dV) of the
         state, over the cells within `radius` (all if radius <= 0)."""
         return lib().or_residual_volume(self._h, float(radius))
+
+    def set_bc_order(self, order: int) -> None:
+        """Order (2 or 4) of the one-sided xx0 difference in the outer radiation
+        condition (2 by default)."""
+        if lib().or_set_bc_order(self._h, int(order)) != 0:
+            raise ValueError(f"bc order {order} not available on this grid")
 
     def rk4_steps(self, eta: float, kappa: float, dt: float, nsteps: int) -> None:
         lib().or_rk4_steps(self._h, eta, kappa, dt, int(nsteps))

@@ -117,6 +117,10 @@ struct Grid {
   double ds_g;
   // outer-boundary geometry on the padded (i0,i1) plane
   std::vector<double> rcart, drdxx0;
+  // radiation condition: order of the one-sided xx0 difference (2 or 4) and
+  // its weights for the offsets 0, -1, ..., -order (Fornberg, spacing 1)
+  int bc_order = 2;
+  std::vector<double> wbc;
   // Cartesian coordinates of every padded point
   std::vector<double> X, Y, Z;
   // constant sources on every padded point
@@ -436,9 +440,22 @@ void rhs(const Grid& g, double eta, double kappa, const double* u,
         const double c = kappa * g.dsmin[k2] / g.ds_g;
         const double r = g.rcart[k2];
         const double drdx = g.drdxx0[k2];
-        const long im1 = g.idx(i0 - 1, i1, i2), im2 = g.idx(i0 - 2, i1, i2);
-        const double dudx = (3.0 * u[id] - 4.0 * u[im1] + u[im2]) / (2.0 * g.dxx[0]);
-        const double dvdx = (3.0 * v[id] - 4.0 * v[im1] + v[im2]) / (2.0 * g.dxx[0]);
+        double dudx, dvdx;
+        if (g.bc_order == 2) {
+          const long im1 = g.idx(i0 - 1, i1, i2), im2 = g.idx(i0 - 2, i1, i2);
+          dudx = (3.0 * u[id] - 4.0 * u[im1] + u[im2]) / (2.0 * g.dxx[0]);
+          dvdx = (3.0 * v[id] - 4.0 * v[im1] + v[im2]) / (2.0 * g.dxx[0]);
+        } else {
+          dudx = 0.0;
+          dvdx = 0.0;
+          for (int k = 0; k <= g.bc_order; ++k) {
+            const long ik = g.idx(i0 - k, i1, i2);
+            dudx += g.wbc[k] * u[ik];
+            dvdx += g.wbc[k] * v[ik];
+          }
+          dudx /= g.dxx[0];
+          dvdx /= g.dxx[0];
+        }
         ku[id] = -c * (u[id] / r + dudx / drdx);
         kv[id] = -c * (v[id] / r + dvdx / drdx);
       }
@@ -491,6 +508,23 @@ void rk4_step(Grid& g, double eta, double kappa, double dt) {
     u[i] = u[i] + dt / 6.0 * (k1u[i] + 2.0 * k2u[i] + 2.0 * k3u[i] + k4u[i]);
     v[i] = v[i] + dt / 6.0 * (k1v[i] + 2.0 * k2v[i] + 2.0 * k3v[i] + k4v[i]);
   }
+}
+
+// One-sided first-derivative weights of the radiation condition: the
+// derivative at offset 0 of the polynomial through the offsets 0, -1, ...,
+// -order (unit spacing), order 2 or 4. Order 2 is evaluated in the rhs as
+// (3 f0 - 4 f1 + f2) / 2 directly.
+bool set_bc_order(Grid& g, int order) {
+  if (order != 2 && order != 4) return false;
+  if (g.N[0] < order) return false;  // the difference stays on interior points
+  std::vector<double> off(order + 1);
+  for (int k = 0; k <= order; ++k) off[k] = -k;
+  std::vector<std::vector<double>> c;
+  fornberg_weights(0.0, off, 1, c);
+  g.wbc.assign(order + 1, 0.0);
+  for (int k = 0; k <= order; ++k) g.wbc[k] = c[k][1];
+  g.bc_order = order;
+  return true;
 }
 
 // Volume-weighted mean of f over the interior cells: sum f J dV / sum J dV
@@ -569,6 +603,7 @@ void* or_create(int coords, int N0, int N1, int N2, int fd_order, double amax,
   g->b = bscale;
   g->rmax = rmax;
   build_grid(*g);
+  set_bc_order(*g, 2);
   return g;
 }
 
@@ -805,6 +840,12 @@ int or_relax(void* h, double eta, double kappa, double dt, long n_steps,
   if (steps_taken) *steps_taken = s;
   if (n_hist) *n_hist = nh;
   return status;
+}
+
+// Order (2 or 4) of the one-sided xx0 difference in the radiation
+// condition; returns 0, or -1 for another order.
+int or_set_bc_order(void* h, int order) {
+  return set_bc_order(*static_cast<Grid*>(h), order) ? 0 : -1;
 }
 
 int or_num_threads(void) { return omp_get_max_threads(); }
