@@ -270,6 +270,18 @@ hr_status hr_set_kernel_config(hr_grid* g, const hr_kernel_config* cfg);
 hr_status hr_get_kernel_config(const hr_grid* g, hr_kernel_config* cfg);
 
 /*
+ * Order of the one-sided xx0 difference in the outer radiation condition
+ * k_f = -c (f/r + d_r f), with d_r f = (d f / d xx0) / (dr / d xx0) at each
+ * outer point (the outer-boundary step of the paper's Algorithm 1; the
+ * condition itself comes from the companion paper): 2 (default) takes the
+ * point and two inner neighbours along xx0, 4 the point and four. The steady
+ * state depends on the choice through the boundary only. Applies to every
+ * precision, kernel variant and to batches. Errors: HR_EINVAL (null grid,
+ * order not 2 or 4, N0 < order).
+ */
+hr_status hr_set_outer_bc_order(hr_grid* g, int order);
+
+/*
  * Bound on the resident kernel's exchange waits: a block gives up after this
  * many polls of one partner's stage counter (each poll is one memory round
  * trip, ~1-2 us), sets an error word, and every block leaves its loop; the

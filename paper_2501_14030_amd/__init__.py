@@ -101,6 +101,7 @@ _SIGNATURES = {
     "hr_resolved_kernel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
                                           ctypes.POINTER(KernelConfig)]),
     "hr_set_wait_limit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint]),
+    "hr_set_outer_bc_order": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "hr_set_residual_norm": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_double]),
     "hr_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                    ctypes.POINTER(KernelConfig), _dp]),
@@ -321,6 +322,11 @@ class Grid:
         Cartesian radius)."""
         _check(load_library().hr_set_residual_norm(self._h, int(norm), float(radius)),
                "hr_set_residual_norm")
+
+    def set_outer_bc_order(self, order: int = 2) -> None:
+        """Order (2 or 4) of the one-sided xx0 difference in the outer radiation
+        condition."""
+        _check(load_library().hr_set_outer_bc_order(self._h, int(order)), "hr_set_outer_bc_order")
 
     def set_wait_limit(self, polls: int = 0) -> None:
         """Polls of one partner's counter before a resident-kernel wait gives up

@@ -187,6 +187,7 @@ ResidentArgs resident_args(hr_grid* g, double eta, double dt, int nsteps) {
   r.nby = g->res_nby;
   r.nsteps = nsteps;
   r.spin_limit = g->res_wait_limit;
+  r.bc4 = g->bc_order == 4 ? 1 : 0;
   return r;
 }
 
@@ -216,6 +217,7 @@ ResidentArgsT<float> resident_args_split(hr_grid* g, float eta, float dt, int ns
   r.nby = g->res_nby;
   r.nsteps = nsteps;
   r.spin_limit = g->res_wait_limit;
+  r.bc4 = g->bc_order == 4 ? 1 : 0;
   return r;
 }
 
@@ -392,6 +394,7 @@ BaseArgs base_args(const hr_grid* g, double eta) {
   b.sp7 = g->f32.sp7;
   b.eu = g->f32.un;
   b.ev = g->f32.vn;
+  b.bc4 = g->bc_order == 4 ? 1 : 0;
   return b;
 }
 
@@ -428,7 +431,7 @@ hr_status run_interval(hr_grid* g, int kind, int K, double eta, double dt, doubl
     const bool same = g->gexec && g->g_kind == kind && g->g_K == K && g->g_eta == eta &&
                       g->g_dt == dt && g->g_kappa == g->kappa_loaded && g->g_variant == variant &&
                       g->g_chunk == chunk && g->g_streaming == streaming && g->g_norm == g->norm &&
-                      g->g_norm_radius == g->norm_radius;
+                      g->g_norm_radius == g->norm_radius && g->g_bc == g->bc_order;
     if (!same) {
       if (g->gexec) {
         (void)hipGraphExecDestroy(g->gexec);
@@ -459,6 +462,7 @@ hr_status run_interval(hr_grid* g, int kind, int K, double eta, double dt, doubl
       g->g_streaming = streaming;
       g->g_norm = g->norm;
       g->g_norm_radius = g->norm_radius;
+      g->g_bc = g->bc_order;
     }
     HR_HIP(hipGraphLaunch(g->gexec, g->stream));
   } else {
@@ -1044,6 +1048,15 @@ hr_status hr_set_residual_norm(hr_grid* g, hr_norm norm, double radius) {
   g->tab.volw_total = tot;
   g->norm = norm == HR_NORM_VOLUME ? 1 : 0;
   g->norm_radius = radius > 0.0 ? radius : 0.0;
+  return HR_OK;
+}
+
+hr_status hr_set_outer_bc_order(hr_grid* g, int order) {
+  if (!g) return fail(HR_EINVAL, "null grid handle");
+  if (order != 2 && order != 4) return fail(HR_EINVAL, "outer boundary order must be 2 or 4");
+  if (order > g->d.N0)
+    return fail(HR_EINVAL, "the one-sided difference needs N0 >= its order");
+  g->bc_order = order;
   return HR_OK;
 }
 

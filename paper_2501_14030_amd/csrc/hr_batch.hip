@@ -341,6 +341,7 @@ hr_status hr_batch_relax(hr_batch* b, const double* eta, const double* c, long n
     ba.sp7 = g->f32.sp7;
     ba.eu = g->f32.un;
     ba.ev = g->f32.vn;
+    ba.bc4 = g->bc_order == 4 ? 1 : 0;
     hba[i] = ba;
     hrb[i] = RebaseArgs{g->f64.un, g->f64.vn, g->f32.un, g->f32.vn, (int)g->G};
     if (reps) {

@@ -286,10 +286,13 @@ __global__ void __launch_bounds__(kTileThreads) k_stage(StageArgs<T> a) {
     const T c = a.ofac[ko], rinv = a.ofac[o2d + ko], qd = a.ofac[2 * o2d + ko];
     const T u0 = a.uin[o], u1 = a.uin[o - 1], u2 = a.uin[o - 2];
     const T v0 = a.vin[o], v1 = a.vin[o - 1], v2 = a.vin[o - 2];
+    const bool bc4 = a.bc4 != 0;
+    const T u3 = bc4 ? a.uin[o - 3] : (T)0, u4 = bc4 ? a.uin[o - 4] : (T)0;
+    const T v3 = bc4 ? a.vin[o - 3] : (T)0, v4 = bc4 ? a.vin[o - 4] : (T)0;
     CombineIn<STAGE, NT, T> co;
     co.load(a, o);
-    T kuo = -c * (u0 * rinv + ((T)3 * u0 - (T)4 * u1 + u2) * qd);
-    T kvo = -c * (v0 * rinv + ((T)3 * v0 - (T)4 * v1 + v2) * qd);
+    T kuo = -c * (u0 * rinv + outer_diff(u0, u1, u2, u3, u4, qd, bc4));
+    T kvo = -c * (v0 * rinv + outer_diff(v0, v1, v2, v3, v4, qd, bc4));
     if constexpr (CORR) {
       kuo = a.khu[o] + kuo;
       kvo = a.khv[o] + kvo;
@@ -490,10 +493,13 @@ __device__ __forceinline__ void stage_col_body(const StageArgs<T>& a, int bx, in
         const T c = a.ofac[ko], rinv = a.ofac[o2d + ko], qd = a.ofac[2 * o2d + ko];
         const T u0 = a.uin[o], u1 = a.uin[o - 1], u2 = a.uin[o - 2];
         const T v0 = a.vin[o], v1 = a.vin[o - 1], v2 = a.vin[o - 2];
+        const bool bc4 = a.bc4 != 0;
+        const T u3 = bc4 ? a.uin[o - 3] : (T)0, u4 = bc4 ? a.uin[o - 4] : (T)0;
+        const T v3 = bc4 ? a.vin[o - 3] : (T)0, v4 = bc4 ? a.vin[o - 4] : (T)0;
         CombineIn<STAGE, false, T> co;
         co.load(a, o);
-        T kuo = -c * (u0 * rinv + ((T)3 * u0 - (T)4 * u1 + u2) * qd);
-        T kvo = -c * (v0 * rinv + ((T)3 * v0 - (T)4 * v1 + v2) * qd);
+        T kuo = -c * (u0 * rinv + outer_diff(u0, u1, u2, u3, u4, qd, bc4));
+        T kvo = -c * (v0 * rinv + outer_diff(v0, v1, v2, v3, v4, qd, bc4));
         if constexpr (CORR) {
           kuo = a.khu[o] + kuo;
           kvo = a.khv[o] + kvo;
@@ -602,8 +608,11 @@ __device__ __forceinline__ void base_body(const BaseArgs& a, int bx, int by, int
     const double c = a.ofac[ko], rinv = a.ofac[o2d + ko], qd = a.ofac[2 * o2d + ko];
     const double u0 = a.u[o], u1 = a.u[o - 1], u2 = a.u[o - 2];
     const double v0 = a.v[o], v1 = a.v[o - 1], v2 = a.v[o - 2];
-    a.khu[o] = (float)(-c * (u0 * rinv + (3.0 * u0 - 4.0 * u1 + u2) * qd));
-    a.khv[o] = (float)(-c * (v0 * rinv + (3.0 * v0 - 4.0 * v1 + v2) * qd));
+    const bool bc4 = a.bc4 != 0;
+    const double u3 = bc4 ? a.u[o - 3] : 0.0, u4 = bc4 ? a.u[o - 4] : 0.0;
+    const double v3 = bc4 ? a.v[o - 3] : 0.0, v4 = bc4 ? a.v[o - 4] : 0.0;
+    a.khu[o] = (float)(-c * (u0 * rinv + outer_diff(u0, u1, u2, u3, u4, qd, bc4)));
+    a.khv[o] = (float)(-c * (v0 * rinv + outer_diff(v0, v1, v2, v3, v4, qd, bc4)));
     a.pb[o] = (float)(a.psi[o] + u0);
     a.sp7[o] = 0.0f;
     a.eu[o] = 0.0f;

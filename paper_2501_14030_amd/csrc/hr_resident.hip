@@ -234,12 +234,12 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
     const int stage = (e - 1) & 3;
     // (1) stage input of the patch into LDS: own points and own outer points
     // from registers; v only where the outer points' radiation condition
-    // reads it (the last two interior columns and the outer points)
+    // reads it (the last four interior columns and the outer points)
 #pragma unroll
     for (int j = 0; j < NPT; ++j) {
       if (grp + PG * j < N2) {
         ut[lidx[j]] = su[j];
-        if (last && x0l >= RB - 2) vt[vidx[j]] = sv[j];
+        if (last && x0l >= RB - 4) vt[vidx[j]] = sv[j];
       }
     }
 #pragma unroll
@@ -314,8 +314,11 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
       // radiation condition with a one-sided xx0 derivative
       const T u0 = ut[otl[q]], u1 = ut[otl[q] - 1], u2 = ut[otl[q] - 2];
       const T v0 = osv[q], v1 = vt[ovl[q] - 1], v2 = vt[ovl[q] - 2];
-      T kuo = -oc[q] * (u0 * ori[q] + ((T)3 * u0 - (T)4 * u1 + u2) * oqd[q]);
-      T kvo = -oc[q] * (v0 * ori[q] + ((T)3 * v0 - (T)4 * v1 + v2) * oqd[q]);
+      const bool bc4 = a.bc4 != 0;
+      const T u3 = bc4 ? ut[otl[q] - 3] : (T)0, u4 = bc4 ? ut[otl[q] - 4] : (T)0;
+      const T v3 = bc4 ? vt[ovl[q] - 3] : (T)0, v4 = bc4 ? vt[ovl[q] - 4] : (T)0;
+      T kuo = -oc[q] * (u0 * ori[q] + outer_diff(u0, u1, u2, u3, u4, oqd[q], bc4));
+      T kvo = -oc[q] * (v0 * ori[q] + outer_diff(v0, v1, v2, v3, v4, oqd[q], bc4));
       if constexpr (CORR) {
         kuo = ohu[q] + kuo;
         kvo = ohv[q] + kvo;

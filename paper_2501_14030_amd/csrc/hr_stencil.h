@@ -53,6 +53,20 @@ __device__ __forceinline__ float source_delta(float sp7, float pb, float e) {
   return sp7 * expm1f(-7.0f * log1pf(e / pb));
 }
 
+// Radial-derivative term of the outer radiation condition, qd x (one-sided
+// xx0 difference of f at an outer point, times 2 dxx0), with qd = 1 /
+// (2 dxx0 dr/dxx0) and f0 the point itself, f1 ... its inner neighbours along
+// xx0: second order (3 f0 - 4 f1 + f2) / 2, or with bc4 fourth order
+// (25 f0 - 48 f1 + 36 f2 - 16 f3 + 3 f4) / 12, the derivative at f0 of the
+// quartic through the five values.
+template <typename T>
+__device__ __forceinline__ T outer_diff(T f0, T f1, T f2, T f3, T f4, T qd, bool bc4) {
+  if (bc4)
+    return ((T)25 * f0 - (T)48 * f1 + (T)36 * f2 - (T)16 * f3 + (T)3 * f4) *
+           (qd * (T)(1.0 / 6.0));
+  return ((T)3 * f0 - (T)4 * f1 + f2) * qd;
+}
+
 // Plane index of phi + pi (N2 even).
 __device__ __forceinline__ int half_turn(int i2, int N2) {
   const int h = i2 + (N2 >> 1);

@@ -120,3 +120,20 @@ def test_residual_norm_arguments_on_an_unbound_grid(lib):
     assert f(None, hr.NORM_POINTS, 0.0) == hr.EINVAL
     assert f(h, hr.NORM_POINTS, 0.0) == hr.OK
     lib.hr_grid_destroy(h)
+
+
+def test_outer_bc_order_arguments(lib):
+    p = hr.default_params(rmax=2.0)
+    st, h = _create(lib, 1, 20, 14, 6, 8, p)
+    assert st == hr.OK
+    f = lib.hr_set_outer_bc_order
+    assert f(h, 4) == hr.OK and f(h, 2) == hr.OK
+    for bad in (0, 1, 3, 6):
+        assert f(h, bad) == hr.EINVAL
+    assert f(None, 2) == hr.EINVAL
+    lib.hr_grid_destroy(h)
+    st, h = _create(lib, 1, 3, 14, 6, 4, p)          # N0 = 3 < 4
+    assert st == hr.OK
+    assert lib.hr_set_outer_bc_order(h, 4) == hr.EINVAL
+    assert lib.hr_set_outer_bc_order(h, 2) == hr.OK
+    lib.hr_grid_destroy(h)
