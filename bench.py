@@ -335,6 +335,7 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--no-spherical", action="store_true")
     ap.add_argument("--kernel-profile", metavar="N0xN1xN2", default=None,
                     help="only run the stage kernels at this shape (counter passes)")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32"])
@@ -438,6 +439,32 @@ def main() -> int:
             "max_rel_diff_u_vs_fp64": float(np.abs(u32 - u64).max() / np.abs(u64).max()),
             "speedup_time_to_residual": (t64 / args.steps) / (t32 / args.steps),
         }
+    if not args.no_spherical:
+        # the same physics on the Spherical 128x64x8 grid (rmax 100), its own eta
+        ws = workloads.paper_scale(workloads.SPHERICAL, 10)
+        ss = ws.grid
+        gs = hr.grid_create(ss.coords, ss.N0, ss.N1, ss.N2, ss.fd_order,
+                            params=hr.default_params(rmax=ss.rmax))
+        rs64, ts64, tms64 = timed_solves(hr, torch, gs, ws, hr.FP64, args.steps, args.warmup,
+                                         "spherical fp64")
+        gs.set_fp32_switch(0.0, 8, 0)
+        rs32, ts32, tms32 = timed_solves(hr, torch, gs, ws, hr.FP32_FP64FINISH, args.steps, 0,
+                                         "spherical fp32+fp64")
+        out["spherical"] = {
+            "workload": f"paper-scale Spherical {ss.N0}x{ss.N1}x{ss.N2}, 10th-order FD, "
+                        f"rmax {ss.rmax}, same punctures, eta {ws.eta}, to residual 1e-10",
+            "value": sum(ss.n_interior * 4 * r.steps_taken for r in rs64) / ts64,
+            "time_to_residual_s": ts64 / args.steps,
+            "relax_median_s": float(np.median([t[1] for t in tms64])),
+            "rk4_steps_to_tol": rs64[-1].steps_taken,
+            "final_residual": rs64[-1].residual,
+            "kernel": gs.resolved_kernel(hr.FP64),
+            "mixed_value": sum(ss.n_interior * 4 * r.steps_taken for r in rs32) / ts32,
+            "mixed_time_to_residual_s": ts32 / args.steps,
+            "mixed_rk4_steps_to_tol": rs32[-1].steps_taken,
+            "mixed_fp32_steps": rs32[-1].fp32_steps,
+        }
+        gs.close()
     # roofline of the dominant kernel (the resident RK4 kernel at this size)
     g.set_punctures(*w.punctures.as_tuple())
     copy = copy_bandwidth(torch)

@@ -71,8 +71,9 @@ def test_parity_shapes_orders_coords(spec, label):
     np.testing.assert_allclose(res.history, ohist, rtol=1e-7, atol=1e-15)
 
 
-def test_paper_scale_grid_parity_200_steps():
-    w = workloads.paper_scale()
+@pytest.mark.parametrize("coords", [workloads.SINHSYMTP, workloads.SPHERICAL])
+def test_paper_scale_grid_parity_200_steps(coords):
+    w = workloads.paper_scale(coords)
     banner(f"paper-scale parity {w.grid.name()} 200 steps")
     og, gg, ou, ov, ohist, res = _run_both(w.grid, w.punctures, w.eta, 200, 100)
     du = rel_maxdiff(gg.get_u(extended=True), oracle_extended(og, ou))
