@@ -358,8 +358,8 @@ def main() -> int:
     if args.copy_calibration:
         return copy_calibration()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the relaxation of "
-              "one grid is not sharded across GPUs in this build.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the relaxation of "
+              "one grid runs on a single GPU and is not sharded across GPUs.", file=sys.stderr)
         return 2
 
     import torch

@@ -1,8 +1,8 @@
 """Learned warm start: data from the relaxation's own solves, training with the
 library's MLP kernels, and evaluation against the zero initial guess.
 
-The relaxation stays the judge: a warm-started grid is relaxed to the same
-residual tolerance as a cold one, and only the steps and time differ.
+The relaxation still decides convergence: a warm-started grid is relaxed to
+the same residual tolerance as a cold one, and only the steps and time differ.
 
 Run the catalog experiment with ``python -m paper_2501_14030_amd.warmstart``.
 """
