@@ -289,6 +289,42 @@ def timed_solves(hr, torch, g, w, precision, steps, warmup, label):
     return results, t1 - t0, times
 
 
+def precision_form_runs(hr, torch):
+    """The single-precision forms on the 8th-order precision-form grids
+    (equal-mass small-case physics), each relaxed once to residual 1e-10: FP64,
+    the split FP32 bulk with an FP64 finish, and the same with bfloat16 metric
+    factors; errors are stated against the FP64 solution of the same grid."""
+    from paper_2501_14030_amd import workloads
+    res = {}
+    for shape in ((128, 128, 16), (256, 256, 32)):
+        w = workloads.precision_form(*shape)
+        s = w.grid
+        g = hr.grid_create(s.coords, s.N0, s.N1, s.N2, s.fd_order,
+                           params=hr.default_params(bscale=s.bscale))
+        g.set_fp32_switch(0.0, 8, 0)
+        entry = {"grid": list(shape), "fd_order": s.fd_order, "eta": w.eta, "tol": w.tol}
+        u64 = None
+        for label, prec, bits in (("fp64", hr.FP64, 32), ("split", hr.FP32_FP64FINISH, 32),
+                                  ("split_bf16_factors", hr.FP32_FP64FINISH, 16)):
+            g.set_factor_storage(bits)
+            times = []
+            r = run_solve(hr, torch, g, w, prec, times)
+            u = g.get_u()
+            if u64 is None:
+                u64 = u
+            e = {"time_to_residual_s": times[0][1], "rk4_steps_to_tol": r.steps_taken,
+                 "fp32_steps": r.fp32_steps, "final_residual": r.residual, "status": r.status,
+                 "updates_per_s": s.n_interior * 4 * r.steps_taken / times[0][1],
+                 "max_rel_diff_u_vs_fp64": float(np.abs(u - u64).max() / np.abs(u64).max())}
+            log(f"precision form {s.name()} {label}: {r.steps_taken} steps ({r.fp32_steps} fp32), "
+                f"residual {r.residual:.3e}, {times[0][1]:.3f} s, "
+                f"diff vs fp64 {e['max_rel_diff_u_vs_fp64']:.2e}")
+            entry[label] = e
+        res[s.name()] = entry
+        g.close()
+    return res
+
+
 def cpu_baseline(w, budget_s: float):
     """The oracle as it is, on the host cores, on a bounded sample of the same
     workload: RK4 steps of the same grid from the same initial state."""
@@ -336,6 +372,7 @@ def main() -> int:
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-spherical", action="store_true")
+    ap.add_argument("--no-precision-form", action="store_true")
     ap.add_argument("--kernel-profile", metavar="N0xN1xN2", default=None,
                     help="only run the stage kernels at this shape (counter passes)")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32"])
@@ -465,6 +502,8 @@ def main() -> int:
             "mixed_fp32_steps": rs32[-1].fp32_steps,
         }
         gs.close()
+    if not args.no_precision_form:
+        out["precision_form"] = precision_form_runs(hr, torch)
     # roofline of the dominant kernel (the resident RK4 kernel at this size)
     g.set_punctures(*w.punctures.as_tuple())
     copy = copy_bandwidth(torch)

@@ -282,6 +282,19 @@ hr_status hr_get_kernel_config(const hr_grid* g, hr_kernel_config* cfg);
 hr_status hr_set_outer_bc_order(hr_grid* g, int order);
 
 /*
+ * Storage of the metric-factor planes (the five Laplacian coefficients and
+ * c^2 per (xx0, xx1)) read by the single-precision stages (HR_FP32 and the
+ * FP32 increment of HR_FP32_FP64FINISH): bits = 32 (default) reads FP32
+ * copies, bits = 16 reads bfloat16 copies (the FP32 values rounded to the
+ * nearest 8-bit-mantissa value, widened in the kernel). IEEE half precision
+ * cannot hold the range of these factors (near the axis and the origin they
+ * exceed 65504), hence bfloat16. FP64 stages, residuals, base slopes and the
+ * outer-boundary factors always use their own FP64 or FP32 tables.
+ * Errors: HR_EINVAL (null grid, bits not 32 or 16).
+ */
+hr_status hr_set_factor_storage(hr_grid* g, int bits);
+
+/*
  * Bound on the resident kernel's exchange waits: a block gives up after this
  * many polls of one partner's stage counter (each poll is one memory round
  * trip, ~1-2 us), sets an error word, and every block leaves its loop; the

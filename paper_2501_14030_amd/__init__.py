@@ -102,6 +102,7 @@ _SIGNATURES = {
                                           ctypes.POINTER(KernelConfig)]),
     "hr_set_wait_limit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint]),
     "hr_set_outer_bc_order": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "hr_set_factor_storage": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "hr_set_residual_norm": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_double]),
     "hr_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                    ctypes.POINTER(KernelConfig), _dp]),
@@ -327,6 +328,11 @@ class Grid:
         """Order (2 or 4) of the one-sided xx0 difference in the outer radiation
         condition."""
         _check(load_library().hr_set_outer_bc_order(self._h, int(order)), "hr_set_outer_bc_order")
+
+    def set_factor_storage(self, bits: int = 32) -> None:
+        """Storage of the metric factors read by the single-precision stages:
+        32 (FP32 copies) or 16 (bfloat16 copies)."""
+        _check(load_library().hr_set_factor_storage(self._h, int(bits)), "hr_set_factor_storage")
 
     def set_wait_limit(self, polls: int = 0) -> None:
         """Polls of one partner's counter before a resident-kernel wait gives up

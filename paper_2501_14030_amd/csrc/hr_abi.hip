@@ -87,9 +87,20 @@ hr_status load_kappa(hr_grid* g, double kappa) {
     ofac[2 * (size_t)o2d + k] = g->tab.oq[k];
   }
   std::vector<float> fac32(fac.begin(), fac.end()), ofac32(ofac.begin(), ofac.end());
+  // bfloat16 copy: the high 16 bits of each FP32 factor, rounded to nearest
+  // even (the factors are finite)
+  std::vector<unsigned short> facb(fac32.size());
+  for (size_t i = 0; i < fac32.size(); ++i) {
+    unsigned bits;
+    std::memcpy(&bits, &fac32[i], sizeof(bits));
+    bits += 0x7fffu + ((bits >> 16) & 1u);
+    facb[i] = (unsigned short)(bits >> 16);
+  }
   HR_HIPK(hipMemcpyAsync(g->f64.fac, fac.data(), fac.size() * sizeof(double),
                         hipMemcpyHostToDevice, g->stream));
   HR_HIPK(hipMemcpyAsync(g->f32.fac, fac32.data(), fac32.size() * sizeof(float),
+                        hipMemcpyHostToDevice, g->stream));
+  HR_HIPK(hipMemcpyAsync(g->f32.facb, facb.data(), facb.size() * sizeof(unsigned short),
                         hipMemcpyHostToDevice, g->stream));
   HR_HIPK(hipMemcpyAsync(g->f64.ofac, ofac.data(), ofac.size() * sizeof(double),
                         hipMemcpyHostToDevice, g->stream));
@@ -141,6 +152,8 @@ size_t layout(hr_grid* g, char* base) {
   for (float** p : d32) *p = (float*)take(G * sizeof(float));
   g->f64.fac = (double*)take(6 * (size_t)n2d * sizeof(double));
   g->f32.fac = (float*)take(6 * (size_t)n2d * sizeof(float));
+  g->f32.facb = (unsigned short*)take(6 * (size_t)n2d * sizeof(unsigned short));
+  g->f64.facb = nullptr;
   g->f64.ofac = (double*)take(3 * (size_t)o2d * sizeof(double));
   g->f32.ofac = (float*)take(3 * (size_t)o2d * sizeof(float));
   g->rho = (double*)take(e2d * sizeof(double));
@@ -218,6 +231,7 @@ ResidentArgsT<float> resident_args_split(hr_grid* g, float eta, float dt, int ns
   r.nsteps = nsteps;
   r.spin_limit = g->res_wait_limit;
   r.bc4 = g->bc_order == 4 ? 1 : 0;
+  r.facb = g->factors16 ? g->f32.facb : nullptr;
   return r;
 }
 
@@ -431,7 +445,8 @@ hr_status run_interval(hr_grid* g, int kind, int K, double eta, double dt, doubl
     const bool same = g->gexec && g->g_kind == kind && g->g_K == K && g->g_eta == eta &&
                       g->g_dt == dt && g->g_kappa == g->kappa_loaded && g->g_variant == variant &&
                       g->g_chunk == chunk && g->g_streaming == streaming && g->g_norm == g->norm &&
-                      g->g_norm_radius == g->norm_radius && g->g_bc == g->bc_order;
+                      g->g_norm_radius == g->norm_radius && g->g_bc == g->bc_order &&
+                      g->g_f16 == g->factors16;
     if (!same) {
       if (g->gexec) {
         (void)hipGraphExecDestroy(g->gexec);
@@ -463,6 +478,7 @@ hr_status run_interval(hr_grid* g, int kind, int K, double eta, double dt, doubl
       g->g_norm = g->norm;
       g->g_norm_radius = g->norm_radius;
       g->g_bc = g->bc_order;
+      g->g_f16 = g->factors16;
     }
     HR_HIP(hipGraphLaunch(g->gexec, g->stream));
   } else {
@@ -1057,6 +1073,13 @@ hr_status hr_set_outer_bc_order(hr_grid* g, int order) {
   if (order > g->d.N0)
     return fail(HR_EINVAL, "the one-sided difference needs N0 >= its order");
   g->bc_order = order;
+  return HR_OK;
+}
+
+hr_status hr_set_factor_storage(hr_grid* g, int bits) {
+  if (!g) return fail(HR_EINVAL, "null grid handle");
+  if (bits != 32 && bits != 16) return fail(HR_EINVAL, "factor storage must be 32 or 16 bits");
+  g->factors16 = bits == 16 ? 1 : 0;
   return HR_OK;
 }
 

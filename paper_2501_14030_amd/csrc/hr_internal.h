@@ -44,6 +44,9 @@ struct Fields {
   T* khv;
   T* pb;
   T* sp7;
+  // bfloat16 copy of the six factor planes (FP32 set only), read by the
+  // single-precision stages when 16-bit factor storage is selected
+  unsigned short* facb;
 };
 
 // Geometry of one grid, shared by every kernel launch on it.
@@ -85,6 +88,7 @@ struct StageArgs {
   const T* khu;
   const T* khv;
   int bc4;        // fourth-order one-sided difference in the radiation condition
+  const unsigned short* facb;  // bfloat16 factor planes (replace fac when set)
 };
 
 // Base-state slopes for the split-state form (FP64 in, FP32 out).
@@ -208,6 +212,7 @@ struct ResidentArgsT {
   int nsteps;
   unsigned spin_limit;  // polls of one counter before a wait gives up
   int bc4;              // fourth-order one-sided difference in the radiation condition
+  const unsigned short* facb;  // bfloat16 factor planes (replace fac when set)
 };
 using ResidentArgs = ResidentArgsT<double>;
 
@@ -290,6 +295,7 @@ struct hr_grid {
   int norm = 0;                 // residual norm: 0 over points, 1 volume-weighted
   double norm_radius = 0.0;     // integration radius of the volume norm (<= 0: whole grid)
   int bc_order = 2;             // one-sided difference order of the radiation condition
+  int factors16 = 0;            // single-precision stages read bfloat16 factor planes
   int variant = 0;              // kernel variant: 0 auto, 1 plane tiles, 2 phi columns,
                                 // 3 resident (FP64 steps in one launch, state on chip)
   int res_nbx = 0, res_nby = 0; // resident patches (0: grid not eligible)
@@ -304,7 +310,8 @@ struct hr_grid {
   int chunk = 0;                // phi planes per block of the column variant (0 auto)
   int graph = -1;               // graph capture of check intervals: -1 auto (on), 0, 1
   hipGraphExec_t gexec = nullptr;  // captured check interval and its key
-  int g_kind = -1, g_K = 0, g_variant = 0, g_chunk = 0, g_streaming = 0, g_norm = 0, g_bc = 2;
+  int g_kind = -1, g_K = 0, g_variant = 0, g_chunk = 0, g_streaming = 0, g_norm = 0, g_bc = 2,
+      g_f16 = 0;
   double g_eta = 0, g_dt = 0, g_kappa = 0, g_norm_radius = 0;
 
   // FP32 -> FP64 switch rule (sw_residual 0: ten times the tolerance)
@@ -340,6 +347,7 @@ StageArgs<T> stage_args(const hr_grid* g, const Fields<T>& F, int stage, T eta, 
   a.ofac = F.ofac;
   a.eta = eta;
   a.bc4 = g->bc_order == 4 ? 1 : 0;
+  a.facb = g->factors16 ? F.facb : nullptr;
   // non-temporal access measured no faster at any size: off unless asked for
   a.streaming = g->streaming > 0 ? 1 : 0;
   resolve_variant(g, a.variant, a.chunk);

@@ -259,7 +259,7 @@ __global__ void __launch_bounds__(kTileThreads) k_stage(StageArgs<T> a) {
       khv = a.khv[idx];
     }
 #pragma unroll
-    for (int q = 0; q < 6; ++q) f[q] = a.fac[q * n2d + k2];
+    for (int q = 0; q < 6; ++q) f[q] = load_factor(a.fac, a.facb, q * n2d + k2);
     cin.load(a, idx);
   }
   load_tile<NG, T, T>(tile, a.uin, d, x0b, x1b, i2);
@@ -434,7 +434,7 @@ __device__ __forceinline__ void stage_col_body(const StageArgs<T>& a, int bx, in
       jq = step_up<NG>(jq, d.N2);
     }
 #pragma unroll
-    for (int r = 0; r < 6; ++r) f[r] = a.fac[r * n2d + k2];
+    for (int r = 0; r < 6; ++r) f[r] = load_factor(a.fac, a.facb, r * n2d + k2);
     cur.load(a, col + plane * (unsigned)z0);
   }
   // jq now holds (z0 + NG + 1) mod N2: the plane the queue needs next

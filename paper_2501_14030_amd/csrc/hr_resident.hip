@@ -108,7 +108,7 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
   {
     const unsigned k2 = (unsigned)i0 + (unsigned)d.N0 * (unsigned)i1;
 #pragma unroll
-    for (int q = 0; q < 6; ++q) f[q] = a.fac[q * n2d + k2];
+    for (int q = 0; q < 6; ++q) f[q] = load_factor(a.fac, a.facb, q * n2d + k2);
   }
   T yu[NPT], yv[NPT], su[NPT], sv[NPT], au[NPT], av[NPT], ps[NPT], ss[NPT];
   T hu[NPT], hv[NPT];   // split form: base slopes

@@ -67,6 +67,18 @@ __device__ __forceinline__ T outer_diff(T f0, T f1, T f2, T f3, T f4, T qd, bool
   return ((T)3 * f0 - (T)4 * f1 + f2) * qd;
 }
 
+// One metric factor: from the bfloat16 planes when given (single precision
+// only; the 16 stored bits are the high half of the FP32 value), else from the
+// table of the stage's own type.
+template <typename T>
+__device__ __forceinline__ T load_factor(const T* fac, const unsigned short* facb,
+                                         unsigned i) {
+  if constexpr (sizeof(T) == 4) {
+    if (facb) return __uint_as_float((unsigned)facb[i] << 16);
+  }
+  return fac[i];
+}
+
 // Plane index of phi + pi (N2 even).
 __device__ __forceinline__ int half_turn(int i2, int N2) {
   const int h = i2 + (N2 >> 1);

@@ -139,10 +139,14 @@ def paper_scale(coords: int = SINHSYMTP, fd_order: int = 10) -> Workload:
 
 
 def precision_form(N0: int = 128, N1: int = 128, N2: int = 16) -> Workload:
-    """Equal-mass small-case physics on a larger 8th-order grid, for the FP32-bulk form."""
+    """Equal-mass small-case physics on a larger 8th-order grid, for the FP32-bulk
+    form. eta from sweeps of the FP64 steps to 1e-10: 128x128x16 eta 4 -> 52100,
+    16 -> 13600, 80 -> 3900; 256x256x32 eta 80 -> 23200, 120 -> 16100, 160 ->
+    13100, 240 -> 8800, 320 -> 8700."""
     base = equal_mass_small()
     g = GridSpec(SINHSYMTP, N0, N1, N2, 8, bscale=1.0)
-    return Workload(g, base.punctures, eta=ETA_PAPER_SCALE, n_steps=2_000_000, tol=1e-10,
+    eta = ETA_PAPER_SCALE if N0 <= 128 else 3.0 * ETA_PAPER_SCALE
+    return Workload(g, base.punctures, eta=eta, n_steps=2_000_000, tol=1e-10,
                     check_every=100, label=f"precision form {g.name()}")
 
 

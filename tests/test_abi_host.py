@@ -137,3 +137,14 @@ def test_outer_bc_order_arguments(lib):
     assert lib.hr_set_outer_bc_order(h, 4) == hr.EINVAL
     assert lib.hr_set_outer_bc_order(h, 2) == hr.OK
     lib.hr_grid_destroy(h)
+
+
+def test_factor_storage_arguments(lib):
+    st, h = _create(lib, 0, 32, 16, 4, 8, hr.default_params(bscale=1.0))
+    assert st == hr.OK
+    f = lib.hr_set_factor_storage
+    assert f(h, 16) == hr.OK and f(h, 32) == hr.OK
+    for bad in (0, 8, 64):
+        assert f(h, bad) == hr.EINVAL
+    assert f(None, 32) == hr.EINVAL
+    lib.hr_grid_destroy(h)

@@ -75,3 +75,41 @@ def test_split_fp32_converges_to_fp64_solution(spec):
     assert g.residual_l2() < 1e-10
     assert d <= 1e-8
     assert r32.fp32_steps >= 0.8 * r32.steps_taken
+
+
+def test_bfloat16_factor_storage():
+    """16-bit (bfloat16) storage of the metric factors read by the single-
+    precision stages. Stated errors: the split form with these factors, relaxed
+    to residual 1e-10 on the 8th-order 128x128x16 precision-form grid, stays
+    within 1e-8 of the FP64 solution (the FP64 rebase and finish remove the
+    factor rounding from the fixed point); the plain FP32 trajectory moves by
+    the factor rounding (between 1e-6 and 1e-2 of max|u| after 1000 steps); the
+    FP64 form does not read them (bitwise unchanged)."""
+    w = workloads.precision_form(128, 128, 16)
+    eta = 80.0
+    g = gpu_grid(w.grid)
+    g.set_punctures(*w.punctures.as_tuple())
+    r64 = g.relax(eta, 1.0, 0.0, 200000, 1e-10, check_every=100, precision=hr.FP64)
+    u64 = g.get_u(extended=True)
+    g.set_factor_storage(16)
+    g.set_punctures(*w.punctures.as_tuple())
+    r64b = g.relax(eta, 1.0, 0.0, 200000, 1e-10, check_every=100, precision=hr.FP64)
+    assert np.array_equal(g.get_u(extended=True), u64) and r64b.steps_taken == r64.steps_taken
+    g.set_punctures(*w.punctures.as_tuple())
+    r16 = g.relax(eta, 1.0, 0.0, 200000, 1e-10, check_every=100, precision=hr.FP32_FP64FINISH)
+    d16 = rel_maxdiff(g.get_u(extended=True), u64)
+    banner(f"bf16 factors, split form: {r16.steps_taken} steps ({r16.fp32_steps} fp32), "
+           f"rel diff vs fp64 {d16:.2e}, residual {r16.residual:.2e} (fp64: {r64.steps_taken})")
+    assert r16.status == hr.OK and g.residual_l2() < 1e-10
+    assert d16 <= 1e-8
+    # plain FP32 with 32- and 16-bit factors
+    g.set_punctures(*w.punctures.as_tuple())
+    g.relax(eta, 1.0, 0.0, 1000, 0.0, check_every=100, precision=hr.FP32)
+    ub = g.get_u(extended=True)
+    g.set_factor_storage(32)
+    g.set_punctures(*w.punctures.as_tuple())
+    g.relax(eta, 1.0, 0.0, 1000, 0.0, check_every=100, precision=hr.FP32)
+    uf = g.get_u(extended=True)
+    dpl = rel_maxdiff(ub, uf)
+    banner(f"plain FP32, bf16 vs fp32 factors after 1000 steps: {dpl:.2e}")
+    assert 1e-6 < dpl < 1e-2
