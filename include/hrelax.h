@@ -241,18 +241,22 @@ hr_status hr_suggest_dt(const hr_grid* g, double cfl, double* dt);
  *              2 = phi-marching columns (a block walks `chunk` phi planes),
  *              3 = resident (FP64 steps, and the FP32 increment steps of
  *              HR_FP32_FP64FINISH): one kernel launch runs up to
- *              1000 whole RK4 steps with the state of every 8 x 8 (x0, x1)
- *              patch (all phi planes) on one compute unit; the patches
- *              exchange their stage input through the grid's stage buffers.
- *              Needs a bound grid with N0 and N1 multiples of 8, N2 <= 16,
- *              fd_order 8 or 10 and no more patches than the device holds at
- *              once (256 on MI355X: up to 128 x 128 (x0, x1)), else
+ *              1000 whole RK4 steps with the state of every 8 x 8 (or
+ *              8 x 4, see chunk) (x0, x1) patch (all phi planes) on one
+ *              compute unit; the patches exchange their stage input through
+ *              the grid's stage buffers. Needs a bound grid with N0 a
+ *              multiple of 8 and N1 of the patch rows, N2 <= 16, fd_order 8
+ *              or 10 and no more patches than the device holds at once (256
+ *              on MI355X: up to 128 x 128 (x0, x1) with 8 x 8 patches), else
  *              HR_EINVAL. Plain HR_FP32 stages run plane tiles instead.
  *              A timed-out exchange wait (not expected) is reported as
  *              HR_EDEVICE by the relaxing call.
  *   streaming  -1 = automatic (by grid size), 0 = cached, 1 = non-temporal
  *              loads/stores for fields touched once per stage
- *   chunk      phi planes per block for variant 2 (0 = automatic)
+ *   chunk      phi planes per block for variant 2 (0 = automatic); for
+ *              variant 3 the patch rows along x1, 8 or 4 (0 = automatic: 8 x 4
+ *              patches where 8 x 8 ones would leave more than half of the
+ *              compute units idle and 8 x 4 ones fit, else 8 x 8)
  *   graph      -1 = automatic (on), 0 = off, 1 = on: hr_relax captures the
  *              launches of one check interval (RK stages, residual) in a HIP
  *              graph once per (precision form, check_every, eta, dt, c,

@@ -43,13 +43,29 @@ hr_status kfail(hr_status s, const std::string& msg) {
 // Kernel variant for this grid: explicit configuration, else the resident
 // kernel where it applies (whole steps on chip), else by size (phi columns
 // when there are enough (x0, x1) tiles to fill the device).
+//
+// The resident partition: 8 x 8 patches, or 8 x 4 patches where the 8 x 8
+// partition would leave more than half of the compute units idle and the
+// 8 x 4 one fits (an explicit variant 3 with chunk 4 or 8 picks the rows).
+const hr_grid::ResPlan* resident_partition(const hr_grid* g) {
+  const hr_grid::ResPlan& p8 = g->res[0];
+  const hr_grid::ResPlan& p4 = g->res[1];
+  if (g->variant == 3 && (g->chunk == 8 || g->chunk == 4)) return g->chunk == 8 ? &p8 : &p4;
+  const bool ok8 = p8.nbx > 0 && p8.blocks() <= p8.cap;
+  const bool ok4 = p4.nbx > 0 && p4.blocks() <= p4.cap;
+  if (ok4 && (!ok8 || 2 * p8.blocks() <= p8.cap)) return &p4;
+  return &p8;
+}
+
 bool resident_ok(const hr_grid* g) {
-  return g->bound && g->res_nbx > 0 && g->res_nbx * g->res_nby <= g->res_capacity &&
+  const hr_grid::ResPlan* p = resident_partition(g);
+  return g->bound && p->nbx > 0 && p->blocks() <= p->cap &&
          (g->fd_order == 8 || g->fd_order == 10);
 }
 
 bool resident_split_ok(const hr_grid* g) {
-  return resident_ok(g) && g->res_nbx * g->res_nby <= g->res_capacity32;
+  const hr_grid::ResPlan* p = resident_partition(g);
+  return resident_ok(g) && p->blocks() <= p->cap32;
 }
 
 void resolve_variant(const hr_grid* g, int& variant, int& chunk) {
@@ -163,10 +179,11 @@ size_t layout(hr_grid* g, char* base) {
   g->vol = (double*)take((size_t)n2d * sizeof(double));
   g->partial = (double*)take((size_t)g->nblk_res * sizeof(double));
   g->result = (double*)take(4 * sizeof(double));
-  const int nres = g->res_nbx * g->res_nby;
+  const int nres = std::max(g->res[0].blocks(), g->res[1].blocks());
   if (nres > 0) {
     g->res_flags = (unsigned*)take((size_t)nres * kResFlagStride * sizeof(unsigned));
-    g->res_waits = (int*)take(g->res_plan.size() * sizeof(int));
+    for (auto& p : g->res)
+      p.waits = p.nbx > 0 ? (int*)take(p.plan.size() * sizeof(int)) : nullptr;
     g->res_err = (unsigned*)take(sizeof(unsigned));
   }
   return off;
@@ -189,15 +206,17 @@ ResidentArgs resident_args(hr_grid* g, double eta, double dt, int nsteps) {
   r.ofac = g->f64.ofac;
   r.x0 = g->f64.ua;
   r.x1 = g->f64.ub;
+  const hr_grid::ResPlan* p = resident_partition(g);
   r.flags = g->res_flags;
-  r.waits = g->res_waits;
+  r.waits = p->waits;
   r.err = g->res_err;
   r.eta = eta;
   // the stage coefficients of the stage kernels (classic RK4)
   r.cy[0] = dt / 2.0; r.cy[1] = dt / 2.0; r.cy[2] = dt; r.cy[3] = dt;
   r.ca[0] = dt / 6.0; r.ca[1] = dt / 3.0; r.ca[2] = dt / 3.0; r.ca[3] = dt / 6.0;
-  r.nbx = g->res_nbx;
-  r.nby = g->res_nby;
+  r.nbx = p->nbx;
+  r.nby = p->nby;
+  r.ry = p->ry;
   r.nsteps = nsteps;
   r.spin_limit = g->res_wait_limit;
   r.bc4 = g->bc_order == 4 ? 1 : 0;
@@ -219,15 +238,17 @@ ResidentArgsT<float> resident_args_split(hr_grid* g, float eta, float dt, int ns
   r.ofac = g->f32.ofac;
   r.x0 = g->f32.ua;
   r.x1 = g->f32.ub;
+  const hr_grid::ResPlan* p = resident_partition(g);
   r.flags = g->res_flags;
-  r.waits = g->res_waits;
+  r.waits = p->waits;
   r.err = g->res_err;
   r.eta = eta;
   // the stage coefficients of the stage kernels (classic RK4, in FP32)
   r.cy[0] = dt / 2.0f; r.cy[1] = dt / 2.0f; r.cy[2] = dt; r.cy[3] = dt;
   r.ca[0] = dt / 6.0f; r.ca[1] = dt / 3.0f; r.ca[2] = dt / 3.0f; r.ca[3] = dt / 6.0f;
-  r.nbx = g->res_nbx;
-  r.nby = g->res_nby;
+  r.nbx = p->nbx;
+  r.nby = p->nby;
+  r.ry = p->ry;
   r.nsteps = nsteps;
   r.spin_limit = g->res_wait_limit;
   r.bc4 = g->bc_order == 4 ? 1 : 0;
@@ -680,10 +701,13 @@ hr_status hr_grid_create(hr_coords coords, int N0, int N1, int N2, int fd_order,
   g->d.sph = coords == HR_SINHSYMTP ? 0 : 1;  // spherical families: xx0 image mirrors theta
   g->G = align_up((size_t)next, 64);
   g->nblk_res = residual_blocks(g->d);
-  if (fd_order >= 8 && !resident_plan(g->d, g->res_plan, g->res_nbx, g->res_nby)) {
-    g->res_plan.clear();
-    g->res_nbx = g->res_nby = 0;
-  }
+  g->res[0].ry = 8;
+  g->res[1].ry = 4;
+  for (auto& p : g->res)
+    if (fd_order < 8 || !resident_plan(g->d, p.ry, p.plan, p.nbx, p.nby)) {
+      p.plan.clear();
+      p.nbx = p.nby = 0;
+    }
   std::string err;
   if (!build_tables(coords, g->d, prm, g->tab, err)) {
     delete g;
@@ -761,13 +785,14 @@ hr_status hr_grid_bind(hr_grid* g, void* dev_ptr, size_t bytes, void* hip_stream
   float* z32[] = {g->f32.un, g->f32.vn, g->f32.ua, g->f32.va, g->f32.ub,
                   g->f32.vb, g->f32.au, g->f32.av, g->f32.psi, g->f32.ssrc};
   for (float* p : z32) HR_HIP(launch_fill(p, 0.0f, G, g->stream));
-  if (g->res_nbx > 0) {
-    HR_HIP(hipMemcpyAsync(g->res_waits, g->res_plan.data(), g->res_plan.size() * sizeof(int),
-                          hipMemcpyHostToDevice, g->stream));
-    HR_HIP(hipMemsetAsync(g->res_err, 0, sizeof(unsigned), g->stream));
-    g->res_capacity = resident_capacity(g->fd_order, g->d);
-    g->res_capacity32 = resident_capacity(g->fd_order, g->d, true);
-  }
+  for (auto& p : g->res)
+    if (p.nbx > 0) {
+      HR_HIP(hipMemcpyAsync(p.waits, p.plan.data(), p.plan.size() * sizeof(int),
+                            hipMemcpyHostToDevice, g->stream));
+      p.cap = resident_capacity(g->fd_order, g->d, false, p.ry);
+      p.cap32 = resident_capacity(g->fd_order, g->d, true, p.ry);
+    }
+  if (g->res_err) HR_HIP(hipMemsetAsync(g->res_err, 0, sizeof(unsigned), g->stream));
   g->kappa_loaded = -1.0;
   hr_status st = load_kappa(g, 1.0);
   if (st != HR_OK) return st;
@@ -1011,9 +1036,19 @@ hr_status hr_set_kernel_config(hr_grid* g, const hr_kernel_config* cfg) {
   if (cfg->variant < 0 || cfg->variant > 3 || cfg->streaming < -1 || cfg->streaming > 1 ||
       cfg->chunk < 0 || cfg->graph < -1 || cfg->graph > 1)
     return fail(HR_EINVAL, "invalid kernel configuration");
-  if (cfg->variant == 3 && !resident_ok(g))
-    return fail(HR_EINVAL, "resident variant needs a bound grid of whole 8x8 (x0, x1) patches, "
-                           "N2 <= 16, order 8 or 10, and one compute unit per patch");
+  if (cfg->variant == 3) {
+    if (cfg->chunk != 0 && cfg->chunk != 4 && cfg->chunk != 8)
+      return fail(HR_EINVAL, "resident variant: chunk selects the patch rows (0, 4 or 8)");
+    const int v0 = g->variant, c0 = g->chunk;
+    g->variant = 3;
+    g->chunk = cfg->chunk;
+    const bool ok = resident_ok(g);
+    g->variant = v0;
+    g->chunk = c0;
+    if (!ok)
+      return fail(HR_EINVAL, "resident variant needs a bound grid of whole 8x8 or 8x4 (x0, x1) "
+                             "patches, N2 <= 16, order 8 or 10, and one compute unit per patch");
+  }
   g->variant = cfg->variant;
   g->streaming = cfg->streaming;
   g->chunk = cfg->chunk;
@@ -1030,7 +1065,7 @@ hr_status hr_resolved_kernel(const hr_grid* g, hr_precision prec, hr_kernel_conf
   if (variant == 3 && !(prec == HR_FP64 || (prec == HR_FP32_FP64FINISH && resident_split_ok(g))))
     variant = 1;
   cfg->variant = variant;
-  cfg->chunk = variant == 2 ? chunk : 0;
+  cfg->chunk = variant == 2 ? chunk : variant == 3 ? resident_partition(g)->ry : 0;
   cfg->streaming = g->streaming > 0 ? 1 : 0;
   cfg->graph = (variant == 3 || g->graph == 0) ? 0 : 1;
   return HR_OK;

@@ -197,23 +197,24 @@ bool build_tables(hr_coords coords, const Dims& d, const hr_grid_params& p,
   return true;
 }
 
-// Partition of a grid into the resident kernel's 8 x 8 (x0, x1) patches and
+// Partition of a grid into the resident kernel's 8 x ry (x0, x1) patches and
 // the exchange partners of each patch: the owners of the stored points its
 // rim taps read (inner-boundary images resolved as in the stage kernels), and
 // the patches whose rims read it, so that every reader of a patch's exchange
 // slot is one of its partners (the double-buffered exchange relies on it).
-bool resident_plan(const Dims& d, std::vector<int>& waits, int& nbx, int& nby) {
+bool resident_plan(const Dims& d, int ry, std::vector<int>& waits, int& nbx, int& nby) {
   constexpr int RB = kResPatch;
   nbx = nby = 0;
-  if (d.N0 % RB || d.N1 % RB || d.NG > RB || d.N2 > 16 || d.N2 < 2) return false;
-  const int bx_n = d.N0 / RB, by_n = d.N1 / RB, nb = bx_n * by_n;
+  if (ry != 8 && ry != 4) return false;
+  if (d.N0 % RB || d.N1 % ry || d.NG > RB || d.N2 > 16 || d.N2 < 2) return false;
+  const int bx_n = d.N0 / RB, by_n = d.N1 / ry, nb = bx_n * by_n;
   if (nb > kResMaxBlocks) return false;
   const int NG = d.NG;
   // owner patch of a stored (s0, s1); outer points belong to the last x0 patch
-  auto owner = [&](int s0, int s1) { return std::min(s0 / RB, bx_n - 1) + bx_n * (s1 / RB); };
+  auto owner = [&](int s0, int s1) { return std::min(s0 / RB, bx_n - 1) + bx_n * (s1 / ry); };
   std::vector<std::set<int>> rel(nb);
   for (int b = 0; b < nb; ++b) {
-    const int x0b = (b % bx_n) * RB, x1b = (b / bx_n) * RB;
+    const int x0b = (b % bx_n) * RB, x1b = (b / bx_n) * ry;
     auto tap = [&](int j0, int j1) {
       int s0 = j0, s1 = j1;
       if (j0 < 0) {
@@ -230,13 +231,16 @@ bool resident_plan(const Dims& d, std::vector<int>& waits, int& nbx, int& nby) {
         rel[o].insert(b);
       }
     };
-    for (int r = 0; r < RB; ++r)
-      for (int k = 1; k <= NG; ++k) {
+    for (int k = 1; k <= NG; ++k) {
+      for (int r = 0; r < ry; ++r) {
         tap(x0b - k, x1b + r);
         tap(x0b + RB - 1 + k, x1b + r);
-        tap(x0b + r, x1b - k);
-        tap(x0b + r, x1b + RB - 1 + k);
       }
+      for (int c = 0; c < RB; ++c) {
+        tap(x0b + c, x1b - k);
+        tap(x0b + c, x1b + ry - 1 + k);
+      }
+    }
   }
   waits.assign((size_t)nb * (kResMaxWait + 1), 0);
   for (int b = 0; b < nb; ++b) {

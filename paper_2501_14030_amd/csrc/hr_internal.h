@@ -209,6 +209,7 @@ struct ResidentArgsT {
   T cy[4];              // Y_{s+1} = y_n + cy[s] k (stage 4: y_{n+1} = acc + ca[3] k)
   T ca[4];              // accumulator weights
   int nbx, nby;         // patches along x0 and x1
+  int ry;               // patch rows along x1 (8 or 4; 8 columns along x0)
   int nsteps;
   unsigned spin_limit;  // polls of one counter before a wait gives up
   int bc4;              // fourth-order one-sided difference in the radiation condition
@@ -219,15 +220,16 @@ using ResidentArgs = ResidentArgsT<double>;
 // Exchange partners of every patch (count, then ids; kResMaxWait + 1 ints per
 // block) for dims d: the owners of every stencil tap outside the patch,
 // including inner-boundary images, and every patch whose taps reach this one.
-// False if the grid is not made of whole 8 x 8 patches or has too many blocks.
-bool resident_plan(const Dims& d, std::vector<int>& waits, int& nbx, int& nby);
-// Dynamic LDS bytes of the resident kernel for these dims and element size (at
-// least enough to keep one block per compute unit).
-size_t resident_lds_bytes(const Dims& d, size_t elem);
+// Patches are 8 columns (x0) by ry = 8 or 4 rows (x1). False if the grid is
+// not made of whole patches or has too many blocks.
+bool resident_plan(const Dims& d, int ry, std::vector<int>& waits, int& nbx, int& nby);
+// Dynamic LDS bytes of the resident kernel for these dims, element size and
+// patch rows (at least enough to keep one block per compute unit).
+size_t resident_lds_bytes(const Dims& d, size_t elem, int ry);
 // Largest number of co-resident blocks of the resident kernel (FP64 form, or
-// the split form with split = true) on the current device for these dims (0 if
-// the order or N2 is not supported).
-int resident_capacity(int order, const Dims& d, bool split = false);
+// the split form with split = true) on the current device for these dims and
+// patch rows (0 if the order or N2 is not supported).
+int resident_capacity(int order, const Dims& d, bool split, int ry);
 // Resets the counters and launches the resident kernel (one block per
 // compute unit, all resident at once); events (optional) bracket the kernel.
 hipError_t launch_resident(int order, const ResidentArgsT<double>& a, hipStream_t s,
@@ -298,13 +300,17 @@ struct hr_grid {
   int factors16 = 0;            // single-precision stages read bfloat16 factor planes
   int variant = 0;              // kernel variant: 0 auto, 1 plane tiles, 2 phi columns,
                                 // 3 resident (FP64 steps in one launch, state on chip)
-  int res_nbx = 0, res_nby = 0; // resident patches (0: grid not eligible)
-  int res_capacity = 0;         // co-resident blocks the device allows for it (FP64)
-  int res_capacity32 = 0;       // the same for the split-state FP32 form
+  // resident-kernel partitions, [0]: 8 x 8 patches, [1]: 8 x 4 patches
+  struct ResPlan {
+    int ry = 8;
+    int nbx = 0, nby = 0;       // patches (0: grid not eligible)
+    int cap = 0, cap32 = 0;     // co-resident blocks the device allows (FP64, split FP32)
+    std::vector<int> plan;      // exchange partners (host copy, uploaded at bind)
+    int* waits = nullptr;       // device copy
+    int blocks() const { return nbx * nby; }
+  } res[2];
   unsigned res_wait_limit = 1u << 19;  // polls of one partner counter before giving up
-  std::vector<int> res_plan;    // exchange partners (host copy, uploaded at bind)
-  unsigned* res_flags = nullptr;
-  int* res_waits = nullptr;
+  unsigned* res_flags = nullptr;  // stage counters, sized for the larger partition
   unsigned* res_err = nullptr;
   int streaming = -1;           // non-temporal field access: -1 auto (by size), 0, 1
   int chunk = 0;                // phi planes per block of the column variant (0 auto)

@@ -5,9 +5,10 @@
 // launch runs many whole RK4 steps (Algorithm 1, inner loop; RHS
 // of Eq. 5 with the radiation condition at the outer points) and the state
 // never leaves the chip:
-//   * block b owns an 8 x 8 patch of (x0, x1) columns through all N2 phi planes
-//     (the last x0 patch also the NG outer points of its rows); its threads
-//     are 64 (x0, x1) positions x up to 16 plane groups;
+//   * block b owns an 8 x 8 (or, for grids with few such patches, 8 x 4)
+//     patch of (x0, x1) columns through all N2 phi planes (the last x0 patch
+//     also the NG outer points of its rows); its threads are the patch's
+//     (x0, x1) positions x up to 16 plane groups;
 //   * y_n, the stage input v, the accumulator, psi_s and S_src of the block's
 //     points sit in registers; the stage input u of the whole patch plus its
 //     NG-deep rim (all planes) sits in LDS, so every stencil tap, phi included,
@@ -17,7 +18,8 @@
 //     next stage waits only for the counters of its exchange partners (the
 //     owners of its rim taps; the relation is symmetric), then loads its rim
 //     from the exchange array. The exchange array is packed by patch
-//     ([patch][plane][x1][x0], 512 contiguous bytes per patch plane in FP64),
+//     ([patch][plane][x1][x0], 512 contiguous bytes per 8 x 8 patch plane in
+//     FP64),
 //     so a block's publish is whole cache lines and each rim strip spans a few
 //     lines of one patch plane instead of one line per grid row; the initial
 //     state is published the same way before the first stage. Rim cells that
@@ -73,18 +75,22 @@ __global__ void k_zero_u32(unsigned* p, int n) {
   if (i < n) p[i] = 0u;
 }
 
-// RT threads = 64 (x0, x1) positions x PG plane groups; plane group g holds
+// A patch is RB = 8 columns (x0) by RY = 8 or 4 rows (x1), NP = RB RY
+// positions. RT threads = NP positions x PG plane groups; plane group g holds
 // planes g, g + PG, ... (NPT of them). T = double: the FP64 state; T = float
 // with CORR: the split-state form's increment (slopes as in the stage kernels).
-template <typename T, int NG, int NPT, int RT, bool CORR>
+template <typename T, int NG, int NPT, int RT, bool CORR, int RY>
 __global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
-  constexpr int PG = RT / 64;
+  constexpr int NP = RB * RY;                    // positions per plane
+  constexpr int PG = RT / NP;
   constexpr int RW = tile_row(RB + 2 * NG);      // LDS tile row (x0) stride, padded
-  constexpr int TP = RW * (RB + 2 * NG);         // tile cells per plane (corners unused)
+  constexpr int TP = RW * (RY + 2 * NG);         // tile cells per plane (corners unused)
   constexpr int VW = tile_row(RB + NG);          // v tile row: patch columns + outer
-  constexpr int NRIM = 4 * NG * RB;              // rim cells per plane
+  constexpr int NRX = 2 * NG * RY;               // x0-side rim cells per plane
+  constexpr int NRIM = NRX + 2 * NG * RB;        // rim cells per plane
   constexpr int NR = (NRIM * PG * NPT + RT - 1) / RT;
-  constexpr int NQ = (NG * RB * PG * NPT + RT - 1) / RT;
+  constexpr int NQ = (NG * RY * PG * NPT + RT - 1) / RT;
+  static_assert(NP * PG == RT && (NP & (NP - 1)) == 0, "block shape");
   constexpr Weights<NG> Wt{};
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
@@ -92,11 +98,11 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
 
   const Dims& d = a.d;
   const int N2 = d.N2;
-  T* ut = smem;                      // [N2][RB + 2 NG][RW]
-  T* vt = smem + N2 * TP;            // [N2][RB][VW]
-  const int t = threadIdx.x, pos = t & 63, x0l = pos & 7, x1l = pos >> 3, grp = t >> 6;
+  T* ut = smem;                      // [N2][RY + 2 NG][RW]
+  T* vt = smem + N2 * TP;            // [N2][RY][VW]
+  const int t = threadIdx.x, pos = t & (NP - 1), x0l = pos & 7, x1l = pos >> 3, grp = t / NP;
   const int b = blockIdx.x, bx = b % a.nbx, by = b / a.nbx;
-  const int x0b = bx * RB, x1b = by * RB;
+  const int x0b = bx * RB, x1b = by * RY;
   const int i0 = x0b + x0l, i1 = x1b + x1l;
   const bool last = bx == a.nbx - 1;
   const unsigned P0 = (unsigned)d.P0, N1 = (unsigned)d.N1;
@@ -121,7 +127,7 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
     const int i2c = ok ? i2 : 0;
     gidx[j] = P0 * ((unsigned)i1 + N1 * (unsigned)i2c) + (unsigned)i0;
     lidx[j] = i2c * TP + (x1l + NG) * RW + (x0l + NG);
-    vidx[j] = (i2c * RB + x1l) * VW + x0l;
+    vidx[j] = (i2c * RY + x1l) * VW + x0l;
     yu[j] = ok ? a.u[gidx[j]] : (T)0;
     yv[j] = ok ? a.v[gidx[j]] : (T)0;
     ps[j] = ok ? a.psi[gidx[j]] : (T)0;
@@ -144,12 +150,12 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
   for (int q = 0; q < NQ; ++q) {
     const int o = t + RT * q;
     const int col = o % NG, rest = o / NG;
-    const int r = rest % RB, pl = rest / RB;
+    const int r = rest % RY, pl = rest / RY;
     oval[q] = last && pl < N2;
     const int plc = oval[q] ? pl : 0;
     oidx[q] = P0 * ((unsigned)(x1b + r) + N1 * (unsigned)plc) + (unsigned)(d.N0 + col);
     otl[q] = plc * TP + (NG + r) * RW + (NG + RB + col);
-    ovl[q] = (plc * RB + r) * VW + RB + col;
+    ovl[q] = (plc * RY + r) * VW + RB + col;
     const unsigned ko = (unsigned)col + (unsigned)NG * (unsigned)(x1b + r);
     oc[q] = oval[q] ? a.ofac[ko] : (T)0;
     ori[q] = oval[q] ? a.ofac[o2d + ko] : (T)0;
@@ -176,12 +182,15 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
     const int c = t + RT * q;
     const int pl = c / NRIM, w = c - pl * NRIM;
     const int plc = pl < N2 ? pl : 0;
-    const int side = w / (NG * RB), w2 = w - side * (NG * RB);
+    // sides 0/1: NG columns left/right of the patch (RY rows each); sides
+    // 2/3: NG rows below/above (RB columns each)
+    const int side = w < NRX ? w / (NG * RY) : 2 + (w - NRX) / (NG * RB);
+    const int w2 = w < NRX ? w - side * (NG * RY) : w - NRX - (side - 2) * (NG * RB);
     int l0, l1;
     if (side == 0) { l0 = w2 % NG; l1 = NG + w2 / NG; }
     else if (side == 1) { l0 = NG + RB + w2 % NG; l1 = NG + w2 / NG; }
     else if (side == 2) { l0 = NG + w2 % RB; l1 = w2 / RB; }
-    else { l0 = NG + w2 % RB; l1 = NG + RB + w2 / RB; }
+    else { l0 = NG + w2 % RB; l1 = NG + RY + w2 / RB; }
     const int j0 = x0b + l0 - NG, j1 = x1b + l1 - NG;
     int s0 = j0, s1 = j1;
     bool flip = false;
@@ -199,10 +208,10 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
     const int sp = flip ? half_turn(plc, N2) : plc;
     // packed exchange slot of (s0, s1, sp); only read for cells of other
     // patches, which are interior points (outer points stay with their patch)
-    const int ox = s0 / RB, oy = s1 / RB;
-    rg[q] = ((unsigned)(ox + a.nbx * oy) * (unsigned)N2 + (unsigned)sp) * 64u +
-            (unsigned)((s1 - oy * RB) * RB + (s0 - ox * RB));
-    const bool self = min(s0 / RB, a.nbx - 1) == bx && s1 / RB == by;
+    const int ox = s0 / RB, oy = s1 / RY;
+    rg[q] = ((unsigned)(ox + a.nbx * oy) * (unsigned)N2 + (unsigned)sp) * (unsigned)NP +
+            (unsigned)((s1 - oy * RY) * RB + (s0 - ox * RB));
+    const bool self = min(s0 / RB, a.nbx - 1) == bx && s1 / RY == by;
     const unsigned kind = pl >= N2 ? 0u : !self ? 1u : flip ? 2u : 3u;
     const unsigned rl = (unsigned)(plc * TP + l1 * RW + l0);
     const unsigned rs =
@@ -215,13 +224,13 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
   const int wt = t < nw ? a.waits[b * (kResMaxWait + 1) + 1 + t] : 0;
 
   // packed exchange slot of this thread's point in plane 0
-  const unsigned pslot = (unsigned)b * (unsigned)N2 * 64u + (unsigned)pos;
+  const unsigned pslot = (unsigned)b * (unsigned)N2 * (unsigned)NP + (unsigned)pos;
 
   // publish the initial stage input (counter 1); stage e waits for counters
   // >= e and publishes its result with counter e + 1
 #pragma unroll
   for (int j = 0; j < NPT; ++j)
-    if (grp + PG * j < N2) xstore(a.x0 + pslot + 64u * (unsigned)(grp + PG * j), su[j]);
+    if (grp + PG * j < N2) xstore(a.x0 + pslot + (unsigned)NP * (unsigned)(grp + PG * j), su[j]);
   __builtin_amdgcn_s_waitcnt(0);
   if (t == 0) bad = 0;
   __syncthreads();
@@ -396,7 +405,8 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
       T* dst = (e & 1) ? a.x1 : a.x0;
 #pragma unroll
       for (int j = 0; j < NPT; ++j)
-        if (grp + PG * j < N2) xstore(dst + pslot + 64u * (unsigned)(grp + PG * j), su[j]);
+        if (grp + PG * j < N2)
+          xstore(dst + pslot + (unsigned)NP * (unsigned)(grp + PG * j), su[j]);
       // (outer points are read only by their own patch, through LDS)
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
@@ -420,27 +430,30 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
   }
 }
 
-// Threads by N2: one plane per thread (1024 threads for N2 > 8: four waves per
-// SIMD to hide LDS and exchange latency). Deeper grids would need several
-// planes per thread and more registers than a 1024-thread block has.
+// Threads by N2: one plane per thread (for 8 x 8 patches 1024 threads when
+// N2 > 8: four waves per SIMD to hide LDS and exchange latency). Deeper grids
+// would need several planes per thread and more registers than a 1024-thread
+// block has.
 struct ResShape {
   const void* kernel;
   int threads;
 };
 
-template <typename T, int NG, bool CORR>
+template <typename T, int NG, bool CORR, int RY>
 ResShape shape_for(int N2) {
-  if (N2 <= 4) return {(const void*)k_resident<T, NG, 1, 256, CORR>, 256};
-  if (N2 <= 8) return {(const void*)k_resident<T, NG, 1, 512, CORR>, 512};
-  if (N2 <= 16) return {(const void*)k_resident<T, NG, 1, 1024, CORR>, 1024};
+  constexpr int NP = kResPatch * RY;
+  if (N2 <= 4) return {(const void*)k_resident<T, NG, 1, 4 * NP, CORR, RY>, 4 * NP};
+  if (N2 <= 8) return {(const void*)k_resident<T, NG, 1, 8 * NP, CORR, RY>, 8 * NP};
+  if (N2 <= 16) return {(const void*)k_resident<T, NG, 1, 16 * NP, CORR, RY>, 16 * NP};
   return {nullptr, 0};
 }
 
 template <typename T, bool CORR>
-ResShape resident_kernel(int order, int N2) {
+ResShape resident_kernel(int order, int N2, int ry) {
+  if (ry != 8 && ry != 4) return {nullptr, 0};
   switch (order) {
-    case 8: return shape_for<T, 4, CORR>(N2);
-    case 10: return shape_for<T, 5, CORR>(N2);
+    case 8: return ry == 8 ? shape_for<T, 4, CORR, 8>(N2) : shape_for<T, 4, CORR, 4>(N2);
+    case 10: return ry == 8 ? shape_for<T, 5, CORR, 8>(N2) : shape_for<T, 5, CORR, 4>(N2);
     default: return {nullptr, 0};
   }
 }
@@ -448,7 +461,7 @@ ResShape resident_kernel(int order, int N2) {
 template <typename T, bool CORR>
 hipError_t launch_resident_t(int order, const ResidentArgsT<T>& a, hipStream_t s, hipEvent_t t0,
                              hipEvent_t t1) {
-  const ResShape rs = resident_kernel<T, CORR>(order, a.d.N2);
+  const ResShape rs = resident_kernel<T, CORR>(order, a.d.N2, a.ry);
   const void* k = rs.kernel;
   if (!k) return hipErrorInvalidValue;
   const int nb = a.nbx * a.nby;
@@ -457,7 +470,7 @@ hipError_t launch_resident_t(int order, const ResidentArgsT<T>& a, hipStream_t s
   k_zero_u32<<<(nflags + 255) / 256, 256, 0, s>>>(a.flags, nflags);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const size_t lds = resident_lds_bytes(a.d, sizeof(T));
+  const size_t lds = resident_lds_bytes(a.d, sizeof(T), a.ry);
   e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   ResidentArgsT<T> arg = a;
@@ -472,19 +485,19 @@ hipError_t launch_resident_t(int order, const ResidentArgsT<T>& a, hipStream_t s
 
 }  // namespace
 
-size_t resident_lds_bytes(const Dims& d, size_t elem) {
-  const int RH = RB + 2 * d.NG, RW = tile_row(RH), VW = tile_row(RB + d.NG);
-  const size_t need = (size_t)d.N2 * (RW * RH + RB * VW) * elem;
+size_t resident_lds_bytes(const Dims& d, size_t elem, int ry) {
+  const int RH = ry + 2 * d.NG, RW = tile_row(RB + 2 * d.NG), VW = tile_row(RB + d.NG);
+  const size_t need = (size_t)d.N2 * (RW * RH + ry * VW) * elem;
   // more than half of the 160 KiB of LDS per compute unit: one block per CU
   return std::max<size_t>(need, 82 * 1024);
 }
 
-int resident_capacity(int order, const Dims& d, bool split) {
-  const ResShape rs = split ? resident_kernel<float, true>(order, d.N2)
-                            : resident_kernel<double, false>(order, d.N2);
+int resident_capacity(int order, const Dims& d, bool split, int ry) {
+  const ResShape rs = split ? resident_kernel<float, true>(order, d.N2, ry)
+                            : resident_kernel<double, false>(order, d.N2, ry);
   const void* k = rs.kernel;
   if (!k) return 0;
-  const size_t lds = resident_lds_bytes(d, split ? sizeof(float) : sizeof(double));
+  const size_t lds = resident_lds_bytes(d, split ? sizeof(float) : sizeof(double), ry);
   if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return 0;
   int per = 0, dev = 0, cus = 0;

@@ -17,19 +17,25 @@ namespace hr {
 void set_error(const std::string&) {}
 }
 
-// Owner patch of every rim cell of patch b, as the kernel walks them: per
-// plane, 4 sides of NG x 8 cells (x0 low, x0 high, x1 low, x1 high).
-static std::set<int> rim_owners(const hr::Dims& d, int nbx, int b) {
+// Owner patch of every rim cell of patch b (8 columns x ry rows), as the
+// kernel walks them: per plane, NG x ry cells on each x0 side (low, high),
+// then NG x 8 cells on each x1 side (low, high).
+static std::set<int> rim_owners(const hr::Dims& d, int ry, int nbx, int b) {
   const int RB = hr::kResPatch, NG = d.NG;
-  const int x0b = (b % nbx) * RB, x1b = (b / nbx) * RB;
+  const int x0b = (b % nbx) * RB, x1b = (b / nbx) * ry;
+  const int nrx = 2 * NG * ry;
   std::set<int> out;
-  for (int w = 0; w < 4 * NG * RB; ++w) {
-    const int side = w / (NG * RB), w2 = w % (NG * RB);
+  for (int w = 0; w < nrx + 2 * NG * RB; ++w) {
     int l0, l1;
-    if (side == 0) { l0 = w2 % NG; l1 = NG + w2 / NG; }
-    else if (side == 1) { l0 = NG + RB + w2 % NG; l1 = NG + w2 / NG; }
-    else if (side == 2) { l0 = NG + w2 % RB; l1 = w2 / RB; }
-    else { l0 = NG + w2 % RB; l1 = NG + RB + w2 / RB; }
+    if (w < nrx) {
+      const int side = w / (NG * ry), w2 = w % (NG * ry);
+      l0 = (side == 0 ? 0 : NG + RB) + w2 % NG;
+      l1 = NG + w2 / NG;
+    } else {
+      const int side = (w - nrx) / (NG * RB), w2 = (w - nrx) % (NG * RB);
+      l0 = NG + w2 % RB;
+      l1 = (side == 0 ? 0 : NG + ry) + w2 / RB;
+    }
     int s0 = x0b + l0 - NG, s1 = x1b + l1 - NG;
     if (s0 < 0) {
       s0 = -1 - s0;
@@ -41,7 +47,7 @@ static std::set<int> rim_owners(const hr::Dims& d, int nbx, int b) {
     }
     if (s0 < 0 || s0 >= d.P0 || s1 < 0 || s1 >= d.N1) return {-1};
     const int bx = s0 >= d.N0 ? nbx - 1 : s0 / RB;
-    out.insert(bx + nbx * (s1 / RB));
+    out.insert(bx + nbx * (s1 / ry));
   }
   out.erase(b);
   return out;
@@ -51,6 +57,7 @@ static int check_plans() {
   int checked = 0;
   const int shapes[][3] = {{8, 8, 2}, {16, 8, 2}, {64, 32, 8}, {64, 64, 8}, {128, 128, 16},
                            {24, 40, 14}, {256, 256, 8}};
+  for (int ry : {8, 4})
   for (int sph = 0; sph < 2; ++sph)
     for (const auto& sh : shapes)
       for (int NG : {4, 5}) {
@@ -58,14 +65,15 @@ static int check_plans() {
         d.N0 = sh[0]; d.N1 = sh[1]; d.N2 = sh[2]; d.NG = NG; d.P0 = sh[0] + NG; d.sph = sph;
         std::vector<int> w;
         int nbx = 0, nby = 0;
-        if (!hr::resident_plan(d, w, nbx, nby)) return 10;
-        if (nbx != d.N0 / 8 || nby != d.N1 / 8) return 11;
+        if (ry == 4 && (d.N0 / 8) * (d.N1 / 4) > hr::kResMaxBlocks) continue;
+        if (!hr::resident_plan(d, ry, w, nbx, nby)) return 10;
+        if (nbx != d.N0 / 8 || nby != d.N1 / ry) return 11;
         const int W = hr::kResMaxWait + 1;
         for (int b = 0; b < nbx * nby; ++b) {
           const int n = w[(size_t)b * W];
           std::set<int> part(w.begin() + (size_t)b * W + 1, w.begin() + (size_t)b * W + 1 + n);
           if ((int)part.size() != n || part.count(b)) return 12;
-          for (int o : rim_owners(d, nbx, b))
+          for (int o : rim_owners(d, ry, nbx, b))
             if (o < 0 || !part.count(o)) return 13;       // a rim owner is a partner
           for (int o : part) {                            // the relation is symmetric
             const int m = w[(size_t)o * W];
@@ -83,7 +91,16 @@ static int check_plans() {
     d.N0 = sh[0]; d.N1 = sh[1]; d.N2 = sh[2]; d.NG = sh[3]; d.P0 = sh[0] + sh[3];
     std::vector<int> w;
     int nbx = 1, nby = 1;
-    if (hr::resident_plan(d, w, nbx, nby) || nbx || nby) return 15;
+    if (hr::resident_plan(d, 8, w, nbx, nby) || nbx || nby) return 15;
+  }
+  {
+    // 8 x 4 patches on N1 = 12 (not a multiple of 8); no other patch rows
+    hr::Dims d{};
+    d.N0 = 16; d.N1 = 12; d.N2 = 4; d.NG = 4; d.P0 = 20;
+    std::vector<int> w;
+    int nbx = 0, nby = 0;
+    if (!hr::resident_plan(d, 4, w, nbx, nby) || nbx != 2 || nby != 3) return 16;
+    if (hr::resident_plan(d, 8, w, nbx, nby) || hr::resident_plan(d, 2, w, nbx, nby)) return 17;
   }
   std::printf("resident partitions checked: %d\n", checked);
   return 0;

@@ -1,6 +1,6 @@
 """Resident RK4 kernel (kernel variant 3): whole RK4 steps in one kernel
-launch, the state of every 8 x 8 (x0, x1) patch held on chip and the stage
-input exchanged between patches through global memory.
+launch, the state of every 8 x 8 (or 8 x 4) (x0, x1) patch held on chip and
+the stage input exchanged between patches through global memory.
 
 It evaluates the stage kernels' arithmetic in the same order, so its
 trajectories must agree with the plane-tile kernels to a few roundoff units
@@ -26,6 +26,8 @@ CASES = [
     (workloads.GridSpec(0, 16, 8, 2, 10, amax=100.0, sinhwaa=0.2, bscale=1.0), True),
     (workloads.GridSpec(0, 8, 8, 6, 10, amax=100.0, sinhwaa=0.2, bscale=1.0), False),
     (workloads.GridSpec(0, 24, 40, 14, 8, bscale=2.0), False),
+    # N1 = 12: only 8 x 4 patches fit
+    (workloads.GridSpec(0, 32, 12, 4, 8, amax=100.0, sinhwaa=0.2, bscale=1.0), True),
 ]
 
 
@@ -34,12 +36,25 @@ def _punctures(spec):
     return workloads.quasi_circular(1.7, D, [0.1, 0.2, 0.3], [0.0, -0.2, 0.1])
 
 
-def _run(spec, variant, n_steps, dt, eta=6.0, tol=0.0):
+def _run(spec, variant, n_steps, dt, eta=6.0, tol=0.0, chunk=0):
     g = gpu_grid(spec)
-    g.set_kernel_config(variant=variant)
+    g.set_kernel_config(variant=variant, chunk=chunk)
     g.set_punctures(*_punctures(spec).as_tuple())
     r = g.relax(eta, 1.0, dt, n_steps, tol, check_every=100)
     return g, r
+
+
+def _rows_available(spec):
+    """Patch rows (8, 4) the resident kernel accepts for this grid."""
+    g = gpu_grid(spec)
+    rows = []
+    for r in (8, 4):
+        try:
+            g.set_kernel_config(variant=3, chunk=r)
+            rows.append(r)
+        except hr.HRError:
+            pass
+    return rows
 
 
 @pytest.mark.parametrize("spec,with_oracle", CASES)
@@ -47,27 +62,34 @@ def test_resident_matches_plane_kernels_and_oracle(spec, with_oracle):
     banner(f"resident {spec.name()}")
     og = oracle_grid(spec)
     dt = og.suggest_dt(0.5)
-    # 250 steps: two checked intervals and an unchecked tail of 50
-    gr, rr = _run(spec, 3, 250, dt)
     gp, rp = _run(spec, 1, 250, dt)
-    assert rr.status == hr.OK and rr.steps_taken == 250
-    du = rel_maxdiff(gr.get_u(extended=True), gp.get_u(extended=True))
-    dv = rel_maxdiff(gr.get_v(extended=True), gp.get_v(extended=True))
-    banner(f"resident vs plane: u {du:.2e}, v {dv:.2e}")
-    # same arithmetic, contracted into FMAs where the compiler chose: u agrees to
-    # a few roundoff units; v (c^2 times the Laplacian, with large cancelling
-    # terms at the outer cells) to a few hundred relative to its maximum
-    assert du <= 1e-13 and dv <= 1e-12
-    # the residual is a small difference of much larger Laplacian and source
-    # terms, so roundoff-level changes of u move it by ~1e-10 relative
-    np.testing.assert_allclose(rr.history, rp.history, rtol=1e-9, atol=1e-16)
+    ou = None
     if with_oracle:
         og.set_punctures(*_punctures(spec).as_tuple())
         og.relax(6.0, 1.0, dt, 250, 0.0, 100)
-        ou, ov = og.state()
-        d_or = rel_maxdiff(gr.get_u(extended=True), oracle_extended(og, ou))
-        banner(f"resident vs oracle: {d_or:.2e}")
-        assert d_or <= 1e-12
+        ou, _ = og.state()
+    rows = _rows_available(spec)
+    assert rows, "no resident partition"
+    for r in rows:
+        # 250 steps: two checked intervals and an unchecked tail of 50
+        gr, rr = _run(spec, 3, 250, dt, chunk=r)
+        assert gr.resolved_kernel(hr.FP64)["chunk"] == r
+        assert rr.status == hr.OK and rr.steps_taken == 250
+        du = rel_maxdiff(gr.get_u(extended=True), gp.get_u(extended=True))
+        dv = rel_maxdiff(gr.get_v(extended=True), gp.get_v(extended=True))
+        banner(f"resident (8 x {r} patches) vs plane: u {du:.2e}, v {dv:.2e}")
+        # same arithmetic, contracted into FMAs where the compiler chose: u
+        # agrees to a few roundoff units; v (c^2 times the Laplacian, with large
+        # cancelling terms at the outer cells) to a few hundred relative to its
+        # maximum
+        assert du <= 1e-13 and dv <= 1e-12
+        # the residual is a small difference of much larger Laplacian and
+        # source terms, so roundoff-level changes of u move it by ~1e-10
+        np.testing.assert_allclose(rr.history, rp.history, rtol=1e-9, atol=1e-16)
+        if with_oracle:
+            d_or = rel_maxdiff(gr.get_u(extended=True), oracle_extended(og, ou))
+            banner(f"resident (8 x {r}) vs oracle: {d_or:.2e}")
+            assert d_or <= 1e-12
 
 
 def test_resident_relaxes_paper_scale_to_tolerance():
@@ -95,10 +117,19 @@ def test_resident_rejected_where_not_applicable():
         g = gpu_grid(spec)
         with pytest.raises(hr.HRError):
             g.set_kernel_config(variant=3)
-    # more patches than compute units
+    # more patches than compute units (8 x 8 or 8 x 4)
     g = gpu_grid(workloads.GridSpec(0, 256, 256, 8, 10, bscale=1.0))
     with pytest.raises(hr.HRError):
         g.set_kernel_config(variant=3)
+    # patch rows other than 4 and 8, and 8-row patches on N1 = 12
+    g = gpu_grid(workloads.GridSpec(0, 32, 16, 4, 8, bscale=1.0))
+    with pytest.raises(hr.HRError):
+        g.set_kernel_config(variant=3, chunk=6)
+    g = gpu_grid(workloads.GridSpec(0, 32, 12, 4, 8, bscale=1.0))
+    with pytest.raises(hr.HRError):
+        g.set_kernel_config(variant=3, chunk=8)
+    g.set_kernel_config(variant=3, chunk=4)
+    assert g.resolved_kernel(hr.FP64)["chunk"] == 4
 
 
 def test_resident_stage_timing_keeps_trajectory():

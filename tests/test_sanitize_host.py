@@ -27,4 +27,4 @@ def test_geometry_tables_clean_under_asan_ubsan(tmp_path):
                        env=dict(os.environ, ASAN_OPTIONS="detect_leaks=1"))
     assert r.returncode == 0, (r.stdout + r.stderr)[-2000:]
     assert "geometry tables checked" in r.stdout
-    assert "resident partitions checked: 28" in r.stdout
+    assert "resident partitions checked: 52" in r.stdout
