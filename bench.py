@@ -476,6 +476,22 @@ def main() -> int:
             "max_rel_diff_u_vs_fp64": float(np.abs(u32 - u64).max() / np.abs(u64).max()),
             "speedup_time_to_residual": (t64 / args.steps) / (t32 / args.steps),
         }
+        # fixed form: single precision for 95% of the FP64 form's steps to the
+        # tolerance (at check granularity), then FP64 to the tolerance
+        cap = int(round(0.95 * steps64 / w.check_every)) * w.check_every
+        g.set_fp32_switch(1e-300, 1 << 30, cap)
+        resf, tf, tmf = timed_solves(hr, torch, g, w, hr.FP32_FP64FINISH, args.steps, 0,
+                                     "fp32 95% fixed")
+        uf = g.get_u()
+        out["mixed"]["fixed_95"] = {
+            "time_to_residual_s": tf / args.steps,
+            "relax_median_s": float(np.median([t[1] for t in tmf])),
+            "rk4_steps_to_tol": resf[-1].steps_taken,
+            "fp32_steps": resf[-1].fp32_steps,
+            "final_residual": resf[-1].residual,
+            "max_rel_diff_u_vs_fp64": float(np.abs(uf - u64).max() / np.abs(u64).max()),
+        }
+        g.set_fp32_switch(0.0, 8, 0)
     if not args.no_spherical:
         # the same physics on the Spherical 128x64x8 grid (rmax 100), its own eta
         ws = workloads.paper_scale(workloads.SPHERICAL, 10)
