@@ -71,7 +71,7 @@ bool resident_split_ok(const hr_grid* g) {
 void resolve_variant(const hr_grid* g, int& variant, int& chunk) {
   variant = g->variant;
   chunk = g->chunk;
-  const long tiles = (long)((g->d.N0 + 63) / 64) * ((g->d.N1 + 7) / 8);
+  const long tiles = (long)((g->d.N0 + kTileX - 1) / kTileX) * ((g->d.N1 + kTileY - 1) / kTileY);
   if (variant == 0) {
     if (resident_ok(g))
       variant = 3;

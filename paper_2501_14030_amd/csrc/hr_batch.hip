@@ -70,8 +70,8 @@ hr_status bfail(hr_status s, const std::string& msg) {
 
 size_t up256(size_t x) { return (x + 255) / 256 * 256; }
 
-int tiles0(const hr_grid* g) { return (g->d.N0 + 63) / 64; }
-int tiles1(const hr_grid* g) { return (g->d.N1 + 7) / 8; }
+int tiles0(const hr_grid* g) { return (g->d.N0 + kTileX - 1) / kTileX; }
+int tiles1(const hr_grid* g) { return (g->d.N1 + kTileY - 1) / kTileY; }
 
 size_t batch_layout(hr_batch* b, char* base) {
   size_t off = 0;

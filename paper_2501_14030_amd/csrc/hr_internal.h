@@ -181,6 +181,9 @@ hipError_t launch_fill(float* dst, float value, int n, hipStream_t s);
 // points its stencils reach through a double-buffered global array, ordered by
 // per-block stage counters.
 constexpr int kResPatch = 8;          // patch width along x0 and x1
+// Stage-kernel tile: one wavefront along x0 times kTileY rows along x1.
+constexpr int kTileX = 64;
+constexpr int kTileY = 8;
 constexpr int kResMaxWait = 16;       // blocks one block exchanges with, at most
 constexpr int kResFlagStride = 32;    // one 128-byte line per block counter
 constexpr int kResMaxBlocks = 1024;

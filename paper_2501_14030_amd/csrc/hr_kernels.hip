@@ -39,8 +39,8 @@ namespace {
 // phi + pi), through theta = 0 or pi (phi + pi). The x0 and x1 stencil taps
 // then read LDS; the x2 taps (periodic in phi) read global memory directly,
 // where neighbouring planes' blocks make them cache hits.
-constexpr int TX = 64;   // threads along x0 (one wavefront)
-constexpr int TY = 8;    // threads along x1
+constexpr int TX = kTileX;  // threads along x0 (one wavefront)
+constexpr int TY = kTileY;  // threads along x1
 constexpr int kTileThreads = TX * TY;
 
 template <int NG>
