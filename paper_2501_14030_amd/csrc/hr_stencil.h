@@ -47,10 +47,18 @@ struct Weights {
   }
 };
 
-// Source difference of the split-state form: S p^-7 [(1 + x)^-7 - 1], x = e/p,
-// evaluated without cancellation for small increments.
+// Source difference of the split-state form: S p^-7 [(1 + x)^-7 - 1], x = e/p.
+// With q = p + e and y = p/q = 1/(1 + x): (1 + x)^-7 - 1 = y^7 - 1 =
+// (y - 1)(1 + y + ... + y^6) and y - 1 = -e/q, so the small difference is
+// formed without cancellation from one division, two products and a
+// six-step Horner sum (FP32 relative error within a few ulp).
 __device__ __forceinline__ float source_delta(float sp7, float pb, float e) {
-  return sp7 * expm1f(-7.0f * log1pf(e / pb));
+  const float r = 1.0f / (pb + e);
+  const float y = pb * r;
+  float s = 1.0f;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) s = s * y + 1.0f;
+  return -sp7 * (e * r) * s;
 }
 
 // Radial-derivative term of the outer radiation condition, qd x (one-sided
