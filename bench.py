@@ -325,6 +325,50 @@ def precision_form_runs(hr, torch):
     return res
 
 
+def warm_start_runs(hr, torch, g, w, steps, steps_cold, t_cold):
+    """The learned warm start on the paper-scale configuration: an MLP trained
+    (inside this run) on 512 catalog solves at 64x64x8 predicts u, v = eta u is
+    set, and the FP64 relaxation runs to the same tolerance. The timed solve
+    includes the network's inference; training is reported separately."""
+    from paper_2501_14030_amd import warmstart, workloads
+    from paper_2501_14030_amd.mlp import MLP, config_features
+
+    t0 = time.perf_counter()
+    train_ws = workloads.catalog(512, seed=14031, shapes=((64, 64, 8),))
+    mlp = MLP(width=256, seed=1, max_batch=65536)
+    X, T = warmstart.dataset(train_ws, (64, 64, 8), 512, 7, mlp, log=log)
+    t_data = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    losses = warmstart.train(mlp, X, T, 20, 8192, 2e-3, 3, log=lambda m: None)
+    t_train = time.perf_counter() - t0
+    # q = 1, chi1 = chi2 = (0, 0, 0.8) (S = 0.2 on m = 0.5), |P| = 0.095, D = 10
+    cfg = config_features(1.0, [0.0, 0.0, 0.8], [0.0, 0.0, 0.8], 0.095, 10.0)
+    out = {"train_configs": 512, "train_shape": [64, 64, 8], "data_s": t_data,
+           "train_s": t_train, "final_loss": losses[-1]}
+    for label, prec in (("fp64", hr.FP64), ("split", hr.FP32_FP64FINISH)):
+        times, res = [], None
+        for _ in range(steps):
+            g.set_punctures(*w.punctures.as_tuple())
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            mlp.warm_start(g, cfg, w.eta)
+            res = g.relax(w.eta, w.kappa, 0.0, w.n_steps, w.tol, check_every=w.check_every,
+                          precision=prec)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t1)
+            if res.status != hr.OK:
+                raise RuntimeError(f"warm-started {label} solve did not converge")
+        out[label] = {"time_to_residual_s": float(np.median(times)),
+                      "rk4_steps_to_tol": res.steps_taken, "fp32_steps": res.fp32_steps,
+                      "final_residual": res.residual}
+        log(f"warm start {label}: {res.steps_taken} steps, {np.median(times) * 1e3:.2f} ms")
+    out["fp64"]["steps_vs_cold"] = out["fp64"]["rk4_steps_to_tol"] / steps_cold
+    out["fp64"]["speedup_vs_cold_fp64"] = t_cold / out["fp64"]["time_to_residual_s"]
+    out["split"]["speedup_vs_cold_fp64"] = t_cold / out["split"]["time_to_residual_s"]
+    mlp.close()
+    return out
+
+
 def cpu_baseline(w, budget_s: float):
     """The oracle as it is, on the host cores, on a bounded sample of the same
     workload: RK4 steps of the same grid from the same initial state."""
@@ -373,6 +417,7 @@ def main() -> int:
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-spherical", action="store_true")
     ap.add_argument("--no-precision-form", action="store_true")
+    ap.add_argument("--no-warm-start", action="store_true")
     ap.add_argument("--kernel-profile", metavar="N0xN1xN2", default=None,
                     help="only run the stage kernels at this shape (counter passes)")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32"])
@@ -492,6 +537,9 @@ def main() -> int:
             "max_rel_diff_u_vs_fp64": float(np.abs(uf - u64).max() / np.abs(u64).max()),
         }
         g.set_fp32_switch(0.0, 8, 0)
+    if not args.no_warm_start:
+        out["warm_start"] = warm_start_runs(hr, torch, g, w, args.steps, steps64,
+                                            float(np.median([t[1] for t in tm64])))
     if not args.no_spherical:
         # the same physics on the Spherical 128x64x8 grid (rmax 100), its own eta
         ws = workloads.paper_scale(workloads.SPHERICAL, 10)
