@@ -175,7 +175,7 @@ def kernel_profile(shape_s: str, prec_s: str, variant: int = 0) -> int:
     if variant:
         g.set_kernel_config(variant=variant)
     g.set_punctures(*w.punctures.as_tuple())
-    prec = hr.FP64 if prec_s == "fp64" else hr.FP32
+    prec = {"fp64": hr.FP64, "fp32": hr.FP32, "split": hr.FP32_FP64FINISH}[prec_s]
     us = g.time_stage_kernels(w.eta, w.kappa, 0.0, 3, prec)
     print(json.dumps({"shape": shape, "prec": prec_s, "avg_launch_us": list(us),
                       "config": g.kernel_config(), "kernel_sha": kernel_sha()}), flush=True)
@@ -420,7 +420,7 @@ def main() -> int:
     ap.add_argument("--no-warm-start", action="store_true")
     ap.add_argument("--kernel-profile", metavar="N0xN1xN2", default=None,
                     help="only run the stage kernels at this shape (counter passes)")
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "split"])
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--catalog", type=int, default=0, metavar="N",
                     help="relax the seeded N-configuration catalog with the batched path")
