@@ -321,8 +321,9 @@ hr_status hr_resolved_kernel(const hr_grid* g, hr_precision prec, hr_kernel_conf
 /*
  * Autotuner: times the stage kernels of this grid in precision prec (HR_FP64
  * or HR_FP32) for every candidate configuration -- plane tiles, phi columns
- * with chunk 1, 2, 4, ... up to N2, and (FP64, where it applies) the resident
- * kernel -- over n_steps (>= 1) rounds of stages 1-3 (which never write the
+ * with chunk 1, 2, 4, ... up to N2, and (FP64, where they apply) the resident
+ * kernel on 8 x 8 and on 8 x 4 patches -- over n_steps (>= 1) rounds of
+ * stages 1-3 (which never write the
  * state y_n; the resident kernel runs whole steps on a copy of the state that
  * is put back afterwards, so the state is unchanged),
  * keeps the fastest in the grid (as hr_set_kernel_config would) and in a

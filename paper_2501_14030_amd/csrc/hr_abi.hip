@@ -1161,7 +1161,17 @@ hr_status hr_autotune(hr_grid* g, hr_precision prec, int n_steps, hr_kernel_conf
   std::vector<hr_kernel_config> cand;
   cand.push_back(hr_kernel_config{1, 0, 0, g->graph});
   for (int c = 1; c <= g->d.N2; c *= 2) cand.push_back(hr_kernel_config{2, 0, c, g->graph});
-  if (prec == HR_FP64 && resident_ok(g)) cand.push_back(hr_kernel_config{3, 0, 0, g->graph});
+  if (prec == HR_FP64) {
+    // the resident kernel on each patch shape that fits
+    const int v0 = g->variant, c0 = g->chunk;
+    for (int rows : {8, 4}) {
+      g->variant = 3;
+      g->chunk = rows;
+      if (resident_ok(g)) cand.push_back(hr_kernel_config{3, 0, rows, g->graph});
+    }
+    g->variant = v0;
+    g->chunk = c0;
+  }
   hipEvent_t e0, e1;
   HR_HIP(hipEventCreate(&e0));
   HR_HIP(hipEventCreate(&e1));
