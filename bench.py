@@ -548,9 +548,11 @@ def main() -> int:
                             params=hr.default_params(rmax=ss.rmax))
         rs64, ts64, tms64 = timed_solves(hr, torch, gs, ws, hr.FP64, args.steps, args.warmup,
                                          "spherical fp64")
+        us64 = gs.get_u()
         gs.set_fp32_switch(0.0, 8, 0)
         rs32, ts32, tms32 = timed_solves(hr, torch, gs, ws, hr.FP32_FP64FINISH, args.steps, 0,
                                          "spherical fp32+fp64")
+        us32 = gs.get_u()
         out["spherical"] = {
             "workload": f"paper-scale Spherical {ss.N0}x{ss.N1}x{ss.N2}, 10th-order FD, "
                         f"rmax {ss.rmax}, same punctures, eta {ws.eta}, to residual 1e-10",
@@ -564,6 +566,7 @@ def main() -> int:
             "mixed_time_to_residual_s": ts32 / args.steps,
             "mixed_rk4_steps_to_tol": rs32[-1].steps_taken,
             "mixed_fp32_steps": rs32[-1].fp32_steps,
+            "mixed_max_rel_diff_u_vs_fp64": float(np.abs(us32 - us64).max() / np.abs(us64).max()),
         }
         gs.close()
     if not args.no_precision_form:
