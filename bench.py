@@ -325,7 +325,7 @@ def precision_form_runs(hr, torch):
     return res
 
 
-def warm_start_runs(hr, torch, g, w, steps, steps_cold, t_cold):
+def warm_start_runs(hr, torch, g, w, steps, steps_cold, t_cold, u_cold):
     """The learned warm start on the paper-scale configuration: an MLP trained
     (inside this run) on 512 catalog solves at 64x64x8 predicts u, v = eta u is
     set, and the FP64 relaxation runs to the same tolerance. The timed solve
@@ -358,9 +358,12 @@ def warm_start_runs(hr, torch, g, w, steps, steps_cold, t_cold):
             times.append(time.perf_counter() - t1)
             if res.status != hr.OK:
                 raise RuntimeError(f"warm-started {label} solve did not converge")
+        u = g.get_u()
         out[label] = {"time_to_residual_s": float(np.median(times)),
                       "rk4_steps_to_tol": res.steps_taken, "fp32_steps": res.fp32_steps,
-                      "final_residual": res.residual}
+                      "final_residual": res.residual,
+                      "max_rel_diff_u_vs_cold_fp64": float(np.abs(u - u_cold).max() /
+                                                           np.abs(u_cold).max())}
         log(f"warm start {label}: {res.steps_taken} steps, {np.median(times) * 1e3:.2f} ms")
     out["fp64"]["steps_vs_cold"] = out["fp64"]["rk4_steps_to_tol"] / steps_cold
     out["fp64"]["speedup_vs_cold_fp64"] = t_cold / out["fp64"]["time_to_residual_s"]
@@ -539,7 +542,7 @@ def main() -> int:
         g.set_fp32_switch(0.0, 8, 0)
     if not args.no_warm_start:
         out["warm_start"] = warm_start_runs(hr, torch, g, w, args.steps, steps64,
-                                            float(np.median([t[1] for t in tm64])))
+                                            float(np.median([t[1] for t in tm64])), u64)
     if not args.no_spherical:
         # the same physics on the Spherical 128x64x8 grid (rmax 100), its own eta
         ws = workloads.paper_scale(workloads.SPHERICAL, 10)
