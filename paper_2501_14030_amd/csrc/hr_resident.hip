@@ -19,15 +19,15 @@
 //     owners of its rim taps; the relation is symmetric), then loads its rim
 //     from the exchange array. The exchange array is packed by patch
 //     ([patch][plane][x1][x0], 512 contiguous bytes per 8 x 8 patch plane in
-//     FP64),
-//     so a block's publish is whole cache lines and each rim strip spans a few
-//     lines of one patch plane instead of one line per grid row; the initial
-//     state is published the same way before the first stage. Rim cells that
-//     are images of the patch's own points (inner-boundary reflections onto
-//     itself) are copied within LDS, and the outer points, read only by their
-//     own patch, stay in LDS;
-//   * the phi sums and the source term need only the patch's own planes and
-//     are computed while the rim loads are in flight.
+//     FP64), so a block's publish is whole cache lines and each rim strip
+//     spans a few lines of one patch plane instead of one line per grid row;
+//     the initial state is published the same way before the first stage.
+//     Rim cells that are images of the patch's own points (inner-boundary
+//     reflections onto itself) are copied within LDS, and the outer points,
+//     read only by their own patch, stay in LDS;
+//   * the image copies, the phi sums, the source term and the outer points'
+//     radiation condition need only the patch's own cells and are computed
+//     while the rim loads are in flight.
 // All blocks are resident at once: each takes more than half of a compute
 // unit's LDS, and the grid has at most as many blocks as the device has
 // compute units (checked by occupancy before use).
