@@ -148,3 +148,21 @@ def test_factor_storage_arguments(lib):
         assert f(h, bad) == hr.EINVAL
     assert f(None, 32) == hr.EINVAL
     lib.hr_grid_destroy(h)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """The binding has no fallback: loading a library that is not there raises
+    with a message that names the build step (run in a child process so that
+    this process's loaded library is untouched)."""
+    import subprocess
+    import sys
+    code = ("import paper_2501_14030_amd as hr\n"
+            "try:\n"
+            f"    hr.load_library({str(tmp_path / 'libhrelax.so')!r})\n"
+            "except Exception as e:\n"
+            "    print('raised:', e)\n"
+            "else:\n"
+            "    print('loaded')\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT,
+                       timeout=300)
+    assert "raised:" in r.stdout and "missing" in r.stdout, r.stdout + r.stderr
