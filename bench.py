@@ -325,6 +325,64 @@ def precision_form_runs(hr, torch):
     return res
 
 
+def multi_patch_runs(hr, torch, w, u_ref, n_max: int = 7):
+    """The independent-patches experiment of Sec. 4 (multiple, independent
+    patches): N = 1 .. n_max identical paper-scale grids relaxed from u = v = 0
+    to the tolerance, (a) as one batch (one persistent launch per RK stage over
+    every grid, graph-captured per check interval) and (b) one after another
+    with the single-grid path. t_N counts the sources and the relaxation, after
+    one untimed run of the same N; t_N / t_1 is the quantity of the paper's
+    figure (it found the GPU code close to linear in N)."""
+    s = w.grid
+    prm = hr.default_params(amax=s.amax, sinhwaa=s.sinhwaa, bscale=s.bscale, rmax=s.rmax)
+    grids = [hr.grid_create(s.coords, s.N0, s.N1, s.N2, s.fd_order, params=prm)
+             for _ in range(n_max)]
+    for g in grids:
+        run_solve(hr, torch, g, w, hr.FP64)   # untimed: workspace bound, graphs captured
+    rows = []
+    for n in range(1, n_max + 1):
+        sub = grids[:n]
+        b = hr.Batch(sub)
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for g in sub:
+                g.set_punctures(*w.punctures.as_tuple())
+            torch.cuda.synchronize()
+            res = b.relax([w.eta] * n, w.kappa, n_steps=w.n_steps, tol=w.tol,
+                          check_every=w.check_every)
+            torch.cuda.synchronize()
+            tb = time.perf_counter() - t0
+        b.close()
+        steps_b = [r.steps_taken for r in res]
+        if any(r.status != hr.OK for r in res):
+            raise RuntimeError(f"multi-patch batch of {n} did not converge")
+        diff = max(float(np.abs(g.get_u() - u_ref).max() / np.abs(u_ref).max()) for g in sub)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        seq = [run_solve(hr, torch, g, w, hr.FP64) for g in sub]
+        torch.cuda.synchronize()
+        tq = time.perf_counter() - t0
+        if any(r.status != hr.OK for r in seq):
+            raise RuntimeError(f"multi-patch sequential run of {n} did not converge")
+        rows.append({"n": n, "batched_s": tb, "sequential_s": tq, "rk4_steps_batched": steps_b,
+                     "rk4_steps_sequential": [r.steps_taken for r in seq],
+                     "max_rel_diff_u_batched_vs_single": diff})
+        log(f"multi-patch N={n}: batched {tb:.3f} s (steps {steps_b[0]}), sequential {tq:.3f} s, "
+            f"batched u vs single solve {diff:.2e}")
+    for g in grids:
+        g.close()
+    t1b, t1q = rows[0]["batched_s"], rows[0]["sequential_s"]
+    best1 = min(t1b, t1q)
+    for r in rows:
+        r["batched_over_t1"] = r["batched_s"] / t1b
+        r["sequential_over_t1"] = r["sequential_s"] / t1q
+        r["best_over_best_t1"] = min(r["batched_s"], r["sequential_s"]) / best1
+    return {"workload": f"N identical {s.name()} relaxations from u = v = 0 to residual "
+                        f"{w.tol} (paper-scale punctures, eta {w.eta}), N = 1..{n_max}",
+            "rows": rows}
+
+
 def warm_start_runs(hr, torch, g, w, steps, steps_cold, t_cold, u_cold):
     """The learned warm start on the paper-scale configuration: an MLP trained
     (inside this run) on 512 catalog solves at 64x64x8 predicts u, v = eta u is
@@ -421,6 +479,7 @@ def main() -> int:
     ap.add_argument("--no-spherical", action="store_true")
     ap.add_argument("--no-precision-form", action="store_true")
     ap.add_argument("--no-warm-start", action="store_true")
+    ap.add_argument("--no-multi-patch", action="store_true")
     ap.add_argument("--kernel-profile", metavar="N0xN1xN2", default=None,
                     help="only run the stage kernels at this shape (counter passes)")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "split"])
@@ -574,6 +633,8 @@ def main() -> int:
         gs.close()
     if not args.no_precision_form:
         out["precision_form"] = precision_form_runs(hr, torch)
+    if not args.no_multi_patch:
+        out["multi_patch"] = multi_patch_runs(hr, torch, w, u64)
     # roofline of the dominant kernel (the resident RK4 kernel at this size)
     g.set_punctures(*w.punctures.as_tuple())
     copy = copy_bandwidth(torch)
@@ -598,6 +659,11 @@ def main() -> int:
         cb = cpu_baseline(w, args.cpu_seconds)
         cb["time_to_residual_s_extrapolated"] = steps64 * spec.n_interior * 4 / cb["value"]
         out["cpu_baseline"] = cb
+        if "multi_patch" in out:
+            # the oracle relaxes one grid after another: N times its one-grid time
+            for r in out["multi_patch"]["rows"]:
+                r["speedup_vs_oracle"] = (r["n"] * cb["time_to_residual_s_extrapolated"]
+                                          / min(r["batched_s"], r["sequential_s"]))
     print(json.dumps(out), flush=True)
     g.close()
     return 0

@@ -13,6 +13,7 @@
 // lengths in device memory change. The host reads back one norm per grid per
 // check and applies each grid's own stop test.
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -49,6 +50,7 @@ struct hr_batch {
   double* host_out = nullptr;
   int nblk_tile = 512;
   int nblk_flat = 2048;
+  int cus = 256;
   hipGraphExec_t exec = nullptr;
   int exec_mode = -1;
   int exec_K = 0;
@@ -72,6 +74,27 @@ size_t up256(size_t x) { return (x + 255) / 256 * 256; }
 
 int tiles0(const hr_grid* g) { return (g->d.N0 + kTileX - 1) / kTileX; }
 int tiles1(const hr_grid* g) { return (g->d.N1 + kTileY - 1) / kTileY; }
+
+// An explicit phi-column configuration of a grid keeps its chunk in a batch.
+bool explicit_chunk(const hr_grid* g) { return g->variant == 2 && g->chunk > 0; }
+
+// The phi chunk of the other grids of a batch: the largest of 16, 8, 4, 2 planes
+// (capped at each grid's N2) whose work list still holds an item per compute
+// unit, else single planes. Longer chunks load each column's phi taps once for
+// more planes; shorter ones give small batches more items to spread over the
+// chip (swept over 1..7 grids of 64x64x8, 128x128x16 and 256x256x32).
+int batch_chunk(const hr_batch* b) {
+  for (int c = 16; c > 1; c /= 2) {
+    long items = 0;
+    for (int i = 0; i < b->n; ++i) {
+      const hr_grid* g = b->g[i];
+      const int ch = explicit_chunk(g) ? g->chunk : std::min(c, g->d.N2);
+      items += (long)tiles0(g) * tiles1(g) * ((g->d.N2 + ch - 1) / ch);
+    }
+    if (items >= b->cus) return c;
+  }
+  return 1;
+}
 
 size_t batch_layout(hr_batch* b, char* base) {
   size_t off = 0;
@@ -263,6 +286,7 @@ hr_status hr_batch_bind(hr_batch* b, void* dev_ptr, size_t bytes, void* hip_stre
   HR_HIPB(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
   b->nblk_tile = 2 * cus;
   b->nblk_flat = 8 * cus;
+  b->cus = cus;
   b->bound = true;
   return HR_OK;
 }
@@ -304,14 +328,13 @@ hr_status hr_batch_relax(hr_batch* b, const double* eta, const double* c, long n
   std::vector<ResidualArgs> hra(b->n);
   std::vector<BaseArgs> hba(b->n);
   std::vector<RebaseArgs> hrb(b->n);
+  const int bchunk = batch_chunk(b);
   for (int i = 0; i < b->n; ++i) {
     hr_grid* g = b->g[i];
     hr_status st = load_kappa(g, c[i]);
     if (st != HR_OK) return st;
     const double dt = g->prm.cfl * g->tab.ds_g;
-    int variant = 0, chunk = 1;
-    resolve_variant(g, variant, chunk);
-    if (variant != 2) chunk = 1;
+    const int chunk = explicit_chunk(g) ? g->chunk : std::min(bchunk, g->d.N2);
     run[i].chunk = chunk;
     run[i].phase = prec == HR_FP32_FP64FINISH ? 0 : 1;
     run[i].sw = g->sw_residual > 0 ? g->sw_residual : (tol > 0 ? 10.0 * tol : 0.0);

@@ -97,3 +97,68 @@ def test_batch_rejects_mixed_orders_and_unbound():
         hr.Batch([a, c])
     with pytest.raises(hr.HRError):
         hr.Batch([a, a])
+
+
+def test_identical_grids_in_one_batch_and_batch_reuse():
+    # the independent-patches setup of Sec. 4: N identical grids in one batch
+    # relax exactly alike (no cross-talk between work-list entries), match one
+    # eager solve, and a batch relaxed a second time from u = v = 0 repeats itself
+    banner("identical grids in one batch, reused")
+    spec = workloads.GridSpec(0, 64, 64, 8, 10, bscale=4.0)
+    pz = _punctures(spec, 1)
+    gs = [gpu_grid(spec) for _ in range(5)]
+    for g in gs:
+        g.set_punctures(*pz.as_tuple())
+    b = hr.Batch(gs)
+    res = b.relax([6.0] * 5, 1.0, n_steps=60000, tol=1e-10, check_every=100)
+    u0 = gs[0].get_u(extended=True)
+    for g, r in zip(gs, res):
+        assert r.status == hr.OK and r.steps_taken == res[0].steps_taken
+        assert np.array_equal(g.get_u(extended=True), u0)
+        np.testing.assert_array_equal(r.history, res[0].history)
+    e = gpu_grid(spec)
+    e.set_punctures(*pz.as_tuple())
+    r = e.relax(6.0, 1.0, 0.0, 60000, 1e-10, check_every=100)
+    banner(f"  batch steps {res[0].steps_taken}, eager {r.steps_taken}")
+    assert r.steps_taken == res[0].steps_taken
+    assert rel_maxdiff(u0, e.get_u(extended=True)) <= 1e-11
+    for g in gs:
+        g.set_punctures(*pz.as_tuple())
+    res2 = b.relax([6.0] * 5, 1.0, n_steps=60000, tol=1e-10, check_every=100)
+    b.close()
+    for g, r in zip(gs, res2):
+        assert r.steps_taken == res[0].steps_taken
+        assert np.array_equal(g.get_u(extended=True), u0)
+
+
+def test_batch_phi_chunks_with_ragged_tails():
+    # two 128x128x14 grids and one 128x128x10: the batch walks phi in chunks of
+    # 4 planes (352 work items), so each column ends on a ragged chunk (2 planes)
+    banner("batch phi chunks of 4 with ragged tails")
+    specs = [workloads.GridSpec(0, 128, 128, 14, 10, bscale=4.0),
+             workloads.GridSpec(0, 128, 128, 14, 10, bscale=5.0),
+             workloads.GridSpec(0, 128, 128, 10, 10, bscale=4.0)]
+    etas = [20.0, 30.0, 25.0]
+    gs = []
+    for k, spec in enumerate(specs):
+        g = gpu_grid(spec)
+        g.set_punctures(*_punctures(spec, k).as_tuple())
+        gs.append(g)
+    b = hr.Batch(gs)
+    res = b.relax(etas, 1.0, n_steps=200, tol=0.0, check_every=100)
+    b.close()
+    for k, spec in enumerate(specs):
+        assert res[k].steps_taken == 200
+        e = gpu_grid(spec)
+        e.set_punctures(*_punctures(spec, k).as_tuple())
+        r = e.relax(etas[k], 1.0, 0.0, 200, 0.0, check_every=100)
+        d = rel_maxdiff(gs[k].get_u(extended=True), e.get_u(extended=True))
+        banner(f"  {spec.name()}: batch vs eager {d:.2e}")
+        assert d <= 1e-13
+        np.testing.assert_allclose(res[k].history, r.history, rtol=1e-9, atol=1e-16)
+    spec = specs[2]
+    og = oracle_grid(spec)
+    og.set_punctures(*_punctures(spec, 2).as_tuple())
+    og.relax(etas[2], 1.0, og.suggest_dt(0.5), 200, 0.0, 100)
+    ou, _ = og.state()
+    assert rel_maxdiff(gs[2].get_u(extended=True), oracle_extended(og, ou)) <= 1e-12
