@@ -246,7 +246,9 @@ def catalog_run(n: int, precision_s: str, autotune: bool, max_steps: int,
         e["max_steps"] = int(np.max(e.pop("steps")))
     print(json.dumps({"catalog_configs": n, "precision": precision_s, "converged": conv,
                       "wall_s": el, "grid_point_rhs_updates_per_s": upd / el,
-                      "groups": len(catalog.cache_groups(grids, prec, budget)),
+                      "groups": len(catalog.plan_groups(
+                          grids, prec, budget,
+                          torch.cuda.get_device_properties(0).multi_processor_count)),
                       "cache_budget_bytes": budget,
                       "by_shape": by_shape,
                       "autotuned": {"x".join(map(str, k)): v[0] for k, v in tuned.items()}}),

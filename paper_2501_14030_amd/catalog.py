@@ -8,6 +8,12 @@ grids of a catalog together streams every stage from HBM; relaxing them in
 cache-sized groups lets each stage re-read what the previous one wrote from the
 cache. Grids are placed largest first into the first group with room (a grid
 larger than the budget gets a group of its own).
+
+A grid whose own kernel is the resident one with a patch on every compute unit
+(128x128x16 and larger (x0, x1) planes that fit it) is relaxed alone instead:
+the resident kernel keeps its state on chip and already fills the chip, which
+no batch of stage kernels matches (3.2 us per stage alone against ~7 us per
+grid and stage in a batch at 128x128x16, FP64).
 """
 from __future__ import annotations
 
@@ -43,6 +49,27 @@ def cache_groups(grids, precision: int, budget: int = CACHE_BUDGET) -> list:
     return groups
 
 
+def runs_alone(g, precision: int, cus: int) -> bool:
+    """True if `g` relaxes faster by itself: its automatic kernel in this
+    precision is the resident kernel and its patches (8 x0 points by `chunk`
+    x1 rows) cover at least `cus` compute units."""
+    cfg = g.resolved_kernel(precision)
+    if cfg["variant"] != 3:
+        return False
+    N0, N1, _ = g.N
+    return (N0 // 8) * (N1 // cfg["chunk"]) >= cus
+
+
+def plan_groups(grids, precision: int, budget: int = CACHE_BUDGET, cus: int = 256) -> list:
+    """Index groups in the order they are relaxed: each grid that runs alone
+    (`runs_alone`), then the cache groups of the others."""
+    solo = [i for i, g in enumerate(grids) if runs_alone(g, precision, cus)]
+    taken = set(solo)
+    rest = [i for i in range(len(grids)) if i not in taken]
+    sub = cache_groups([grids[i] for i in rest], precision, budget)
+    return [[i] for i in solo] + [[rest[j] for j in grp] for grp in sub]
+
+
 def relax_catalog(grids, etas, tols, precision: int = FP64, max_steps: int = 60000,
                   chunk: int = 5000, check_every: int = 100, budget: int = CACHE_BUDGET,
                   log=None):
@@ -51,10 +78,15 @@ def relax_catalog(grids, etas, tols, precision: int = FP64, max_steps: int = 600
     in chunks of `chunk` steps (one batched call per tolerance within the group),
     a grid leaving its batch at its first check below its tolerance; a group of
     one grid is relaxed by the single-grid path."""
+    import torch
+
     steps = [0] * len(grids)
     resid = [float("inf")] * len(grids)
     t0 = time.perf_counter()
-    groups = cache_groups(grids, precision, budget)
+    if not grids:
+        return steps, resid
+    cus = torch.cuda.get_device_properties(grids[0].device).multi_processor_count
+    groups = plan_groups(grids, precision, budget, cus)
     for gi, group in enumerate(groups):
         if len(group) == 1:
             # a grid alone: the single-grid path (same kernels, no work lists)
