@@ -72,3 +72,37 @@ def test_catalog_size_batch_parity():
         banner(f"  batch grid {g.N}: du {du:.2e}")
         assert du <= 1e-12
         np.testing.assert_allclose(r.history, ohist, rtol=1e-9)
+
+
+_PATCH_REF = {}
+
+
+@pytest.mark.parametrize("n", [1, 3, 7])
+def test_independent_patches_batch_parity(n):
+    # the independent-patches bench: n identical paper-scale grids in one batch
+    # (phi chunks of 2, 4 and 8 planes for n = 1, 3, 7), each against the oracle
+    w = workloads.paper_scale()
+    spec = w.grid
+    banner(f"{n} identical {spec.name()} in one batch, {STEPS} steps")
+    if "ref" not in _PATCH_REF:
+        og, _, ohist = _oracle(spec, w.punctures, w.eta)
+        _PATCH_REF["ref"] = (oracle_extended(og, og.state()[0]), ohist)
+    ref, ohist = _PATCH_REF["ref"]
+    grids = []
+    for _ in range(n):
+        g = gpu_grid(spec)
+        g.set_punctures(*w.punctures.as_tuple())
+        grids.append(g)
+    b = hr.Batch(grids)
+    try:
+        res = b.relax([w.eta] * n, 1.0, n_steps=STEPS, tol=0.0, check_every=K)
+    finally:
+        b.close()
+    u0 = grids[0].get_u(extended=True)
+    du = rel_maxdiff(u0, ref)
+    banner(f"  du {du:.2e}")
+    assert du <= 1e-12
+    for g, r in zip(grids, res):
+        assert r.steps_taken == STEPS
+        assert np.array_equal(g.get_u(extended=True), u0)
+        np.testing.assert_allclose(r.history, ohist, rtol=1e-9)
