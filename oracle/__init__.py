@@ -42,26 +42,44 @@ _lp = ctypes.POINTER(ctypes.c_long)
 _ip = ctypes.POINTER(ctypes.c_int)
 
 
+def compile_source(src: str, out: str) -> str:
+    """Compile an oracle source file with g++ (plain -O2, OpenMP, no FP
+    contraction, no fast-math) into the shared library ``out``."""
+    tmp = out + ".tmp"
+    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", "-shared", "-fPIC", src, "-o", tmp]
+    subprocess.check_call(cmd)
+    os.replace(tmp, out)
+    return out
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with g++ (plain -O2, OpenMP, no FP contraction)."""
+    """Compile the oracle (``hr_oracle.cpp`` -> ``libhr_oracle.so``)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off",
-               "-fno-fast-math", "-shared", "-fPIC", _SRC, "-o", tmp]
-        subprocess.check_call(cmd)
-        os.replace(tmp, _LIB)
+        compile_source(_SRC, _LIB)
     return _LIB
 
 
 _lib = None
+_lib_path = _LIB
+
+
+def use_library(path: str | None = None) -> None:
+    """Load the oracle from another build of ``hr_oracle.cpp`` for the grids
+    created afterwards (``None``: the default library). Used by the tests that
+    plant a mistake in a copy of the source and check that a pin catches it;
+    a grid keeps the library it was created with."""
+    global _lib, _lib_path
+    _lib = None
+    _lib_path = path if path is not None else _LIB
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        if _lib_path == _LIB and not os.path.exists(_LIB):
             build()
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(_lib_path)
         L.or_create.restype = ctypes.c_void_p
         L.or_create.argtypes = [ctypes.c_int] * 5 + [ctypes.c_double] * 4
         L.or_destroy.argtypes = [ctypes.c_void_p]
@@ -159,6 +177,7 @@ class OracleGrid:
                  amax: float = DEFAULT_AMAX, sinhwaa: float = DEFAULT_SINHWAA,
                  bscale: float = 1.0, rmax: float = DEFAULT_RMAX):
         L = lib()
+        self._L = L
         h = L.or_create(int(coords), N0, N1, N2, fd_order, amax, sinhwaa, bscale, rmax)
         if not h:
             raise ValueError("invalid oracle grid arguments")
@@ -175,55 +194,56 @@ class OracleGrid:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and _lib is not None:
-            _lib.or_destroy(h)
+        L = getattr(self, "_L", None)
+        if h is not None and L is not None:
+            L.or_destroy(h)
             self._h = None
 
     # --- geometry -------------------------------------------------------
     def xx(self, d: int) -> np.ndarray:
         out = np.zeros(self.Nx[d])
-        lib().or_xx(self._h, d, _p(out))
+        self._L.or_xx(self._h, d, _p(out))
         return out
 
     def dxx(self) -> np.ndarray:
         out = np.zeros(3)
-        lib().or_dxx(self._h, _p(out))
+        self._L.or_dxx(self._h, _p(out))
         return out
 
     def cart(self):
         X = np.zeros(self.npad)
         Y = np.zeros(self.npad)
         Z = np.zeros(self.npad)
-        lib().or_cart(self._h, _p(X), _p(Y), _p(Z))
+        self._L.or_cart(self._h, _p(X), _p(Y), _p(Z))
         return X.reshape(self.shape), Y.reshape(self.shape), Z.reshape(self.shape)
 
     def metric(self) -> dict:
         """a0,a1,a2,b0,b1,dsmin over the padded (i0,i1) plane, shape (Nx1,Nx0)."""
         n = self.Nx[0] * self.Nx[1]
         out = np.zeros(6 * n)
-        lib().or_metric(self._h, _p(out))
+        self._L.or_metric(self._h, _p(out))
         names = ["a0", "a1", "a2", "b0", "b1", "dsmin"]
         return {k: out[i * n:(i + 1) * n].reshape(self.Nx[1], self.Nx[0]) for i, k in enumerate(names)}
 
     def scale_factors(self, x0: float, x1: float) -> np.ndarray:
         out = np.zeros(3)
-        lib().or_scale_factors(self._h, float(x0), float(x1), _p(out))
+        self._L.or_scale_factors(self._h, float(x0), float(x1), _p(out))
         return out
 
     def to_cart(self, x0: float, x1: float, x2: float) -> np.ndarray:
         out = np.zeros(3)
-        lib().or_to_cart(self._h, float(x0), float(x1), float(x2), _p(out))
+        self._L.or_to_cart(self._h, float(x0), float(x1), float(x2), _p(out))
         return out
 
     def ds_g(self) -> float:
-        return lib().or_ds_g(self._h)
+        return self._L.or_ds_g(self._h)
 
     def suggest_dt(self, cfl: float = 0.5) -> float:
-        return lib().or_suggest_dt(self._h, cfl)
+        return self._L.or_suggest_dt(self._h, cfl)
 
     def bc_images(self) -> np.ndarray:
         out = np.zeros(self.npad, dtype=np.int64)
-        lib().or_bc_images(self._h, out.ctypes.data_as(_lp))
+        self._L.or_bc_images(self._h, out.ctypes.data_as(_lp))
         return out
 
     def interior(self, f: np.ndarray) -> np.ndarray:
@@ -238,29 +258,29 @@ class OracleGrid:
         x = _f64(x).reshape(n, 3)
         P = _f64(P).reshape(n, 3)
         S = _f64(S).reshape(n, 3)
-        lib().or_set_punctures(self._h, n, _p(m), _p(x), _p(P), _p(S))
+        self._L.or_set_punctures(self._h, n, _p(m), _p(x), _p(P), _p(S))
 
     def sources(self):
         psi = np.zeros(self.npad)
         ssrc = np.zeros(self.npad)
-        lib().or_get_sources(self._h, _p(psi), _p(ssrc))
+        self._L.or_get_sources(self._h, _p(psi), _p(ssrc))
         return psi.reshape(self.shape), ssrc.reshape(self.shape)
 
     def set_state(self, u: np.ndarray, v: np.ndarray) -> None:
         u = _f64(u).reshape(-1)
         v = _f64(v).reshape(-1)
         assert u.size == self.npad and v.size == self.npad
-        lib().or_set_state(self._h, _p(u), _p(v))
+        self._L.or_set_state(self._h, _p(u), _p(v))
 
     def state(self):
         u = np.zeros(self.npad)
         v = np.zeros(self.npad)
-        lib().or_get_state(self._h, _p(u), _p(v))
+        self._L.or_get_state(self._h, _p(u), _p(v))
         return u.reshape(self.shape), v.reshape(self.shape)
 
     def fill_ghosts(self, f: np.ndarray) -> np.ndarray:
         f = _f64(f).reshape(-1).copy()
-        lib().or_fill_ghosts(self._h, _p(f))
+        self._L.or_fill_ghosts(self._h, _p(f))
         return f.reshape(self.shape)
 
     def pad_interior(self, f_int: np.ndarray) -> np.ndarray:
@@ -273,7 +293,7 @@ class OracleGrid:
     def laplacian(self, f: np.ndarray) -> np.ndarray:
         f = _f64(f).reshape(-1)
         out = np.zeros(self.npad)
-        lib().or_laplacian(self._h, _p(f), _p(out))
+        self._L.or_laplacian(self._h, _p(f), _p(out))
         return out.reshape(self.shape)
 
     def rhs(self, eta: float, kappa: float, u: np.ndarray, v: np.ndarray):
@@ -281,17 +301,17 @@ class OracleGrid:
         v = _f64(v).reshape(-1)
         ku = np.zeros(self.npad)
         kv = np.zeros(self.npad)
-        lib().or_rhs(self._h, eta, kappa, _p(u), _p(v), _p(ku), _p(kv))
+        self._L.or_rhs(self._h, eta, kappa, _p(u), _p(v), _p(ku), _p(kv))
         return ku.reshape(self.shape), kv.reshape(self.shape)
 
     def residual(self, u: np.ndarray | None = None, want_H: bool = False):
         H = np.zeros(self.npad) if want_H else None
         Hp = _p(H) if want_H else None
         if u is None:
-            r = lib().or_residual(self._h, Hp)
+            r = self._L.or_residual(self._h, Hp)
         else:
             uu = _f64(u).reshape(-1)
-            r = lib().or_residual_of(self._h, _p(uu), Hp)
+            r = self._L.or_residual_of(self._h, _p(uu), Hp)
         return (r, H.reshape(self.shape)) if want_H else r
 
     def volume_mean(self, f: np.ndarray, radius: float = 0.0):
@@ -301,22 +321,22 @@ class OracleGrid:
         f = _f64(f).reshape(-1)
         assert f.size == self.npad
         vol = ctypes.c_double()
-        m = lib().or_volume_mean(self._h, _p(f), float(radius), ctypes.byref(vol))
+        m = self._L.or_volume_mean(self._h, _p(f), float(radius), ctypes.byref(vol))
         return m, vol.value
 
     def residual_volume(self, radius: float = 0.0) -> float:
         """Volume-weighted residual norm sqrt(sum H^2 J dV / sum J dV) of the
         state, over the cells within `radius` (all if radius <= 0)."""
-        return lib().or_residual_volume(self._h, float(radius))
+        return self._L.or_residual_volume(self._h, float(radius))
 
     def set_bc_order(self, order: int) -> None:
         """Order (2 or 4) of the one-sided xx0 difference in the outer radiation
         condition (2 by default)."""
-        if lib().or_set_bc_order(self._h, int(order)) != 0:
+        if self._L.or_set_bc_order(self._h, int(order)) != 0:
             raise ValueError(f"bc order {order} not available on this grid")
 
     def rk4_steps(self, eta: float, kappa: float, dt: float, nsteps: int) -> None:
-        lib().or_rk4_steps(self._h, eta, kappa, dt, int(nsteps))
+        self._L.or_rk4_steps(self._h, eta, kappa, dt, int(nsteps))
 
     def relax(self, eta: float, kappa: float, dt: float, n_steps: int, tol: float = 0.0,
               check_every: int = 100):
@@ -326,7 +346,7 @@ class OracleGrid:
         hist = np.zeros(cap)
         st = ctypes.c_long(0)
         nh = ctypes.c_long(0)
-        status = lib().or_relax(self._h, eta, kappa, dt, int(n_steps), tol, int(check_every),
+        status = self._L.or_relax(self._h, eta, kappa, dt, int(n_steps), tol, int(check_every),
                                 _p(hist), cap, ctypes.byref(st), ctypes.byref(nh))
         return status, st.value, hist[:min(nh.value, cap)].copy()
 
