@@ -88,7 +88,11 @@ typedef struct {
 void hr_default_params(hr_grid_params* p);
 
 /*
- * Creates a grid (host side only; no device memory yet).
+ * Creates a grid (host side only; no device memory yet): the setup steps of
+ * Algorithm 1 that sample the coordinates xx^i and precompute the reference
+ * metric (here the Laplacian factors of Eq. 4 per (xx0, xx1), the wave speed
+ * and the outer-boundary geometry), on the SinhSymTP or Spherical-like grids
+ * of the "Basic equations" section.
  *   coords   HR_SINHSYMTP, HR_SPHERICAL or HR_SINHSPHERICAL
  *   N0,N1,N2 interior points along xx0, xx1 (theta), xx2 (phi);
  *            N0 >= NG, N1 >= NG, N2 even and >= 2 (phi + pi parity images),
@@ -101,11 +105,13 @@ void hr_default_params(hr_grid_params* p);
 hr_status hr_grid_create(hr_coords coords, int N0, int N1, int N2, int fd_order,
                          const hr_grid_params* p, hr_grid** out);
 
-/* Frees the handle and its host resources (never the caller's device memory).
- * NULL is accepted. */
+/* Frees the handle and its host resources (the "free storage" step at the end
+ * of Algorithm 1; never the caller's device memory, which the caller frees).
+ * Waits for the grid's outstanding device work first. NULL is accepted. */
 void hr_grid_destroy(hr_grid* g);
 
-/* Interior and extended point counts (either pointer may be NULL). */
+/* Interior and extended point counts (either pointer may be NULL); they size
+ * the arrays of hr_get_u/v and hr_set_u/v. Errors: HR_EINVAL (null grid). */
 hr_status hr_grid_sizes(const hr_grid* g, size_t* n_interior, size_t* n_extended);
 
 /* Device workspace the grid needs (all precisions), in bytes. The paper sizes
@@ -115,6 +121,9 @@ size_t hr_workspace_bytes(const hr_grid* g);
 /*
  * Binds caller-owned device memory and a HIP stream (hipStream_t passed as
  * void*; NULL = the library creates and owns a stream of default priority).
+ * This is the allocation step of Algorithm 1: the whole device footprint
+ * (Runge-Kutta stage storage, source terms, coefficient tables) is one block
+ * sized up front, as the "Memory Management" subsection of Sec. 4 does.
  * dev_ptr must be 256-byte aligned and at least hr_workspace_bytes() long; it
  * stays owned by the caller and must outlive the handle's device work.
  * Uploads the coordinate tables and zeroes the state. Synchronous.
@@ -124,7 +133,8 @@ hr_status hr_grid_bind(hr_grid* g, void* dev_ptr, size_t bytes, void* hip_stream
 
 /*
  * Sets the punctures (paper "Basic equations": Brandt-Bruegmann punctures with
- * the Bowen-York extrinsic curvature) and computes on the device
+ * the Bowen-York extrinsic curvature; Algorithm 1's "compute constant source
+ * terms" step) and computes on the device
  *   psi_s = 1 + sum_n m_n/(2 r_n),
  *   S_src = (1/8) A_ij A^ij,
  *   A^ij = sum_n 3/(2 r_n^2)[P^i n^j + P^j n^i - (delta^ij - n^i n^j) P.n]
@@ -133,6 +143,11 @@ hr_status hr_grid_bind(hr_grid* g, void* dev_ptr, size_t bytes, void* hip_stream
  *   n  number of punctures, 1..4
  *   m  n bare masses (> 0); x, P, S: 3n doubles each (position, linear
  *      momentum, spin), host memory.
+ * On a SinhSymTP grid every puncture must lie at one of the two foci
+ * (0, 0, +-bscale), each coordinate within 1e-12 bscale: the coordinates put
+ * their finest cells there (the paper's binary punctures sit at the foci).
+ * Arguments are checked before the grid's state, so an invalid argument is
+ * HR_EINVAL even on an unbound grid.
  * Errors: HR_EINVAL, HR_ESTATE (not bound), HR_EDEVICE.
  */
 hr_status hr_set_punctures(hr_grid* g, int n, const double* m, const double* x,
@@ -188,14 +203,20 @@ hr_status hr_relax(hr_grid* g, double eta, double c, double dt, long n_steps,
 hr_status hr_set_fp32_switch(hr_grid* g, double switch_residual, int stall_checks,
                              long max_fp32_steps);
 
-/* Copies u or v (FP64 state) to host memory; n must be the interior or the
- * extended count, which selects the layout. */
+/* Copies u or v (FP64 state) to host memory -- the solution transfer from
+ * device to host of the "Data Transfer Optimization" subsection; n must be
+ * the interior or the extended count, which selects the layout. Waits for the
+ * grid's stream. Errors: HR_EINVAL (null pointer, other n), HR_ESTATE (not
+ * bound), HR_EDEVICE. */
 hr_status hr_get_u(const hr_grid* g, double* host_out, size_t n);
 hr_status hr_get_v(const hr_grid* g, double* host_out, size_t n);
 
-/* Sets u or v from host memory (warm start, resume). n = extended count sets
- * every stored point; n = interior count sets the interior and fills each
- * outer point by the 1/r continuation f(i0) = f(N0-1) r(N0-1)/r(i0). */
+/* Sets u or v from host memory: Algorithm 1's "set initial conditions" step
+ * with a caller-given state (warm start, resume; u = v = 0 is what
+ * hr_set_punctures leaves). n = extended count sets every stored point; n =
+ * interior count sets the interior and fills each outer point by the 1/r
+ * continuation f(i0) = f(N0-1) r(N0-1)/r(i0). Synchronous. Errors: HR_EINVAL
+ * (null pointer, other n), HR_ESTATE (not bound), HR_EDEVICE. */
 hr_status hr_set_u(hr_grid* g, const double* host_in, size_t n);
 hr_status hr_set_v(hr_grid* g, const double* host_in, size_t n);
 
@@ -229,7 +250,11 @@ typedef enum {
  */
 hr_status hr_set_residual_norm(hr_grid* g, hr_norm norm, double radius);
 
-/* cfl * ds_g. */
+/* dt = cfl * ds_g, ds_g the smallest proper cell width over the interior: the
+ * time step that keeps the CFL condition everywhere with the wave speed
+ * proportional to the local grid spacing (end of the "Basic equations"
+ * section; Algorithm 1's "compute timestep"). Host only. Errors: HR_EINVAL
+ * (null pointer, cfl <= 0). */
 hr_status hr_suggest_dt(const hr_grid* g, double cfl, double* dt);
 
 /*
@@ -407,8 +432,12 @@ void hr_batch_destroy(hr_batch* b);
  *                          and its gradient w.r.t. every parameter (host).
  *   hr_mlp_train_step      device x[B x 15], device t[B]: loss, gradient and
  *                          one Adam step (beta1 0.9, beta2 0.999, eps 1e-8).
+ *                          x and t are read on the network's stream: work
+ *                          that writes them on another stream must be
+ *                          ordered before the call (event wait or sync).
  *   hr_mlp_grid_features   device out[n_extended x 15] for a bound grid with
- *                          punctures set.
+ *                          punctures set, written on the grid's stream
+ *                          (same ordering rule for earlier users of out).
  *   hr_warm_start          sets u = exp(scale y + shift) and v = eta u at every
  *                          stored point of the grid (punctures must be set).
  * Errors: HR_EINVAL, HR_ESTATE, HR_ENOMEM, HR_EDEVICE.

@@ -802,8 +802,8 @@ hr_status hr_grid_bind(hr_grid* g, void* dev_ptr, size_t bytes, void* hip_stream
 
 hr_status hr_set_punctures(hr_grid* g, int n, const double* m, const double* x,
                            const double* P, const double* S) {
-  hr_status st = check_ready(g, false);
-  if (st != HR_OK) return st;
+  // arguments first (a host-only check), then the grid's state
+  if (!g) return fail(HR_EINVAL, "null grid handle");
   if (n < 1 || n > kMaxPunctures) return fail(HR_EINVAL, "need 1..4 punctures");
   if (!m || !x || !P || !S) return fail(HR_EINVAL, "null puncture array");
   Punctures pz{};
@@ -819,7 +819,18 @@ hr_status hr_set_punctures(hr_grid* g, int n, const double* m, const double* x,
       pz.P[i][k] = P[3 * i + k];
       pz.S[i][k] = S[3 * i + k];
     }
+    // SinhSymTP resolves the two foci (0, 0, +-bscale) with its finest cells;
+    // a puncture elsewhere would sit where the grid is coarse.
+    if (g->coords == HR_SINHSYMTP) {
+      const double b = g->prm.bscale, tolb = 1e-12 * b;
+      const bool on_focus = std::fabs(pz.x[i][0]) <= tolb && std::fabs(pz.x[i][1]) <= tolb &&
+                            std::fabs(std::fabs(pz.x[i][2]) - b) <= tolb;
+      if (!on_focus)
+        return fail(HR_EINVAL, "SinhSymTP punctures must lie at the foci (0, 0, +-bscale)");
+    }
   }
+  hr_status st = check_ready(g, false);
+  if (st != HR_OK) return st;
   HR_HIP(launch_sources(g->d, g->rho, g->zc, g->cphi, g->sphi, pz, g->f64.psi, g->f64.ssrc,
                         g->f32.psi, g->f32.ssrc, g->stream));
   const int G = (int)g->G;

@@ -114,7 +114,14 @@ class MLP:
         return float(loss.value), g
 
     def train_step(self, x_dev, t_dev, lr: float) -> float:
-        """x_dev (B x 15) and t_dev (B) are contiguous float32 torch tensors on the device."""
+        """x_dev (B x 15) and t_dev (B) are contiguous float32 torch tensors on the device.
+
+        The library copies them on the network's stream; that stream first waits
+        for the work already queued on torch's current stream (where the caller
+        produced the batch), so the copy never reads a half-written batch."""
+        import torch
+
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         loss = ctypes.c_float()
         _check(_lib().hr_mlp_train_step(self._h, ctypes.c_void_p(x_dev.data_ptr()),
                                         ctypes.c_void_p(t_dev.data_ptr()), int(x_dev.shape[0]),
@@ -126,6 +133,10 @@ class MLP:
 
         cfg9 = np.ascontiguousarray(np.asarray(cfg9, dtype=np.float64))
         out = torch.empty((grid.n_extended, N_FEAT), dtype=torch.float32, device=self.device)
+        # `out` comes from torch's allocator on the current stream and the library
+        # writes it on the grid's stream: order that write after the current
+        # stream's pending work (an earlier reader of the same memory).
+        grid.stream.wait_stream(torch.cuda.current_stream(self.device))
         _check(_lib().hr_mlp_grid_features(self._h, grid.handle, cfg9.ctypes.data_as(_dp),
                                            ctypes.c_void_p(out.data_ptr())), "hr_mlp_grid_features")
         return out

@@ -166,3 +166,35 @@ def test_missing_library_fails_loudly(tmp_path):
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT,
                        timeout=300)
     assert "raised:" in r.stdout and "missing" in r.stdout, r.stdout + r.stderr
+
+
+def test_sinhsymtp_punctures_must_sit_at_the_foci(lib):
+    """hr_set_punctures checks its arguments before the grid's state: on a
+    SinhSymTP grid a puncture off the foci (0, 0, +-bscale) is HR_EINVAL (the
+    coordinates concentrate resolution there); on the foci, or on a Spherical
+    grid anywhere, the arguments pass and the unbound grid gives HR_ESTATE."""
+    b = 2.5
+    st, h = _create(lib, 0, 16, 8, 4, 8, hr.default_params(bscale=b))
+    assert st == hr.OK
+    dp = ctypes.POINTER(ctypes.c_double)
+
+    def call(handle, xs):
+        n = len(xs)
+        m = np.full(n, 0.5)
+        x = np.ascontiguousarray(np.asarray(xs, dtype=np.float64).reshape(n, 3))
+        z = np.zeros((n, 3))
+        return lib.hr_set_punctures(handle, n, m.ctypes.data_as(dp), x.ctypes.data_as(dp),
+                                    z.ctypes.data_as(dp), z.ctypes.data_as(dp))
+
+    assert call(h, [[0, 0, b], [0, 0, -b]]) == hr.ESTATE
+    assert call(h, [[0, 0, -b]]) == hr.ESTATE
+    assert call(h, [[0, 0, b * (1 + 5e-13)]]) == hr.ESTATE      # within 1e-12 bscale
+    for bad in ([[0, 0, b * (1 + 1e-9)]], [[0, 0, 0]], [[1e-6, 0, b]], [[0, 1e-6, -b]],
+                [[0, 0, b], [0, 0, 0.5 * b]]):
+        assert call(h, bad) == hr.EINVAL, bad
+        assert "foci" in lib.hr_last_error().decode()
+    lib.hr_grid_destroy(h)
+    st, h = _create(lib, 1, 16, 8, 4, 8, hr.default_params(rmax=10.0))
+    assert st == hr.OK
+    assert call(h, [[0.3, -0.2, 0.7]]) == hr.ESTATE
+    lib.hr_grid_destroy(h)

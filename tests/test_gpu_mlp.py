@@ -58,6 +58,25 @@ def test_training_reduces_loss():
     assert l < 0.05 * first
 
 
+def test_training_is_deterministic():
+    """Two networks created with the same seed and trained on the same data
+    (features computed by the library on the grid's stream, batches gathered
+    on torch's stream) end with bitwise-equal parameters: the library orders
+    its copies after the producer's work, and every reduction has a fixed order."""
+    banner("mlp training determinism")
+    shape = (32, 32, 8)
+    ws = workloads.catalog(6, seed=14031, shapes=(shape,))
+    params = []
+    for _ in range(2):
+        net = MLP(width=64, seed=4, max_batch=8192)
+        X, T = warmstart.dataset(ws, shape, 2048, 7, net, batch=6, log=lambda m: None)
+        warmstart.train(net, X, T, epochs=4, batch=2048, lr=3e-3, seed=3, log=lambda m: None)
+        params.append(net.get_params())
+        net.close()
+    banner(f"max |dp| {np.abs(params[0] - params[1]).max():.3e}")
+    assert np.array_equal(params[0], params[1])
+
+
 def test_warm_start_predicts_solution_and_saves_steps():
     """A network trained on 512 solved configurations at 64x64x8 (1024 stored
     points each) predicts held-out configurations at the same resolution within
