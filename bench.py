@@ -30,6 +30,20 @@ import numpy as np  # noqa: E402
 
 METRIC = ("grid-pt RHS updates/sec (FP64 vs FP32+FP64 finish); wall time to residual 1e-10")
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6    # MI355X vector FP64
+FP32_PEAK_TFLOPS = 157.3   # MI355X vector FP32
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def flops_per_update(fd_order: int) -> int:
+    """Algorithmic floating-point operations of one grid-point RHS update (one
+    fused RK4 stage at one interior point), NG = fd_order / 2 taps a side:
+    second-derivative sums 3 x (3 NG + 2), first-derivative sums 2 x 3 NG, the
+    five-term Laplacian 9, the source (psi + u)^-7 S with one division 6, the
+    two right-hand sides 4, the stage combine 7 (mean over the four stages).
+    107 at 10th order, 92 at 8th."""
+    ng = fd_order // 2
+    return 3 * (3 * ng + 2) + 2 * 3 * ng + 9 + 6 + 4 + 7
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2501_14030_amd", "csrc", f)
                for f in ("hr_kernels.hip", "hr_resident.hip", "hr_stencil.h")]
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "stage_kernel_pmc.json")
@@ -138,6 +152,86 @@ def roofline_entry(g, hr, spec, w, prec, nsteps=20):
         out["stages_per_launch"] = 1
         out["avg_launch_us"] = [float(x) for x in us[:4]]
     return out
+
+
+def pmc_summary():
+    """The committed rocprofv3 PMC summary if it was taken on the current kernel
+    sources, else None."""
+    try:
+        with open(PMC_SUMMARY) as f:
+            pmc = json.load(f)
+    except (OSError, ValueError):
+        return None
+    return pmc if pmc.get("kernel_sha") == kernel_sha() else None
+
+
+def resident_roofline(hr, spec, prec, timing):
+    """Roofline entry of the resident RK4 kernel, timed on the launches of the
+    timed solves themselves (HIP events inside each dispatch, on the grid's
+    stream). The kernel keeps the whole state in registers and LDS, so HBM does
+    not bound it; the entry is placed on the vector-ALU roof of its precision
+    (algorithmic flops per launch over the mean launch duration), with the
+    measured HBM counter traffic, LDS activity and the rate a fused stage kernel
+    streaming the state through HBM would need beside it."""
+    fp64 = prec == hr.FP64
+    nl = max(1, timing["launches"])
+    avg_us = timing["total_us"] / nl
+    stages = timing["stages"] / nl
+    n_int = spec.n_interior
+    fpu = flops_per_update(spec.fd_order)
+    flops = fpu * n_int * stages
+    achieved = flops / (avg_us * 1e-6) / 1e12
+    peak = FP64_PEAK_TFLOPS if fp64 else FP32_PEAK_TFLOPS
+    item = 8 if fp64 else 4
+    # bytes a fused stage kernel must move per interior point (mean of the four
+    # stages' 8, 12, 12, 8 values) if the state lived in HBM
+    stream_bytes = item * 10 * n_int * stages
+    out = {
+        "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+        "frac": achieved / peak, "traffic": None,
+        "kernel": f"resident RK4 kernel ({'FP64' if fp64 else 'FP32 split-state increment'}, "
+                  f"order {spec.fd_order}, {spec.N0}x{spec.N1}x{spec.N2}), launches of the timed "
+                  f"solves",
+        "launches_timed": timing["launches"], "stages_per_launch": stages,
+        "avg_launch_us": avg_us, "avg_stage_us": avg_us / stages,
+        "flops_per_update": fpu, "algorithmic_flops_per_launch": flops,
+        "limiter": "latency of the per-stage patch exchange (publish, counter, rim load) plus "
+                   "LDS-bound stencil work; neither HBM nor the vector ALU is saturated",
+        "as_if_streamed": {"bytes_per_update": item * 10,
+                           "gbs": stream_bytes / (avg_us * 1e-6) / 1e9,
+                           "frac_of_hbm_peak": stream_bytes / (avg_us * 1e-6) / 1e9 /
+                                               HBM_PEAK_GBS},
+    }
+    pmc = pmc_summary()
+    if pmc:
+        if fp64:
+            ent = pmc.get("runs", {}).get(f"{spec.N0}x{spec.N1}x{spec.N2}_fp64_resident")
+            if ent:
+                ff = pmc["calibration"]["fetch_factor"]
+                wf = pmc["calibration"]["write_factor"]
+                per_stage = 1024.0 * (ff * ent["fetch_kib"][0] + wf * ent["write_kib"][0])
+                out["traffic"] = per_stage * stages
+                out["hbm_counter_gbs"] = out["traffic"] / (avg_us * 1e-6) / 1e9
+                out["hbm_counter_frac"] = out["hbm_counter_gbs"] / HBM_PEAK_GBS
+        key = "valu_fp64" if fp64 else "valu_fp32_split"
+        if key in pmc:
+            out["valu_counter_flops_per_point_stage"] = pmc[key].get(
+                "fp64_flops_per_point_stage" if fp64 else "fp32_flops_per_point_stage")
+        if fp64 and "lds_fp64" in pmc and "lds_busy_us_per_stage" in pmc["lds_fp64"]:
+            out["lds_busy_frac"] = pmc["lds_fp64"]["lds_busy_us_per_stage"] / (avg_us / stages)
+    return out
+
+
+def oracle_diff(u_ext, name: str):
+    """max |u - u_oracle| / max |u_oracle| over the sampled stored points of the
+    committed converged oracle solution `name` (tests/golden, written by the
+    oracle alone), or None when the file is absent."""
+    path = os.path.join(GOLDEN, f"oracle_{name}.npz")
+    if not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        idx, uo, umax = z["idx"], z["u"], float(z["max_abs_u"])
+    return float(np.abs(np.asarray(u_ext).reshape(-1)[idx] - uo).max() / umax)
 
 
 def copy_bandwidth(torch, nbytes: int = 1 << 30) -> float:
@@ -271,10 +365,15 @@ def run_solve(hr, torch, g, w, precision, times=None):
     return res
 
 
-def timed_solves(hr, torch, g, w, precision, steps, warmup, label):
+def timed_solves(hr, torch, g, w, precision, steps, warmup, label, timing=None):
+    """Warm-up solves, then `steps` timed solves. With a dict `timing`, the
+    resident launches of the timed solves are timed by the library (HIP events
+    inside each dispatch) and their totals stored in it."""
     for i in range(warmup):
         r = run_solve(hr, torch, g, w, precision)
         log(f"{label} warmup {i}: status {r.status} steps {r.steps_taken} residual {r.residual:.3e}")
+    if timing is not None:
+        g.set_launch_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results, times = [], []
@@ -283,6 +382,9 @@ def timed_solves(hr, torch, g, w, precision, steps, warmup, label):
         results.append(r)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if timing is not None:
+        timing.update(g.launch_timing())
+        g.set_launch_timing(False)
     for i, r in enumerate(results):
         log(f"{label} solve {i}: status {r.status} rk4 steps {r.steps_taken} "
             f"(fp32 {r.fp32_steps}) residual {r.residual:.3e} ({times[i][1] * 1e3:.2f} ms)")
@@ -317,11 +419,16 @@ def precision_form_runs(hr, torch):
             e = {"time_to_residual_s": times[0][1], "rk4_steps_to_tol": r.steps_taken,
                  "fp32_steps": r.fp32_steps, "final_residual": r.residual, "status": r.status,
                  "updates_per_s": s.n_interior * 4 * r.steps_taken / times[0][1],
-                 "max_rel_diff_u_vs_fp64": float(np.abs(u - u64).max() / np.abs(u64).max())}
+                 "max_rel_diff_u_vs_fp64": float(np.abs(u - u64).max() / np.abs(u64).max()),
+                 "max_rel_diff_u_vs_oracle": oracle_diff(
+                     g.get_u(extended=True), f"precision_form_{shape[0]}x{shape[1]}x{shape[2]}")}
             log(f"precision form {s.name()} {label}: {r.steps_taken} steps ({r.fp32_steps} fp32), "
                 f"residual {r.residual:.3e}, {times[0][1]:.3f} s, "
                 f"diff vs fp64 {e['max_rel_diff_u_vs_fp64']:.2e}")
             entry[label] = e
+        entry["oracle_reference"] = (f"converged FP64 oracle solution at 4096 seeded stored "
+                                     f"points and the largest |u| (tests/golden/oracle_"
+                                     f"precision_form_{shape[0]}x{shape[1]}x{shape[2]}.npz)")
         res[s.name()] = entry
         g.close()
     return res
@@ -385,7 +492,7 @@ def multi_patch_runs(hr, torch, w, u_ref, n_max: int = 7):
             "rows": rows}
 
 
-def warm_start_runs(hr, torch, g, w, steps, steps_cold, t_cold, u_cold):
+def warm_start_runs(hr, torch, g, w, steps, steps_cold, t_cold, u_cold, sols=None):
     """The learned warm start on the paper-scale configuration: an MLP trained
     (inside this run) on 512 catalog solves at 64x64x8 predicts u, v = eta u is
     set, and the FP64 relaxation runs to the same tolerance. The timed solve
@@ -419,6 +526,8 @@ def warm_start_runs(hr, torch, g, w, steps, steps_cold, t_cold, u_cold):
             if res.status != hr.OK:
                 raise RuntimeError(f"warm-started {label} solve did not converge")
         u = g.get_u()
+        if sols is not None:
+            sols[f"warm_{label}"] = g.get_u(extended=True)
         out[label] = {"time_to_residual_s": float(np.median(times)),
                       "rk4_steps_to_tol": res.steps_taken, "fp32_steps": res.fp32_steps,
                       "final_residual": res.residual,
@@ -432,9 +541,13 @@ def warm_start_runs(hr, torch, g, w, steps, steps_cold, t_cold, u_cold):
     return out
 
 
-def cpu_baseline(w, budget_s: float):
-    """The oracle as it is, on the host cores, on a bounded sample of the same
-    workload: RK4 steps of the same grid from the same initial state."""
+def cpu_baseline(w, budget_s: float, full_s: float, steps_gpu: int):
+    """The oracle as it is, on the host cores. When the whole solve to the
+    tolerance fits in `full_s` seconds (estimated from two steps) it runs the
+    whole solve, exactly as the GPU does (residual every check_every steps);
+    else a bounded sample of RK4 steps of the same grid from the same initial
+    state. Returns the entry and the oracle's final u (extended layout) when
+    the whole solve ran, else None."""
     import oracle
 
     oracle.build()
@@ -447,10 +560,24 @@ def cpu_baseline(w, budget_s: float):
     t0 = time.perf_counter()
     og.rk4_steps(w.eta, w.kappa, dt, 2)
     per_step = (time.perf_counter() - t0) / 2
-    n = max(2, int(budget_s / max(per_step, 1e-6)))
-    t0 = time.perf_counter()
-    og.rk4_steps(w.eta, w.kappa, dt, n)
-    el = time.perf_counter() - t0
+    u_full = None
+    if per_step * steps_gpu <= full_s:
+        og.set_punctures(*w.punctures.as_tuple())
+        t0 = time.perf_counter()
+        st, n, hist = og.relax(w.eta, w.kappa, dt, w.n_steps, w.tol, w.check_every)
+        el = time.perf_counter() - t0
+        u, _ = og.state()
+        ng = og.NG
+        u_full = u[ng:ng + spec.N2, ng:ng + spec.N1, ng:ng + spec.N0 + ng]
+        sample = (f"the whole solve: {n} RK4 steps of {spec.name()} from rest to residual "
+                  f"{hist[-1]:.3e} (status {st}), residual every {w.check_every} steps ({el:.1f} s)")
+    else:
+        n = max(2, int(budget_s / max(per_step, 1e-6)))
+        t0 = time.perf_counter()
+        og.rk4_steps(w.eta, w.kappa, dt, n)
+        el = time.perf_counter() - t0
+        sample = (f"{n} RK4 steps of {spec.name()} from rest ({el:.1f} s); time to residual "
+                  f"1e-10 extrapolates as steps_to_tol / {n / el:.2f} steps/s")
     upd = spec.n_interior * 4 * n / el
     cores = oracle.num_threads()
     # the same on one thread (fewer steps: about a third of the budget)
@@ -461,12 +588,9 @@ def cpu_baseline(w, budget_s: float):
     el1 = time.perf_counter() - t0
     oracle.set_num_threads(cores)
     return {"value": upd, "unit": "grid-pt RHS updates/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{n} RK4 steps of {spec.name()} from rest ({el:.1f} s); "
-                      f"time to residual 1e-10 extrapolates as steps_to_tol / "
-                      f"{n / el:.2f} steps/s",
+            "kind": "oracle", "sample": sample, "oracle_steps": n,
             "value_1_thread": spec.n_interior * 4 * n1 / el1,
-            "sample_1_thread": f"{n1} RK4 steps, same grid, 1 thread ({el1:.1f} s)"}
+            "sample_1_thread": f"{n1} RK4 steps, same grid, 1 thread ({el1:.1f} s)"}, u_full
 
 
 def main() -> int:
@@ -476,6 +600,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-full-seconds", type=float, default=40.0,
+                    help="run the oracle's whole solve when it is estimated to fit in this time")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-spherical", action="store_true")
@@ -531,10 +657,13 @@ def main() -> int:
     setup_s = time.perf_counter() - t_setup   # host tables, device workspace, sources
     if args.variant:
         g.set_kernel_config(variant=args.variant)
-    res64, t64, tm64 = timed_solves(hr, torch, g, w, hr.FP64, args.steps, args.warmup, "fp64")
+    tim64, tim32 = {}, {}
+    res64, t64, tm64 = timed_solves(hr, torch, g, w, hr.FP64, args.steps, args.warmup, "fp64",
+                                    tim64)
     steps64 = res64[-1].steps_taken
     upd64 = sum(spec.n_interior * 4 * r.steps_taken for r in res64) / t64
     u64 = g.get_u()
+    sols = {"fp64": g.get_u(extended=True)}   # compared with the oracle's solve below
     out = {
         "metric": METRIC,
         "value": upd64,
@@ -571,8 +700,9 @@ def main() -> int:
     if not args.no_mixed:
         g.set_fp32_switch(0.0, 8, 0)  # FP64 finish below 10 x tol
         res32, t32, tm32 = timed_solves(hr, torch, g, w, hr.FP32_FP64FINISH, args.steps, 0,
-                                        "fp32+fp64")
+                                        "fp32+fp64", tim32)
         u32 = g.get_u()
+        sols["mixed"] = g.get_u(extended=True)
         out["mixed"] = {
             "precision": "FP32 bulk (split state: FP64 base + FP32 increment, FP64 slopes, "
                          "rebase and residual every check) + plain FP64 finish below 10 x tol",
@@ -592,6 +722,7 @@ def main() -> int:
         resf, tf, tmf = timed_solves(hr, torch, g, w, hr.FP32_FP64FINISH, args.steps, 0,
                                      "fp32 95% fixed")
         uf = g.get_u()
+        sols["mixed_fixed_95"] = g.get_u(extended=True)
         out["mixed"]["fixed_95"] = {
             "time_to_residual_s": tf / args.steps,
             "relax_median_s": float(np.median([t[1] for t in tmf])),
@@ -603,7 +734,7 @@ def main() -> int:
         g.set_fp32_switch(0.0, 8, 0)
     if not args.no_warm_start:
         out["warm_start"] = warm_start_runs(hr, torch, g, w, args.steps, steps64,
-                                            float(np.median([t[1] for t in tm64])), u64)
+                                            float(np.median([t[1] for t in tm64])), u64, sols)
     if not args.no_spherical:
         # the same physics on the Spherical 128x64x8 grid (rmax 100), its own eta
         ws = workloads.paper_scale(workloads.SPHERICAL, 10)
@@ -613,10 +744,12 @@ def main() -> int:
         rs64, ts64, tms64 = timed_solves(hr, torch, gs, ws, hr.FP64, args.steps, args.warmup,
                                          "spherical fp64")
         us64 = gs.get_u()
+        ds64 = oracle_diff(gs.get_u(extended=True), "paper_scale_spherical_128x64x8")
         gs.set_fp32_switch(0.0, 8, 0)
         rs32, ts32, tms32 = timed_solves(hr, torch, gs, ws, hr.FP32_FP64FINISH, args.steps, 0,
                                          "spherical fp32+fp64")
         us32 = gs.get_u()
+        ds32 = oracle_diff(gs.get_u(extended=True), "paper_scale_spherical_128x64x8")
         out["spherical"] = {
             "workload": f"paper-scale Spherical {ss.N0}x{ss.N1}x{ss.N2}, 10th-order FD, "
                         f"rmax {ss.rmax}, same punctures, eta {ws.eta}, to residual 1e-10",
@@ -631,21 +764,33 @@ def main() -> int:
             "mixed_rk4_steps_to_tol": rs32[-1].steps_taken,
             "mixed_fp32_steps": rs32[-1].fp32_steps,
             "mixed_max_rel_diff_u_vs_fp64": float(np.abs(us32 - us64).max() / np.abs(us64).max()),
+            "max_rel_diff_u_vs_oracle": ds64,
+            "mixed_max_rel_diff_u_vs_oracle": ds32,
+            "oracle_reference": "converged FP64 oracle solution at 4096 seeded stored points and "
+                                "the largest |u| "
+                                "(tests/golden/oracle_paper_scale_spherical_128x64x8.npz)",
         }
         gs.close()
     if not args.no_precision_form:
         out["precision_form"] = precision_form_runs(hr, torch)
     if not args.no_multi_patch:
         out["multi_patch"] = multi_patch_runs(hr, torch, w, u64)
-    # roofline of the dominant kernel (the resident RK4 kernel at this size)
+    # roofline of the dominant kernel: the resident RK4 kernel at this size,
+    # timed on the launches of the timed solves themselves
     g.set_punctures(*w.punctures.as_tuple())
     copy = copy_bandwidth(torch)
-    out["roofline"] = roofline_entry(g, hr, spec, w, hr.FP64)
+    if g.resolved_kernel(hr.FP64)["variant"] == 3 and tim64.get("launches"):
+        out["roofline"] = resident_roofline(hr, spec, hr.FP64, tim64)
+    else:
+        out["roofline"] = roofline_entry(g, hr, spec, w, hr.FP64)
+    if tim32.get("launches"):
+        out["roofline_split"] = resident_roofline(hr, spec, hr.FP32_FP64FINISH, tim32)
     out["roofline_fp32"] = roofline_entry(g, hr, spec, w, hr.FP32)
-    out["roofline_split"] = roofline_entry(g, hr, spec, w, hr.FP32_FP64FINISH)
     for k in ("roofline", "roofline_fp32", "roofline_split"):
-        out[k]["copy_gbs"] = copy
-        out[k]["frac_of_copy"] = out[k]["achieved"] / copy
+        if k in out and out[k]["unit"] == "GB/s":
+            out[k]["copy_gbs"] = copy
+            out[k]["frac_of_copy"] = out[k]["achieved"] / copy
+    out["copy_gbs"] = copy
     if not args.no_large:
         # the paper's roofline grid, 512x512x64: working set well beyond the caches
         big = workloads.GridSpec(0, 512, 512, 64, 10, bscale=spec.bscale)
@@ -658,9 +803,22 @@ def main() -> int:
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        cb = cpu_baseline(w, args.cpu_seconds)
+        cb, u_or = cpu_baseline(w, args.cpu_seconds, args.cpu_full_seconds, steps64)
         cb["time_to_residual_s_extrapolated"] = steps64 * spec.n_interior * 4 / cb["value"]
         out["cpu_baseline"] = cb
+        if u_or is not None:
+            # every form of the paper-scale solve against the oracle's own solve
+            scale = float(np.abs(u_or).max())
+            errs = {k: float(np.abs(v - u_or).max() / scale) for k, v in sols.items()}
+            out["max_rel_diff_u_vs_oracle"] = errs["fp64"]
+            out["oracle_steps_to_tol"] = cb["oracle_steps"]
+            for k, e in errs.items():
+                if k == "mixed" and "mixed" in out:
+                    out["mixed"]["max_rel_diff_u_vs_oracle"] = e
+                elif k == "mixed_fixed_95" and "mixed" in out:
+                    out["mixed"]["fixed_95"]["max_rel_diff_u_vs_oracle"] = e
+                elif k.startswith("warm_") and "warm_start" in out:
+                    out["warm_start"][k[5:]]["max_rel_diff_u_vs_oracle"] = e
         if "multi_patch" in out:
             # the oracle relaxes one grid after another: N times its one-grid time
             for r in out["multi_patch"]["rows"]:

@@ -374,6 +374,22 @@ hr_status hr_time_stage_kernels(hr_grid* g, double eta, double c, double dt, lon
                                 hr_precision prec, double* avg_us);
 
 /*
+ * Measurement of the relaxation's own launches: with on != 0, each resident
+ * kernel launch that later hr_relax calls on this grid issue (its FP64 steps,
+ * and the FP32 increment steps of HR_FP32_FP64FINISH where the resident
+ * kernel runs them) is bracketed by a pair of HIP events recorded inside the
+ * dispatch on the grid's stream, and read after the check interval's own
+ * synchronisation (no extra synchronisation). hr_set_launch_timing resets the
+ * totals; hr_get_launch_timing returns the summed launch durations in
+ * microseconds, the number of launches timed and the RK stages they ran (any
+ * pointer may be NULL). Launches of the stage kernels (graph-captured check
+ * intervals) are not timed here; hr_time_stage_kernels times those. Errors:
+ * HR_EINVAL (null grid), HR_EDEVICE.
+ */
+hr_status hr_set_launch_timing(hr_grid* g, int on);
+hr_status hr_get_launch_timing(const hr_grid* g, double* total_us, long* launches, long* stages);
+
+/*
  * Batched relaxation (catalogs of configurations; the paper relaxes several
  * independent patches with one CUDA stream each, "Multiple, Independent
  * Patches" subsection). A batch groups n bound grids of the same fd_order on

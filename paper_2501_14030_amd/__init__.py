@@ -101,6 +101,9 @@ _SIGNATURES = {
     "hr_resolved_kernel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
                                           ctypes.POINTER(KernelConfig)]),
     "hr_set_wait_limit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint]),
+    "hr_set_launch_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "hr_get_launch_timing": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.POINTER(ctypes.c_long),
+                                            ctypes.POINTER(ctypes.c_long)]),
     "hr_set_outer_bc_order": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "hr_set_factor_storage": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "hr_set_residual_norm": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_double]),
@@ -339,6 +342,21 @@ class Grid:
         (0: the default, about a second); small values force the timeout path."""
         _check(load_library().hr_set_wait_limit(self._h, int(polls)), "hr_set_wait_limit")
 
+    def set_launch_timing(self, on: bool = True) -> None:
+        """Time each resident launch that later relax calls issue (HIP events
+        inside the dispatch on the grid's stream); resets the totals."""
+        _check(load_library().hr_set_launch_timing(self._h, 1 if on else 0),
+               "hr_set_launch_timing")
+
+    def launch_timing(self) -> dict:
+        """Summed durations (us), launches and RK stages of the timed launches."""
+        us = ctypes.c_double()
+        nl = ctypes.c_long()
+        ns = ctypes.c_long()
+        _check(load_library().hr_get_launch_timing(self._h, ctypes.byref(us), ctypes.byref(nl),
+                                                   ctypes.byref(ns)), "hr_get_launch_timing")
+        return {"total_us": us.value, "launches": nl.value, "stages": ns.value}
+
     def resolved_kernel(self, precision: int = FP64) -> dict:
         """The configuration the relaxation runs in this precision, automatic
         choices resolved (variant 3 = resident kernel)."""
@@ -401,9 +419,16 @@ class Batch:
         if st not in (OK, ENOTCONV, ENONFINITE) or (raise_on_error and st == ENONFINITE):
             _check(st, "hr_batch_relax")
         self.status = st
-        return [RelaxResult(OK if reps[i].residual < tol or tol <= 0 else ENOTCONV,
-                            reps[i].steps_taken, reps[i].fp32_steps, reps[i].residual,
-                            reps[i].dt_used, hists[i][:min(reps[i].n_history, cap)].copy())
+
+        def grid_status(r) -> int:
+            # per grid, as hr_relax would report it: a non-finite residual first
+            if r.n_history > 0 and not np.isfinite(r.residual):
+                return ENONFINITE
+            return OK if tol <= 0 or r.residual < tol else ENOTCONV
+
+        return [RelaxResult(grid_status(reps[i]), reps[i].steps_taken, reps[i].fp32_steps,
+                            reps[i].residual, reps[i].dt_used,
+                            hists[i][:min(reps[i].n_history, cap)].copy())
                 for i in range(n)]
 
     def close(self) -> None:

@@ -256,12 +256,46 @@ ResidentArgsT<float> resident_args_split(hr_grid* g, float eta, float dt, int ns
   return r;
 }
 
+// The event pair that times the next resident launch of hr_relax, or nulls
+// when launch timing is off (or more launches than pairs are pending).
+hr_status timing_pair(hr_grid* g, int steps, hipEvent_t* e0, hipEvent_t* e1) {
+  *e0 = *e1 = nullptr;
+  if (!g->time_launches || g->tev_used >= 8) return HR_OK;
+  const size_t need = 2 * (size_t)(g->tev_used + 1);
+  while (g->tev.size() < need) {
+    hipEvent_t e = nullptr;
+    HR_HIP(hipEventCreate(&e));
+    g->tev.push_back(e);
+  }
+  *e0 = g->tev[2 * g->tev_used];
+  *e1 = g->tev[2 * g->tev_used + 1];
+  g->tev_stages[g->tev_used] = 4L * steps;
+  g->tev_used++;
+  return HR_OK;
+}
+
+// Adds the recorded launch durations to the totals (the stream has been
+// synchronised).
+hr_status collect_timing(hr_grid* g) {
+  for (int i = 0; i < g->tev_used; ++i) {
+    float ms = 0.0f;
+    HR_HIP(hipEventElapsedTime(&ms, g->tev[2 * i], g->tev[2 * i + 1]));
+    g->t_us += 1e3 * (double)ms;
+    g->t_launches += 1;
+    g->t_stages += g->tev_stages[i];
+  }
+  g->tev_used = 0;
+  return HR_OK;
+}
+
 // Reads the resident kernel's error word (synchronous); a timed-out exchange
 // wait leaves the state unchanged from the launch's start and is reported.
 hr_status check_resident(hr_grid* g) {
   unsigned e = 0;
   HR_HIP(hipMemcpyAsync(&e, g->res_err, sizeof(unsigned), hipMemcpyDeviceToHost, g->stream));
   HR_HIP(hipStreamSynchronize(g->stream));
+  hr_status st = collect_timing(g);
+  if (st != HR_OK) return st;
   if (e) {
     HR_HIP(hipMemsetAsync(g->res_err, 0, sizeof(unsigned), g->stream));
     HR_HIP(hipStreamSynchronize(g->stream));
@@ -286,7 +320,10 @@ hr_status launch_steps(hr_grid* g, const Fields<T>& F, T eta, T dt, long nsteps,
       // whole RK4 steps in resident launches of at most 1000 steps
       for (long n = 0; n < nsteps; n += 1000) {
         const int k = (int)std::min<long>(1000, nsteps - n);
-        HR_HIP(launch_resident(g->fd_order, resident_args(g, eta, dt, k), g->stream));
+        hipEvent_t e0, e1;
+        hr_status st = timing_pair(g, k, &e0, &e1);
+        if (st != HR_OK) return st;
+        HR_HIP(launch_resident(g->fd_order, resident_args(g, eta, dt, k), g->stream, e0, e1));
       }
       return HR_OK;
     }
@@ -294,7 +331,11 @@ hr_status launch_steps(hr_grid* g, const Fields<T>& F, T eta, T dt, long nsteps,
     if (corr && use_resident_split(g)) {
       for (long n = 0; n < nsteps; n += 1000) {
         const int k = (int)std::min<long>(1000, nsteps - n);
-        HR_HIP(launch_resident(g->fd_order, resident_args_split(g, eta, dt, k), g->stream));
+        hipEvent_t e0, e1;
+        hr_status st = timing_pair(g, k, &e0, &e1);
+        if (st != HR_OK) return st;
+        HR_HIP(launch_resident(g->fd_order, resident_args_split(g, eta, dt, k), g->stream, e0,
+                               e1));
       }
       return HR_OK;
     }
@@ -514,6 +555,8 @@ hr_status run_interval(hr_grid* g, int kind, int K, double eta, double dt, doubl
                           g->stream));
   HR_HIP(hipStreamSynchronize(g->stream));
   *res = g->host_res[0];
+  hr_status stt = collect_timing(g);
+  if (stt != HR_OK) return stt;
   if (resident && *err_word) {
     *err_word = 0;
     HR_HIP(hipMemsetAsync(g->res_err, 0, sizeof(unsigned), g->stream));
@@ -722,6 +765,7 @@ void hr_grid_destroy(hr_grid* g) {
   if (g->bound) {
     (void)hipSetDevice(g->device);
     (void)hipStreamSynchronize(g->stream);
+    for (hipEvent_t e : g->tev) (void)hipEventDestroy(e);
     if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
     if (g->host_res) (void)hipHostFree(g->host_res);
     if (g->own_stream) (void)hipStreamDestroy(g->stream);
@@ -931,6 +975,25 @@ hr_status hr_residual_l2(hr_grid* g, double* out) {
   if (!out) return fail(HR_EINVAL, "null output pointer");
   HR_HIP(hipSetDevice(g->device));
   return residual_of(g, g->f64.un, false, out);
+}
+
+hr_status hr_set_launch_timing(hr_grid* g, int on) {
+  if (!g) return fail(HR_EINVAL, "null grid handle");
+  g->time_launches = on ? 1 : 0;
+  g->tev_used = 0;
+  g->t_us = 0.0;
+  g->t_launches = 0;
+  g->t_stages = 0;
+  return HR_OK;
+}
+
+hr_status hr_get_launch_timing(const hr_grid* g, double* total_us, long* launches,
+                               long* stages) {
+  if (!g) return fail(HR_EINVAL, "null grid handle");
+  if (total_us) *total_us = g->t_us;
+  if (launches) *launches = g->t_launches;
+  if (stages) *stages = g->t_stages;
+  return HR_OK;
 }
 
 hr_status hr_suggest_dt(const hr_grid* g, double cfl, double* dt) {

@@ -327,6 +327,17 @@ struct hr_grid {
   double sw_residual = 0.0;
   int sw_stall = 8;
   long sw_max_steps = 0;
+
+  // Durations of the resident launches that hr_relax issues
+  // (hr_set_launch_timing): one event pair per launch, recorded inside the
+  // dispatch, read after the interval's synchronisation.
+  int time_launches = 0;
+  std::vector<hipEvent_t> tev;  // event pairs (2 per launch), created on demand, reused
+  int tev_used = 0;             // pairs recorded and not yet read
+  long tev_stages[8] = {};      // RK stages run by each recorded launch
+  double t_us = 0.0;            // summed launch durations
+  long t_launches = 0;
+  long t_stages = 0;
 };
 
 namespace hr {

@@ -113,3 +113,28 @@ def test_state_errors():
     with pytest.raises(hr.HRError) as e:
         g.relax(-1.0, 1.0, 0.0, 10, 0.0)
     assert e.value.status == hr.EINVAL
+
+
+def test_launch_timing_counts_the_resident_launches():
+    """hr_set_launch_timing times each resident launch hr_relax issues: ten
+    100-step intervals are ten launches of 400 stages, and their summed
+    durations fit inside the call's wall time."""
+    import time
+
+    w = workloads.paper_scale()
+    g = gpu_grid(w.grid)
+    g.set_punctures(*w.punctures.as_tuple())
+    assert g.resolved_kernel(hr.FP64)["variant"] == 3
+    g.relax(w.eta, 1.0, 0.0, 100, 0.0, check_every=100)      # warm-up
+    g.set_launch_timing(True)
+    t0 = time.perf_counter()
+    r = g.relax(w.eta, 1.0, 0.0, 1000, 0.0, check_every=100)
+    wall = time.perf_counter() - t0
+    t = g.launch_timing()
+    banner(f"launch timing {t}, wall {wall * 1e3:.2f} ms")
+    assert r.status == hr.OK
+    assert t["launches"] == 10 and t["stages"] == 4000
+    assert 0.0 < t["total_us"] * 1e-6 <= wall
+    g.set_launch_timing(False)
+    g.relax(w.eta, 1.0, 0.0, 100, 0.0, check_every=100)
+    assert g.launch_timing()["launches"] == 0

@@ -162,3 +162,26 @@ def test_batch_phi_chunks_with_ragged_tails():
     og.relax(etas[2], 1.0, og.suggest_dt(0.5), 200, 0.0, 100)
     ou, _ = og.state()
     assert rel_maxdiff(gs[2].get_u(extended=True), oracle_extended(og, ou)) <= 1e-12
+
+
+def test_batch_reports_a_non_finite_grid():
+    """A grid whose wave speed breaks the RK4 stability limit (kappa 50, local
+    Courant number 25) blows up inside a batch: the batch returns
+    HR_ENONFINITE, that grid's result says so, and the other grid keeps
+    relaxing to its step cap (HR_ENOTCONV under an unreachable tolerance)."""
+    banner("batch with one unstable grid")
+    spec = workloads.GridSpec(0, 32, 16, 4, 8, bscale=1.0)
+    pz = workloads.equal_mass_small().punctures
+    gs = [gpu_grid(spec) for _ in range(2)]
+    for g in gs:
+        g.set_punctures(*pz.as_tuple())
+    b = hr.Batch(gs)
+    res = b.relax([1.0, 1.0], [1.0, 50.0], n_steps=1000, tol=1e-30, check_every=100,
+                  raise_on_error=False)
+    b.close()
+    banner(f"  status {b.status}, grids {[r.status for r in res]}, "
+           f"residuals {[r.residual for r in res]}")
+    assert b.status == hr.ENONFINITE
+    assert res[1].status == hr.ENONFINITE
+    assert res[0].status == hr.ENOTCONV and res[0].steps_taken == 1000
+    assert np.isfinite(res[0].residual)

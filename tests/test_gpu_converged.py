@@ -1,0 +1,102 @@
+"""Converged-state parity at the paper's scale (the consistency study of
+Sec. 5: u compared with the CPU code halfway through the relaxation and at its
+end).
+
+Each paper-scale configuration is relaxed on the GPU in the launch
+configuration the benchmark uses (the automatic choice: the resident RK4
+kernel) and by the FP64 oracle from u = v = 0. Both stop at the first check
+(every 100 steps) whose residual is below 1e-10.
+
+* SinhSymTP 128x128x16, 10th order, eta 80.
+* Spherical 128x64x8, 10th order, rmax 100, eta 2.
+
+Both sides first run a fixed half of the steps and compare there, then relax
+to the tolerance and compare again.
+
+Bars:
+* FP64: max|f_gpu - f_oracle| / max|f_oracle| <= 1e-12 for f = u and f = v,
+  over every stored point, with equal step counts and residual histories
+  within 1e-9 relative.
+* FP32 bulk + FP64 finish (HR_FP32_FP64FINISH), relaxed to the same
+  tolerance: <= 1e-10 on u against the oracle's converged u. In exact
+  arithmetic the split state follows the FP64 trajectory. Its FP32 rounding is
+  relative to the per-interval increment, which is about the residual level
+  near the end. The FP64 finish then lowers the residual a further 10x.
+* The same with bfloat16 metric factors: <= 1e-9. The FP64 base slopes and
+  finish keep the fixed point; only the increments see the 8-bit factors.
+"""
+import numpy as np
+import pytest
+
+import paper_2501_14030_amd as hr
+from paper_2501_14030_amd import workloads
+
+from gpu_common import banner, gpu_grid, oracle_extended, oracle_grid, rel_maxdiff
+
+pytestmark = pytest.mark.gpu
+
+CASES = {"sinhsymtp": (workloads.SINHSYMTP, 2000), "spherical": (workloads.SPHERICAL, 2800)}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def converged(request):
+    coords, n_mid = CASES[request.param]
+    w = workloads.paper_scale(coords, 10)
+    banner(f"oracle: {w.grid.name()} to residual {w.tol} (mid state at {n_mid} steps)")
+    og = oracle_grid(w.grid)
+    og.set_punctures(*w.punctures.as_tuple())
+    dt = og.suggest_dt(w.cfl)
+    st, n1, h1 = og.relax(w.eta, w.kappa, dt, n_mid, 0.0, w.check_every)
+    assert st == 0 and n1 == n_mid
+    mid = tuple(oracle_extended(og, f) for f in og.state())
+    st, n2, h2 = og.relax(w.eta, w.kappa, dt, 200000, w.tol, w.check_every)
+    assert st == 0
+    end = tuple(oracle_extended(og, f) for f in og.state())
+    banner(f"oracle: {n_mid + n2} steps, final residual {h2[-1]:.3e}")
+    return {"w": w, "dt": dt, "n_mid": n_mid, "mid": mid, "end": end,
+            "steps": n_mid + n2, "hist": np.concatenate([h1, h2])}
+
+
+def test_fp64_mid_and_end_states_match_oracle(converged):
+    c = converged
+    w = c["w"]
+    g = gpu_grid(w.grid)
+    g.set_punctures(*w.punctures.as_tuple())
+    kern = g.resolved_kernel(hr.FP64)
+    r1 = g.relax(w.eta, w.kappa, c["dt"], c["n_mid"], 0.0, check_every=w.check_every)
+    assert r1.status == hr.OK and r1.steps_taken == c["n_mid"]
+    du = rel_maxdiff(g.get_u(extended=True), c["mid"][0])
+    dv = rel_maxdiff(g.get_v(extended=True), c["mid"][1])
+    banner(f"{w.grid.name()} kernel {kern}: mid ({c['n_mid']} steps) du {du:.2e} dv {dv:.2e}")
+    assert du <= 1e-12 and dv <= 1e-12
+    r2 = g.relax(w.eta, w.kappa, c["dt"], 200000, w.tol, check_every=w.check_every)
+    assert r2.status == hr.OK
+    steps = c["n_mid"] + r2.steps_taken
+    du = rel_maxdiff(g.get_u(extended=True), c["end"][0])
+    dv = rel_maxdiff(g.get_v(extended=True), c["end"][1])
+    banner(f"{w.grid.name()}: end ({steps} steps, oracle {c['steps']}) du {du:.2e} dv {dv:.2e}, "
+           f"residual {r2.residual:.3e}")
+    assert steps == c["steps"]
+    assert du <= 1e-12 and dv <= 1e-12
+    hist = np.concatenate([r1.history, r2.history])
+    np.testing.assert_allclose(hist, c["hist"], rtol=1e-9, atol=1e-15)
+    if w.grid.coords == workloads.SINHSYMTP:
+        assert kern["variant"] == 3      # the resident kernel, as benchmarked
+
+
+@pytest.mark.parametrize("bits,bound", [(32, 1e-10), (16, 1e-9)])
+def test_split_fp32_converged_state_matches_oracle(converged, bits, bound):
+    c = converged
+    w = c["w"]
+    g = gpu_grid(w.grid)
+    g.set_fp32_switch(0.0, 8, 0)
+    g.set_factor_storage(bits)
+    g.set_punctures(*w.punctures.as_tuple())
+    r = g.relax(w.eta, w.kappa, c["dt"], 200000, w.tol, check_every=w.check_every,
+                precision=hr.FP32_FP64FINISH)
+    assert r.status == hr.OK and g.residual_l2() < w.tol
+    du = rel_maxdiff(g.get_u(extended=True), c["end"][0])
+    banner(f"{w.grid.name()} split form, {bits}-bit factors: {r.steps_taken} steps "
+           f"({r.fp32_steps} fp32; oracle {c['steps']}), du vs oracle {du:.2e}")
+    assert du <= bound
+    assert r.fp32_steps >= 0.5 * r.steps_taken
