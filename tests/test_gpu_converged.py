@@ -16,7 +16,10 @@ to the tolerance and compare again.
 Bars:
 * FP64: max|f_gpu - f_oracle| / max|f_oracle| <= 1e-12 for f = u and f = v,
   over every stored point, with equal step counts and residual histories
-  within 1e-9 relative.
+  within 1e-9 relative or 1e-3 of the tolerance absolute. Near convergence H
+  is the small sum of a Laplacian and a source term that are each orders of
+  magnitude larger, so its rounding floor is an absolute ~1e-14 (measured
+  8.5e-15 at 1e-10), not a relative one.
 * FP32 bulk + FP64 finish (HR_FP32_FP64FINISH), relaxed to the same
   tolerance: <= 1e-10 on u against the oracle's converged u. In exact
   arithmetic the split state follows the FP64 trajectory. Its FP32 rounding is
@@ -79,7 +82,7 @@ def test_fp64_mid_and_end_states_match_oracle(converged):
     assert steps == c["steps"]
     assert du <= 1e-12 and dv <= 1e-12
     hist = np.concatenate([r1.history, r2.history])
-    np.testing.assert_allclose(hist, c["hist"], rtol=1e-9, atol=1e-15)
+    np.testing.assert_allclose(hist, c["hist"], rtol=1e-9, atol=1e-3 * w.tol)
     if w.grid.coords == workloads.SINHSYMTP:
         assert kern["variant"] == 3      # the resident kernel, as benchmarked
 
