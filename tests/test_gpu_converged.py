@@ -15,11 +15,14 @@ to the tolerance and compare again.
 
 Bars:
 * FP64: max|f_gpu - f_oracle| / max|f_oracle| <= 1e-12 for f = u and f = v,
-  over every stored point, with equal step counts and residual histories
-  within 1e-9 relative or 1e-3 of the tolerance absolute. Near convergence H
-  is the small sum of a Laplacian and a source term that are each orders of
-  magnitude larger, so its rounding floor is an absolute ~1e-14 (measured
-  8.5e-15 at 1e-10), not a relative one.
+  over every stored point, with equal step counts (the stop decisions) and
+  residual histories within 1e-6 relative or 0.2 of the tolerance absolute.
+  H is the small sum of a Laplacian and a source term that are each orders of
+  magnitude larger, and near the axis and the origin of the SinhSymTP grid the
+  Laplacian's coefficients reach ~1e7 (1/(A sin(xx1) dxx2)^2 with A ~ 0.07 in
+  the first cell), so differences of the states at the roundoff level
+  (~1e-14 of max|u|) move H by up to ~1e-11 absolute: measured 7.7e-12 at
+  residual 1e-10 on SinhSymTP 128x128x16, 8.5e-15 on Spherical 128x64x8.
 * FP32 bulk + FP64 finish (HR_FP32_FP64FINISH), relaxed to the same
   tolerance: <= 1e-10 on u against the oracle's converged u. In exact
   arithmetic the split state follows the FP64 trajectory. Its FP32 rounding is
@@ -82,7 +85,7 @@ def test_fp64_mid_and_end_states_match_oracle(converged):
     assert steps == c["steps"]
     assert du <= 1e-12 and dv <= 1e-12
     hist = np.concatenate([r1.history, r2.history])
-    np.testing.assert_allclose(hist, c["hist"], rtol=1e-9, atol=1e-3 * w.tol)
+    np.testing.assert_allclose(hist, c["hist"], rtol=1e-6, atol=0.2 * w.tol)
     if w.grid.coords == workloads.SINHSYMTP:
         assert kern["variant"] == 3      # the resident kernel, as benchmarked
 
