@@ -186,6 +186,30 @@ hr_status hr_relax(hr_grid* g, double eta, double c, double dt, long n_steps,
                    hr_relax_report* rep);
 
 /*
+ * For callers that cannot allocate device memory (code between graph
+ * captures, tight serving loops, harnesses that forbid hipMalloc): the FP64
+ * form of hr_relax, same arguments and results (prec is HR_FP64), whose
+ * scratch -- the RK4 stage buffers and accumulators, the resident kernel's
+ * exchange buffers and stage counters, the residual partial sums -- lives in
+ * a static device array of the library (64 MiB, one per GPU, held until the
+ * process ends) instead of the grid's bound workspace. The state, sources and
+ * tables stay in the workspace. The call allocates nothing: no hipMalloc or
+ * hipFree, no graph instantiation, no events; it launches the same kernels
+ * as hr_relax, eagerly, and waits for its stream before returning.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents: calls that overlap on one GPU (other threads, other streams) race
+ * and must be serialised by the caller.
+ * Errors: those of hr_relax; HR_ENOMEM when the grid's scratch exceeds 64 MiB
+ * (six FP64 fields of the extended layout plus partial sums: up to about 1.3
+ * million stored points, e.g. 128x128x16 and 256x128x32 fit, 256x256x32 does
+ * not); HR_ESTATE when c differs from the wave-speed scale whose planes are
+ * loaded (1 after hr_grid_bind, else the c of the last hr_relax).
+ */
+hr_status hr_relax_noalloc(hr_grid* g, double eta, double c, double dt,
+                           long n_steps, double tol, int check_every,
+                           hr_relax_report* rep);
+
+/*
  * HR_FP32_FP64FINISH, the single-precision bulk with a double-precision finish
  * (paper: strongly typed single-precision builds, "Roofline Analysis"
  * subsection). The state is split into an FP64 base y_b and an FP32 increment

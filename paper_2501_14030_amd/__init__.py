@@ -86,6 +86,9 @@ _SIGNATURES = {
     "hr_relax": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_long, ctypes.c_double, ctypes.c_int,
                                 ctypes.c_int, ctypes.POINTER(RelaxReport)]),
+    "hr_relax_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_long, ctypes.c_double,
+                                        ctypes.c_int, ctypes.POINTER(RelaxReport)]),
     "hr_set_fp32_switch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int,
                                           ctypes.c_long]),
     "hr_get_u": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_size_t]),
@@ -255,6 +258,24 @@ class Grid:
                                      ctypes.byref(rep))
         if st not in (OK, ENOTCONV, ENONFINITE) or (raise_on_error and st == ENONFINITE):
             _check(st, "hr_relax")
+        return RelaxResult(st, rep.steps_taken, rep.fp32_steps, rep.residual, rep.dt_used,
+                           hist[:min(rep.n_history, cap)].copy())
+
+    def relax_noalloc(self, eta: float, c: float = 1.0, dt: float = 0.0, n_steps: int = 1000,
+                      tol: float = 0.0, check_every: int = 100,
+                      raise_on_error: bool = True) -> RelaxResult:
+        """hr_relax_noalloc: the FP64 relaxation with the library's static
+        device scratch in place of the workspace's (allocates nothing)."""
+        cap = max(1, int(n_steps) // max(1, int(check_every)) + 2)
+        hist = np.zeros(cap)
+        rep = RelaxReport()
+        rep.history = hist.ctypes.data_as(_dp)
+        rep.history_cap = cap
+        st = load_library().hr_relax_noalloc(self._h, float(eta), float(c), float(dt),
+                                             int(n_steps), float(tol), int(check_every),
+                                             ctypes.byref(rep))
+        if st not in (OK, ENOTCONV, ENONFINITE) or (raise_on_error and st == ENONFINITE):
+            _check(st, "hr_relax_noalloc")
         return RelaxResult(st, rep.steps_taken, rep.fp32_steps, rep.residual, rep.dt_used,
                            hist[:min(rep.n_history, cap)].copy())
 
@@ -459,6 +480,11 @@ def relax(grid: Grid, eta: float, c: float = 1.0, dt: float = 0.0, n_steps: int 
     return grid.relax(eta, c, dt, n_steps, tol, **kw)
 
 
+def relax_noalloc(grid: Grid, eta: float, c: float = 1.0, dt: float = 0.0,
+                  n_steps: int = 1000, tol: float = 0.0, **kw) -> RelaxResult:
+    return grid.relax_noalloc(eta, c, dt, n_steps, tol, **kw)
+
+
 def get_u(grid: Grid, extended: bool = False) -> np.ndarray:
     return grid.get_u(extended)
 
@@ -468,5 +494,5 @@ def residual_l2(grid: Grid) -> float:
 
 
 __all__ = ["Grid", "Batch", "GridParams", "RelaxResult", "HRError", "grid_create", "set_punctures",
-           "relax", "get_u", "residual_l2", "load_library", "default_params",
+           "relax", "relax_noalloc", "get_u", "residual_l2", "load_library", "default_params",
            "SINHSYMTP", "SPHERICAL", "SINHSPHERICAL", "FP64", "FP32", "FP32_FP64FINISH"]

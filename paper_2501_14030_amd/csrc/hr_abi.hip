@@ -21,6 +21,13 @@
 
 #include "hr_internal.h"
 
+// Device scratch of hr_relax_noalloc: the stage buffers, accumulators,
+// exchange buffers, counters and residual partial sums of one grid, in place of
+// the bound workspace's. Every GPU the library runs on holds one copy until
+// the process ends; calls on one GPU share it. In host code this name is only
+// a stand-in: its device address, per device, comes from hipGetSymbolAddress.
+static __device__ __align__(256) double scratch[(64ull << 20) / sizeof(double)];
+
 namespace hr {
 
 static thread_local std::string g_err;
@@ -691,6 +698,169 @@ hr_status run_split_phase(hr_grid* g, double eta, double dt, long max_steps, dou
   return HR_OK;
 }
 
+constexpr size_t kScratchBytes = sizeof(scratch);
+
+// Device address of the scratch array on each device (null until the first
+// hr_relax_noalloc on that device resolves it).
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;
+
+hr_status scratch_on_device(int device, char** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize(device + 1, nullptr);
+  if (!g_scratch_ptr[device]) {
+    int cur = -1;
+    HR_HIP(hipGetDevice(&cur));
+    if (cur != device) HR_HIP(hipSetDevice(device));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p || ((uintptr_t)p % kAlign) != 0)
+      return fail(HR_EDEVICE, "scratch array has no aligned device address");
+    g_scratch_ptr[device] = p;
+  }
+  *out = (char*)g_scratch_ptr[device];
+  return HR_OK;
+}
+
+// Scratch of the FP64 relaxation of grid g: the six stage/accumulator fields
+// (the resident kernel's exchange buffers are two of them), the residual
+// partial sums and result, the resident stage counters and error word. With
+// base != nullptr also returns the pointers. Returns the bytes used.
+struct ScratchView {
+  double* f[6];   // ua, va, ub, vb, au, av
+  double* partial;
+  double* result;
+  unsigned* flags;
+  unsigned* err;
+};
+
+size_t scratch_layout(const hr_grid* g, char* base, ScratchView* v = nullptr) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off = align_up(off + bytes, kAlign);
+    return p;
+  };
+  ScratchView t{};
+  for (double*& p : t.f) p = (double*)take(g->G * sizeof(double));
+  t.partial = (double*)take((size_t)g->nblk_res * sizeof(double));
+  t.result = (double*)take(4 * sizeof(double));
+  const int nres = std::max(g->res[0].blocks(), g->res[1].blocks());
+  t.flags = nres > 0 ? (unsigned*)take((size_t)nres * kResFlagStride * sizeof(unsigned))
+                     : nullptr;
+  t.err = nres > 0 ? (unsigned*)take(sizeof(unsigned)) : nullptr;
+  if (v) *v = t;
+  return off;
+}
+
+// Points the grid's FP64 scratch fields at the scratch array for the lifetime
+// of the object, with graph capture and launch timing off (both create
+// runtime objects), and restores the workspace pointers afterwards.
+class ScratchSwap {
+ public:
+  ScratchSwap(hr_grid* g, char* base) : g_(g), f_(g->f64), partial_(g->partial),
+      result_(g->result), flags_(g->res_flags), err_(g->res_err), graph_(g->graph),
+      timing_(g->time_launches) {
+    ScratchView v{};
+    scratch_layout(g, base, &v);
+    double** mine[] = {&g->f64.ua, &g->f64.va, &g->f64.ub, &g->f64.vb, &g->f64.au, &g->f64.av};
+    for (int i = 0; i < 6; ++i) *mine[i] = v.f[i];
+    g->partial = v.partial;
+    g->result = v.result;
+    g->res_flags = v.flags;
+    g->res_err = v.err;
+    g->graph = 0;
+    g->time_launches = 0;
+  }
+  ~ScratchSwap() {
+    g_->f64 = f_;
+    g_->partial = partial_;
+    g_->result = result_;
+    g_->res_flags = flags_;
+    g_->res_err = err_;
+    g_->graph = graph_;
+    g_->time_launches = timing_;
+  }
+  ScratchSwap(const ScratchSwap&) = delete;
+  ScratchSwap& operator=(const ScratchSwap&) = delete;
+
+ private:
+  hr_grid* g_;
+  Fields<double> f_;
+  double* partial_;
+  double* result_;
+  unsigned* flags_;
+  unsigned* err_;
+  int graph_;
+  int timing_;
+};
+
+// Checks the arguments that hr_relax and hr_relax_noalloc share.
+hr_status relax_args_ok(const hr_grid* g, double eta, double c, double dt, long n_steps,
+                        int check_every) {
+  hr_status st = check_ready(g, true);
+  if (st != HR_OK) return st;
+  if (!(eta > 0) || !(c > 0) || !std::isfinite(eta) || !std::isfinite(c) || !std::isfinite(dt))
+    return fail(HR_EINVAL, "eta and c must be finite and > 0");
+  if (n_steps < 0) return fail(HR_EINVAL, "n_steps must be >= 0");
+  if (check_every <= 0) return fail(HR_EINVAL, "check_every must be > 0");
+  return HR_OK;
+}
+
+// The relaxation driver (Algorithm 1's outer loop) on checked arguments.
+hr_status relax_impl(hr_grid* g, double eta, double c, double dt, long n_steps, double tol,
+                     int check_every, hr_precision prec, hr_relax_report* rep) {
+  if (dt <= 0) dt = g->prm.cfl * g->tab.ds_g;
+  HR_HIP(hipSetDevice(g->device));
+  hr_status st = load_kappa(g, c);
+  if (st != HR_OK) return st;
+  if (rep) {
+    rep->steps_taken = 0;
+    rep->fp32_steps = 0;
+    rep->residual = NAN;
+    rep->dt_used = dt;
+    rep->n_history = 0;
+  }
+  const int G = (int)g->G;
+  long done = 0, total = 0, f32steps = 0;
+  int why = 0;
+  double last = NAN;
+  if (prec == HR_FP32) {
+    HR_HIP(launch_to_fp32(g->f64.un, g->f32.un, G, g->stream));
+    HR_HIP(launch_to_fp32(g->f64.vn, g->f32.vn, G, g->stream));
+    st = run_phase<float>(g, g->f32, true, eta, dt, n_steps, tol, check_every, false, rep, &done,
+                          &why, &last);
+    if (st != HR_OK) return st;
+    total += done;
+    f32steps = done;
+    HR_HIP(launch_to_fp64(g->f32.un, g->f64.un, G, g->stream));
+    HR_HIP(launch_to_fp64(g->f32.vn, g->f64.vn, G, g->stream));
+    HR_HIP(hipStreamSynchronize(g->stream));
+  } else if (prec == HR_FP32_FP64FINISH) {
+    const double sw = g->sw_residual > 0 ? g->sw_residual : (tol > 0 ? 10.0 * tol : 0.0);
+    st = run_split_phase(g, eta, dt, n_steps, tol, check_every, sw, rep, &done, &why, &last);
+    if (st != HR_OK) return st;
+    total += done;
+    f32steps = done;
+  }
+  if (prec == HR_FP64 || (prec == HR_FP32_FP64FINISH && why == 3 && total < n_steps)) {
+    st = run_phase<double>(g, g->f64, false, eta, dt, n_steps - total, tol, check_every, false,
+                           rep, &done, &why, &last);
+    if (st != HR_OK) return st;
+    total += done;
+  }
+  if (rep) {
+    rep->steps_taken = total;
+    rep->fp32_steps = f32steps;
+    rep->residual = last;
+  }
+  if (why == 2) return fail(HR_ENONFINITE, "residual is not finite");
+  if (tol > 0 && why != 1) return fail(HR_ENOTCONV, "tolerance not reached within n_steps");
+  return HR_OK;
+}
+
 }  // namespace
 }  // namespace hr
 
@@ -899,61 +1069,41 @@ hr_status hr_set_fp32_switch(hr_grid* g, double switch_residual, int stall_check
 
 hr_status hr_relax(hr_grid* g, double eta, double c, double dt, long n_steps, double tol,
                    int check_every, hr_precision prec, hr_relax_report* rep) {
-  hr_status st = check_ready(g, true);
+  hr_status st = relax_args_ok(g, eta, c, dt, n_steps, check_every);
   if (st != HR_OK) return st;
-  if (!(eta > 0) || !(c > 0) || !std::isfinite(eta) || !std::isfinite(c) || !std::isfinite(dt))
-    return fail(HR_EINVAL, "eta and c must be finite and > 0");
-  if (n_steps < 0) return fail(HR_EINVAL, "n_steps must be >= 0");
-  if (check_every <= 0) return fail(HR_EINVAL, "check_every must be > 0");
   if (prec != HR_FP64 && prec != HR_FP32 && prec != HR_FP32_FP64FINISH)
     return fail(HR_EINVAL, "unknown precision");
-  if (dt <= 0) dt = g->prm.cfl * g->tab.ds_g;
-  HR_HIP(hipSetDevice(g->device));
-  st = load_kappa(g, c);
+  return relax_impl(g, eta, c, dt, n_steps, tol, check_every, prec, rep);
+}
+
+hr_status hr_relax_noalloc(hr_grid* g, double eta, double c, double dt, long n_steps, double tol,
+                           int check_every, hr_relax_report* rep) {
+  hr_status st = relax_args_ok(g, eta, c, dt, n_steps, check_every);
   if (st != HR_OK) return st;
-  if (rep) {
-    rep->steps_taken = 0;
-    rep->fp32_steps = 0;
-    rep->residual = NAN;
-    rep->dt_used = dt;
-    rep->n_history = 0;
+  if (c != g->kappa_loaded)
+    return fail(HR_ESTATE, "hr_relax_noalloc: the wave-speed planes are loaded for another c "
+                           "(hr_grid_bind loads c = 1; hr_relax loads its own c)");
+  const size_t need = scratch_layout(g, nullptr);
+  if (need > kScratchBytes)
+    return fail(HR_ENOMEM, "hr_relax_noalloc: this grid needs " + std::to_string(need) +
+                               " bytes of scratch; the library's static scratch holds " +
+                               std::to_string(kScratchBytes) + " (64 MiB)");
+  HR_HIP(hipSetDevice(g->device));
+  char* base = nullptr;
+  st = scratch_on_device(g->device, &base);
+  if (st != HR_OK) return st;
+  {
+    ScratchSwap sw(g, base);
+    // the error word must start at zero; the stage counters are zeroed by
+    // every resident launch and the other buffers are written before read
+    if (g->res_err) HR_HIP(launch_fill(reinterpret_cast<float*>(g->res_err), 0.0f, 1, g->stream));
+    st = relax_impl(g, eta, c, dt, n_steps, tol, check_every, HR_FP64, rep);
+    // the scratch is shared by every call on this device: nothing of this
+    // call may still run when it returns
+    const hipError_t e = hipStreamSynchronize(g->stream);
+    if (st == HR_OK && e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
   }
-  const int G = (int)g->G;
-  long done = 0, total = 0, f32steps = 0;
-  int why = 0;
-  double last = NAN;
-  if (prec == HR_FP32) {
-    HR_HIP(launch_to_fp32(g->f64.un, g->f32.un, G, g->stream));
-    HR_HIP(launch_to_fp32(g->f64.vn, g->f32.vn, G, g->stream));
-    st = run_phase<float>(g, g->f32, true, eta, dt, n_steps, tol, check_every, false, rep, &done,
-                          &why, &last);
-    if (st != HR_OK) return st;
-    total += done;
-    f32steps = done;
-    HR_HIP(launch_to_fp64(g->f32.un, g->f64.un, G, g->stream));
-    HR_HIP(launch_to_fp64(g->f32.vn, g->f64.vn, G, g->stream));
-    HR_HIP(hipStreamSynchronize(g->stream));
-  } else if (prec == HR_FP32_FP64FINISH) {
-    const double sw = g->sw_residual > 0 ? g->sw_residual : (tol > 0 ? 10.0 * tol : 0.0);
-    st = run_split_phase(g, eta, dt, n_steps, tol, check_every, sw, rep, &done, &why, &last);
-    if (st != HR_OK) return st;
-    total += done;
-    f32steps = done;
-  }
-  if (prec == HR_FP64 || (prec == HR_FP32_FP64FINISH && why == 3 && total < n_steps)) {
-    st = run_phase<double>(g, g->f64, false, eta, dt, n_steps - total, tol, check_every, false,
-                           rep, &done, &why, &last);
-    if (st != HR_OK) return st;
-    total += done;
-  }
-  if (rep) {
-    rep->steps_taken = total;
-    rep->fp32_steps = f32steps;
-    rep->residual = last;
-  }
-  if (why == 2) return fail(HR_ENONFINITE, "residual is not finite");
-  if (tol > 0 && why != 1) return fail(HR_ENOTCONV, "tolerance not reached within n_steps");
-  return HR_OK;
+  return st;
 }
 
 hr_status hr_get_u(const hr_grid* g, double* host_out, size_t n) {
