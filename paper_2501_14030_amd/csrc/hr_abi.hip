@@ -203,6 +203,18 @@ double norm_divisor(const hr_grid* g) {
 }
 
 ResidentArgs resident_args(hr_grid* g, double eta, double dt, int nsteps) {
+  return resident_args_part(g, resident_partition(g), eta, dt, nsteps);
+}
+
+ResidentArgsT<float> resident_args_split(hr_grid* g, float eta, float dt, int nsteps) {
+  return resident_args_split_part(g, resident_partition(g), eta, dt, nsteps);
+}
+
+}  // namespace
+
+// Resident arguments of the FP64 state with patch partition p.
+ResidentArgs resident_args_part(hr_grid* g, const hr_grid::ResPlan* p, double eta, double dt,
+                                int nsteps) {
   ResidentArgs r{};
   r.d = g->d;
   r.u = g->f64.un;
@@ -213,7 +225,6 @@ ResidentArgs resident_args(hr_grid* g, double eta, double dt, int nsteps) {
   r.ofac = g->f64.ofac;
   r.x0 = g->f64.ua;
   r.x1 = g->f64.ub;
-  const hr_grid::ResPlan* p = resident_partition(g);
   r.flags = g->res_flags;
   r.waits = p->waits;
   r.err = g->res_err;
@@ -232,7 +243,8 @@ ResidentArgs resident_args(hr_grid* g, double eta, double dt, int nsteps) {
 
 // Resident arguments of the split-state form: the FP32 increment, the base
 // quantities (p_b, S_src p_b^-7, k(y_b)) of the last base evaluation.
-ResidentArgsT<float> resident_args_split(hr_grid* g, float eta, float dt, int nsteps) {
+ResidentArgsT<float> resident_args_split_part(hr_grid* g, const hr_grid::ResPlan* p, float eta,
+                                              float dt, int nsteps) {
   ResidentArgsT<float> r{};
   r.d = g->d;
   r.u = g->f32.un;
@@ -245,7 +257,6 @@ ResidentArgsT<float> resident_args_split(hr_grid* g, float eta, float dt, int ns
   r.ofac = g->f32.ofac;
   r.x0 = g->f32.ua;
   r.x1 = g->f32.ub;
-  const hr_grid::ResPlan* p = resident_partition(g);
   r.flags = g->res_flags;
   r.waits = p->waits;
   r.err = g->res_err;
@@ -262,6 +273,28 @@ ResidentArgsT<float> resident_args_split(hr_grid* g, float eta, float dt, int ns
   r.facb = g->factors16 ? g->f32.facb : nullptr;
   return r;
 }
+
+// Patch partition of grid g when it runs resident inside a batch (null: it
+// runs on the batched stage kernels). An explicit stage-kernel variant keeps
+// the stage kernels and an explicit resident partition is kept; otherwise 8 x 8
+// patches where they fit (more grids share one launch than with 8 x 4), else
+// 8 x 4 ones.
+const hr_grid::ResPlan* batch_resident_part(const hr_grid* g, bool split) {
+  if (g->variant == 1 || g->variant == 2) return nullptr;
+  if (g->fd_order != 8 && g->fd_order != 10) return nullptr;
+  auto fits = [&](const hr_grid::ResPlan& p) {
+    return p.nbx > 0 && p.blocks() <= (split ? std::min(p.cap, p.cap32) : p.cap);
+  };
+  if (g->variant == 3 && (g->chunk == 8 || g->chunk == 4)) {
+    const hr_grid::ResPlan& p = g->res[g->chunk == 8 ? 0 : 1];
+    return fits(p) ? &p : nullptr;
+  }
+  if (fits(g->res[0])) return &g->res[0];
+  if (fits(g->res[1])) return &g->res[1];
+  return nullptr;
+}
+
+namespace {
 
 // The event pair that times the next resident launch of hr_relax, or nulls
 // when launch timing is off (or more launches than pairs are pending).

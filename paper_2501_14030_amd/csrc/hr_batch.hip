@@ -12,6 +12,13 @@
 // from the single-precision phase to the FP64 finish, only the lists and their
 // lengths in device memory change. The host reads back one norm per grid per
 // check and applies each grid's own stop test.
+//
+// Grids small enough for the resident kernel (state on chip, one patch per
+// compute unit) skip the stage lists: per check interval they run K whole
+// RK4 steps in resident launches, several grids per launch where their patches
+// fit on the device together (each grid with its own counters and exchange
+// buffers). These launches are part of the captured interval; the graph is
+// captured again when the set of resident grids changes.
 
 #include <algorithm>
 #include <cmath>
@@ -54,6 +61,21 @@ struct hr_batch {
   hipGraphExec_t exec = nullptr;
   int exec_mode = -1;
   int exec_K = 0;
+  // resident grids: device argument tables (FP64 state, split-form increment),
+  // their host copies, the launches they form and the shared error word
+  ResidentArgsT<double>* rt64 = nullptr;
+  ResidentArgsT<float>* rt32 = nullptr;
+  unsigned* rerr = nullptr;
+  std::vector<ResidentArgsT<double>> h_rt64;
+  std::vector<ResidentArgsT<float>> h_rt32;
+  struct ResGroup {
+    bool split;
+    int first;   // first entry of the group in its table
+    int n;       // grids in the launch
+  };
+  std::vector<ResGroup> groups;
+  std::vector<int> groups_sig;  // grouping of the resident grids (grid ids, phases)
+  std::vector<int> exec_sig;    // grouping captured in exec
 };
 
 namespace {
@@ -118,6 +140,9 @@ size_t batch_layout(hr_batch* b, char* base) {
   b->ranges = (int4*)take(n * sizeof(int4));
   b->partial = (double*)take(b->cap_plane * sizeof(double));
   b->out = (double*)take(n * sizeof(double));
+  b->rt64 = (ResidentArgsT<double>*)take(n * sizeof(ResidentArgsT<double>));
+  b->rt32 = (ResidentArgsT<float>*)take(n * sizeof(ResidentArgsT<float>));
+  b->rerr = (unsigned*)take(sizeof(unsigned));
   return off;
 }
 
@@ -133,6 +158,8 @@ struct GridRun {
   int stall = 0;
   double sw = 0.0;
   int chunk = 1;
+  double eta = 0.0;
+  double dt = 0.0;
 };
 
 hr_status capture(hr_batch* b, int mode, int K) {
@@ -148,13 +175,21 @@ hr_status capture(hr_batch* b, int mode, int K) {
   if (mode & 1) ok(launch_batch_base(b->order, b->ba, b->itbase, b->counts + 3, b->nblk_tile, b->stream));
   for (int k = 0; k < K; ++k)
     for (int s = 1; s <= 4; ++s) {
-      if (mode & 1)
+      if (mode & 4)
         ok(launch_batch_stage(b->order, s, true, b->sa32, b->it32, b->counts + 1, b->nblk_tile,
                               b->stream));
       if (mode & 2)
         ok(launch_batch_stage(b->order, s, false, b->sa64, b->it64, b->counts + 0, b->nblk_tile,
                               b->stream));
     }
+  for (const hr_batch::ResGroup& rg : b->groups) {
+    if (rg.split)
+      ok(launch_resident_multi(b->order, b->rt32 + rg.first, b->h_rt32.data() + rg.first, rg.n,
+                               b->stream));
+    else
+      ok(launch_resident_multi(b->order, b->rt64 + rg.first, b->h_rt64.data() + rg.first, rg.n,
+                               b->stream));
+  }
   if (mode & 1) ok(launch_batch_rebase(b->rb, b->itreb, b->counts + 4, b->nblk_flat, b->stream));
   ok(launch_batch_residual(b->order, b->ra, b->itres, b->counts + 2, b->partial, b->nblk_tile,
                            b->stream));
@@ -170,14 +205,104 @@ hr_status capture(hr_batch* b, int mode, int K) {
   }
   b->exec_mode = mode;
   b->exec_K = K;
+  b->exec_sig = b->groups_sig;
   return HR_OK;
 }
 
-// Rebuilds and uploads the work lists for the grids still relaxing.
-hr_status upload_lists(hr_batch* b, const std::vector<GridRun>& run, int* mode) {
+// Packs the running grids that run resident in their current phase into
+// launches: first fit, largest grids first, into launches of one kernel
+// instance whose patches all fit on the device at once. Builds the argument
+// tables (K steps each, every grid's error flag the batch's word) and the
+// grouping's signature; the tables are uploaded by the caller.
+hr_status plan_resident(hr_batch* b, const std::vector<GridRun>& run, int K,
+                        std::vector<bool>& resident) {
+  struct Cand {
+    int i;
+    const hr_grid::ResPlan* p;
+  };
+  std::vector<Cand> cand;
+  resident.assign(b->n, false);
+  for (int i = 0; i < b->n; ++i) {
+    if (run[i].done) continue;
+    const hr_grid::ResPlan* p = batch_resident_part(b->g[i], run[i].phase == 0);
+    if (p) cand.push_back({i, p});
+  }
+  std::stable_sort(cand.begin(), cand.end(),
+                   [](const Cand& x, const Cand& y) { return x.p->blocks() > y.p->blocks(); });
+  struct Open {
+    bool split;
+    const void* key;
+    int ry, N2, blocks;
+    size_t lds;
+    std::vector<Cand> members;
+  };
+  std::vector<Open> open;
+  for (const Cand& c : cand) {
+    const hr_grid* g = b->g[c.i];
+    const bool split = run[c.i].phase == 0;
+    const void* key = resident_kernel_key(b->order, g->d.N2, split, c.p->ry);
+    if (!key) continue;
+    const size_t lds = resident_lds_bytes(g->d, split ? sizeof(float) : sizeof(double), c.p->ry);
+    bool placed = false;
+    for (Open& o : open) {
+      if (o.split != split || o.key != key) continue;
+      const size_t l = std::max(o.lds, lds);
+      const int cap = resident_multi_capacity(b->order, o.N2, split, o.ry, l);
+      if (o.blocks + c.p->blocks() > std::min(cap, kResMaxBlocks)) continue;
+      o.lds = l;
+      o.blocks += c.p->blocks();
+      o.members.push_back(c);
+      placed = true;
+      break;
+    }
+    if (!placed) {
+      const int cap = resident_multi_capacity(b->order, g->d.N2, split, c.p->ry, lds);
+      if (c.p->blocks() > std::min(cap, kResMaxBlocks)) continue;  // stays on the stage lists
+      open.push_back({split, key, c.p->ry, g->d.N2, c.p->blocks(), lds, {c}});
+    }
+  }
+  b->groups.clear();
+  b->h_rt64.clear();
+  b->h_rt32.clear();
+  b->groups_sig.clear();
+  for (const Open& o : open) {
+    hr_batch::ResGroup rg{o.split, o.split ? (int)b->h_rt32.size() : (int)b->h_rt64.size(),
+                          (int)o.members.size()};
+    int block0 = 0;
+    b->groups_sig.push_back(o.split ? -2 : -1);
+    for (const Cand& c : o.members) {
+      hr_grid* g = b->g[c.i];
+      resident[c.i] = true;
+      b->groups_sig.push_back(c.i);
+      b->groups_sig.push_back(c.p == &g->res[0] ? 8 : 4);
+      if (o.split) {
+        ResidentArgsT<float> a =
+            resident_args_split_part(g, c.p, (float)run[c.i].eta, (float)run[c.i].dt, K);
+        a.block0 = block0;
+        a.err = b->rerr;
+        b->h_rt32.push_back(a);
+      } else {
+        ResidentArgsT<double> a = resident_args_part(g, c.p, run[c.i].eta, run[c.i].dt, K);
+        a.block0 = block0;
+        a.err = b->rerr;
+        b->h_rt64.push_back(a);
+      }
+      block0 += c.p->blocks();
+    }
+    b->groups.push_back(rg);
+  }
+  return HR_OK;
+}
+
+// Rebuilds and uploads the work lists (and the resident launches) for the
+// grids still relaxing.
+hr_status upload_lists(hr_batch* b, const std::vector<GridRun>& run, int K, int* mode) {
   std::vector<int4> l64, l32, lres, lbase;
   std::vector<int2> lreb;
   std::vector<int4> rng(b->n);
+  std::vector<bool> resident;
+  hr_status pst = plan_resident(b, run, K, resident);
+  if (pst != HR_OK) return pst;
   *mode = 0;
   for (int i = 0; i < b->n; ++i) {
     const hr_grid* g = b->g[i];
@@ -186,10 +311,14 @@ hr_status upload_lists(hr_batch* b, const std::vector<GridRun>& run, int* mode) 
     if (run[i].done) continue;
     const int nch = (N2 + run[i].chunk - 1) / run[i].chunk;
     std::vector<int4>& ls = run[i].phase == 0 ? l32 : l64;
-    *mode |= run[i].phase == 0 ? 1 : 2;
-    for (int z = 0; z < nch; ++z)
-      for (int y = 0; y < t1; ++y)
-        for (int x = 0; x < t0; ++x) ls.push_back(make_int4(i, x, y, z));
+    // mode bits: 1 split-form grids (base slopes and rebase), 2 FP64 stage
+    // items, 4 split-form stage items, 8 resident launches
+    if (run[i].phase == 0) *mode |= 1;
+    *mode |= resident[i] ? 8 : run[i].phase == 0 ? 4 : 2;
+    if (!resident[i])
+      for (int z = 0; z < nch; ++z)
+        for (int y = 0; y < t1; ++y)
+          for (int x = 0; x < t0; ++x) ls.push_back(make_int4(i, x, y, z));
     for (int z = 0; z < N2; ++z)
       for (int y = 0; y < t1; ++y)
         for (int x = 0; x < t0; ++x) {
@@ -219,6 +348,12 @@ hr_status upload_lists(hr_batch* b, const std::vector<GridRun>& run, int* mode) 
     HR_HIPB(hipMemcpyAsync(b->itreb, lreb.data(), lreb.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
   HR_HIPB(hipMemcpyAsync(b->counts, cnt, sizeof(cnt), hipMemcpyHostToDevice, b->stream));
   HR_HIPB(hipMemcpyAsync(b->ranges, rng.data(), rng.size() * sizeof(int4), hipMemcpyHostToDevice, b->stream));
+  if (!b->h_rt64.empty())
+    HR_HIPB(hipMemcpyAsync(b->rt64, b->h_rt64.data(), b->h_rt64.size() * sizeof(b->h_rt64[0]),
+                           hipMemcpyHostToDevice, b->stream));
+  if (!b->h_rt32.empty())
+    HR_HIPB(hipMemcpyAsync(b->rt32, b->h_rt32.data(), b->h_rt32.size() * sizeof(b->h_rt32[0]),
+                           hipMemcpyHostToDevice, b->stream));
   HR_HIPB(hipStreamSynchronize(b->stream));
   return HR_OK;
 }
@@ -280,7 +415,8 @@ hr_status hr_batch_bind(hr_batch* b, void* dev_ptr, size_t bytes, void* hip_stre
     HR_HIPB(hipStreamCreate(&b->stream));
     b->own_stream = true;
   }
-  HR_HIPB(hipHostMalloc((void**)&b->host_out, b->n * sizeof(double), hipHostMallocDefault));
+  // one norm per grid, then the resident launches' error word
+  HR_HIPB(hipHostMalloc((void**)&b->host_out, (b->n + 1) * sizeof(double), hipHostMallocDefault));
   batch_layout(b, (char*)dev_ptr);
   int cus = 0;
   HR_HIPB(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
@@ -336,6 +472,8 @@ hr_status hr_batch_relax(hr_batch* b, const double* eta, const double* c, long n
     const double dt = g->prm.cfl * g->tab.ds_g;
     const int chunk = explicit_chunk(g) ? g->chunk : std::min(bchunk, g->d.N2);
     run[i].chunk = chunk;
+    run[i].eta = eta[i];
+    run[i].dt = dt;
     run[i].phase = prec == HR_FP32_FP64FINISH ? 0 : 1;
     run[i].sw = g->sw_residual > 0 ? g->sw_residual : (tol > 0 ? 10.0 * tol : 0.0);
     for (int s = 1; s <= 4; ++s) {
@@ -380,6 +518,7 @@ hr_status hr_batch_relax(hr_batch* b, const double* eta, const double* c, long n
   HR_HIPB(hipMemcpyAsync(b->ra, hra.data(), hra.size() * sizeof(hra[0]), hipMemcpyHostToDevice, b->stream));
   HR_HIPB(hipMemcpyAsync(b->ba, hba.data(), hba.size() * sizeof(hba[0]), hipMemcpyHostToDevice, b->stream));
   HR_HIPB(hipMemcpyAsync(b->rb, hrb.data(), hrb.size() * sizeof(hrb[0]), hipMemcpyHostToDevice, b->stream));
+  HR_HIPB(launch_fill(reinterpret_cast<float*>(b->rerr), 0.0f, 1, b->stream));
   HR_HIPB(hipStreamSynchronize(b->stream));
 
   const long max_cycles = (n_steps + K - 1) / K;
@@ -387,19 +526,27 @@ hr_status hr_batch_relax(hr_batch* b, const double* eta, const double* c, long n
   int mode = 0;
   for (long cyc = 0; cyc < max_cycles; ++cyc) {
     if (lists_dirty) {
-      hr_status st = upload_lists(b, run, &mode);
+      hr_status st = upload_lists(b, run, K, &mode);
       if (st != HR_OK) return st;
       lists_dirty = false;
     }
     if (mode == 0) break;
-    if (!b->exec || b->exec_mode != mode || b->exec_K != K) {
+    if (!b->exec || b->exec_mode != mode || b->exec_K != K || b->exec_sig != b->groups_sig) {
       hr_status st = capture(b, mode, K);
       if (st != HR_OK) return st;
     }
     HR_HIPB(hipGraphLaunch(b->exec, b->stream));
     HR_HIPB(hipMemcpyAsync(b->host_out, b->out, b->n * sizeof(double), hipMemcpyDeviceToHost,
                            b->stream));
+    unsigned* err_word = reinterpret_cast<unsigned*>(b->host_out + b->n);
+    if (!b->groups.empty())
+      HR_HIPB(hipMemcpyAsync(err_word, b->rerr, sizeof(unsigned), hipMemcpyDeviceToHost,
+                             b->stream));
     HR_HIPB(hipStreamSynchronize(b->stream));
+    if (!b->groups.empty() && *err_word) {
+      *err_word = 0;
+      return bfail(HR_EDEVICE, "resident kernel in a batch: an exchange wait timed out");
+    }
     for (int i = 0; i < b->n; ++i) {
       GridRun& r = run[i];
       if (r.done) continue;

@@ -217,6 +217,7 @@ struct ResidentArgsT {
   unsigned spin_limit;  // polls of one counter before a wait gives up
   int bc4;              // fourth-order one-sided difference in the radiation condition
   const unsigned short* facb;  // bfloat16 factor planes (replace fac when set)
+  int block0;           // first block of this grid in a multi-grid launch (else 0)
 };
 using ResidentArgs = ResidentArgsT<double>;
 
@@ -239,6 +240,22 @@ hipError_t launch_resident(int order, const ResidentArgsT<double>& a, hipStream_
                            hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t launch_resident(int order, const ResidentArgsT<float>& a, hipStream_t s,
                            hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+// Several grids in one resident launch: host_tab[i] is a host copy of
+// dev_tab[i] (which must be in device memory, in stream order, before the
+// launch) and describes grid i, whose blocks start at host_tab[i].block0, the
+// sum of the earlier grids' patches. All grids take the same kernel instance
+// (order, patch rows and plane group: resident_kernel_key); each keeps its own
+// counters (zeroed here), partners and exchange buffers.
+hipError_t launch_resident_multi(int order, const ResidentArgsT<double>* dev_tab,
+                                 const ResidentArgsT<double>* host_tab, int n, hipStream_t s);
+hipError_t launch_resident_multi(int order, const ResidentArgsT<float>* dev_tab,
+                                 const ResidentArgsT<float>* host_tab, int n, hipStream_t s);
+// Identifies the kernel instance of a grid with N2 planes (null: none); grids
+// with equal keys can share a launch.
+const void* resident_kernel_key(int order, int N2, bool split, int ry);
+// Co-resident blocks of a multi-grid launch of that instance with lds bytes of
+// LDS per block (the largest of its grids').
+int resident_multi_capacity(int order, int N2, bool split, int ry, size_t lds);
 
 // Host geometry (hr_geometry.cpp).
 struct HostTables {
@@ -351,6 +368,15 @@ bool resident_ok(const hr_grid* g);
 
 // Uploads the wave-speed planes (c, c^2) for scale kappa if not loaded (synchronous).
 hr_status load_kappa(hr_grid* g, double kappa);
+
+// Resident-kernel arguments of grid g with patch partition p: the FP64 state,
+// or the split form's FP32 increment on its FP64 base (hr_abi.hip).
+ResidentArgsT<double> resident_args_part(hr_grid* g, const hr_grid::ResPlan* p, double eta,
+                                         double dt, int nsteps);
+ResidentArgsT<float> resident_args_split_part(hr_grid* g, const hr_grid::ResPlan* p, float eta,
+                                              float dt, int nsteps);
+// Partition with which grid g runs resident in a batch (null: stage kernels).
+const hr_grid::ResPlan* batch_resident_part(const hr_grid* g, bool split);
 
 // Stage-s arguments of grid g in precision T; corr selects the split-state form.
 template <typename T>

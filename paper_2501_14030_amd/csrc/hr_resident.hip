@@ -44,6 +44,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "hr_internal.h"
 #include "hr_stencil.h"
@@ -80,7 +82,7 @@ __global__ void k_zero_u32(unsigned* p, int n) {
 // planes g, g + PG, ... (NPT of them). T = double: the FP64 state; T = float
 // with CORR: the split-state form's increment (slopes as in the stage kernels).
 template <typename T, int NG, int NPT, int RT, bool CORR, int RY>
-__global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
+__device__ __forceinline__ void resident_body(const ResidentArgsT<T>& a, const int b) {
   constexpr int NP = RB * RY;                    // positions per plane
   constexpr int PG = RT / NP;
   constexpr int RW = tile_row(RB + 2 * NG);      // LDS tile row (x0) stride, padded
@@ -101,7 +103,7 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
   T* ut = smem;                      // [N2][RY + 2 NG][RW]
   T* vt = smem + N2 * TP;            // [N2][RY][VW]
   const int t = threadIdx.x, pos = t & (NP - 1), x0l = pos & 7, x1l = pos >> 3, grp = t / NP;
-  const int b = blockIdx.x, bx = b % a.nbx, by = b / a.nbx;
+  const int bx = b % a.nbx, by = b / a.nbx;
   const int x0b = bx * RB, x1b = by * RY;
   const int i0 = x0b + x0l, i1 = x1b + x1l;
   const bool last = bx == a.nbx - 1;
@@ -430,31 +432,59 @@ __global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
   }
 }
 
+// One grid per launch: block b is patch b.
+template <typename T, int NG, int NPT, int RT, bool CORR, int RY>
+__global__ void __launch_bounds__(RT) k_resident(ResidentArgsT<T> a) {
+  resident_body<T, NG, NPT, RT, CORR, RY>(a, (int)blockIdx.x);
+}
+
+// Several grids per launch (same order, plane group and patch rows): grid i
+// owns blocks [tab[i].block0, tab[i].block0 + its patches); each grid has its
+// own counters, exchange partners and exchange buffers, so the grids never
+// wait for each other.
+template <typename T, int NG, int NPT, int RT, bool CORR, int RY>
+__global__ void __launch_bounds__(RT) k_resident_multi(const ResidentArgsT<T>* __restrict__ tab,
+                                                       int n) {
+  int gi = 0;
+  while (gi + 1 < n && (int)blockIdx.x >= tab[gi + 1].block0) ++gi;
+  // read in place (uniform scalar loads); a private copy would be indexed
+  // with the runtime stage number and spill
+  const ResidentArgsT<T>& a = tab[gi];
+  resident_body<T, NG, NPT, RT, CORR, RY>(a, (int)blockIdx.x - a.block0);
+}
+
 // Threads by N2: one plane per thread (for 8 x 8 patches 1024 threads when
 // N2 > 8: four waves per SIMD to hide LDS and exchange latency). Deeper grids
 // would need several planes per thread and more registers than a 1024-thread
 // block has.
 struct ResShape {
-  const void* kernel;
+  const void* kernel;   // one grid per launch
+  const void* multi;    // several grids per launch
   int threads;
 };
 
 template <typename T, int NG, bool CORR, int RY>
 ResShape shape_for(int N2) {
   constexpr int NP = kResPatch * RY;
-  if (N2 <= 4) return {(const void*)k_resident<T, NG, 1, 4 * NP, CORR, RY>, 4 * NP};
-  if (N2 <= 8) return {(const void*)k_resident<T, NG, 1, 8 * NP, CORR, RY>, 8 * NP};
-  if (N2 <= 16) return {(const void*)k_resident<T, NG, 1, 16 * NP, CORR, RY>, 16 * NP};
-  return {nullptr, 0};
+  if (N2 <= 4)
+    return {(const void*)k_resident<T, NG, 1, 4 * NP, CORR, RY>,
+            (const void*)k_resident_multi<T, NG, 1, 4 * NP, CORR, RY>, 4 * NP};
+  if (N2 <= 8)
+    return {(const void*)k_resident<T, NG, 1, 8 * NP, CORR, RY>,
+            (const void*)k_resident_multi<T, NG, 1, 8 * NP, CORR, RY>, 8 * NP};
+  if (N2 <= 16)
+    return {(const void*)k_resident<T, NG, 1, 16 * NP, CORR, RY>,
+            (const void*)k_resident_multi<T, NG, 1, 16 * NP, CORR, RY>, 16 * NP};
+  return {nullptr, nullptr, 0};
 }
 
 template <typename T, bool CORR>
 ResShape resident_kernel(int order, int N2, int ry) {
-  if (ry != 8 && ry != 4) return {nullptr, 0};
+  if (ry != 8 && ry != 4) return {nullptr, nullptr, 0};
   switch (order) {
     case 8: return ry == 8 ? shape_for<T, 4, CORR, 8>(N2) : shape_for<T, 4, CORR, 4>(N2);
     case 10: return ry == 8 ? shape_for<T, 5, CORR, 8>(N2) : shape_for<T, 5, CORR, 4>(N2);
-    default: return {nullptr, 0};
+    default: return {nullptr, nullptr, 0};
   }
 }
 
@@ -481,6 +511,57 @@ hipError_t launch_resident_t(int order, const ResidentArgsT<T>& a, hipStream_t s
   // block could not start, its partners' waits would time out (err) instead
   // of hanging.
   return hipExtLaunchKernel(k, dim3(nb), dim3(rs.threads), args, lds, s, t0, t1, 0);
+}
+
+// Raises the dynamic-LDS limit of kernel k to at least lds bytes, never
+// lowering it: a captured interval holds launches of one kernel instance with
+// different LDS sizes, each of which must stay within the limit.
+std::mutex g_lds_mu;
+std::map<const void*, size_t> g_lds_set;
+
+hipError_t raise_lds_limit(const void* k, size_t lds) {
+  std::lock_guard<std::mutex> lk(g_lds_mu);
+  size_t& cur = g_lds_set[k];
+  if (lds <= cur) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess) cur = lds;
+  return e;
+}
+
+// Several grids in one launch; see launch_resident_multi.
+template <typename T, bool CORR>
+hipError_t launch_resident_multi_t(int order, const ResidentArgsT<T>* dev_tab,
+                                   const ResidentArgsT<T>* host_tab, int n, hipStream_t s) {
+  if (n <= 0 || !dev_tab || !host_tab) return hipErrorInvalidValue;
+  const int ry = host_tab[0].ry;
+  const ResShape r0 = resident_kernel<T, CORR>(order, host_tab[0].d.N2, ry);
+  if (!r0.multi) return hipErrorInvalidValue;
+  int total = 0;
+  size_t lds = 0;
+  for (int i = 0; i < n; ++i) {
+    const ResidentArgsT<T>& a = host_tab[i];
+    const int nb = a.nbx * a.nby;
+    // every grid runs the same kernel instance, its blocks follow the
+    // previous grid's
+    if (a.ry != ry || resident_kernel<T, CORR>(order, a.d.N2, ry).multi != r0.multi ||
+        nb <= 0 || a.block0 != total || a.nsteps <= 0)
+      return hipErrorInvalidValue;
+    total += nb;
+    lds = std::max(lds, resident_lds_bytes(a.d, sizeof(T), ry));
+    const int nflags = nb * kResFlagStride;
+    k_zero_u32<<<(nflags + 255) / 256, 256, 0, s>>>(a.flags, nflags);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (total > kResMaxBlocks) return hipErrorInvalidValue;
+  const hipError_t e = raise_lds_limit(r0.multi, lds);
+  if (e != hipSuccess) return e;
+  const ResidentArgsT<T>* tab = dev_tab;
+  int cnt = n;
+  void* args[] = {&tab, &cnt};
+  // the caller has checked that all blocks fit at once (resident_multi_capacity)
+  return hipExtLaunchKernel(r0.multi, dim3(total), dim3(r0.threads), args, lds, s, nullptr,
+                            nullptr, 0);
 }
 
 }  // namespace
@@ -517,6 +598,35 @@ hipError_t launch_resident(int order, const ResidentArgsT<double>& a, hipStream_
 hipError_t launch_resident(int order, const ResidentArgsT<float>& a, hipStream_t s,
                            hipEvent_t t0, hipEvent_t t1) {
   return launch_resident_t<float, true>(order, a, s, t0, t1);
+}
+
+hipError_t launch_resident_multi(int order, const ResidentArgsT<double>* dev_tab,
+                                 const ResidentArgsT<double>* host_tab, int n, hipStream_t s) {
+  return launch_resident_multi_t<double, false>(order, dev_tab, host_tab, n, s);
+}
+
+hipError_t launch_resident_multi(int order, const ResidentArgsT<float>* dev_tab,
+                                 const ResidentArgsT<float>* host_tab, int n, hipStream_t s) {
+  return launch_resident_multi_t<float, true>(order, dev_tab, host_tab, n, s);
+}
+
+const void* resident_kernel_key(int order, int N2, bool split, int ry) {
+  return split ? resident_kernel<float, true>(order, N2, ry).multi
+               : resident_kernel<double, false>(order, N2, ry).multi;
+}
+
+int resident_multi_capacity(int order, int N2, bool split, int ry, size_t lds) {
+  const ResShape rs = split ? resident_kernel<float, true>(order, N2, ry)
+                            : resident_kernel<double, false>(order, N2, ry);
+  if (!rs.multi) return 0;
+  if (raise_lds_limit(rs.multi, lds) != hipSuccess) return 0;
+  int per = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, rs.multi, rs.threads, lds) != hipSuccess)
+    return 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return per * cus;
 }
 
 }  // namespace hr

@@ -185,3 +185,54 @@ def test_batch_reports_a_non_finite_grid():
     assert res[1].status == hr.ENONFINITE
     assert res[0].status == hr.ENOTCONV and res[0].steps_taken == 1000
     assert np.isfinite(res[0].residual)
+
+
+# Grids small enough for the resident kernel share resident launches inside a
+# batch: five 64x64x8 grids (64 patches of 8 x 8 each) and two 48x32x6 grids
+# (24 each) take the same kernel instance (10th order, up to 8 planes), so
+# they pack into launches of at most one patch per compute unit; a ragged
+# grid stays on the batched stage kernels. Each grid keeps its own counters
+# and exchange buffers, so every result must equal its eager single-grid
+# solve (the resident and the stage kernels evaluate the same arithmetic in
+# the same order), and the first grid is compared with the oracle as well.
+SMALL = [workloads.GridSpec(0, 64, 64, 8, 10, bscale=1.0 + 0.5 * k) for k in range(5)] + \
+        [workloads.GridSpec(0, 48, 32, 6, 10, bscale=2.0), workloads.GridSpec(0, 48, 32, 6, 10, bscale=3.0),
+         workloads.GridSpec(0, 37, 19, 6, 10, bscale=3.0)]
+
+
+@pytest.mark.parametrize("prec", [hr.FP64, hr.FP32_FP64FINISH])
+def test_small_grids_share_resident_launches(prec):
+    banner(f"small grids in shared resident launches, prec {prec}")
+    gs = []
+    etas = []
+    for k, spec in enumerate(SMALL):
+        g = gpu_grid(spec)
+        g.set_punctures(*_punctures(spec, k).as_tuple())
+        gs.append(g)
+        etas.append(workloads.eta_for_dt(g.suggest_dt(0.5)))
+    b = hr.Batch(gs)
+    res = b.relax(etas, 1.0, n_steps=60000, tol=1e-10, check_every=100, precision=prec)
+    assert b.status == hr.OK
+    for k, spec in enumerate(SMALL):
+        e = gpu_grid(spec)
+        e.set_punctures(*_punctures(spec, k).as_tuple())
+        if prec == hr.FP32_FP64FINISH:
+            e.set_fp32_switch(0.0, 8, 0)
+        r = e.relax(etas[k], 1.0, 0.0, 60000, 1e-10, check_every=100, precision=prec)
+        d = rel_maxdiff(gs[k].get_u(extended=True), e.get_u(extended=True))
+        banner(f"  {spec.name()}: batch {res[k].steps_taken} steps ({res[k].fp32_steps} fp32), "
+               f"eager {r.steps_taken} ({r.fp32_steps}); u {d:.2e}")
+        assert res[k].steps_taken == r.steps_taken and res[k].fp32_steps == r.fp32_steps
+        assert d <= (1e-13 if prec == hr.FP64 else 1e-12)
+        np.testing.assert_allclose(res[k].history, r.history, rtol=1e-9, atol=1e-13)
+        e.close()
+    if prec == hr.FP64:
+        spec = SMALL[0]
+        og = oracle_grid(spec)
+        og.set_punctures(*_punctures(spec, 0).as_tuple())
+        og.relax(etas[0], 1.0, og.suggest_dt(0.5), res[0].steps_taken, 0.0, 100)
+        ou, _ = og.state()
+        d = rel_maxdiff(gs[0].get_u(extended=True), oracle_extended(og, ou))
+        banner(f"  {spec.name()} vs oracle after {res[0].steps_taken} steps: {d:.2e}")
+        assert d <= 1e-12
+    b.close()
