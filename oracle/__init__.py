@@ -31,6 +31,7 @@ _LIB = os.path.join(_HERE, "libhr_oracle.so")
 SINHSYMTP = 0
 SPHERICAL = 1
 SINHSPHERICAL = 2
+SINHCYLINDRICAL = 3
 
 # Readings of parameters the paper leaves to its companion paper.
 DEFAULT_AMAX = 1.0e6

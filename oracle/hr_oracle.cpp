@@ -35,6 +35,15 @@
 //   * SinhSpherical (one of the further coordinate families the paper's
 //     conclusions list): r = A(xx0) with the same sinh stretching, xx0 in
 //     [0,1], theta, phi as for Spherical;
+//   * SinhCylindrical (the cylindrical-like family of the conclusions):
+//     rho = A(xx0), z = A(xx1) with the same sinh stretching, xx0 in [0,1],
+//     xx1 in [-1,1], phi = xx2 in [-pi,pi]; x = rho cos(phi), y = rho sin(phi).
+//     Both z faces are outer boundaries (stored outer points, radiation
+//     condition), the xx0 = 0 face reflects through the axis with phi + pi,
+//     phi is periodic. An outer point beyond a z face takes its one-sided
+//     difference along xx1 where |z| >= rho and along xx0 elsewhere (the
+//     corners toward the rho face), so that the chosen direction is within
+//     45 degrees of the radial one and d r / d xx_i never becomes small;
 //   * psi_singular = 1 + sum_n m_n / (2 r_n);
 //   * A^ij = sum_n 3/(2 r^2) [P^i n^j + P^j n^i - (delta^ij - n^i n^j) P.n]
 //              + 3/r^3 [(S x n)^i n^j + (S x n)^j n^i];
@@ -63,7 +72,7 @@ namespace {
 
 const double kPi = 3.14159265358979323846;
 
-enum { OR_SINHSYMTP = 0, OR_SPHERICAL = 1, OR_SINHSPHERICAL = 2 };
+enum { OR_SINHSYMTP = 0, OR_SPHERICAL = 1, OR_SINHSPHERICAL = 2, OR_SINHCYLINDRICAL = 3 };
 
 // Fornberg's algorithm (B. Fornberg, "Generation of finite difference formulas
 // on arbitrarily spaced grids", Math. Comp. 51 (1988) 699): weights c[j][k] of
@@ -115,8 +124,12 @@ struct Grid {
   // minimum
   std::vector<double> dsmin;
   double ds_g;
-  // outer-boundary geometry on the padded (i0,i1) plane
-  std::vector<double> rcart, drdxx0;
+  // outer-boundary geometry on the padded (i0,i1) plane (d r / d xx1: the
+  // z faces of SinhCylindrical)
+  std::vector<double> rcart, drdxx0, drdxx1;
+  // SinhCylindrical outer points beyond a z face: 1 where the radiation
+  // condition's difference runs along xx1 (|z| >= rho), 0 along xx0
+  std::vector<char> along1;
   // radiation condition: order of the one-sided xx0 difference (2 or 4) and
   // its weights for the offsets 0, -1, ..., -order (Fornberg, spacing 1)
   int bc_order = 2;
@@ -141,9 +154,17 @@ struct Grid {
     return i0 >= NG && i0 < NG + N[0] && i1 >= NG && i1 < NG + N[1] &&
            i2 >= NG && i2 < NG + N[2];
   }
+  // stored outer points: beyond xx0's maximum (interior xx1), and for
+  // SinhCylindrical also every point beyond either z face with xx0 >= 0
   bool outer(int i0, int i1, int i2) const {
-    return i0 >= NG + N[0] && i1 >= NG && i1 < NG + N[1] && i2 >= NG &&
-           i2 < NG + N[2];
+    if (i2 < NG || i2 >= NG + N[2]) return false;
+    const bool in1 = i1 >= NG && i1 < NG + N[1];
+    if (coords == 3 && !in1) return i0 >= NG;
+    return i0 >= NG + N[0] && in1;
+  }
+  // outer point on a z face (SinhCylindrical), corners included
+  bool zface(int i0, int i1, int i2) const {
+    return coords == 3 && outer(i0, i1, i2) && (i1 < NG || i1 >= NG + N[1]);
   }
 };
 
@@ -166,6 +187,13 @@ void to_cart(const Grid& g, double x0, double x1, double x2, double& x,
     x = A * std::sin(x1) * std::cos(x2);
     y = A * std::sin(x1) * std::sin(x2);
     z = R * std::cos(x1);
+  } else if (g.coords == OR_SINHCYLINDRICAL) {
+    double rho, Zc, d1, d2;
+    sinh_radial(g, x0, rho, d1, d2);
+    sinh_radial(g, x1, Zc, d1, d2);
+    x = rho * std::cos(x2);
+    y = rho * std::sin(x2);
+    z = Zc;
   } else {
     // spherical: r = xx0 (Spherical) or the sinh-stretched A(xx0) (SinhSpherical)
     double r = x0;
@@ -201,6 +229,26 @@ void metric_at(const Grid& g, double x0, double x1, double h[3], double* a,
       bb[0] = (2.0 * A * A + g.b * g.b - A * R2 * App / (Ap * Ap)) / (A * Ap * S);
       // (1/J) d_1 (J/h1^2) with J/h1^2 = A A' sin(x1)/R
       bb[1] = c / (s * S);
+    }
+  } else if (g.coords == OR_SINHCYLINDRICAL) {
+    // rho = A(xx0), z = Z(xx1): h = (A', Z', A), J = A' Z' A
+    double A, Ap, App, Z, Zp, Zpp;
+    sinh_radial(g, x0, A, Ap, App);
+    sinh_radial(g, x1, Z, Zp, Zpp);
+    h[0] = Ap;
+    h[1] = Zp;
+    h[2] = A;
+    if (a) {
+      a[0] = 1.0 / (Ap * Ap);
+      a[1] = 1.0 / (Zp * Zp);
+      a[2] = 1.0 / (A * A);
+      // (1/J) d_0 (J/h0^2), J/h0^2 = Z' A / A': Z' (A'^2 - A A'')/A'^2 / (A' Z' A),
+      // with A'^2 - A A'' = (amax / (w sinh(1/w)))^2 exactly (cosh^2 - sinh^2 = 1;
+      // the difference itself cancels to a few digits where xx0 >> w)
+      const double k = g.amax / (g.w * std::sinh(1.0 / g.w));
+      bb[0] = k * k / (Ap * Ap * Ap * A);
+      // (1/J) d_1 (J/h1^2), J/h1^2 = A' A / Z': -A' A Z''/Z'^2 / (A' Z' A)
+      bb[1] = -Zpp / (Zp * Zp * Zp);
     }
   } else if (g.coords == OR_SINHSPHERICAL) {
     // r = A(xx0): h = (A', A, A sin x1), J = A' A^2 sin x1
@@ -241,13 +289,15 @@ long image_of(const Grid& g, int i0, int i1, int i2) {
   const int NG = g.NG, N1 = g.N[1], N2 = g.N[2];
   for (int guard = 0; guard < 8; ++guard) {
     if (i0 < NG) {
-      if (g.coords != OR_SINHSYMTP) i1 = N1 + 2 * NG - 1 - i1;  // spherical: theta mirrors
+      // spherical: theta mirrors; SinhSymTP and SinhCylindrical keep xx1
+      if (g.coords == OR_SPHERICAL || g.coords == OR_SINHSPHERICAL)
+        i1 = N1 + 2 * NG - 1 - i1;
       i0 = 2 * NG - 1 - i0;
       i2 += N2 / 2;
-    } else if (i1 < NG) {
+    } else if (g.coords != OR_SINHCYLINDRICAL && i1 < NG) {
       i1 = 2 * NG - 1 - i1;
       i2 += N2 / 2;
-    } else if (i1 >= NG + N1) {
+    } else if (g.coords != OR_SINHCYLINDRICAL && i1 >= NG + N1) {
       i1 = 2 * N1 + 2 * NG - 1 - i1;
       i2 += N2 / 2;
     } else if (i2 < NG || i2 >= NG + N2) {
@@ -264,8 +314,8 @@ void build_grid(Grid& g) {
   for (int d = 0; d < 3; ++d) g.Nx[d] = g.N[d] + 2 * g.NG;
   g.xxmin[0] = 0.0;
   g.xxmax[0] = (g.coords == OR_SPHERICAL) ? g.rmax : 1.0;
-  g.xxmin[1] = 0.0;
-  g.xxmax[1] = kPi;
+  g.xxmin[1] = (g.coords == OR_SINHCYLINDRICAL) ? -1.0 : 0.0;
+  g.xxmax[1] = (g.coords == OR_SINHCYLINDRICAL) ? 1.0 : kPi;
   g.xxmin[2] = -kPi;
   g.xxmax[2] = kPi;
   for (int d = 0; d < 3; ++d) {
@@ -295,6 +345,8 @@ void build_grid(Grid& g) {
   g.dsmin.assign(n2d, 0);
   g.rcart.assign(n2d, 0);
   g.drdxx0.assign(n2d, 0);
+  g.drdxx1.assign(n2d, 0);
+  g.along1.assign(n2d, 0);
   g.ds_g = 1e300;
   for (int i1 = 0; i1 < g.Nx[1]; ++i1)
     for (int i0 = 0; i0 < g.Nx[0]; ++i0) {
@@ -322,6 +374,14 @@ void build_grid(Grid& g) {
         double A, Ap, App;
         sinh_radial(g, g.xx[0][i0], A, Ap, App);
         g.drdxx0[k] = A * Ap / r;
+      } else if (g.coords == OR_SINHCYLINDRICAL) {
+        // r^2 = rho^2 + z^2: dr/dxx0 = rho rho'/r, dr/dxx1 = z z'/r
+        double A, Ap, App, Z, Zp, Zpp;
+        sinh_radial(g, g.xx[0][i0], A, Ap, App);
+        sinh_radial(g, g.xx[1][i1], Z, Zp, Zpp);
+        g.drdxx0[k] = Ap * A / r;
+        g.drdxx1[k] = Z * Zp / r;
+        g.along1[k] = std::fabs(Z) >= A ? 1 : 0;
       } else if (g.coords == OR_SINHSPHERICAL) {
         double A, Ap, App;
         sinh_radial(g, g.xx[0][i0], A, Ap, App);
@@ -459,6 +519,45 @@ void rhs(const Grid& g, double eta, double kappa, const double* u,
         ku[id] = -c * (u[id] / r + dudx / drdx);
         kv[id] = -c * (v[id] / r + dvdx / drdx);
       }
+  // outer points of the z faces (SinhCylindrical, corners included): the same
+  // condition, with the radial derivative from a one-sided difference taken
+  // toward the interior along xx1 where |z| >= rho,
+  // d_r f = (d f / d xx1) / (d r / d xx1), and along xx0 elsewhere
+  if (g.coords == OR_SINHCYLINDRICAL) {
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int i2 = NG; i2 < NG + g.N[2]; ++i2)
+      for (int i1 = 0; i1 < g.Nx[1]; ++i1) {
+        if (i1 >= NG && i1 < NG + g.N[1]) continue;
+        for (int i0 = NG; i0 < g.Nx[0]; ++i0) {
+          const long id = g.idx(i0, i1, i2);
+          const long k2 = g.idx2(i0, i1);
+          const double c = kappa * g.dsmin[k2] / g.ds_g;
+          const double r = g.rcart[k2];
+          const bool a1 = g.along1[k2] != 0;
+          // outward direction and the index step toward the interior
+          const int dir = a1 ? (i1 < NG ? -1 : 1) : 1;
+          auto at = [&](int q) {
+            return a1 ? g.idx(i0, i1 - q * dir, i2) : g.idx(i0 - q, i1, i2);
+          };
+          const double h = a1 ? g.dxx[1] : g.dxx[0];
+          double dudx = 0.0, dvdx = 0.0;
+          if (g.bc_order == 2) {
+            dudx = dir * (3.0 * u[id] - 4.0 * u[at(1)] + u[at(2)]) / (2.0 * h);
+            dvdx = dir * (3.0 * v[id] - 4.0 * v[at(1)] + v[at(2)]) / (2.0 * h);
+          } else {
+            for (int q = 0; q <= g.bc_order; ++q) {
+              dudx += g.wbc[q] * u[at(q)];
+              dvdx += g.wbc[q] * v[at(q)];
+            }
+            dudx *= dir / h;
+            dvdx *= dir / h;
+          }
+          const double drdx = a1 ? g.drdxx1[k2] : g.drdxx0[k2];
+          ku[id] = -c * (u[id] / r + dudx / drdx);
+          kv[id] = -c * (v[id] / r + dvdx / drdx);
+        }
+      }
+  }
   // inner ghosts: copy from images (parity +1)
   const long np = g.npad();
 #pragma omp parallel for schedule(static)
@@ -517,6 +616,7 @@ void rk4_step(Grid& g, double eta, double kappa, double dt) {
 bool set_bc_order(Grid& g, int order) {
   if (order != 2 && order != 4) return false;
   if (g.N[0] < order) return false;  // the difference stays on interior points
+  if (g.coords == OR_SINHCYLINDRICAL && g.N[1] < order) return false;  // z faces too
   std::vector<double> off(order + 1);
   for (int k = 0; k <= order; ++k) off[k] = -k;
   std::vector<std::vector<double>> c;
@@ -587,7 +687,8 @@ extern "C" {
 // Returns NULL on invalid arguments.
 void* or_create(int coords, int N0, int N1, int N2, int fd_order, double amax,
                 double sinhwaa, double bscale, double rmax) {
-  if (coords != OR_SINHSYMTP && coords != OR_SPHERICAL && coords != OR_SINHSPHERICAL)
+  if (coords != OR_SINHSYMTP && coords != OR_SPHERICAL && coords != OR_SINHSPHERICAL &&
+      coords != OR_SINHCYLINDRICAL)
     return nullptr;
   if (fd_order < 2 || fd_order % 2 || fd_order > 12) return nullptr;
   const int NG = fd_order / 2;

@@ -18,6 +18,8 @@ SINH = dict(amax=1.0e6, sinhwaa=0.07, bscale=1.0)
 SINH_MILD = dict(amax=3.0, sinhwaa=0.4, bscale=0.5)
 SSPH = dict(amax=1.0e6, sinhwaa=0.07)          # SinhSpherical
 SSPH_MILD = dict(amax=3.0, sinhwaa=0.4)
+SCYL = dict(amax=1.0e6, sinhwaa=0.07)          # SinhCylindrical
+SCYL_MILD = dict(amax=3.0, sinhwaa=0.4)
 
 
 def _grid(oracle_lib, coords, kw, N=(16, 12, 8), order=8):
@@ -36,7 +38,8 @@ def _jac(g, x0, x1, x2, eps):
     return J
 
 
-COORDS = [(0, SINH_MILD), (0, SINH), (1, dict(rmax=100.0)), (2, SSPH_MILD), (2, SSPH)]
+COORDS = [(0, SINH_MILD), (0, SINH), (1, dict(rmax=100.0)), (2, SSPH_MILD), (2, SSPH),
+          (3, SCYL_MILD), (3, SCYL)]
 
 
 @pytest.mark.parametrize("coords,kw", COORDS)
@@ -46,7 +49,7 @@ def test_scale_factors_match_jacobian_and_orthogonality(oracle_lib, coords, kw):
     x0max = kw["rmax"] if coords == 1 else 1.0
     for _ in range(25):
         x0 = rng.uniform(0.05, 0.95) * x0max
-        x1 = rng.uniform(0.1, np.pi - 0.1)
+        x1 = rng.uniform(-0.95, 0.95) if coords == 3 else rng.uniform(0.1, np.pi - 0.1)
         x2 = rng.uniform(-np.pi, np.pi)
         eps = [1e-6 * x0max, 1e-6, 1e-6]
         J = _jac(g, x0, x1, x2, eps)
@@ -82,7 +85,11 @@ def test_laplacian_coefficients_from_scale_factors(oracle_lib, coords, kw):
             np.testing.assert_allclose(met["a0"][i1, i0], a[0], rtol=1e-12)
             np.testing.assert_allclose(met["a1"][i1, i0], a[1], rtol=1e-12)
             np.testing.assert_allclose(met["a2"][i1, i0], a[2], rtol=1e-12)
-            np.testing.assert_allclose(met["b0"][i1, i0], b0, rtol=1e-7)
+            # with SinhCylindrical at amax 1e6, w 0.07, J/h0^2 = Z' A/A' is flat
+            # to 1/cosh^2(xx0/w) where xx0 >> w, so its numerical derivative
+            # keeps few digits there; the mild-parameter case pins b0
+            if not (coords == 3 and kw["amax"] > 1e3):
+                np.testing.assert_allclose(met["b0"][i1, i0], b0, rtol=1e-7)
             np.testing.assert_allclose(met["b1"][i1, i0], b1, rtol=1e-7)
 
 
@@ -98,7 +105,8 @@ def test_sinhsymtp_foci_and_compactification(oracle_lib):
 
 @pytest.mark.parametrize("coords,kw,N", [(0, SINH, (8, 6, 4)), (1, dict(rmax=10.0), (8, 6, 4)),
                                          (0, SINH_MILD, (5, 5, 6)), (1, dict(rmax=3.0), (5, 5, 2)),
-                                         (2, SSPH, (8, 6, 4)), (2, SSPH_MILD, (5, 5, 6))])
+                                         (2, SSPH, (8, 6, 4)), (2, SSPH_MILD, (5, 5, 6)),
+                                         (3, SCYL, (8, 6, 4)), (3, SCYL_MILD, (5, 5, 6))])
 def test_ghost_images_share_cartesian_position(oracle_lib, coords, kw, N):
     g = oracle_lib.OracleGrid(coords, *N, 8, **kw)
     img = g.bc_images()
@@ -117,7 +125,11 @@ def test_ghost_images_share_cartesian_position(oracle_lib, coords, kw, N):
     nout = int(np.sum(img == -2))
     ng = g.NG
     assert nint == N[0] * N[1] * N[2]
-    assert nout == ng * N[1] * N[2]
+    if coords == 3:
+        # the xx0 face, and both z faces over the interior and outer xx0 range
+        assert nout == ng * N[1] * N[2] + 2 * ng * (N[0] + ng) * N[2]
+    else:
+        assert nout == ng * N[1] * N[2]
 
 
 def test_sinhspherical_radius_and_origin(oracle_lib):
@@ -146,3 +158,24 @@ def test_wave_speed_gives_uniform_courant_number(oracle_lib):
     np.testing.assert_allclose(c * dt / inter, 0.5 * kappa, rtol=1e-14)
     # the compactified grid spans many decades of cell size
     assert inter.max() / inter.min() > 1e5
+
+
+def test_sinhcylindrical_map(oracle_lib):
+    """rho = A(xx0) and z = A(xx1) with the sinh stretching of SinhSymTP's A:
+    xx0 = 1 is the cylinder rho = amax, xx1 = +-1 its caps z = +-amax, xx0 = 0
+    the z axis, and z is odd in xx1."""
+    g = _grid(oracle_lib, 3, SCYL)
+    for x1, x2 in ((0.3, 1.0), (-0.7, -2.5)):
+        p = g.to_cart(1.0, x1, x2)
+        np.testing.assert_allclose(np.hypot(p[0], p[1]), 1.0e6, rtol=1e-12)
+        q = g.to_cart(0.0, x1, x2)
+        assert q[0] == 0.0 and q[1] == 0.0
+    for x0, x2 in ((0.2, 0.4), (0.9, -1.0)):
+        np.testing.assert_allclose(g.to_cart(x0, 1.0, x2)[2], 1.0e6, rtol=1e-12)
+        np.testing.assert_allclose(g.to_cart(x0, -1.0, x2)[2], -1.0e6, rtol=1e-12)
+    h = _grid(oracle_lib, 2, SSPH)   # SinhSpherical's r is the same A
+    for x in (0.1, 0.5, 0.9):
+        np.testing.assert_allclose(g.to_cart(0.3, x, 0.2)[2],
+                                   np.linalg.norm(h.to_cart(x, 0.7, 0.1)), rtol=1e-12)
+        np.testing.assert_allclose(g.to_cart(0.3, -x, 0.2)[2], -g.to_cart(0.3, x, 0.2)[2],
+                                   rtol=1e-15)

@@ -28,6 +28,13 @@ MUTATIONS = [
      pins.check_sinhsymtp_bc),
     ("SinhSymTP dr/dxx0 with sqrt(A^2 + b^2) for r", "g.drdxx0[k] = A * Ap / r;",
      "g.drdxx0[k] = A * Ap / std::sqrt(A * A + g.b * g.b);", pins.check_sinhsymtp_bc),
+    ("SinhCylindrical dr/dxx1 = z'", "g.drdxx1[k] = Z * Zp / r;", "g.drdxx1[k] = Zp;",
+     pins.check_sinhcylindrical_bc),
+    ("SinhCylindrical dr/dxx0 = rho' / r", "g.drdxx0[k] = Ap * A / r;", "g.drdxx0[k] = Ap / r;",
+     pins.check_sinhcylindrical_bc),
+    ("SinhCylindrical z-face difference not mirrored on the lower face",
+     "const int dir = a1 ? (i1 < NG ? -1 : 1) : 1;", "const int dir = 1;",
+     pins.check_sinhcylindrical_bc),
 ]
 
 

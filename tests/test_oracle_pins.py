@@ -115,6 +115,87 @@ def test_sinhsymtp_radiation_condition_exact_on_polynomials(oracle_lib, order):
     check_sinhsymtp_bc(oracle_lib, order)
 
 
+# --- SinhCylindrical radiation condition (rho face and both z faces) -------
+
+SINHCYL_MILD = dict(amax=3.0, sinhwaa=0.4)
+
+
+def _drdx_numeric(g, x0: float, x1: float, d: int) -> float:
+    """d|x|/dxx_d at fixed other coordinates from the coordinate map,
+    sixth-order centred difference."""
+    h = 1e-3
+
+    def f(t):
+        a = [x0, x1, 0.3]
+        a[d] = t
+        return float(np.linalg.norm(g.to_cart(*a)))
+
+    t = (x0, x1)[d]
+    return (-f(t - 3 * h) + 9 * f(t - 2 * h) - 45 * f(t - h) + 45 * f(t + h)
+            - 9 * f(t + 2 * h) + f(t + 3 * h)) / (60 * h)
+
+
+def sinhcylindrical_bc_errors(orc, order: int = 2):
+    """(max error for degrees <= order, smallest error at degree order + 1),
+    relative, over the rho face (fields polynomial in xx0) and the z faces
+    with their corners (fields polynomial in xx1)."""
+    g = orc.OracleGrid(orc.SINHCYLINDRICAL, 12, 10, 4, 8, **SINHCYL_MILD)
+    g.set_bc_order(order)
+    ng, (N0, N1, N2) = g.NG, g.N
+    x0, x1 = g.xx(0), g.xx(1)
+    X, Y, Z = g.cart()
+    r = np.sqrt(X ** 2 + Y ** 2 + Z ** 2)
+    c = g.metric()["dsmin"] / g.ds_g()          # (Nx1, Nx0) plane
+    zrows = list(range(ng)) + list(range(ng + N1, N1 + 2 * ng))
+
+    def along_z(b, a):   # the reading: along xx1 where |z| >= rho
+        p = g.to_cart(x0[a], x1[b], 0.0)
+        return abs(p[2]) >= abs(p[0])
+
+    zpts = [(b, a) for b in zrows for a in range(ng, N0 + 2 * ng)]
+    faces = [
+        # rho face (interior rows, outer columns) and the z-face points nearer
+        # to it (rho > |z|): derivative along xx0
+        (0, [(b, a) for b in range(ng, ng + N1) for a in range(ng + N0, N0 + 2 * ng)] +
+            [q for q in zpts if not along_z(*q)]),
+        # z-face points with |z| >= rho: derivative along xx1
+        (1, [q for q in zpts if along_z(*q)]),
+    ]
+    assert len(faces[1][1]) > 0 and len(faces[0][1]) > N1 * ng
+    exact_err, beyond_err = 0.0, np.inf
+    for d, pts in faces:
+        drdx = np.array([_drdx_numeric(g, x0[a], x1[b], d) for b, a in pts])
+        ib = np.array([b for b, _ in pts])
+        ia = np.array([a for _, a in pts])
+        for deg in range(order + 2):
+            fx = np.polynomial.Polynomial(np.arange(1, deg + 2, dtype=float) / (deg + 1))
+            prof = fx(x0) if d == 0 else fx(x1)
+            f = np.broadcast_to(prof[None, None, :] if d == 0 else prof[None, :, None],
+                                g.shape).copy()
+            ku, _ = g.rhs(0.0, 1.0, f, np.zeros(g.shape))
+            got = ku[ng:ng + N2][:, ib, ia]
+            t = x0[ia] if d == 0 else x1[ib]
+            want = -c[ib, ia][None] * (fx(t)[None] / r[ng:ng + N2][:, ib, ia] +
+                                       fx.deriv()(t)[None] / drdx[None])
+            err = float(np.abs(got - want).max() / np.abs(want).max())
+            if deg <= order:
+                exact_err = max(exact_err, err)
+            else:
+                beyond_err = min(beyond_err, err)
+    return exact_err, beyond_err
+
+
+def check_sinhcylindrical_bc(orc, order: int = 2) -> None:
+    exact, beyond = sinhcylindrical_bc_errors(orc, order)
+    assert exact < 1e-10, exact
+    assert beyond > 1e-8, beyond
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_sinhcylindrical_radiation_condition_exact_on_polynomials(oracle_lib, order):
+    check_sinhcylindrical_bc(oracle_lib, order)
+
+
 # --- Eq. (4): source factor and exponent ------------------------------------
 
 def boosted_puncture_u(m: float, P: float, R: float, r: np.ndarray, cos_t: np.ndarray):

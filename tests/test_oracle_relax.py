@@ -124,9 +124,11 @@ def _newton_steady_state(g, eta, kappa):
     return stored, x, np.abs(F(x)).max()
 
 
-@pytest.mark.parametrize("shape,order", [((8, 4, 2), 4), ((6, 4, 4), 8)])
-def test_relaxation_converges_to_newton_solution(oracle_lib, shape, order):
-    g = oracle_lib.OracleGrid(0, *shape, order, **TINY)
+@pytest.mark.parametrize("coords,shape,order", [(0, (8, 4, 2), 4), (0, (6, 4, 4), 8),
+                                                (3, (6, 6, 2), 4), (3, (4, 4, 2), 8)])
+def test_relaxation_converges_to_newton_solution(oracle_lib, coords, shape, order):
+    # coords 3 (SinhCylindrical) adds the z faces' outer points to the unknowns
+    g = oracle_lib.OracleGrid(coords, *shape, order, **TINY)
     m = [0.5, 0.5]
     x = [[0, 0, 1.0], [0, 0, -1.0]]
     P = [[0, 0.2, 0], [0, -0.2, 0]]
@@ -135,7 +137,14 @@ def test_relaxation_converges_to_newton_solution(oracle_lib, shape, order):
     eta, kappa = 4.0, 1.0
     stored, ustar, fres = _newton_steady_state(g, eta, kappa)
     assert fres < 1e-9
-    st, n, hist = g.relax(eta, kappa, g.suggest_dt(0.5), 400000, 1e-13, 500)
+    # the stop test sees only the interior residual; the outer points settle
+    # later (SinhCylindrical's z-face points next to the axis much later: at an
+    # interior residual of 1e-14 they are still 3e-7 off), so relax below 1e-14,
+    # and SinhCylindrical for a fixed 160000 steps (then 2e-16 off)
+    if coords == 3:
+        st, n, hist = g.relax(eta, kappa, g.suggest_dt(0.5), 160000, 0.0, 10000)
+    else:
+        st, n, hist = g.relax(eta, kappa, g.suggest_dt(0.5), 400000, 1e-14, 500)
     assert st == 0, hist[-5:]
     u, v = g.state()
     u = u.reshape(-1)
@@ -143,7 +152,11 @@ def test_relaxation_converges_to_newton_solution(oracle_lib, shape, order):
     # in the steady state v = eta u
     np.testing.assert_allclose(v.reshape(-1)[stored], eta * u[stored], rtol=0,
                                atol=1e-9 * np.abs(ustar).max())
-    assert ustar.min() > 0
+    # a positive source keeps the interior solution positive (maximum
+    # principle); the outer points' one-sided extrapolation on these very
+    # coarse grids need not be
+    ninter = int(np.sum(g.bc_images() == -1))
+    assert ustar[:ninter].min() > 0
 
 
 def test_small_momentum_scaling(oracle_lib):
