@@ -25,8 +25,10 @@
  *     doubles, index i0 + N0*(i1 + N1*i2) (x0 fastest). "Extended" arrays
  *     also hold the NG outer-boundary points beyond xx0's maximum:
  *     (N0+NG)*N1*N2 doubles, index i0 + (N0+NG)*(i1 + N1*i2). NG = fd_order/2.
- *     All other ghost points are images of stored points (parity +1) and are
- *     never stored.
+ *     SinhCylindrical grids also hold the NG outer rows beyond each z face:
+ *     (N0+NG)*(N1+2NG)*N2 doubles, index i0 + (N0+NG)*(i1 + NG + (N1+2NG)*i2)
+ *     for i1 in [-NG, N1+NG). All other ghost points are images of stored
+ *     points (parity +1) and are never stored.
  *   * Host pointers are only read or written during the call; the caller
  *     keeps ownership. Device memory is owned by the caller (hr_grid_bind).
  */
@@ -54,7 +56,10 @@ typedef enum {
 typedef enum {
   HR_SINHSYMTP = 0,    /* prolate-spheroidal, sinh-stretched radial coordinate */
   HR_SPHERICAL = 1,    /* uniform r in [0, rmax], theta, phi */
-  HR_SINHSPHERICAL = 2 /* r = amax sinh(xx0/w)/sinh(1/w), xx0 in [0,1], theta, phi */
+  HR_SINHSPHERICAL = 2, /* r = amax sinh(xx0/w)/sinh(1/w), xx0 in [0,1], theta, phi */
+  HR_SINHCYLINDRICAL = 3 /* rho = A(xx0), z = A(xx1), xx1 in [-1,1], phi; the
+                            same sinh stretching A for rho and z; both z faces
+                            are outer boundaries */
 } hr_coords;
 
 typedef enum {
@@ -91,12 +96,16 @@ void hr_default_params(hr_grid_params* p);
  * Creates a grid (host side only; no device memory yet): the setup steps of
  * Algorithm 1 that sample the coordinates xx^i and precompute the reference
  * metric (here the Laplacian factors of Eq. 4 per (xx0, xx1), the wave speed
- * and the outer-boundary geometry), on the SinhSymTP or Spherical-like grids
- * of the "Basic equations" section.
- *   coords   HR_SINHSYMTP, HR_SPHERICAL or HR_SINHSPHERICAL
- *   N0,N1,N2 interior points along xx0, xx1 (theta), xx2 (phi);
- *            N0 >= NG, N1 >= NG, N2 even and >= 2 (phi + pi parity images),
- *            total stored points below 2^31.
+ * and the outer-boundary geometry), on the SinhSymTP grids of the "Basic
+ * equations" section or the spherical-like and cylindrical-like families the
+ * conclusions name.
+ *   coords   HR_SINHSYMTP, HR_SPHERICAL, HR_SINHSPHERICAL or HR_SINHCYLINDRICAL
+ *   N0,N1,N2 interior points along xx0, xx1 (theta, or z for SinhCylindrical),
+ *            xx2 (phi); N0 >= NG, N1 >= NG, N2 even and >= 2 (phi + pi parity
+ *            images), total stored points below 2^31. SinhCylindrical also
+ *            stores NG outer rows beyond each z face, so its extended layout
+ *            (hr_get_u) is (N0 + NG) x (N1 + 2 NG) x N2; the warm-start
+ *            network does not take these grids.
  *   fd_order centred finite-difference order: 2, 4, 6, 8 or 10
  *   p        coordinate parameters, NULL for defaults (copied)
  *   out      receives the handle; free it with hr_grid_destroy.
@@ -163,6 +172,10 @@ typedef struct {
   double* history;
   long history_cap;
   long n_history;     /* checks done (may exceed history_cap) */
+  long resident_fallbacks;  /* check intervals (or the final unchecked tail)
+                               rerun on the stage kernels because a resident
+                               launch's exchange wait timed out; the call then
+                               continues on the stage kernels */
 } hr_relax_report;
 
 /*
@@ -180,6 +193,8 @@ typedef struct {
  * Residuals are always computed in FP64 (FP32 states are promoted).
  * Returns HR_OK, HR_ENOTCONV (tol > 0 not reached), HR_ENONFINITE,
  * HR_EINVAL, HR_ESTATE or HR_EDEVICE. Blocks until the last residual readback.
+ * A resident launch whose exchange wait times out is undone and its interval
+ * rerun on the stage kernels (see hr_set_wait_limit).
  */
 hr_status hr_relax(hr_grid* g, double eta, double c, double dt, long n_steps,
                    double tol, int check_every, hr_precision prec,
@@ -239,10 +254,20 @@ hr_status hr_get_v(const hr_grid* g, double* host_out, size_t n);
  * with a caller-given state (warm start, resume; u = v = 0 is what
  * hr_set_punctures leaves). n = extended count sets every stored point; n =
  * interior count sets the interior and fills each outer point by the 1/r
- * continuation f(i0) = f(N0-1) r(N0-1)/r(i0). Synchronous. Errors: HR_EINVAL
+ * continuation f(i0) = f(N0-1) r(N0-1)/r(i0) (SinhCylindrical's z-face rows
+ * then continue the nearest interior row the same way along xx1).
+ * Synchronous. Errors: HR_EINVAL
  * (null pointer, other n), HR_ESTATE (not bound), HR_EDEVICE. */
 hr_status hr_set_u(hr_grid* g, const double* host_in, size_t n);
 hr_status hr_set_v(hr_grid* g, const double* host_in, size_t n);
+
+/* Sets v = eta u at every stored point of the FP64 state: the relation that
+ * the steady state of Eq. (5) obeys for damping eta (u_t = v - eta u = 0).
+ * Lets a relaxation continue with another damping factor from a state relaxed
+ * with the first (e.g. after a heavily damped smoothing phase of a warm
+ * start), u unchanged. Synchronous. Errors: HR_EINVAL (null grid, eta not
+ * finite and > 0), HR_ESTATE (not bound), HR_EDEVICE. */
+hr_status hr_reset_v(hr_grid* g, double eta);
 
 /* L2 norm of the Hamiltonian-constraint residual of the current state, in
  * FP64: by default the grid norm over points, sqrt(sum_interior H^2 /
@@ -350,11 +375,16 @@ hr_status hr_set_factor_storage(hr_grid* g, int bits);
 /*
  * Bound on the resident kernel's exchange waits: a block gives up after this
  * many polls of one partner's stage counter (each poll is one memory round
- * trip, ~1-2 us), sets an error word, and every block leaves its loop; the
- * relaxing call then returns HR_EDEVICE and the grid's state is unspecified
- * until it is set again (hr_set_punctures, hr_set_u/v). polls = 0 restores the
- * default, 2^19 (about a second). Small values force the timeout path.
- * Errors: HR_EINVAL.
+ * trip, ~1-2 us), sets an error word, and every block leaves its loop. A
+ * timeout means the device could not hold every block at once (other work
+ * occupied compute units). hr_relax and hr_relax_noalloc then restore the
+ * state of the interval's start (copied before every resident launch) and
+ * rerun the interval on the stage kernels, which the rest of the call uses
+ * (counted in hr_relax_report.resident_fallbacks); the timing utilities
+ * (hr_time_stage_kernels, hr_autotune) return HR_EDEVICE; hr_batch_relax
+ * returns HR_EDEVICE and the resident grids' states are unspecified until set
+ * again (hr_set_punctures, hr_set_u/v). polls = 0 restores the default, 2^19
+ * (about a second). Small values force the timeout path. Errors: HR_EINVAL.
  */
 hr_status hr_set_wait_limit(hr_grid* g, unsigned polls);
 

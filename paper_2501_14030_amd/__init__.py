@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_PKG, "libhrelax.so")
 SINHSYMTP = 0
 SPHERICAL = 1
 SINHSPHERICAL = 2
+SINHCYLINDRICAL = 3
 
 FP64 = 0
 FP32 = 1
@@ -64,7 +65,7 @@ class RelaxReport(ctypes.Structure):
     _fields_ = [("steps_taken", ctypes.c_long), ("fp32_steps", ctypes.c_long),
                 ("residual", ctypes.c_double), ("dt_used", ctypes.c_double),
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_long),
-                ("n_history", ctypes.c_long)]
+                ("n_history", ctypes.c_long), ("resident_fallbacks", ctypes.c_long)]
 
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -91,6 +92,7 @@ _SIGNATURES = {
                                         ctypes.c_int, ctypes.POINTER(RelaxReport)]),
     "hr_set_fp32_switch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int,
                                           ctypes.c_long]),
+    "hr_reset_v": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
     "hr_get_u": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_size_t]),
     "hr_get_v": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_size_t]),
     "hr_set_u": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_size_t]),
@@ -183,6 +185,7 @@ class RelaxResult:
     residual: float
     dt: float
     history: np.ndarray
+    resident_fallbacks: int = 0
 
 
 class Grid:
@@ -259,7 +262,7 @@ class Grid:
         if st not in (OK, ENOTCONV, ENONFINITE) or (raise_on_error and st == ENONFINITE):
             _check(st, "hr_relax")
         return RelaxResult(st, rep.steps_taken, rep.fp32_steps, rep.residual, rep.dt_used,
-                           hist[:min(rep.n_history, cap)].copy())
+                           hist[:min(rep.n_history, cap)].copy(), rep.resident_fallbacks)
 
     def relax_noalloc(self, eta: float, c: float = 1.0, dt: float = 0.0, n_steps: int = 1000,
                       tol: float = 0.0, check_every: int = 100,
@@ -277,7 +280,7 @@ class Grid:
         if st not in (OK, ENOTCONV, ENONFINITE) or (raise_on_error and st == ENONFINITE):
             _check(st, "hr_relax_noalloc")
         return RelaxResult(st, rep.steps_taken, rep.fp32_steps, rep.residual, rep.dt_used,
-                           hist[:min(rep.n_history, cap)].copy())
+                           hist[:min(rep.n_history, cap)].copy(), rep.resident_fallbacks)
 
     def set_fp32_switch(self, switch_residual: float = 0.0, stall_checks: int = 8,
                         max_fp32_steps: int = 0) -> None:
@@ -285,12 +288,20 @@ class Grid:
                                                  int(stall_checks), int(max_fp32_steps)),
                "hr_set_fp32_switch")
 
+    def reset_v(self, eta: float) -> None:
+        """hr_reset_v: v = eta u at every stored point."""
+        _check(load_library().hr_reset_v(self._h, float(eta)), "hr_reset_v")
+
     def _get(self, fn, extended: bool) -> np.ndarray:
         n = self.n_extended if extended else self.n_interior
         out = np.zeros(n)
         _check(fn(self._h, out.ctypes.data_as(_dp), n), fn.__name__)
         N0, N1, N2 = self.N
-        return out.reshape(N2, N1, N0 + self.NG if extended else N0)
+        if not extended:
+            return out.reshape(N2, N1, N0)
+        # SinhCylindrical stores NG outer rows beyond each z face
+        rows = N1 + 2 * self.NG if self.coords == SINHCYLINDRICAL else N1
+        return out.reshape(N2, rows, N0 + self.NG)
 
     def get_u(self, extended: bool = False) -> np.ndarray:
         return self._get(load_library().hr_get_u, extended)
@@ -495,4 +506,4 @@ def residual_l2(grid: Grid) -> float:
 
 __all__ = ["Grid", "Batch", "GridParams", "RelaxResult", "HRError", "grid_create", "set_punctures",
            "relax", "relax_noalloc", "get_u", "residual_l2", "load_library", "default_params",
-           "SINHSYMTP", "SPHERICAL", "SINHSPHERICAL", "FP64", "FP32", "FP32_FP64FINISH"]
+           "SINHSYMTP", "SPHERICAL", "SINHSPHERICAL", "SINHCYLINDRICAL", "FP64", "FP32", "FP32_FP64FINISH"]

@@ -109,7 +109,16 @@ hr_status load_kappa(hr_grid* g, double kappa) {
     ofac[o2d + k] = g->tab.orinv[k];
     ofac[2 * (size_t)o2d + k] = g->tab.oq[k];
   }
+  const int z2d = d.P0 * 2 * d.zo;
+  std::vector<double> zfac(4 * (size_t)z2d);
+  for (int k = 0; k < z2d; ++k) {
+    zfac[k] = kappa * g->tab.zcrat[k];
+    zfac[z2d + k] = g->tab.zrinv[k];
+    zfac[2 * (size_t)z2d + k] = g->tab.zq[k];
+    zfac[3 * (size_t)z2d + k] = g->tab.zstep[k];   // small integers: exact in FP32
+  }
   std::vector<float> fac32(fac.begin(), fac.end()), ofac32(ofac.begin(), ofac.end());
+  std::vector<float> zfac32(zfac.begin(), zfac.end());
   // bfloat16 copy: the high 16 bits of each FP32 factor, rounded to nearest
   // even (the factors are finite)
   std::vector<unsigned short> facb(fac32.size());
@@ -129,6 +138,12 @@ hr_status load_kappa(hr_grid* g, double kappa) {
                         hipMemcpyHostToDevice, g->stream));
   HR_HIPK(hipMemcpyAsync(g->f32.ofac, ofac32.data(), ofac32.size() * sizeof(float),
                         hipMemcpyHostToDevice, g->stream));
+  if (z2d > 0) {
+    HR_HIPK(hipMemcpyAsync(g->f64.zfac, zfac.data(), zfac.size() * sizeof(double),
+                          hipMemcpyHostToDevice, g->stream));
+    HR_HIPK(hipMemcpyAsync(g->f32.zfac, zfac32.data(), zfac32.size() * sizeof(float),
+                          hipMemcpyHostToDevice, g->stream));
+  }
   HR_HIPK(hipStreamSynchronize(g->stream));
   g->kappa_loaded = kappa;
   return HR_OK;
@@ -165,7 +180,8 @@ size_t layout(hr_grid* g, char* base) {
     return p;
   };
   const size_t G = g->G;
-  const int n2d = g->d.N0 * g->d.N1, o2d = g->d.NG * g->d.N1, e2d = g->d.P0 * g->d.N1;
+  const int n2d = g->d.N0 * g->d.N1, o2d = g->d.NG * g->d.N1, e2d = g->d.P0 * g->d.R1;
+  const int z2d = g->d.P0 * 2 * g->d.zo;
   double** d64[] = {&g->f64.un, &g->f64.vn, &g->f64.ua, &g->f64.va, &g->f64.ub,
                     &g->f64.vb, &g->f64.au, &g->f64.av, &g->f64.psi, &g->f64.ssrc};
   for (double** p : d64) *p = (double*)take(G * sizeof(double));
@@ -178,6 +194,8 @@ size_t layout(hr_grid* g, char* base) {
   g->f32.facb = (unsigned short*)take(6 * (size_t)n2d * sizeof(unsigned short));
   g->f64.facb = nullptr;
   g->f64.ofac = (double*)take(3 * (size_t)o2d * sizeof(double));
+  g->f64.zfac = z2d ? (double*)take(4 * (size_t)z2d * sizeof(double)) : nullptr;
+  g->f32.zfac = z2d ? (float*)take(4 * (size_t)z2d * sizeof(float)) : nullptr;
   g->f32.ofac = (float*)take(3 * (size_t)o2d * sizeof(float));
   g->rho = (double*)take(e2d * sizeof(double));
   g->zc = (double*)take(e2d * sizeof(double));
@@ -328,26 +346,55 @@ hr_status collect_timing(hr_grid* g) {
   return HR_OK;
 }
 
-// Reads the resident kernel's error word (synchronous); a timed-out exchange
-// wait leaves the state unchanged from the launch's start and is reported.
-hr_status check_resident(hr_grid* g) {
+// Reads the resident kernel's error word (synchronous) into *timed_out and
+// clears it; the caller restores the state and reruns on the stage kernels.
+hr_status check_resident(hr_grid* g, bool* timed_out) {
   unsigned e = 0;
   HR_HIP(hipMemcpyAsync(&e, g->res_err, sizeof(unsigned), hipMemcpyDeviceToHost, g->stream));
   HR_HIP(hipStreamSynchronize(g->stream));
   hr_status st = collect_timing(g);
   if (st != HR_OK) return st;
+  *timed_out = e != 0;
   if (e) {
-    HR_HIP(hipMemsetAsync(g->res_err, 0, sizeof(unsigned), g->stream));
+    HR_HIP(launch_fill(reinterpret_cast<float*>(g->res_err), 0.0f, 1, g->stream));
     HR_HIP(hipStreamSynchronize(g->stream));
-    return fail(HR_EDEVICE, "resident kernel: an exchange wait timed out");
   }
+  return HR_OK;
+}
+
+// For the timing utilities: a timed-out wait makes the measurement void.
+hr_status check_resident_timing(hr_grid* g) {
+  bool timed_out = false;
+  hr_status st = check_resident(g, &timed_out);
+  if (st != HR_OK) return st;
+  if (timed_out) return fail(HR_EDEVICE, "resident kernel: an exchange wait timed out");
+  return HR_OK;
+}
+
+// The FP64 state (u, v) copied to the FP64 accumulator fields, which no
+// resident launch uses (its accumulator lives in registers; the split form's
+// increments are FP32 and its base is rebuilt from u, v): the state to go back
+// to when a resident launch's exchange wait times out, since blocks that
+// did not wait may already have written their part of the new state.
+hr_status snapshot_state(hr_grid* g) {
+  HR_HIP(launch_scale(g->f64.au, g->f64.un, 1.0, (int)g->G, g->stream));
+  HR_HIP(launch_scale(g->f64.av, g->f64.vn, 1.0, (int)g->G, g->stream));
+  return HR_OK;
+}
+
+// Back to the snapshot; resident launches off for the rest of the call.
+hr_status restore_state(hr_grid* g) {
+  HR_HIP(launch_scale(g->f64.un, g->f64.au, 1.0, (int)g->G, g->stream));
+  HR_HIP(launch_scale(g->f64.vn, g->f64.av, 1.0, (int)g->G, g->stream));
+  g->res_off = true;
+  g->res_fallbacks++;
   return HR_OK;
 }
 
 bool use_resident(const hr_grid* g) {
   int variant = 0, chunk = 0;
   resolve_variant(g, variant, chunk);
-  return variant == 3;
+  return variant == 3 && !g->res_off;
 }
 
 bool use_resident_split(const hr_grid* g) { return use_resident(g) && resident_split_ok(g); }
@@ -412,7 +459,7 @@ hr_status residual_of(hr_grid* g, const void* u, bool fp32, double* out) {
   return HR_OK;
 }
 
-int ext_count(const hr_grid* g) { return g->d.P0 * g->d.N1 * g->d.N2; }
+int ext_count(const hr_grid* g) { return g->d.P0 * g->d.R1 * g->d.N2; }
 
 hr_status check_ready(const hr_grid* g, bool need_sources) {
   if (!g) return fail(HR_EINVAL, "null grid handle");
@@ -439,8 +486,7 @@ hr_status get_field(const hr_grid* g, const double* dev, double* host, size_t n)
     const Dims& d = g->d;
     for (int i2 = 0; i2 < d.N2; ++i2)
       for (int i1 = 0; i1 < d.N1; ++i1)
-        std::memcpy(host + (size_t)d.N0 * (i1 + (size_t)d.N1 * i2),
-                    tmp.data() + (size_t)d.P0 * (i1 + (size_t)d.N1 * i2),
+        std::memcpy(host + (size_t)d.N0 * (i1 + (size_t)d.N1 * i2), tmp.data() + sidx(d, 0, i1, i2),
                     d.N0 * sizeof(double));
   }
   return HR_OK;
@@ -461,13 +507,25 @@ hr_status set_field(hr_grid* g, double* dev, const double* host, size_t n) {
     for (int i2 = 0; i2 < d.N2; ++i2)
       for (int i1 = 0; i1 < d.N1; ++i1) {
         const size_t ri = (size_t)d.N0 * (i1 + (size_t)d.N1 * i2);
-        const size_t re = (size_t)d.P0 * (i1 + (size_t)d.N1 * i2);
+        const size_t re = sidx(d, 0, i1, i2);
+        const size_t te = (size_t)d.P0 * (i1 + d.zo);   // row in the 2D tables
         std::memcpy(tmp.data() + re, host + ri, d.N0 * sizeof(double));
         const double flast = host[ri + d.N0 - 1];
-        const double rlast = g->tab.rcart[(d.N0 - 1) + (size_t)d.P0 * i1];
+        const double rlast = g->tab.rcart[(d.N0 - 1) + te];
         for (int q = 0; q < d.NG; ++q) {
-          const double ro = g->tab.rcart[(d.N0 + q) + (size_t)d.P0 * i1];
+          const double ro = g->tab.rcart[(d.N0 + q) + te];
           tmp[re + d.N0 + q] = flast * rlast / ro;
+        }
+      }
+    // z-face rows (SinhCylindrical): the nearest interior row, continued as 1/r
+    for (int i2 = 0; i2 < d.N2; ++i2)
+      for (int i1 = -d.zo; i1 < d.N1 + d.zo; ++i1) {
+        if (i1 >= 0 && i1 < d.N1) continue;
+        const int edge = i1 < 0 ? 0 : d.N1 - 1;
+        for (int i0 = 0; i0 < d.P0; ++i0) {
+          const double re = g->tab.rcart[i0 + (size_t)d.P0 * (edge + d.zo)];
+          const double ro = g->tab.rcart[i0 + (size_t)d.P0 * (i1 + d.zo)];
+          tmp[sidx(d, i0, i1, i2)] = tmp[sidx(d, i0, edge, i2)] * re / ro;
         }
       }
   }
@@ -511,6 +569,7 @@ BaseArgs base_args(const hr_grid* g, double eta) {
   b.eu = g->f32.un;
   b.ev = g->f32.vn;
   b.bc4 = g->bc_order == 4 ? 1 : 0;
+  b.zfac = g->f64.zfac;
   return b;
 }
 
@@ -542,7 +601,12 @@ hr_status run_interval(hr_grid* g, int kind, int K, double eta, double dt, doubl
   int variant = 0, chunk = 0;
   resolve_variant(g, variant, chunk);
   const int streaming = g->streaming > 0 ? 1 : 0;
-  const bool resident = variant == 3 && (kind == 0 || (kind == 2 && resident_split_ok(g)));
+  const bool resident =
+      variant == 3 && !g->res_off && (kind == 0 || (kind == 2 && resident_split_ok(g)));
+  if (resident) {
+    hr_status st = snapshot_state(g);
+    if (st != HR_OK) return st;
+  }
   if (g->graph != 0 && !resident) {
     const bool same = g->gexec && g->g_kind == kind && g->g_K == K && g->g_eta == eta &&
                       g->g_dt == dt && g->g_kappa == g->kappa_loaded && g->g_variant == variant &&
@@ -598,10 +662,14 @@ hr_status run_interval(hr_grid* g, int kind, int K, double eta, double dt, doubl
   hr_status stt = collect_timing(g);
   if (stt != HR_OK) return stt;
   if (resident && *err_word) {
+    // an exchange wait timed out (the device could not hold every block at
+    // once): back to the interval's start and the interval again on the
+    // stage kernels, which the rest of the call then uses
     *err_word = 0;
-    HR_HIP(hipMemsetAsync(g->res_err, 0, sizeof(unsigned), g->stream));
-    HR_HIP(hipStreamSynchronize(g->stream));
-    return fail(HR_EDEVICE, "resident kernel: an exchange wait timed out");
+    HR_HIP(launch_fill(reinterpret_cast<float*>(g->res_err), 0.0f, 1, g->stream));
+    hr_status st = restore_state(g);
+    if (st != HR_OK) return st;
+    return run_interval(g, kind, K, eta, dt, res);
   }
   return HR_OK;
 }
@@ -621,11 +689,20 @@ hr_status run_phase(hr_grid* g, const Fields<T>& F, bool fp32, double eta, doubl
     const long chunk = std::min<long>(K, max_steps - s);
     if (chunk != K) {
       // a shorter tail is run without a check
-      hr_status st = launch_steps<T>(g, F, (T)eta, (T)dt, chunk);
+      const bool res = !fp32 && use_resident(g);
+      hr_status st = res ? snapshot_state(g) : HR_OK;
       if (st != HR_OK) return st;
-      if (!fp32 && use_resident(g)) {
-        st = check_resident(g);
+      st = launch_steps<T>(g, F, (T)eta, (T)dt, chunk);
+      if (st != HR_OK) return st;
+      if (res) {
+        bool timed_out = false;
+        st = check_resident(g, &timed_out);
         if (st != HR_OK) return st;
+        if (timed_out) {   // again on the stage kernels, from the tail's start
+          st = restore_state(g);
+          if (st == HR_OK) st = launch_steps<T>(g, F, (T)eta, (T)dt, chunk);
+          if (st != HR_OK) return st;
+        }
       }
       s += chunk;
       break;
@@ -688,13 +765,26 @@ hr_status run_split_phase(hr_grid* g, double eta, double dt, long max_steps, dou
     const long chunk = std::min<long>(K, max_steps - s);
     if (chunk != K) {
       // a shorter tail is run without a check
-      HR_HIP(launch_base(g->fd_order, b, g->stream));
-      hr_status st = launch_steps<float>(g, g->f32, (float)eta, (float)dt, chunk, true);
-      if (st != HR_OK) return st;
-      HR_HIP(launch_rebase(g->f64.un, g->f64.vn, g->f32.un, g->f32.vn, G, g->stream));
-      if (use_resident_split(g)) {
-        st = check_resident(g);
+      auto tail = [&]() -> hr_status {
+        HR_HIP(launch_base(g->fd_order, b, g->stream));
+        hr_status st = launch_steps<float>(g, g->f32, (float)eta, (float)dt, chunk, true);
         if (st != HR_OK) return st;
+        HR_HIP(launch_rebase(g->f64.un, g->f64.vn, g->f32.un, g->f32.vn, G, g->stream));
+        return HR_OK;
+      };
+      const bool res = use_resident_split(g);
+      hr_status st = res ? snapshot_state(g) : HR_OK;
+      if (st == HR_OK) st = tail();
+      if (st != HR_OK) return st;
+      if (res) {
+        bool timed_out = false;
+        st = check_resident(g, &timed_out);
+        if (st != HR_OK) return st;
+        if (timed_out) {   // again on the stage kernels, from the tail's start
+          st = restore_state(g);
+          if (st == HR_OK) st = tail();
+          if (st != HR_OK) return st;
+        }
       }
       s += chunk;
       break;
@@ -842,6 +932,9 @@ hr_status relax_args_ok(const hr_grid* g, double eta, double c, double dt, long 
   return HR_OK;
 }
 
+hr_status relax_phases(hr_grid* g, double eta, double dt, long n_steps, double tol,
+                       int check_every, hr_precision prec, hr_relax_report* rep);
+
 // The relaxation driver (Algorithm 1's outer loop) on checked arguments.
 hr_status relax_impl(hr_grid* g, double eta, double c, double dt, long n_steps, double tol,
                      int check_every, hr_precision prec, hr_relax_report* rep) {
@@ -855,7 +948,20 @@ hr_status relax_impl(hr_grid* g, double eta, double c, double dt, long n_steps, 
     rep->residual = NAN;
     rep->dt_used = dt;
     rep->n_history = 0;
+    rep->resident_fallbacks = 0;
   }
+  g->res_off = false;
+  g->res_fallbacks = 0;
+  st = relax_phases(g, eta, dt, n_steps, tol, check_every, prec, rep);
+  g->res_off = false;
+  if (rep) rep->resident_fallbacks = g->res_fallbacks;
+  return st;
+}
+
+// The precision phases of one hr_relax call (see relax_impl).
+hr_status relax_phases(hr_grid* g, double eta, double dt, long n_steps, double tol,
+                       int check_every, hr_precision prec, hr_relax_report* rep) {
+  hr_status st = HR_OK;
   const int G = (int)g->G;
   long done = 0, total = 0, f32steps = 0;
   int why = 0;
@@ -914,14 +1020,16 @@ hr_status hr_grid_create(hr_coords coords, int N0, int N1, int N2, int fd_order,
                          const hr_grid_params* p, hr_grid** out) {
   if (!out) return fail(HR_EINVAL, "null output handle pointer");
   *out = nullptr;
-  if (coords != HR_SINHSYMTP && coords != HR_SPHERICAL && coords != HR_SINHSPHERICAL)
+  if (coords != HR_SINHSYMTP && coords != HR_SPHERICAL && coords != HR_SINHSPHERICAL &&
+      coords != HR_SINHCYLINDRICAL)
     return fail(HR_EINVAL, "unknown coordinate system");
   if (fd_order != 2 && fd_order != 4 && fd_order != 6 && fd_order != 8 && fd_order != 10)
     return fail(HR_EINVAL, "fd_order must be 2, 4, 6, 8 or 10");
   const int NG = fd_order / 2;
   if (N0 < NG || N0 < 2 || N1 < NG || N2 < 2 || (N2 % 2) != 0)
     return fail(HR_EINVAL, "need N0 >= max(NG,2), N1 >= NG, N2 even and >= 2");
-  const long long next = (long long)(N0 + NG) * N1 * N2;
+  const int zo = coords == HR_SINHCYLINDRICAL ? NG : 0;
+  const long long next = (long long)(N0 + NG) * (N1 + 2 * zo) * N2;
   if (next >= (1LL << 31) - 4096) return fail(HR_EINVAL, "grid too large");
   hr_grid_params prm;
   hr_default_params(&prm);
@@ -931,6 +1039,8 @@ hr_status hr_grid_create(hr_coords coords, int N0, int N1, int N2, int fd_order,
   if (coords == HR_SPHERICAL && !(prm.rmax > 0)) return fail(HR_EINVAL, "rmax must be > 0");
   if (coords == HR_SINHSPHERICAL && !(prm.amax > 0 && prm.sinhwaa > 0))
     return fail(HR_EINVAL, "SinhSpherical needs amax, sinhwaa > 0");
+  if (coords == HR_SINHCYLINDRICAL && !(prm.amax > 0 && prm.sinhwaa > 0))
+    return fail(HR_EINVAL, "SinhCylindrical needs amax, sinhwaa > 0");
   if (!(prm.cfl > 0)) return fail(HR_EINVAL, "cfl must be > 0");
   hr_grid* g = new (std::nothrow) hr_grid();
   if (!g) return fail(HR_ENOMEM, "host allocation failed");
@@ -944,7 +1054,10 @@ hr_status hr_grid_create(hr_coords coords, int N0, int N1, int N2, int fd_order,
   g->d.P0 = N0 + NG;
   g->d.nint = N0 * N1 * N2;
   g->d.nout = NG * N1 * N2;
-  g->d.sph = coords == HR_SINHSYMTP ? 0 : 1;  // spherical families: xx0 image mirrors theta
+  // spherical families: the xx0 image mirrors theta
+  g->d.sph = coords == HR_SPHERICAL || coords == HR_SINHSPHERICAL ? 1 : 0;
+  g->d.zo = zo;
+  g->d.R1 = N1 + 2 * zo;
   g->G = align_up((size_t)next, 64);
   g->nblk_res = residual_blocks(g->d);
   g->res[0].ry = 8;
@@ -1014,7 +1127,7 @@ hr_status hr_grid_bind(hr_grid* g, void* dev_ptr, size_t bytes, void* hip_stream
   layout(g, (char*)dev_ptr);
   g->bound = true;
   const Dims& d = g->d;
-  const int e2d = d.P0 * d.N1;
+  const int e2d = d.P0 * d.R1;
   HR_HIP(hipMemcpyAsync(g->rho, g->tab.rho.data(), e2d * sizeof(double),
                         hipMemcpyHostToDevice, g->stream));
   HR_HIP(hipMemcpyAsync(g->zc, g->tab.zc.data(), e2d * sizeof(double), hipMemcpyHostToDevice,
@@ -1139,6 +1252,16 @@ hr_status hr_relax_noalloc(hr_grid* g, double eta, double c, double dt, long n_s
   return st;
 }
 
+hr_status hr_reset_v(hr_grid* g, double eta) {
+  hr_status st = check_ready(g, false);
+  if (st != HR_OK) return st;
+  if (!(eta > 0) || !std::isfinite(eta)) return fail(HR_EINVAL, "eta must be finite and > 0");
+  HR_HIP(hipSetDevice(g->device));
+  HR_HIP(launch_scale(g->f64.vn, g->f64.un, eta, (int)g->G, g->stream));
+  HR_HIP(hipStreamSynchronize(g->stream));
+  return HR_OK;
+}
+
 hr_status hr_get_u(const hr_grid* g, double* host_out, size_t n) {
   return get_field(g, g ? g->f64.un : nullptr, host_out, n);
 }
@@ -1215,7 +1338,7 @@ hr_status hr_time_stage_kernels(hr_grid* g, double eta, double c, double dt, lon
       float ms = 0.f;
       HR_HIP(hipEventElapsedTime(&ms, e0, e1));
       for (int s = 0; s < 4; ++s) sum[s] = ms * (double)n_steps / (4.0 * nrun);
-      st = check_resident(g);
+      st = check_resident_timing(g);
       if (st != HR_OK) return st;
     } else {
       for (long n = 0; n < n_steps; ++n)
@@ -1249,7 +1372,7 @@ hr_status hr_time_stage_kernels(hr_grid* g, double eta, double c, double dt, lon
     HR_HIP(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    st = check_resident(g);
+    st = check_resident_timing(g);
     if (st != HR_OK) return st;
     for (int s = 0; s < 5; ++s) avg_us[s] = 1e3 * ms / (4.0 * nrun);
     return HR_OK;
@@ -1342,7 +1465,7 @@ hr_status hr_set_residual_norm(hr_grid* g, hr_norm norm, double radius) {
     for (int i1 = 0; i1 < d.N1; ++i1)
       for (int i0 = 0; i0 < d.N0; ++i0) {
         const int k = i0 + d.N0 * i1;
-        if (!(g->tab.rcart[i0 + d.P0 * i1] < radius)) w[k] = 0.0;
+        if (!(g->tab.rcart[i0 + d.P0 * (i1 + d.zo)] < radius)) w[k] = 0.0;
         tot += w[k] * d.N2;
       }
     if (!(tot > 0.0)) return fail(HR_EINVAL, "no interior cell centre lies within the radius");
@@ -1364,6 +1487,8 @@ hr_status hr_set_outer_bc_order(hr_grid* g, int order) {
   if (order != 2 && order != 4) return fail(HR_EINVAL, "outer boundary order must be 2 or 4");
   if (order > g->d.N0)
     return fail(HR_EINVAL, "the one-sided difference needs N0 >= its order");
+  if (g->d.zo && order > g->d.N1)
+    return fail(HR_EINVAL, "on the z faces the one-sided difference needs N1 >= its order");
   g->bc_order = order;
   return HR_OK;
 }
@@ -1461,7 +1586,7 @@ hr_status hr_autotune(hr_grid* g, hr_precision prec, int n_steps, hr_kernel_conf
         rs = hip_fail(e, "autotune timing");
         break;
       }
-      rs = check_resident(g);
+      rs = check_resident_timing(g);
       if (rs != HR_OK) break;
       const double us = 1e3 * ms / (4.0 * n_steps);
       if (us < best_t) {

@@ -172,15 +172,18 @@ hr_status capture(hr_batch* b, int mode, int K) {
   auto ok = [&](hipError_t x) {
     if (e == hipSuccess && x != hipSuccess) e = x;
   };
-  if (mode & 1) ok(launch_batch_base(b->order, b->ba, b->itbase, b->counts + 3, b->nblk_tile, b->stream));
+  bool zf = false;   // a grid with stored z-face rows (SinhCylindrical)
+  for (const hr_grid* g : b->g) zf = zf || g->d.zo > 0;
+  if (mode & 1)
+    ok(launch_batch_base(b->order, zf, b->ba, b->itbase, b->counts + 3, b->nblk_tile, b->stream));
   for (int k = 0; k < K; ++k)
     for (int s = 1; s <= 4; ++s) {
       if (mode & 4)
-        ok(launch_batch_stage(b->order, s, true, b->sa32, b->it32, b->counts + 1, b->nblk_tile,
-                              b->stream));
+        ok(launch_batch_stage(b->order, s, true, zf, b->sa32, b->it32, b->counts + 1,
+                              b->nblk_tile, b->stream));
       if (mode & 2)
-        ok(launch_batch_stage(b->order, s, false, b->sa64, b->it64, b->counts + 0, b->nblk_tile,
-                              b->stream));
+        ok(launch_batch_stage(b->order, s, false, zf, b->sa64, b->it64, b->counts + 0,
+                              b->nblk_tile, b->stream));
     }
   for (const hr_batch::ResGroup& rg : b->groups) {
     if (rg.split)
@@ -191,8 +194,8 @@ hr_status capture(hr_batch* b, int mode, int K) {
                                b->stream));
   }
   if (mode & 1) ok(launch_batch_rebase(b->rb, b->itreb, b->counts + 4, b->nblk_flat, b->stream));
-  ok(launch_batch_residual(b->order, b->ra, b->itres, b->counts + 2, b->partial, b->nblk_tile,
-                           b->stream));
+  ok(launch_batch_residual(b->order, zf, b->ra, b->itres, b->counts + 2, b->partial,
+                           b->nblk_tile, b->stream));
   ok(launch_batch_finalize(b->ranges, b->partial, b->out, b->n, b->stream));
   hipGraph_t graph = nullptr;
   const hipError_t ee = hipStreamEndCapture(b->stream, &graph);
@@ -503,6 +506,7 @@ hr_status hr_batch_relax(hr_batch* b, const double* eta, const double* c, long n
     ba.eu = g->f32.un;
     ba.ev = g->f32.vn;
     ba.bc4 = g->bc_order == 4 ? 1 : 0;
+    ba.zfac = g->f64.zfac;
     hba[i] = ba;
     hrb[i] = RebaseArgs{g->f64.un, g->f64.vn, g->f32.un, g->f32.vn, (int)g->G};
     if (reps) {
@@ -511,6 +515,7 @@ hr_status hr_batch_relax(hr_batch* b, const double* eta, const double* c, long n
       reps[i].residual = NAN;
       reps[i].dt_used = dt;
       reps[i].n_history = 0;
+      reps[i].resident_fallbacks = 0;
     }
   }
   HR_HIPB(hipMemcpyAsync(b->sa64, h64.data(), h64.size() * sizeof(h64[0]), hipMemcpyHostToDevice, b->stream));

@@ -11,7 +11,10 @@
 //   Spherical  rho = r sin xx1, z = r cos xx1, r = xx0 in [0, rmax];
 //   SinhSpherical  the same with r = A(xx0), xx0 in [0,1] (one of the further
 //              coordinate families the paper's conclusions name);
-// with xx1 in [0,pi] and xx2 = phi in [-pi,pi], cell-centred.
+// with xx1 in [0,pi] and xx2 = phi in [-pi,pi], cell-centred;
+//   SinhCylindrical  (the cylindrical-like family of the conclusions)
+//              rho = A(xx0), z = A(xx1) with xx1 in [-1,1], phi = xx2; both z
+//              faces are outer boundaries with NG stored rows each.
 //
 // Both metrics are diagonal, so with scale factors h_i and J = h0 h1 h2
 //   lap f = sum_i  f,ii / h_i^2 + (1/J) d_i (J / h_i^2) f,i .
@@ -37,6 +40,7 @@ struct Local {
   double b0, b1;       // (1/J) d_i (J / h_i^2), i = 0, 1 (the phi term vanishes)
   double rho, z;       // cylindrical position at phi = 0
   double drdx0;        // d r_cartesian / d xx0 along the coordinate line
+  double drdx1;        // d r_cartesian / d xx1 (SinhCylindrical's z faces)
 };
 
 Local local_sinhsymtp(const hr_grid_params& p, double x0, double x1) {
@@ -63,6 +67,7 @@ Local local_sinhsymtp(const hr_grid_params& p, double x0, double x1) {
   L.z = std::sqrt(R2) * cs;
   const double r = std::sqrt(L.rho * L.rho + L.z * L.z);
   L.drdx0 = A * dA / r;  // r^2 = A^2 + b^2 cos^2 xx1
+  L.drdx1 = 0.0;
   return L;
 }
 
@@ -88,6 +93,40 @@ Local local_sinhspherical(const hr_grid_params& p, double x0, double x1) {
   L.rho = A * sn;
   L.z = A * cs;
   L.drdx0 = dA;
+  L.drdx1 = 0.0;
+  return L;
+}
+
+// SinhCylindrical: rho = A(xx0), z = A(xx1), both with SinhSymTP's sinh
+// stretching; scale factors (A'(xx0), A'(xx1), rho), J = A'(xx0) A'(xx1) rho:
+//   (1/J) d_0 (J / h0^2) = (A'^2 - A A'') / (A'^3 A)  at xx0,
+//   (1/J) d_1 (J / h1^2) = -Z'' / Z'^3                at xx1 (Z = A(xx1)),
+// where A'^2 - A A'' = (amax / (w sinh(1/w)))^2 exactly (the difference of
+// the two terms would lose most digits where xx0 >> w).
+Local local_sinhcylindrical(const hr_grid_params& p, double x0, double x1) {
+  const double w = p.sinhwaa;
+  const double norm = std::sinh(1.0 / w);
+  const double A = p.amax * std::sinh(x0 / w) / norm;
+  const double dA = p.amax * std::cosh(x0 / w) / (w * norm);
+  const double d2A = A / (w * w);
+  const double Z = p.amax * std::sinh(x1 / w) / norm;
+  const double dZ = p.amax * std::cosh(x1 / w) / (w * norm);
+  const double d2Z = Z / (w * w);
+  Local L;
+  L.h0 = dA;
+  L.h1 = dZ;
+  L.h2 = A;
+  L.a0 = 1.0 / (dA * dA);
+  L.a1 = 1.0 / (dZ * dZ);
+  L.a2 = 1.0 / (A * A);
+  const double kk = p.amax / (w * norm);
+  L.b0 = kk * kk / (dA * dA * dA * A);
+  L.b1 = -d2Z / (dZ * dZ * dZ);
+  L.rho = A;
+  L.z = Z;
+  const double r = std::sqrt(A * A + Z * Z);
+  L.drdx0 = A * dA / r;
+  L.drdx1 = Z * dZ / r;
   return L;
 }
 
@@ -105,6 +144,7 @@ Local local_spherical(double x0, double x1) {
   L.rho = r * sn;
   L.z = r * cs;
   L.drdx0 = 1.0;
+  L.drdx1 = 0.0;
   return L;
 }
 
@@ -112,15 +152,17 @@ Local local_spherical(double x0, double x1) {
 
 bool build_tables(hr_coords coords, const Dims& d, const hr_grid_params& p,
                   HostTables& t, std::string& err) {
+  const bool cyl = coords == HR_SINHCYLINDRICAL;
   const double x0max = (coords == HR_SPHERICAL) ? p.rmax : 1.0;
-  const double dx[3] = {x0max / d.N0, kPi / d.N1, 2.0 * kPi / d.N2};
+  const double dx[3] = {x0max / d.N0, (cyl ? 2.0 : kPi) / d.N1, 2.0 * kPi / d.N2};
   auto coord = [&](int dir, int j) {  // j = stored index (0 = first interior)
-    const double lo = (dir == 2) ? -kPi : 0.0;
+    const double lo = (dir == 2) ? -kPi : (dir == 1 && cyl) ? -1.0 : 0.0;
     return lo + (j + 0.5) * dx[dir];
   };
   auto local = [&](int i0, int i1) {
     if (coords == HR_SINHSYMTP) return local_sinhsymtp(p, coord(0, i0), coord(1, i1));
     if (coords == HR_SINHSPHERICAL) return local_sinhspherical(p, coord(0, i0), coord(1, i1));
+    if (cyl) return local_sinhcylindrical(p, coord(0, i0), coord(1, i1));
     return local_spherical(coord(0, i0), coord(1, i1));
   };
   auto dsmin = [&](const Local& L) {
@@ -129,12 +171,16 @@ bool build_tables(hr_coords coords, const Dims& d, const hr_grid_params& p,
     s = std::fmin(s, std::fabs(L.h2) * dx[2]);
     return s;
   };
-  const int n2d = d.N0 * d.N1, o2d = d.NG * d.N1, e2d = d.P0 * d.N1;
+  const int n2d = d.N0 * d.N1, o2d = d.NG * d.N1, e2d = d.P0 * d.R1, z2d = d.P0 * 2 * d.zo;
   t.alpha.assign(5 * (size_t)n2d, 0.0);
   t.crat.assign(n2d, 0.0);
   t.ocrat.assign(o2d, 0.0);
   t.orinv.assign(o2d, 0.0);
   t.oq.assign(o2d, 0.0);
+  t.zcrat.assign(z2d, 0.0);
+  t.zrinv.assign(z2d, 0.0);
+  t.zq.assign(z2d, 0.0);
+  t.zstep.assign(z2d, 0.0);
   t.rho.assign(e2d, 0.0);
   t.zc.assign(e2d, 0.0);
   t.rcart.assign(e2d, 0.0);
@@ -145,15 +191,30 @@ bool build_tables(hr_coords coords, const Dims& d, const hr_grid_params& p,
 
   std::vector<double> ds(e2d);
   double dsg = INFINITY;
-  for (int i1 = 0; i1 < d.N1; ++i1)
+  for (int i1 = -d.zo; i1 < d.N1 + d.zo; ++i1)
     for (int i0 = 0; i0 < d.P0; ++i0) {
       const Local L = local(i0, i1);
-      const int e = i0 + d.P0 * i1;
+      const int e = i0 + d.P0 * (i1 + d.zo);
       ds[e] = dsmin(L);
       t.rho[e] = L.rho;
       t.zc[e] = L.z;
       t.rcart[e] = std::sqrt(L.rho * L.rho + L.z * L.z);
-      if (i0 < d.N0) {
+      if (i1 < 0 || i1 >= d.N1) {
+        // an outer row of a z face: lower rows first, then upper ones. The
+        // radiation condition's one-sided difference runs along xx1 where
+        // |z| >= rho, else along xx0 (only corner points beyond the rho face
+        // qualify), so the direction is within 45 degrees of the radial one
+        const int zr = i1 < 0 ? i1 + d.zo : d.zo + (i1 - d.N1);
+        const int k = i0 + d.P0 * zr;
+        t.zrinv[k] = 1.0 / t.rcart[e];
+        if (std::fabs(L.z) >= L.rho) {
+          t.zq[k] = (i1 < 0 ? -1.0 : 1.0) / (2.0 * dx[1] * L.drdx1);
+          t.zstep[k] = i1 < 0 ? d.P0 : -d.P0;
+        } else {
+          t.zq[k] = 1.0 / (2.0 * dx[0] * L.drdx0);
+          t.zstep[k] = -1.0;
+        }
+      } else if (i0 < d.N0) {
         const int k = i0 + d.N0 * i1;
         t.alpha[0 * (size_t)n2d + k] = L.a0 / (dx[0] * dx[0]);
         t.alpha[1 * (size_t)n2d + k] = L.a1 / (dx[1] * dx[1]);
@@ -176,10 +237,12 @@ bool build_tables(hr_coords coords, const Dims& d, const hr_grid_params& p,
   t.ds_g = dsg;
   t.volw = t.vol;
   t.volw_total = t.vol_total;
-  for (int i1 = 0; i1 < d.N1; ++i1)
+  for (int i1 = -d.zo; i1 < d.N1 + d.zo; ++i1)
     for (int i0 = 0; i0 < d.P0; ++i0) {
-      const int e = i0 + d.P0 * i1;
-      if (i0 < d.N0)
+      const int e = i0 + d.P0 * (i1 + d.zo);
+      if (i1 < 0 || i1 >= d.N1)
+        t.zcrat[i0 + d.P0 * (i1 < 0 ? i1 + d.zo : d.zo + (i1 - d.N1))] = ds[e] / dsg;
+      else if (i0 < d.N0)
         t.crat[i0 + d.N0 * i1] = ds[e] / dsg;
       else
         t.ocrat[(i0 - d.N0) + d.NG * i1] = ds[e] / dsg;
@@ -206,6 +269,9 @@ bool resident_plan(const Dims& d, int ry, std::vector<int>& waits, int& nbx, int
   constexpr int RB = kResPatch;
   nbx = nby = 0;
   if (ry != 8 && ry != 4) return false;
+  // stored outer rows on the x1 faces (SinhCylindrical) are not handled by the
+  // resident kernel: such grids run on the stage kernels
+  if (d.zo) return false;
   if (d.N0 % RB || d.N1 % ry || d.NG > RB || d.N2 > 16 || d.N2 < 2) return false;
   const int bx_n = d.N0 / RB, by_n = d.N1 / ry, nb = bx_n * by_n;
   if (nb > kResMaxBlocks) return false;

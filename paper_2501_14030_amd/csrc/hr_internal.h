@@ -38,6 +38,10 @@ struct Fields {
   T* ssrc;  // (1/8) A_ij A^ij
   T* fac;   // 6 planes of N0*N1: alpha0, alpha1, alpha2, beta0, beta1, c^2
   T* ofac;  // 3 planes of NG*N1: c, 1/r, 1/(2 dxx0 dr/dxx0)
+  T* zfac;  // SinhCylindrical z faces, 4 planes of P0*2NG (lower rows, then
+            // upper): c, 1/r, q = +-1/(2 dxx dr/dxx) of the point's difference
+            // direction (sign: outward), and the index step to the next point
+            // toward the interior (+-P0 along xx1, -1 along xx0)
   // split-state single-precision form (FP32 set only): slopes of the FP64 base
   // state, base p = psi_s + u_base and S_src p^-7
   T* khu;
@@ -57,7 +61,16 @@ struct Dims {
   int nint;        // N0*N1*N2
   int nout;        // NG*N1*N2
   int sph;         // 1 for Spherical (x0 reflection also flips theta)
+  int zo;          // stored outer rows on each x1 face: NG for SinhCylindrical
+                   // (its z faces are outer boundaries), else 0
+  int R1;          // stored rows per plane, N1 + 2 zo
 };
+
+// Flat index of the stored point (i0, i1, i2): i0 in [0, P0), i1 in
+// [-zo, N1 + zo), i2 in [0, N2).
+__host__ __device__ __forceinline__ unsigned sidx(const Dims& d, int i0, int i1, int i2) {
+  return (unsigned)i0 + (unsigned)d.P0 * ((unsigned)(i1 + d.zo) + (unsigned)d.R1 * (unsigned)i2);
+}
 
 // Stage kernel arguments (RK4 stage s of 4, classic Butcher tableau).
 template <typename T>
@@ -89,6 +102,7 @@ struct StageArgs {
   const T* khv;
   int bc4;        // fourth-order one-sided difference in the radiation condition
   const unsigned short* facb;  // bfloat16 factor planes (replace fac when set)
+  const T* zfac;  // z-face planes (SinhCylindrical, d.zo > 0)
 };
 
 // Base-state slopes for the split-state form (FP64 in, FP32 out).
@@ -108,6 +122,7 @@ struct BaseArgs {
   float* eu;   // increment state, zeroed
   float* ev;
   int bc4;     // fourth-order one-sided difference in the radiation condition
+  const double* zfac;  // z-face planes (SinhCylindrical)
 };
 
 struct ResidualArgs {
@@ -155,15 +170,17 @@ hipError_t launch_base(int order, const BaseArgs& a, hipStream_t s);
 // x1 tile, phi chunk); residual and base items (grid, x0 tile, x1 tile,
 // plane); rebase items (grid, element block). descs of the stage launcher
 // are StageArgs<float> (split form) or StageArgs<double>, four per grid.
-hipError_t launch_batch_stage(int order, int stage, bool fp32_split, const void* descs,
-                              const int4* items, const int* nitems, int nblocks_persistent,
-                              hipStream_t s);
-hipError_t launch_batch_residual(int order, const ResidualArgs* descs, const int4* items,
-                                 const int* nitems, double* partial, int nblocks_persistent,
-                                 hipStream_t s);
+// zfaces: some grid of the batch stores outer rows on its x1 faces
+// (SinhCylindrical); the kernels then run the instances that handle them.
+hipError_t launch_batch_stage(int order, int stage, bool fp32_split, bool zfaces,
+                              const void* descs, const int4* items, const int* nitems,
+                              int nblocks_persistent, hipStream_t s);
+hipError_t launch_batch_residual(int order, bool zfaces, const ResidualArgs* descs,
+                                 const int4* items, const int* nitems, double* partial,
+                                 int nblocks_persistent, hipStream_t s);
 hipError_t launch_batch_finalize(const int4* ranges, const double* partial, double* out,
                                  int ngrids, hipStream_t s);
-hipError_t launch_batch_base(int order, const BaseArgs* descs, const int4* items,
+hipError_t launch_batch_base(int order, bool zfaces, const BaseArgs* descs, const int4* items,
                              const int* nitems, int nblocks_persistent, hipStream_t s);
 hipError_t launch_batch_rebase(const RebaseArgs* descs, const int2* items, const int* nitems,
                                int nblocks_persistent, hipStream_t s);
@@ -171,6 +188,8 @@ hipError_t launch_batch_rebase(const RebaseArgs* descs, const int2* items, const
 hipError_t launch_rebase(double* ub, double* vb, const float* eu, const float* ev, int n,
                          hipStream_t s);
 hipError_t launch_fill(double* dst, double value, int n, hipStream_t s);
+// dst = a * src over n values.
+hipError_t launch_scale(double* dst, const double* src, double a, int n, hipStream_t s);
 hipError_t launch_fill(float* dst, float value, int n, hipStream_t s);
 
 // Resident RK4 kernel (hr_resident.hip): one launch runs nsteps
@@ -265,9 +284,14 @@ struct HostTables {
   std::vector<double> ocrat;   // NG*N1: ds_min/ds_g at outer (i0,i1)
   std::vector<double> orinv;   // NG*N1: 1/r
   std::vector<double> oq;      // NG*N1: 1/(2 dxx0 dr/dxx0)
-  std::vector<double> rho;     // P0*N1: cylindrical radius at phi = 0
-  std::vector<double> zc;      // P0*N1: z
-  std::vector<double> rcart;   // P0*N1: Cartesian radius
+  std::vector<double> zcrat;   // P0*2NG (SinhCylindrical z faces): ds_min/ds_g
+  std::vector<double> zrinv;   // P0*2NG: 1/r
+  std::vector<double> zq;      // P0*2NG: +-1/(2 dxx dr/dxx), outward sign
+  std::vector<double> zstep;   // P0*2NG: index step toward the interior: +-P0
+                               // (along xx1, where |z| >= rho), -1 (along xx0)
+  std::vector<double> rho;     // P0*R1: cylindrical radius at phi = 0
+  std::vector<double> zc;      // P0*R1: z
+  std::vector<double> rcart;   // P0*R1: Cartesian radius
   std::vector<double> cphi;    // N2
   std::vector<double> sphi;    // N2
   std::vector<double> vol;     // N0*N1: cell volume |h0 h1 h2| dxx0 dxx1 dxx2 (any plane)
@@ -330,6 +354,9 @@ struct hr_grid {
     int blocks() const { return nbx * nby; }
   } res[2];
   unsigned res_wait_limit = 1u << 19;  // polls of one partner counter before giving up
+  bool res_off = false;         // resident launches off for the rest of this hr_relax call
+                                // (a resident launch's exchange wait timed out)
+  long res_fallbacks = 0;       // intervals rerun on the stage kernels in this call
   unsigned* res_flags = nullptr;  // stage counters, sized for the larger partition
   unsigned* res_err = nullptr;
   int streaming = -1;           // non-temporal field access: -1 auto (by size), 0, 1
@@ -391,6 +418,7 @@ StageArgs<T> stage_args(const hr_grid* g, const Fields<T>& F, int stage, T eta, 
   a.khv = F.khv;
   a.fac = F.fac;
   a.ofac = F.ofac;
+  a.zfac = F.zfac;
   a.eta = eta;
   a.bc4 = g->bc_order == 4 ? 1 : 0;
   a.facb = g->factors16 ? F.facb : nullptr;

@@ -49,6 +49,20 @@ struct TileShape {
   static constexpr int H = TY + 2 * NG;
 };
 
+// Stored-row geometry seen by a kernel instance: instances built with
+// ZF = false serve grids without stored outer rows on the x1 faces (zo = 0,
+// R1 = N1 as compile-time facts, so those kernels are unchanged by them); ZF =
+// true instances serve SinhCylindrical grids.
+template <bool ZF>
+__device__ __forceinline__ int zo_of(const Dims& d) { return ZF ? d.zo : 0; }
+template <bool ZF>
+__device__ __forceinline__ int rows_of(const Dims& d) { return ZF ? d.R1 : d.N1; }
+template <bool ZF>
+__device__ __forceinline__ unsigned sidx_t(const Dims& d, int i0, int i1, int i2) {
+  return (unsigned)i0 +
+         (unsigned)d.P0 * ((unsigned)(i1 + zo_of<ZF>(d)) + (unsigned)rows_of<ZF>(d) * (unsigned)i2);
+}
+
 // Loads and stores of fields that are touched once per point and stage. With
 // NT (large grids) they bypass cache retention so that L2 keeps the u planes
 // the stencil re-reads; small grids keep everything cached between launches.
@@ -91,12 +105,12 @@ __device__ __forceinline__ TileId xcd_tile() {
 }
 
 // Stage the rim-extended patch of plane i2 of field U into tile (type C).
-template <int NG, typename C, typename S>
+template <int NG, typename C, typename S, bool ZF = false>
 __device__ __forceinline__ void load_tile(C* __restrict__ tile, const S* __restrict__ U,
                                           const Dims& d, int x0b, int x1b, int i2) {
   constexpr int W = TileShape<NG>::W, H = TileShape<NG>::H;
   const int tid = threadIdx.x + TX * threadIdx.y;
-  const unsigned plane = (unsigned)d.P0 * (unsigned)d.N1;
+  const unsigned plane = (unsigned)d.P0 * (unsigned)rows_of<ZF>(d);
   const unsigned b0 = plane * (unsigned)i2;
   const unsigned bh = plane * (unsigned)half_turn(i2, d.N2);
   for (int e = tid; e < W * H; e += kTileThreads) {
@@ -105,15 +119,16 @@ __device__ __forceinline__ void load_tile(C* __restrict__ tile, const S* __restr
     const int j0 = x0b + l0 - NG;
     const int j1 = x1b + l1 - NG;
     C val = (C)0;
-    if (j1 >= 0 && j1 < d.N1) {
+    // stored rows: the interior ones and, with zo_of<ZF>(d), the z faces' outer rows
+    if (j1 >= -zo_of<ZF>(d) && j1 < d.N1 + zo_of<ZF>(d)) {
       if (j0 >= 0) {
-        if (j0 < d.P0) val = (C)U[b0 + (unsigned)j0 + (unsigned)d.P0 * (unsigned)j1];
+        if (j0 < d.P0) val = (C)U[b0 + (unsigned)j0 + (unsigned)d.P0 * (unsigned)(j1 + zo_of<ZF>(d))];
       } else {  // reflection through xx0 = 0
         const int r1 = d.sph ? d.N1 - 1 - j1 : j1;
-        val = (C)U[bh + (unsigned)(-1 - j0) + (unsigned)d.P0 * (unsigned)r1];
+        val = (C)U[bh + (unsigned)(-1 - j0) + (unsigned)d.P0 * (unsigned)(r1 + zo_of<ZF>(d))];
       }
     } else if (j0 >= 0 && j0 < d.P0 && j1 >= -NG && j1 < d.N1 + NG) {
-      // reflection through theta = 0 or theta = pi
+      // reflection through theta = 0 or theta = pi (no stored outer rows here)
       const int r1 = j1 < 0 ? -1 - j1 : 2 * d.N1 - 1 - j1;
       val = (C)U[bh + (unsigned)j0 + (unsigned)d.P0 * (unsigned)r1];
     }
@@ -133,10 +148,11 @@ struct Sums {
 template <int NG, typename C, typename S>
 struct PhiTaps {
   C p[NG], m[NG];
+  template <bool ZF = false>
   __device__ __forceinline__ void load(const S* __restrict__ U, const Dims& d, int i0, int i1,
                                        int i2) {
-    const unsigned col = (unsigned)i0 + (unsigned)d.P0 * (unsigned)i1;
-    const unsigned plane = (unsigned)d.P0 * (unsigned)d.N1;
+    const unsigned col = (unsigned)i0 + (unsigned)d.P0 * (unsigned)(i1 + zo_of<ZF>(d));
+    const unsigned plane = (unsigned)d.P0 * (unsigned)rows_of<ZF>(d);
     // planes i2 + k and i2 - k (mod N2), stepped one at a time
     int jp = i2, jm = i2;
 #pragma unroll
@@ -226,12 +242,65 @@ __device__ __forceinline__ void combine(const StageArgs<T>& a, unsigned idx,
   }
 }
 
+// Stage update at an outer point of a z face (SinhCylindrical: stored rows
+// i1 in [-zo, 0) and [N1, N1 + zo), any stored i0): the radiation condition
+// k_f = -c (f/r + d_r f) with d_r f a one-sided difference toward the
+// interior divided by d r / d xx of its direction (along xx1 where
+// |z| >= rho, else along xx0; the table holds the index step and q with the
+// outward sign folded in), then the stage combine. Reads only the stage
+// input.
+template <int STAGE, bool NT, bool CORR, typename T>
+__device__ __forceinline__ void zface_point(const StageArgs<T>& a, int i0, int i1, int i2) {
+  const Dims& d = a.d;
+  const int zr = i1 < 0 ? i1 + d.zo : d.zo + (i1 - d.N1);
+  const unsigned z2d = (unsigned)d.P0 * 2u * (unsigned)d.zo;
+  const unsigned kz = (unsigned)i0 + (unsigned)d.P0 * (unsigned)zr;
+  const T c = a.zfac[kz], rinv = a.zfac[z2d + kz], qd = a.zfac[2 * z2d + kz];
+  const int in = (int)a.zfac[3 * z2d + kz];   // one point toward the interior
+  const unsigned o = sidx(d, i0, i1, i2);
+  const T* U = a.uin + o;
+  const T* V = a.vin + o;
+  const bool bc4 = a.bc4 != 0;
+  const T u0 = U[0], u1 = U[in], u2 = U[2 * in];
+  const T v0 = V[0], v1 = V[in], v2 = V[2 * in];
+  const T u3 = bc4 ? U[3 * in] : (T)0, u4 = bc4 ? U[4 * in] : (T)0;
+  const T v3 = bc4 ? V[3 * in] : (T)0, v4 = bc4 ? V[4 * in] : (T)0;
+  CombineIn<STAGE, NT, T> co;
+  co.load(a, o);
+  T kuo = -c * (u0 * rinv + outer_diff(u0, u1, u2, u3, u4, qd, bc4));
+  T kvo = -c * (v0 * rinv + outer_diff(v0, v1, v2, v3, v4, qd, bc4));
+  if constexpr (CORR) {
+    kuo = a.khu[o] + kuo;
+    kvo = a.khv[o] + kvo;
+  }
+  combine<STAGE, NT, T>(a, o, co, u0, v0, kuo, kvo);
+}
+
+// The z-face outer points of a block's x0 range in plane i2: the first x1
+// tile takes the lower rows, the last one the upper rows, one row per thread
+// row ty < zo; threads among the last NG interior columns also take the outer
+// column i0 + NG (the corners).
+template <int STAGE, bool NT, bool CORR, typename T>
+__device__ __forceinline__ void zface_rows(const StageArgs<T>& a, int x0b, int by, int i2) {
+  const Dims& d = a.d;
+  if (!d.zo || (int)threadIdx.y >= d.zo) return;
+  const int nby = (d.N1 + TY - 1) / TY;
+  const int i0 = x0b + (int)threadIdx.x;
+  if (i0 >= d.N0) return;
+  for (int side = 0; side < 2; ++side) {
+    if (side == 0 ? by != 0 : by != nby - 1) continue;
+    const int i1 = side == 0 ? (int)threadIdx.y - d.zo : d.N1 + (int)threadIdx.y;
+    zface_point<STAGE, NT, CORR, T>(a, i0, i1, i2);
+    if (i0 >= d.N0 - d.NG) zface_point<STAGE, NT, CORR, T>(a, i0 + d.NG, i1, i2);
+  }
+}
+
 // One RK4 stage: RHS + boundary conditions + stage combine. Grid:
 // (ceil(N0/TX), ceil(N1/TY), N2). Each interior point is one thread; the
 // threads with i0 in [N0-NG, N0) also update the outer point i0 + NG of their
 // row. Every global load of the interior point is issued before the tile
 // barrier so that the point waits for one memory round trip.
-template <typename T, int NG, int STAGE, bool NT, bool CORR>
+template <typename T, int NG, int STAGE, bool NT, bool CORR, bool ZF>
 __global__ void __launch_bounds__(kTileThreads) k_stage(StageArgs<T> a) {
   constexpr int W = TileShape<NG>::W, H = TileShape<NG>::H;
   __shared__ T tile[W * H];
@@ -244,13 +313,13 @@ __global__ void __launch_bounds__(kTileThreads) k_stage(StageArgs<T> a) {
   const bool active = i0 < d.N0 && i1 < d.N1;
   const unsigned n2d = (unsigned)d.N0 * (unsigned)d.N1;
   const unsigned k2 = (unsigned)i0 + (unsigned)d.N0 * (unsigned)i1;
-  const unsigned row = (unsigned)d.P0 * ((unsigned)i1 + (unsigned)d.N1 * (unsigned)i2);
+  const unsigned row = sidx_t<ZF>(d, 0, i1, i2);
   const unsigned idx = row + (unsigned)i0;
   PhiTaps<NG, T, T> ph;
   CombineIn<STAGE, NT, T> cin;
   T v = 0, psi = 0, ssrc = 0, f[6], khu = 0, khv = 0;
   if (active) {
-    ph.load(a.uin, d, i0, i1, i2);
+    ph.template load<ZF>(a.uin, d, i0, i1, i2);
     v = ld<NT>(a.vin + idx);
     psi = ld<NT>(a.psi + idx);
     ssrc = ld<NT>(a.ssrc + idx);
@@ -262,8 +331,9 @@ __global__ void __launch_bounds__(kTileThreads) k_stage(StageArgs<T> a) {
     for (int q = 0; q < 6; ++q) f[q] = load_factor(a.fac, a.facb, q * n2d + k2);
     cin.load(a, idx);
   }
-  load_tile<NG, T, T>(tile, a.uin, d, x0b, x1b, i2);
+  load_tile<NG, T, T, ZF>(tile, a.uin, d, x0b, x1b, i2);
   __syncthreads();
+  if constexpr (ZF) zface_rows<STAGE, NT, CORR, T>(a, x0b, (int)blockIdx.y, i2);
   if (!active) return;
   const Sums<T> s = stencil<NG, T, T>(tile, ph);
   const T lap = f[0] * s.dd0 + f[1] * s.dd1 + f[2] * s.dd2 + f[3] * s.d0 + f[4] * s.d1;
@@ -317,10 +387,11 @@ struct TileRegs {
   static constexpr int W = TileShape<NG>::W, H = TileShape<NG>::H;
   static constexpr int NE = (W * H + kTileThreads - 1) / kTileThreads;
   T v[NE];
+  template <bool ZF = false>
   __device__ __forceinline__ void fetch(const T* __restrict__ U, const Dims& d, int x0b, int x1b,
                                         int i2) {
     const int tid = threadIdx.x + TX * threadIdx.y;
-    const unsigned plane = (unsigned)d.P0 * (unsigned)d.N1;
+    const unsigned plane = (unsigned)d.P0 * (unsigned)rows_of<ZF>(d);
     const unsigned b0 = plane * (unsigned)i2;
     const unsigned bh = plane * (unsigned)half_turn(i2, d.N2);
 #pragma unroll
@@ -332,12 +403,13 @@ struct TileRegs {
       const int j1 = x1b + l1 - NG;
       T val = (T)0;
       if (e < W * H) {
-        if (j1 >= 0 && j1 < d.N1) {
+        if (j1 >= -zo_of<ZF>(d) && j1 < d.N1 + zo_of<ZF>(d)) {   // stored rows (z-face rows too)
           if (j0 >= 0) {
-            if (j0 < d.P0) val = U[b0 + (unsigned)j0 + (unsigned)d.P0 * (unsigned)j1];
+            if (j0 < d.P0)
+              val = U[b0 + (unsigned)j0 + (unsigned)d.P0 * (unsigned)(j1 + zo_of<ZF>(d))];
           } else {
             const int r1 = d.sph ? d.N1 - 1 - j1 : j1;
-            val = U[bh + (unsigned)(-1 - j0) + (unsigned)d.P0 * (unsigned)r1];
+            val = U[bh + (unsigned)(-1 - j0) + (unsigned)d.P0 * (unsigned)(r1 + zo_of<ZF>(d))];
           }
         } else if (j0 >= 0 && j0 < d.P0 && j1 >= -NG && j1 < d.N1 + NG) {
           const int r1 = j1 < 0 ? -1 - j1 : 2 * d.N1 - 1 - j1;
@@ -402,7 +474,7 @@ __device__ __forceinline__ void combine_pt(const StageArgs<T>& a, unsigned idx,
 template <int NG>
 __device__ __forceinline__ int step_up(int j, int N) { return j + 1 == N ? 0 : j + 1; }
 
-template <typename T, int NG, int STAGE, bool CORR>
+template <typename T, int NG, int STAGE, bool CORR, bool ZF>
 __device__ __forceinline__ void stage_col_body(const StageArgs<T>& a, int bx, int by, int bz,
                                                int chunk,
                                                T (&tile)[2][TileShape<NG>::W * TileShape<NG>::H]) {
@@ -414,8 +486,8 @@ __device__ __forceinline__ void stage_col_body(const StageArgs<T>& a, int bx, in
   const int z1 = min(z0 + chunk, d.N2);
   const int i0 = x0b + threadIdx.x, i1 = x1b + threadIdx.y;
   const bool active = i0 < d.N0 && i1 < d.N1;
-  const unsigned plane = (unsigned)d.P0 * (unsigned)d.N1;
-  const unsigned col = (unsigned)i0 + (unsigned)d.P0 * (unsigned)i1;
+  const unsigned plane = (unsigned)d.P0 * (unsigned)rows_of<ZF>(d);
+  const unsigned col = (unsigned)i0 + (unsigned)d.P0 * (unsigned)(i1 + zo_of<ZF>(d));
   const unsigned n2d = (unsigned)d.N0 * (unsigned)d.N1;
   const unsigned k2 = (unsigned)i0 + (unsigned)d.N0 * (unsigned)i1;
   const bool outer = active && i0 >= d.N0 - NG;
@@ -440,7 +512,7 @@ __device__ __forceinline__ void stage_col_body(const StageArgs<T>& a, int bx, in
   // jq now holds (z0 + NG + 1) mod N2: the plane the queue needs next
   {
     TileRegs<NG, T> t0;
-    t0.fetch(a.uin, d, x0b, x1b, z0);
+    t0.template fetch<ZF>(a.uin, d, x0b, x1b, z0);
     t0.store(tile[0]);
   }
   __syncthreads();
@@ -452,7 +524,7 @@ __device__ __forceinline__ void stage_col_body(const StageArgs<T>& a, int bx, in
     PointIn<STAGE, CORR, T> nxt;
     T qn = (T)0;
     if (more) {
-      tn.fetch(a.uin, d, x0b, x1b, z + 1);
+      tn.template fetch<ZF>(a.uin, d, x0b, x1b, z + 1);
       if (active) {
         qn = a.uin[col + plane * (unsigned)jq];
         nxt.load(a, col + plane * (unsigned)(z + 1));
@@ -507,6 +579,7 @@ __device__ __forceinline__ void stage_col_body(const StageArgs<T>& a, int bx, in
         combine<STAGE, false, T>(a, o, co, u0, v0, kuo, kvo);
       }
     }
+    if constexpr (ZF) zface_rows<STAGE, false, CORR, T>(a, x0b, by, z);
     if (more) {
       tn.store(tile[buf ^ 1]);
 #pragma unroll
@@ -519,11 +592,11 @@ __device__ __forceinline__ void stage_col_body(const StageArgs<T>& a, int bx, in
   }
 }
 
-template <typename T, int NG, int STAGE, bool CORR>
+template <typename T, int NG, int STAGE, bool CORR, bool ZF>
 __global__ void __launch_bounds__(kTileThreads, 4) k_stage_col(StageArgs<T> a, int chunk) {
   __shared__ T tile[2][TileShape<NG>::W * TileShape<NG>::H];
   const TileId tid = xcd_tile();
-  stage_col_body<T, NG, STAGE, CORR>(a, tid.x, tid.y, tid.z, chunk, tile);
+  stage_col_body<T, NG, STAGE, CORR, ZF>(a, tid.x, tid.y, tid.z, chunk, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -533,7 +606,7 @@ __global__ void __launch_bounds__(kTileThreads, 4) k_stage_col(StageArgs<T> a, i
 // in device memory (four entries per grid, one per stage). The list lengths
 // are read from device memory, so a captured launch sequence stays valid when
 // converged grids are dropped from the lists.
-template <typename T, int NG, int STAGE, bool CORR>
+template <typename T, int NG, int STAGE, bool CORR, bool ZF>
 __global__ void __launch_bounds__(kTileThreads, 4)
     k_batch_stage(const StageArgs<T>* __restrict__ descs, const int4* __restrict__ items,
                   const int* __restrict__ nitems) {
@@ -550,13 +623,13 @@ __global__ void __launch_bounds__(kTileThreads, 4)
     for (int it = lo + k; it < hi; it += gk) {
       const int4 w = items[it];
       const StageArgs<T> a = descs[4 * w.x + (STAGE - 1)];
-      stage_col_body<T, NG, STAGE, CORR>(a, w.y, w.z, w.w, a.chunk, tile);
+      stage_col_body<T, NG, STAGE, CORR, ZF>(a, w.y, w.z, w.w, a.chunk, tile);
     }
   } else {
     for (int it = blockIdx.x; it < n; it += G) {
       const int4 w = items[it];
       const StageArgs<T> a = descs[4 * w.x + (STAGE - 1)];
-      stage_col_body<T, NG, STAGE, CORR>(a, w.y, w.z, w.w, a.chunk, tile);
+      stage_col_body<T, NG, STAGE, CORR, ZF>(a, w.y, w.z, w.w, a.chunk, tile);
     }
   }
 }
@@ -565,7 +638,32 @@ __global__ void __launch_bounds__(kTileThreads, 4)
 // Slopes k(y_b) of the FP64 base state for the split-state single-precision
 // form, stored in FP32 with p_b = psi_s + u_b and S_src p_b^-7; the FP32
 // increment state is reset to zero. Same tiling as the plane stage kernel.
-template <int NG>
+// Base slopes at an outer point of a z face (SinhCylindrical; see
+// zface_point), with the other base quantities as at the xx0 face's points.
+__device__ __forceinline__ void base_zface_point(const BaseArgs& a, int i0, int i1, int i2) {
+  const Dims& d = a.d;
+  const int zr = i1 < 0 ? i1 + d.zo : d.zo + (i1 - d.N1);
+  const unsigned z2d = (unsigned)d.P0 * 2u * (unsigned)d.zo;
+  const unsigned kz = (unsigned)i0 + (unsigned)d.P0 * (unsigned)zr;
+  const double c = a.zfac[kz], rinv = a.zfac[z2d + kz], qd = a.zfac[2 * z2d + kz];
+  const int in = (int)a.zfac[3 * z2d + kz];   // one point toward the interior
+  const unsigned o = sidx(d, i0, i1, i2);
+  const double* U = a.u + o;
+  const double* V = a.v + o;
+  const bool bc4 = a.bc4 != 0;
+  const double u0 = U[0], u1 = U[in], u2 = U[2 * in];
+  const double v0 = V[0], v1 = V[in], v2 = V[2 * in];
+  const double u3 = bc4 ? U[3 * in] : 0.0, u4 = bc4 ? U[4 * in] : 0.0;
+  const double v3 = bc4 ? V[3 * in] : 0.0, v4 = bc4 ? V[4 * in] : 0.0;
+  a.khu[o] = (float)(-c * (u0 * rinv + outer_diff(u0, u1, u2, u3, u4, qd, bc4)));
+  a.khv[o] = (float)(-c * (v0 * rinv + outer_diff(v0, v1, v2, v3, v4, qd, bc4)));
+  a.pb[o] = (float)(a.psi[o] + u0);
+  a.sp7[o] = 0.0f;
+  a.eu[o] = 0.0f;
+  a.ev[o] = 0.0f;
+}
+
+template <int NG, bool ZF>
 __device__ __forceinline__ void base_body(const BaseArgs& a, int bx, int by, int i2,
                                           double* __restrict__ tile) {
   const Dims& d = a.d;
@@ -574,20 +672,31 @@ __device__ __forceinline__ void base_body(const BaseArgs& a, int bx, int by, int
   const bool active = i0 < d.N0 && i1 < d.N1;
   const unsigned n2d = (unsigned)d.N0 * (unsigned)d.N1;
   const unsigned k2 = (unsigned)i0 + (unsigned)d.N0 * (unsigned)i1;
-  const unsigned row = (unsigned)d.P0 * ((unsigned)i1 + (unsigned)d.N1 * (unsigned)i2);
+  const unsigned row = sidx_t<ZF>(d, 0, i1, i2);
   const unsigned idx = row + (unsigned)i0;
   PhiTaps<NG, double, double> ph;
   double v = 0, psi = 0, ssrc = 0, f[6];
   if (active) {
-    ph.load(a.u, d, i0, i1, i2);
+    ph.template load<ZF>(a.u, d, i0, i1, i2);
     v = a.v[idx];
     psi = a.psi[idx];
     ssrc = a.ssrc[idx];
 #pragma unroll
     for (int q = 0; q < 6; ++q) f[q] = a.fac[q * n2d + k2];
   }
-  load_tile<NG, double, double>(tile, a.u, d, x0b, x1b, i2);
+  load_tile<NG, double, double, ZF>(tile, a.u, d, x0b, x1b, i2);
   __syncthreads();
+  if (ZF && (int)threadIdx.y < d.zo && i0 < d.N0) {
+    // z-face outer points: lower rows from the first x1 tile, upper rows from
+    // the last (corners by the last NG interior columns)
+    const int nby = (d.N1 + TY - 1) / TY;
+    for (int side = 0; side < 2; ++side) {
+      if (side == 0 ? by != 0 : by != nby - 1) continue;
+      const int z1 = side == 0 ? (int)threadIdx.y - d.zo : d.N1 + (int)threadIdx.y;
+      base_zface_point(a, i0, z1, i2);
+      if (i0 >= d.N0 - NG) base_zface_point(a, i0 + NG, z1, i2);
+    }
+  }
   if (!active) return;
   const Sums<double> s = stencil<NG, double, double>(tile, ph);
   const double lap = f[0] * s.dd0 + f[1] * s.dd1 + f[2] * s.dd2 + f[3] * s.d0 + f[4] * s.d1;
@@ -620,10 +729,10 @@ __device__ __forceinline__ void base_body(const BaseArgs& a, int bx, int by, int
   }
 }
 
-template <int NG>
+template <int NG, bool ZF>
 __global__ void __launch_bounds__(kTileThreads) k_base(BaseArgs a) {
   __shared__ double tile[TileShape<NG>::W * TileShape<NG>::H];
-  base_body<NG>(a, blockIdx.x, blockIdx.y, blockIdx.z, tile);
+  base_body<NG, ZF>(a, blockIdx.x, blockIdx.y, blockIdx.z, tile);
 }
 
 __global__ void __launch_bounds__(kBlock) k_rebase(double* __restrict__ ub,
@@ -657,7 +766,7 @@ __device__ __forceinline__ double block_sum(double x) {
 // Residual H (left-hand side of Eq. 4) in FP64 from a state of storage type S;
 // returns the block's sum of H^2 (valid in thread 0), same tiling as the plane
 // stage kernel.
-template <typename S, int NG>
+template <typename S, int NG, bool ZF>
 __device__ __forceinline__ double residual_body(const ResidualArgs& a, int bx, int by, int i2,
                                                double* __restrict__ tile) {
   const Dims& d = a.d;
@@ -667,18 +776,17 @@ __device__ __forceinline__ double residual_body(const ResidualArgs& a, int bx, i
   const bool active = i0 < d.N0 && i1 < d.N1;
   const unsigned n2d = (unsigned)d.N0 * (unsigned)d.N1;
   const unsigned k2 = (unsigned)i0 + (unsigned)d.N0 * (unsigned)i1;
-  const unsigned idx =
-      (unsigned)i0 + (unsigned)d.P0 * ((unsigned)i1 + (unsigned)d.N1 * (unsigned)i2);
+  const unsigned idx = sidx_t<ZF>(d, i0, i1, i2);
   PhiTaps<NG, double, S> ph;
   double psi = 0, ssrc = 0, f[5];
   if (active) {
-    ph.load(U, d, i0, i1, i2);
+    ph.template load<ZF>(U, d, i0, i1, i2);
     psi = a.psi[idx];
     ssrc = a.ssrc[idx];
 #pragma unroll
     for (int q = 0; q < 5; ++q) f[q] = a.fac[q * n2d + k2];
   }
-  load_tile<NG, double, S>(tile, U, d, x0b, x1b, i2);
+  load_tile<NG, double, S, ZF>(tile, U, d, x0b, x1b, i2);
   __syncthreads();
   double h2 = 0.0;
   if (active) {
@@ -691,17 +799,17 @@ __device__ __forceinline__ double residual_body(const ResidualArgs& a, int bx, i
   return block_sum<kTileThreads>(h2);
 }
 
-template <typename S, int NG>
+template <typename S, int NG, bool ZF>
 __global__ void __launch_bounds__(kTileThreads) k_residual(ResidualArgs a) {
   __shared__ double tile[TileShape<NG>::W * TileShape<NG>::H];
-  const double tot = residual_body<S, NG>(a, blockIdx.x, blockIdx.y, blockIdx.z, tile);
+  const double tot = residual_body<S, NG, ZF>(a, blockIdx.x, blockIdx.y, blockIdx.z, tile);
   if (threadIdx.x == 0 && threadIdx.y == 0)
     a.partial[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = tot;
 }
 
 // Batched residual: items (grid, x0 tile, x1 tile, plane); the block sum of
 // item `it` goes to partial[it]. FP64 states only.
-template <int NG>
+template <int NG, bool ZF>
 __global__ void __launch_bounds__(kTileThreads)
     k_batch_residual(const ResidualArgs* __restrict__ descs, const int4* __restrict__ items,
                      const int* __restrict__ nitems, double* __restrict__ partial) {
@@ -710,7 +818,7 @@ __global__ void __launch_bounds__(kTileThreads)
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
     const int4 w = items[it];
     const ResidualArgs a = descs[w.x];
-    const double tot = residual_body<double, NG>(a, w.y, w.z, w.w, tile);
+    const double tot = residual_body<double, NG, ZF>(a, w.y, w.z, w.w, tile);
     if (threadIdx.x == 0 && threadIdx.y == 0) partial[it] = tot;
   }
 }
@@ -728,7 +836,7 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // Batched base slopes of the split-state form.
-template <int NG>
+template <int NG, bool ZF>
 __global__ void __launch_bounds__(kTileThreads)
     k_batch_base(const BaseArgs* __restrict__ descs, const int4* __restrict__ items,
                  const int* __restrict__ nitems) {
@@ -737,7 +845,7 @@ __global__ void __launch_bounds__(kTileThreads)
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
     const int4 w = items[it];
     const BaseArgs a = descs[w.x];
-    base_body<NG>(a, w.y, w.z, w.w, tile);
+    base_body<NG, ZF>(a, w.y, w.z, w.w, tile);
     __syncthreads();
   }
 }
@@ -779,11 +887,11 @@ __global__ void __launch_bounds__(kBlock) k_sources(Dims d, const double* __rest
                                                     double* __restrict__ ssrc64,
                                                     float* __restrict__ psi32,
                                                     float* __restrict__ ssrc32) {
-  const int next = d.P0 * d.N1 * d.N2;
+  const int next = d.P0 * d.R1 * d.N2;
   const int t = blockIdx.x * kBlock + threadIdx.x;
   if (t >= next) return;
-  const int e = t % (d.P0 * d.N1);
-  const int i2 = t / (d.P0 * d.N1);
+  const int e = t % (d.P0 * d.R1);   // (i0, stored row) of the 2D tables
+  const int i2 = t / (d.P0 * d.R1);
   const double X[3] = {rho[e] * cphi[i2], rho[e] * sphi[i2], zc[e]};
   double psi = 1.0;
   double A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
@@ -834,6 +942,13 @@ __global__ void __launch_bounds__(kBlock) k_fill(T* __restrict__ dst, T value, i
   if (t < n) dst[t] = value;
 }
 
+// dst = a * src elementwise (n values).
+__global__ void __launch_bounds__(kBlock) k_scale(double* __restrict__ dst,
+                                                  const double* __restrict__ src, double a, int n) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t < n) dst[t] = a * src[t];
+}
+
 inline int nblocks(int n) { return (n + kBlock - 1) / kBlock; }
 
 inline dim3 tile_grid(const Dims& d) {
@@ -866,14 +981,34 @@ hipError_t col_launch(K k, const A& args, int chunk, hipStream_t s, hipEvent_t t
   return hipGetLastError();
 }
 
+template <typename T, int NG, bool NT, bool CORR, bool ZF>
+hipError_t stage_dispatch_zf(int stage, const StageArgs<T>& a, hipStream_t s, hipEvent_t t0,
+                             hipEvent_t t1) {
+  switch (stage) {
+    case 1: return tile_launch(k_stage<T, NG, 1, NT, CORR, ZF>, a, a.d, s, t0, t1);
+    case 2: return tile_launch(k_stage<T, NG, 2, NT, CORR, ZF>, a, a.d, s, t0, t1);
+    case 3: return tile_launch(k_stage<T, NG, 3, NT, CORR, ZF>, a, a.d, s, t0, t1);
+    case 4: return tile_launch(k_stage<T, NG, 4, NT, CORR, ZF>, a, a.d, s, t0, t1);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Plane-tile instance for grids with (ZF) or without stored z-face rows.
 template <typename T, int NG, bool NT, bool CORR>
 hipError_t stage_dispatch_nt(int stage, const StageArgs<T>& a, hipStream_t s, hipEvent_t t0,
                              hipEvent_t t1) {
+  return a.d.zo ? stage_dispatch_zf<T, NG, NT, CORR, true>(stage, a, s, t0, t1)
+                : stage_dispatch_zf<T, NG, NT, CORR, false>(stage, a, s, t0, t1);
+}
+
+template <typename T, int NG, bool CORR, bool ZF>
+hipError_t col_dispatch_zf(int stage, const StageArgs<T>& a, int ch, hipStream_t s,
+                           hipEvent_t t0, hipEvent_t t1) {
   switch (stage) {
-    case 1: return tile_launch(k_stage<T, NG, 1, NT, CORR>, a, a.d, s, t0, t1);
-    case 2: return tile_launch(k_stage<T, NG, 2, NT, CORR>, a, a.d, s, t0, t1);
-    case 3: return tile_launch(k_stage<T, NG, 3, NT, CORR>, a, a.d, s, t0, t1);
-    case 4: return tile_launch(k_stage<T, NG, 4, NT, CORR>, a, a.d, s, t0, t1);
+    case 1: return col_launch(k_stage_col<T, NG, 1, CORR, ZF>, a, ch, s, t0, t1);
+    case 2: return col_launch(k_stage_col<T, NG, 2, CORR, ZF>, a, ch, s, t0, t1);
+    case 3: return col_launch(k_stage_col<T, NG, 3, CORR, ZF>, a, ch, s, t0, t1);
+    case 4: return col_launch(k_stage_col<T, NG, 4, CORR, ZF>, a, ch, s, t0, t1);
     default: return hipErrorInvalidValue;
   }
 }
@@ -881,13 +1016,8 @@ hipError_t stage_dispatch_nt(int stage, const StageArgs<T>& a, hipStream_t s, hi
 template <typename T, int NG, bool CORR>
 hipError_t col_dispatch(int stage, const StageArgs<T>& a, int ch, hipStream_t s, hipEvent_t t0,
                         hipEvent_t t1) {
-  switch (stage) {
-    case 1: return col_launch(k_stage_col<T, NG, 1, CORR>, a, ch, s, t0, t1);
-    case 2: return col_launch(k_stage_col<T, NG, 2, CORR>, a, ch, s, t0, t1);
-    case 3: return col_launch(k_stage_col<T, NG, 3, CORR>, a, ch, s, t0, t1);
-    case 4: return col_launch(k_stage_col<T, NG, 4, CORR>, a, ch, s, t0, t1);
-    default: return hipErrorInvalidValue;
-  }
+  return a.d.zo ? col_dispatch_zf<T, NG, CORR, true>(stage, a, ch, s, t0, t1)
+                : col_dispatch_zf<T, NG, CORR, false>(stage, a, ch, s, t0, t1);
 }
 
 
@@ -918,14 +1048,31 @@ hipError_t stage_order(int order, int stage, const StageArgs<T>& a, hipStream_t 
   }
 }
 
+template <typename S, bool ZF>
+hipError_t residual_order_zf(int order, const ResidualArgs& a, hipStream_t s) {
+  switch (order) {
+    case 2: return tile_launch(k_residual<S, 1, ZF>, a, a.d, s, nullptr, nullptr);
+    case 4: return tile_launch(k_residual<S, 2, ZF>, a, a.d, s, nullptr, nullptr);
+    case 6: return tile_launch(k_residual<S, 3, ZF>, a, a.d, s, nullptr, nullptr);
+    case 8: return tile_launch(k_residual<S, 4, ZF>, a, a.d, s, nullptr, nullptr);
+    case 10: return tile_launch(k_residual<S, 5, ZF>, a, a.d, s, nullptr, nullptr);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <typename S>
 hipError_t residual_order(int order, const ResidualArgs& a, hipStream_t s) {
+  return a.d.zo ? residual_order_zf<S, true>(order, a, s) : residual_order_zf<S, false>(order, a, s);
+}
+
+template <bool ZF>
+hipError_t base_order(int order, const BaseArgs& a, hipStream_t s) {
   switch (order) {
-    case 2: return tile_launch(k_residual<S, 1>, a, a.d, s, nullptr, nullptr);
-    case 4: return tile_launch(k_residual<S, 2>, a, a.d, s, nullptr, nullptr);
-    case 6: return tile_launch(k_residual<S, 3>, a, a.d, s, nullptr, nullptr);
-    case 8: return tile_launch(k_residual<S, 4>, a, a.d, s, nullptr, nullptr);
-    case 10: return tile_launch(k_residual<S, 5>, a, a.d, s, nullptr, nullptr);
+    case 2: return tile_launch(k_base<1, ZF>, a, a.d, s, nullptr, nullptr);
+    case 4: return tile_launch(k_base<2, ZF>, a, a.d, s, nullptr, nullptr);
+    case 6: return tile_launch(k_base<3, ZF>, a, a.d, s, nullptr, nullptr);
+    case 8: return tile_launch(k_base<4, ZF>, a, a.d, s, nullptr, nullptr);
+    case 10: return tile_launch(k_base<5, ZF>, a, a.d, s, nullptr, nullptr);
     default: return hipErrorInvalidValue;
   }
 }
@@ -960,21 +1107,14 @@ hipError_t launch_sources(const Dims& d, const double* rho, const double* zc,
                           const double* cphi, const double* sphi, const Punctures& p,
                           double* psi64, double* ssrc64, float* psi32, float* ssrc32,
                           hipStream_t s) {
-  const int next = d.P0 * d.N1 * d.N2;
+  const int next = d.P0 * d.R1 * d.N2;
   k_sources<<<nblocks(next), kBlock, 0, s>>>(d, rho, zc, cphi, sphi, p, psi64, ssrc64, psi32,
                                              ssrc32);
   return hipGetLastError();
 }
 
 hipError_t launch_base(int order, const BaseArgs& a, hipStream_t s) {
-  switch (order) {
-    case 2: return tile_launch(k_base<1>, a, a.d, s, nullptr, nullptr);
-    case 4: return tile_launch(k_base<2>, a, a.d, s, nullptr, nullptr);
-    case 6: return tile_launch(k_base<3>, a, a.d, s, nullptr, nullptr);
-    case 8: return tile_launch(k_base<4>, a, a.d, s, nullptr, nullptr);
-    case 10: return tile_launch(k_base<5>, a, a.d, s, nullptr, nullptr);
-    default: return hipErrorInvalidValue;
-  }
+  return a.d.zo ? base_order<true>(order, a, s) : base_order<false>(order, a, s);
 }
 
 hipError_t launch_rebase(double* ub, double* vb, const float* eu, const float* ev, int n,
@@ -983,58 +1123,78 @@ hipError_t launch_rebase(double* ub, double* vb, const float* eu, const float* e
   return hipGetLastError();
 }
 
-template <int NG>
+template <int NG, bool ZF>
 hipError_t batch_stage_ng(int stage, bool fp32_split, const void* descs, const int4* items,
                           const int* nitems, int nblocks_persistent, hipStream_t s) {
   const dim3 block(TX, TY, 1), grid(nblocks_persistent);
   if (fp32_split) {
     const StageArgs<float>* d = static_cast<const StageArgs<float>*>(descs);
     switch (stage) {
-      case 1: k_batch_stage<float, NG, 1, true><<<grid, block, 0, s>>>(d, items, nitems); break;
-      case 2: k_batch_stage<float, NG, 2, true><<<grid, block, 0, s>>>(d, items, nitems); break;
-      case 3: k_batch_stage<float, NG, 3, true><<<grid, block, 0, s>>>(d, items, nitems); break;
-      case 4: k_batch_stage<float, NG, 4, true><<<grid, block, 0, s>>>(d, items, nitems); break;
+      case 1: k_batch_stage<float, NG, 1, true, ZF><<<grid, block, 0, s>>>(d, items, nitems); break;
+      case 2: k_batch_stage<float, NG, 2, true, ZF><<<grid, block, 0, s>>>(d, items, nitems); break;
+      case 3: k_batch_stage<float, NG, 3, true, ZF><<<grid, block, 0, s>>>(d, items, nitems); break;
+      case 4: k_batch_stage<float, NG, 4, true, ZF><<<grid, block, 0, s>>>(d, items, nitems); break;
       default: return hipErrorInvalidValue;
     }
   } else {
     const StageArgs<double>* d = static_cast<const StageArgs<double>*>(descs);
     switch (stage) {
-      case 1: k_batch_stage<double, NG, 1, false><<<grid, block, 0, s>>>(d, items, nitems); break;
-      case 2: k_batch_stage<double, NG, 2, false><<<grid, block, 0, s>>>(d, items, nitems); break;
-      case 3: k_batch_stage<double, NG, 3, false><<<grid, block, 0, s>>>(d, items, nitems); break;
-      case 4: k_batch_stage<double, NG, 4, false><<<grid, block, 0, s>>>(d, items, nitems); break;
+      case 1: k_batch_stage<double, NG, 1, false, ZF><<<grid, block, 0, s>>>(d, items, nitems); break;
+      case 2: k_batch_stage<double, NG, 2, false, ZF><<<grid, block, 0, s>>>(d, items, nitems); break;
+      case 3: k_batch_stage<double, NG, 3, false, ZF><<<grid, block, 0, s>>>(d, items, nitems); break;
+      case 4: k_batch_stage<double, NG, 4, false, ZF><<<grid, block, 0, s>>>(d, items, nitems); break;
       default: return hipErrorInvalidValue;
     }
   }
   return hipGetLastError();
 }
 
-hipError_t launch_batch_stage(int order, int stage, bool fp32_split, const void* descs,
-                              const int4* items, const int* nitems, int nblocks_persistent,
-                              hipStream_t s) {
+template <bool ZF>
+hipError_t batch_stage_order(int order, int stage, bool fp32_split, const void* descs,
+                             const int4* items, const int* nitems, int nblocks_persistent,
+                             hipStream_t s) {
   switch (order) {
-    case 2: return batch_stage_ng<1>(stage, fp32_split, descs, items, nitems, nblocks_persistent, s);
-    case 4: return batch_stage_ng<2>(stage, fp32_split, descs, items, nitems, nblocks_persistent, s);
-    case 6: return batch_stage_ng<3>(stage, fp32_split, descs, items, nitems, nblocks_persistent, s);
-    case 8: return batch_stage_ng<4>(stage, fp32_split, descs, items, nitems, nblocks_persistent, s);
-    case 10: return batch_stage_ng<5>(stage, fp32_split, descs, items, nitems, nblocks_persistent, s);
+    case 2: return batch_stage_ng<1, ZF>(stage, fp32_split, descs, items, nitems, nblocks_persistent, s);
+    case 4: return batch_stage_ng<2, ZF>(stage, fp32_split, descs, items, nitems, nblocks_persistent, s);
+    case 6: return batch_stage_ng<3, ZF>(stage, fp32_split, descs, items, nitems, nblocks_persistent, s);
+    case 8: return batch_stage_ng<4, ZF>(stage, fp32_split, descs, items, nitems, nblocks_persistent, s);
+    case 10: return batch_stage_ng<5, ZF>(stage, fp32_split, descs, items, nitems, nblocks_persistent, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_batch_residual(int order, const ResidualArgs* descs, const int4* items,
-                                 const int* nitems, double* partial, int nblocks_persistent,
-                                 hipStream_t s) {
+hipError_t launch_batch_stage(int order, int stage, bool fp32_split, bool zfaces, const void* descs,
+                              const int4* items, const int* nitems, int nblocks_persistent,
+                              hipStream_t s) {
+  return zfaces ? batch_stage_order<true>(order, stage, fp32_split, descs, items, nitems,
+                                          nblocks_persistent, s)
+                : batch_stage_order<false>(order, stage, fp32_split, descs, items, nitems,
+                                           nblocks_persistent, s);
+}
+
+template <bool ZF>
+hipError_t batch_residual_order(int order, const ResidualArgs* descs, const int4* items,
+                                const int* nitems, double* partial, int nblocks_persistent,
+                                hipStream_t s) {
   const dim3 block(TX, TY, 1), grid(nblocks_persistent);
   switch (order) {
-    case 2: k_batch_residual<1><<<grid, block, 0, s>>>(descs, items, nitems, partial); break;
-    case 4: k_batch_residual<2><<<grid, block, 0, s>>>(descs, items, nitems, partial); break;
-    case 6: k_batch_residual<3><<<grid, block, 0, s>>>(descs, items, nitems, partial); break;
-    case 8: k_batch_residual<4><<<grid, block, 0, s>>>(descs, items, nitems, partial); break;
-    case 10: k_batch_residual<5><<<grid, block, 0, s>>>(descs, items, nitems, partial); break;
+    case 2: k_batch_residual<1, ZF><<<grid, block, 0, s>>>(descs, items, nitems, partial); break;
+    case 4: k_batch_residual<2, ZF><<<grid, block, 0, s>>>(descs, items, nitems, partial); break;
+    case 6: k_batch_residual<3, ZF><<<grid, block, 0, s>>>(descs, items, nitems, partial); break;
+    case 8: k_batch_residual<4, ZF><<<grid, block, 0, s>>>(descs, items, nitems, partial); break;
+    case 10: k_batch_residual<5, ZF><<<grid, block, 0, s>>>(descs, items, nitems, partial); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_batch_residual(int order, bool zfaces, const ResidualArgs* descs,
+                                 const int4* items, const int* nitems, double* partial,
+                                 int nblocks_persistent, hipStream_t s) {
+  return zfaces ? batch_residual_order<true>(order, descs, items, nitems, partial,
+                                             nblocks_persistent, s)
+                : batch_residual_order<false>(order, descs, items, nitems, partial,
+                                              nblocks_persistent, s);
 }
 
 hipError_t launch_batch_finalize(const int4* ranges, const double* partial, double* out,
@@ -1043,18 +1203,25 @@ hipError_t launch_batch_finalize(const int4* ranges, const double* partial, doub
   return hipGetLastError();
 }
 
-hipError_t launch_batch_base(int order, const BaseArgs* descs, const int4* items,
-                             const int* nitems, int nblocks_persistent, hipStream_t s) {
+template <bool ZF>
+hipError_t batch_base_order(int order, const BaseArgs* descs, const int4* items,
+                            const int* nitems, int nblocks_persistent, hipStream_t s) {
   const dim3 block(TX, TY, 1), grid(nblocks_persistent);
   switch (order) {
-    case 2: k_batch_base<1><<<grid, block, 0, s>>>(descs, items, nitems); break;
-    case 4: k_batch_base<2><<<grid, block, 0, s>>>(descs, items, nitems); break;
-    case 6: k_batch_base<3><<<grid, block, 0, s>>>(descs, items, nitems); break;
-    case 8: k_batch_base<4><<<grid, block, 0, s>>>(descs, items, nitems); break;
-    case 10: k_batch_base<5><<<grid, block, 0, s>>>(descs, items, nitems); break;
+    case 2: k_batch_base<1, ZF><<<grid, block, 0, s>>>(descs, items, nitems); break;
+    case 4: k_batch_base<2, ZF><<<grid, block, 0, s>>>(descs, items, nitems); break;
+    case 6: k_batch_base<3, ZF><<<grid, block, 0, s>>>(descs, items, nitems); break;
+    case 8: k_batch_base<4, ZF><<<grid, block, 0, s>>>(descs, items, nitems); break;
+    case 10: k_batch_base<5, ZF><<<grid, block, 0, s>>>(descs, items, nitems); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_batch_base(int order, bool zfaces, const BaseArgs* descs, const int4* items,
+                             const int* nitems, int nblocks_persistent, hipStream_t s) {
+  return zfaces ? batch_base_order<true>(order, descs, items, nitems, nblocks_persistent, s)
+                : batch_base_order<false>(order, descs, items, nitems, nblocks_persistent, s);
 }
 
 hipError_t launch_batch_rebase(const RebaseArgs* descs, const int2* items, const int* nitems,
@@ -1071,6 +1238,11 @@ hipError_t launch_to_fp64(const float* src, double* dst, int n, hipStream_t s) {
   k_convert<float, double><<<nblocks(n), kBlock, 0, s>>>(src, dst, n);
   return hipGetLastError();
 }
+hipError_t launch_scale(double* dst, const double* src, double a, int n, hipStream_t s) {
+  k_scale<<<nblocks(n), kBlock, 0, s>>>(dst, src, a, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill(double* dst, double value, int n, hipStream_t s) {
   k_fill<double><<<nblocks(n), kBlock, 0, s>>>(dst, value, n);
   return hipGetLastError();

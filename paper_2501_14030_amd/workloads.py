@@ -22,6 +22,7 @@ import numpy as np
 SINHSYMTP = 0
 SPHERICAL = 1
 SINHSPHERICAL = 2
+SINHCYLINDRICAL = 3
 
 
 @dataclass
@@ -57,7 +58,7 @@ class GridSpec:
 
     def name(self) -> str:
         c = {SINHSYMTP: "SinhSymTP", SPHERICAL: "Spherical",
-             SINHSPHERICAL: "SinhSpherical"}[self.coords]
+             SINHSPHERICAL: "SinhSpherical", SINHCYLINDRICAL: "SinhCylindrical"}[self.coords]
         return f"{c} {self.N0}x{self.N1}x{self.N2} order {self.fd_order}"
 
 

@@ -1,3 +1,4 @@
+#include <algorithm>
 // Host-only driver for the library's geometry tables and the resident
 // kernel's patch partition, built with AddressSanitizer and
 // UndefinedBehaviorSanitizer by tests/test_sanitize_host.py. Builds the tables
@@ -63,6 +64,7 @@ static int check_plans() {
       for (int NG : {4, 5}) {
         hr::Dims d{};
         d.N0 = sh[0]; d.N1 = sh[1]; d.N2 = sh[2]; d.NG = NG; d.P0 = sh[0] + NG; d.sph = sph;
+        d.R1 = sh[1];
         std::vector<int> w;
         int nbx = 0, nby = 0;
         if (ry == 4 && (d.N0 / 8) * (d.N1 / 4) > hr::kResMaxBlocks) continue;
@@ -89,6 +91,7 @@ static int check_plans() {
   for (const auto& sh : bad) {
     hr::Dims d{};
     d.N0 = sh[0]; d.N1 = sh[1]; d.N2 = sh[2]; d.NG = sh[3]; d.P0 = sh[0] + sh[3];
+    d.R1 = sh[1];
     std::vector<int> w;
     int nbx = 1, nby = 1;
     if (hr::resident_plan(d, 8, w, nbx, nby) || nbx || nby) return 15;
@@ -96,7 +99,7 @@ static int check_plans() {
   {
     // 8 x 4 patches on N1 = 12 (not a multiple of 8); no other patch rows
     hr::Dims d{};
-    d.N0 = 16; d.N1 = 12; d.N2 = 4; d.NG = 4; d.P0 = 20;
+    d.N0 = 16; d.N1 = 12; d.N2 = 4; d.NG = 4; d.P0 = 20; d.R1 = 12;
     std::vector<int> w;
     int nbx = 0, nby = 0;
     if (!hr::resident_plan(d, 4, w, nbx, nby) || nbx != 2 || nby != 3) return 16;
@@ -114,7 +117,7 @@ int main() {
   int checked = 0;
   const int shapes[][3] = {{5, 5, 2}, {8, 4, 2}, {32, 16, 4}, {37, 19, 6}, {64, 64, 8}, {128, 64, 8}};
   const int orders[] = {2, 4, 6, 8, 10};
-  for (int coords = 0; coords < 3; ++coords)
+  for (int coords = 0; coords < 4; ++coords)
     for (const auto& sh : shapes)
       for (int order : orders) {
         const int NG = order / 2;
@@ -127,7 +130,9 @@ int main() {
         d.P0 = sh[0] + NG;
         d.nint = sh[0] * sh[1] * sh[2];
         d.nout = NG * sh[1] * sh[2];
-        d.sph = coords == 0 ? 0 : 1;
+        d.sph = coords == 1 || coords == 2 ? 1 : 0;
+        d.zo = coords == 3 ? NG : 0;   // SinhCylindrical: outer rows on both z faces
+        d.R1 = sh[1] + 2 * d.zo;
         hr_grid_params p{1.0e6, 0.07, 1.5, 100.0, 0.5};
         hr::HostTables t;
         std::string err;
@@ -140,6 +145,24 @@ int main() {
           if (!(c >= 1.0 - 1e-12)) return 3;  // every interior cell is at least ds_g
         for (double r : t.orinv)
           if (!(r > 0) || !std::isfinite(r)) return 4;
+        for (double r : t.zrinv)
+          if (!(r > 0) || !std::isfinite(r)) return 5;
+        for (double q : t.zq)
+          if (q == 0.0 || !std::isfinite(q)) return 6;
+        // z-face points: up to four steps toward the interior stay on stored
+        // points (rows in [-zo, N1 + zo), columns in [0, P0))
+        for (int zr = 0; zr < 2 * d.zo; ++zr)
+          for (int i0 = 0; i0 < d.P0; ++i0) {
+            const int k = i0 + d.P0 * zr;
+            const int i1 = zr < d.zo ? zr - d.zo : d.N1 + (zr - d.zo);
+            const int st = (int)t.zstep[k];
+            if (st != d.P0 && st != -d.P0 && st != -1) return 7;
+            for (int q = 1; q <= 4 && q <= std::min(d.N0, d.N1); ++q) {
+              const int j0 = st == -1 ? i0 - q : i0;
+              const int j1 = st == -1 ? i1 : i1 + (st > 0 ? q : -q);
+              if (j0 < 0 || j0 >= d.P0 || j1 < -d.zo || j1 >= d.N1 + d.zo) return 8;
+            }
+          }
         ++checked;
       }
   std::printf("geometry tables checked: %d\n", checked);

@@ -49,7 +49,7 @@ def _create(lib, coords, N0, N1, N2, order, params=None):
     (0, 32, 3, 4, 8),      # N1 < NG
     (0, 32, 16, 4, 7),     # odd order
     (0, 32, 16, 4, 12),    # unsupported order
-    (3, 32, 16, 4, 8),     # unknown coordinates
+    (4, 32, 16, 4, 8),     # unknown coordinates
     (0, 32, 16, 0, 8),
 ])
 def test_create_rejects_invalid_arguments(lib, args):
@@ -89,6 +89,8 @@ def test_workspace_and_sizes(lib):
     workloads.GridSpec(0, 128, 128, 16, 10, bscale=5.0),
     workloads.GridSpec(1, 128, 64, 8, 10, rmax=100.0),
     workloads.GridSpec(2, 64, 32, 8, 10),
+    workloads.GridSpec(3, 32, 16, 4, 8, amax=10.0, sinhwaa=0.3),
+    workloads.GridSpec(3, 37, 22, 6, 10, amax=1.0e3, sinhwaa=0.15),
 ])
 def test_suggested_dt_matches_oracle(lib, oracle_lib, spec):
     p = hr.default_params(amax=spec.amax, sinhwaa=spec.sinhwaa, bscale=spec.bscale,

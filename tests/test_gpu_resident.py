@@ -185,26 +185,45 @@ def test_resident_split_form_matches_plane_split_form(spec):
     assert d <= 2 * d_pl + 1e-12
 
 
-def test_resident_wait_timeout_is_reported_and_recoverable():
+def test_resident_wait_timeout_falls_back_to_the_stage_kernels():
     """A wait bound of one poll makes the exchange waits give up (a partner is
-    rarely done at the first poll); the kernel's blocks all leave their loops,
-    the call reports HR_EDEVICE instead of hanging, and the grid relaxes
-    normally once the bound is restored and the state is set again."""
+    rarely done at the first poll), as when the device cannot hold every
+    block at once. The kernel's blocks all leave their loops; hr_relax goes
+    back to the state it copied before the launch, reruns that interval on the
+    stage kernels and stays on them for the rest of the call, counting the
+    fallback. The result equals the plane-tile kernels' (same arithmetic), in
+    a checked interval and in the unchecked tail, FP64 and split form; with
+    the default bound the resident kernel runs again without fallback."""
     w = workloads.paper_scale()
+    ref = {}
+    for steps in (250, 50):   # two checked intervals and a tail; a tail only
+        h = gpu_grid(w.grid)
+        h.set_kernel_config(variant=1)
+        h.set_punctures(*w.punctures.as_tuple())
+        h.relax(w.eta, 1.0, 0.0, steps, 0.0, check_every=100)
+        ref[steps] = h.get_u(extended=True)
+        h.close()
     g = gpu_grid(w.grid)
     g.set_kernel_config(variant=3)
     g.set_punctures(*w.punctures.as_tuple())
     g.set_wait_limit(1)
-    with pytest.raises(hr.HRError) as ei:
-        g.relax(w.eta, 1.0, 0.0, 200, 0.0, check_every=100)
-    assert ei.value.status == hr.EDEVICE
-    banner(f"forced wait timeout reported: {ei.value}")
+    for steps in (250, 50):
+        g.set_punctures(*w.punctures.as_tuple())
+        r = g.relax(w.eta, 1.0, 0.0, steps, 0.0, check_every=100)
+        d = rel_maxdiff(g.get_u(extended=True), ref[steps])
+        banner(f"forced wait timeout, {steps} steps: status {r.status}, "
+               f"{r.resident_fallbacks} fallback(s), u vs plane tiles {d:.2e}")
+        assert r.status == hr.OK and r.steps_taken == steps
+        assert r.resident_fallbacks == 1
+        assert d <= 1e-13
+    g.set_punctures(*w.punctures.as_tuple())
+    g.set_fp32_switch(0.0, 8, 0)
+    r = g.relax(w.eta, 1.0, 0.0, 60000, w.tol, check_every=100, precision=hr.FP32_FP64FINISH)
+    banner(f"split form with the forced timeout: {r.steps_taken} steps, "
+           f"{r.resident_fallbacks} fallback(s), residual {r.residual:.2e}")
+    assert r.status == hr.OK and r.resident_fallbacks >= 1 and r.residual < w.tol
     g.set_wait_limit(0)
     g.set_punctures(*w.punctures.as_tuple())
-    r = g.relax(w.eta, 1.0, 0.0, 200, 0.0, check_every=100)
-    h = gpu_grid(w.grid)
-    h.set_kernel_config(variant=1)
-    h.set_punctures(*w.punctures.as_tuple())
-    h.relax(w.eta, 1.0, 0.0, 200, 0.0, check_every=100)
-    assert r.status == hr.OK
-    assert rel_maxdiff(g.get_u(extended=True), h.get_u(extended=True)) <= 1e-13
+    r = g.relax(w.eta, 1.0, 0.0, 250, 0.0, check_every=100)
+    assert r.status == hr.OK and r.resident_fallbacks == 0
+    assert rel_maxdiff(g.get_u(extended=True), ref[250]) <= 1e-13
