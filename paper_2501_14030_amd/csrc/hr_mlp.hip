@@ -9,6 +9,7 @@
 // epilogue; backward uses the same GEMM in its transposed forms, deterministic
 // column sums for the biases, and Adam.
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -34,6 +35,7 @@ constexpr int kFeat = 15;   // 9 configuration + 4 coordinate + 2 puncture-dista
 //   result register r of lane l is row 8 (r / 4) + 4 (l / 32) + r % 4,
 //   column l % 32.
 constexpr int GBM = 64, GBN = 64, GBK = 16;
+constexpr int kMaxSlices = 32;   // split-K slices of a weight gradient, at most
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -46,21 +48,30 @@ __device__ __forceinline__ float gelu_grad(float z) {
   return cdf + z * pdf;
 }
 
+//
+// Split K (grid z > 1): block z sums k in [z kc, min(K, (z + 1) kc)) and writes
+// its partial product to C + z * cz (no bias, no activation); k_sum_slices
+// then adds the slices in a fixed order. Used for the weight gradients,
+// whose M x N is one layer's weights but whose K is the batch.
 template <bool TA, bool TB>
 __global__ void __launch_bounds__(256)
     k_gemm(int M, int N, int K, const float* __restrict__ A, int lda,
            const float* __restrict__ B, int ldb, float* __restrict__ C, int ldc,
-           const float* __restrict__ bias, float* __restrict__ Zout, int act) {
+           const float* __restrict__ bias, float* __restrict__ Zout, int act, int kc,
+           size_t cz) {
   __shared__ float As[GBK][GBM + 4];
   __shared__ float Bs[GBK][GBN + 4];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+  const int kb = blockIdx.z * kc;
+  const int ke = min(K, kb + kc);
+  C += blockIdx.z * cz;
   f32x16 acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-  for (int k0 = 0; k0 < K; k0 += GBK) {
+  for (int k0 = kb; k0 < ke; k0 += GBK) {
     // stage A (64 x 16) and B (16 x 64) tiles, zero outside the matrices
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -70,13 +81,13 @@ __global__ void __launch_bounds__(256)
       const int amm = TA ? e % GBM : e / GBK;
       const int gm = m0 + amm, gak = k0 + akk;
       float va = 0.0f;
-      if (gm < M && gak < K) va = TA ? A[(size_t)gak * lda + gm] : A[(size_t)gm * lda + gak];
+      if (gm < M && gak < ke) va = TA ? A[(size_t)gak * lda + gm] : A[(size_t)gm * lda + gak];
       As[akk][amm] = va;
       const int bkk = TB ? e % GBK : e / GBN;
       const int bnn = TB ? e / GBK : e % GBN;
       const int gn = n0 + bnn, gbk = k0 + bkk;
       float vb = 0.0f;
-      if (gn < N && gbk < K) vb = TB ? B[(size_t)gn * ldb + gbk] : B[(size_t)gbk * ldb + gn];
+      if (gn < N && gbk < ke) vb = TB ? B[(size_t)gn * ldb + gbk] : B[(size_t)gbk * ldb + gn];
       Bs[bkk][bnn] = vb;
     }
     __syncthreads();
@@ -99,6 +110,16 @@ __global__ void __launch_bounds__(256)
       C[(size_t)row * ldc + col] = act ? gelu(z) : z;
     }
   }
+}
+
+// C[i] = sum over z < nz of P[z n + i], i < n, in the order z = 0, 1, ...
+__global__ void __launch_bounds__(256) k_sum_slices(const float* __restrict__ P, int nz, long n,
+                                                    float* __restrict__ C) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.0f;
+  for (int z = 0; z < nz; ++z) s += P[(size_t)z * n + i];
+  C[i] = s;
 }
 
 // out[j] = sum_i X[i*ld + j], i < M, j < N: per-block partial sums over row
@@ -240,6 +261,7 @@ struct hr_mlp {
   float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
   float *X = nullptr, *Z1 = nullptr, *H1 = nullptr, *Z2 = nullptr, *H2 = nullptr, *Y = nullptr;
   float *dY = nullptr, *dH = nullptr, *dZ = nullptr, *part = nullptr, *T = nullptr;
+  float* kpart = nullptr;         // split-K slices of the weight gradients
   float* host_part = nullptr;
   long adam_t = 0;
   // parameter offsets
@@ -282,6 +304,7 @@ size_t mlp_layout(hr_mlp* n, int B, char* base) {
   n->dH = take((size_t)B * n->Wd);
   n->dZ = take((size_t)B * n->Wd);
   n->part = take((size_t)(B / 64 + 8) * n->Wd + 1024);
+  n->kpart = take((size_t)kMaxSlices * n->Wd * n->Wd);
   return off;
 }
 
@@ -289,7 +312,25 @@ template <bool TA, bool TB>
 hipError_t gemm(hipStream_t s, int M, int N, int K, const float* A, int lda, const float* B,
                 int ldb, float* C, int ldc, const float* bias, float* Z, int act) {
   const dim3 grid(cdiv(N, GBN), cdiv(M, GBM));
-  k_gemm<TA, TB><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, bias, Z, act);
+  k_gemm<TA, TB><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, bias, Z, act, K, 0);
+  return hipGetLastError();
+}
+
+// Weight gradient C[M x N] (ldc = N) = A^T B summed over the batch K, split
+// into slices of K so that the launch has ~512 blocks (at most kMaxSlices,
+// each at least 256 rows of the batch), then the slices added in order.
+hipError_t gemm_wgrad(hipStream_t s, int M, int N, int K, const float* A, int lda, const float* B,
+                      int ldb, float* C, float* slices) {
+  const int tiles = (int)(cdiv(N, GBN) * cdiv(M, GBM));
+  int nz = std::max(1, std::min({kMaxSlices, 512 / tiles, K / 256}));
+  const int kc = (int)cdiv(cdiv(K, nz), GBK) * GBK;   // whole K steps per slice
+  nz = (int)cdiv(K, kc);
+  if (nz == 1) return gemm<true, false>(s, M, N, K, A, lda, B, ldb, C, N, nullptr, nullptr, 0);
+  const size_t cz = (size_t)M * N;
+  const dim3 grid(cdiv(N, GBN), cdiv(M, GBM), nz);
+  k_gemm<true, false><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, slices, N, nullptr, nullptr,
+                                           0, kc, cz);
+  k_sum_slices<<<cdiv((long)cz, 256), 256, 0, s>>>(slices, nz, (long)cz, C);
   return hipGetLastError();
 }
 
@@ -326,24 +367,21 @@ hr_status loss_and_grad(hr_mlp* n, int B, float* loss) {
   const int W = n->Wd, F = n->F;
   float* g = n->g;
   // layer 3: dW3 = dY^T H2 (1 x W), db3 = sum dY, dH2 = dY W3
-  HR_HIPM((gemm<true, false>(n->stream, 1, W, B, n->dY, 1, n->H2, W, g + n->oW3, W, nullptr,
-                             nullptr, 0)));
+  HR_HIPM(gemm_wgrad(n->stream, 1, W, B, n->dY, 1, n->H2, W, g + n->oW3, n->kpart));
   HR_HIPM(colsum(n->stream, n->dY, B, 1, n->part + 1024, g + n->ob3));
   HR_HIPM((gemm<false, false>(n->stream, B, W, 1, n->dY, 1, n->p + n->oW3, W, n->dH, W, nullptr,
                               nullptr, 0)));
   k_gelu_back<<<cdiv((long)B * W, 256), 256, 0, n->stream>>>(n->dH, n->Z2, n->dZ, (long)B * W);
   HR_HIPM(hipGetLastError());
   // layer 2: dW2 = dZ2^T H1, db2 = colsum dZ2, dH1 = dZ2 W2
-  HR_HIPM((gemm<true, false>(n->stream, W, W, B, n->dZ, W, n->H1, W, g + n->oW2, W, nullptr,
-                             nullptr, 0)));
+  HR_HIPM(gemm_wgrad(n->stream, W, W, B, n->dZ, W, n->H1, W, g + n->oW2, n->kpart));
   HR_HIPM(colsum(n->stream, n->dZ, B, W, n->part + 1024, g + n->ob2));
   HR_HIPM((gemm<false, false>(n->stream, B, W, W, n->dZ, W, n->p + n->oW2, W, n->dH, W, nullptr,
                               nullptr, 0)));
   k_gelu_back<<<cdiv((long)B * W, 256), 256, 0, n->stream>>>(n->dH, n->Z1, n->dZ, (long)B * W);
   HR_HIPM(hipGetLastError());
   // layer 1: dW1 = dZ1^T X, db1 = colsum dZ1
-  HR_HIPM((gemm<true, false>(n->stream, W, F, B, n->dZ, W, n->X, F, g + n->oW1, F, nullptr,
-                             nullptr, 0)));
+  HR_HIPM(gemm_wgrad(n->stream, W, F, B, n->dZ, W, n->X, F, g + n->oW1, n->kpart));
   HR_HIPM(colsum(n->stream, n->dZ, B, W, n->part + 1024, g + n->ob1));
   HR_HIPM(hipStreamSynchronize(n->stream));
   double s = 0.0;
@@ -524,6 +562,7 @@ hr_status hr_mlp_grid_features(hr_mlp* n, const hr_grid* g, const double* cfg9, 
   (void)n;
   if (!g->bound) return mfail(HR_ESTATE, "grid not bound");
   if (!g->have_sources) return mfail(HR_ESTATE, "punctures not set");
+  if (g->d.zo) return mfail(HR_EINVAL, "the warm-start features do not cover SinhCylindrical grids");
   FeatArgs a{};
   a.d = g->d;
   a.x0max = g->coords == HR_SPHERICAL ? g->prm.rmax : 1.0;
@@ -548,6 +587,7 @@ hr_status hr_warm_start(hr_grid* g, hr_mlp* n, const double* cfg9, double eta) {
   if (!g->bound || !n->bound) return mfail(HR_ESTATE, "grid and network must be bound");
   if (!g->have_sources) return mfail(HR_ESTATE, "punctures not set");
   if (!(eta > 0)) return mfail(HR_EINVAL, "eta must be > 0");
+  if (g->d.zo) return mfail(HR_EINVAL, "the warm-start features do not cover SinhCylindrical grids");
   HR_HIPM(hipSetDevice(g->device));
   HR_HIPM(hipStreamSynchronize(g->stream));
   FeatArgs a{};
