@@ -151,12 +151,13 @@ def precision_form(N0: int = 128, N1: int = 128, N2: int = 16) -> Workload:
                     check_every=100, label=f"precision form {g.name()}")
 
 
-def quasi_circular(q: float, D: float, chi1, chi2) -> Punctures:
-    """Newtonian quasi-circular momenta for mass ratio q >= 1 and separation D."""
+def quasi_circular(q: float, D: float, chi1, chi2, p_factor: float = 1.0) -> Punctures:
+    """Newtonian quasi-circular momenta for mass ratio q >= 1 and separation D,
+    scaled by p_factor."""
     m1 = q / (1.0 + q)
     m2 = 1.0 / (1.0 + q)
     mu = m1 * m2
-    p = mu * np.sqrt(1.0 / D)
+    p = p_factor * mu * np.sqrt(1.0 / D)
     chi1 = np.asarray(chi1, float)
     chi2 = np.asarray(chi2, float)
     return _pz([m1, m2], [[0, 0, D / 2], [0, 0, -D / 2]], [[0, p, 0], [0, -p, 0]],
@@ -172,11 +173,14 @@ CATALOG_SHAPES = ((64, 64, 8), (128, 128, 16), (256, 256, 32))
 
 
 def catalog(n: int = 64, seed: int = 14030, fd_order: int = 10,
-            shapes=CATALOG_SHAPES) -> list[Workload]:
+            shapes=CATALOG_SHAPES, p_spread=None) -> list[Workload]:
     """Seed-drawn BBH catalog: q ~ U[1,10], D ~ U[6,20], |chi_i| ~ U[0,0.8] with an
     isotropic direction, Newtonian quasi-circular momenta, grid shape uniform over
-    ``shapes`` (SinhSymTP with bscale = D/2)."""
+    ``shapes`` (SinhSymTP with bscale = D/2). With p_spread = (lo, hi) the momenta
+    are the Newtonian ones times U[lo, hi], drawn from a generator of their own,
+    so the other parameters are those of the catalog without it."""
     rng = np.random.default_rng(seed)
+    prng = np.random.default_rng([seed, 1])
     out = []
     for i in range(n):
         q = rng.uniform(1.0, 10.0)
@@ -184,10 +188,11 @@ def catalog(n: int = 64, seed: int = 14030, fd_order: int = 10,
         chi1 = _isotropic(rng, rng.uniform(0.0, 0.8))
         chi2 = _isotropic(rng, rng.uniform(0.0, 0.8))
         N0, N1, N2 = shapes[rng.integers(len(shapes))]
+        pf = 1.0 if p_spread is None else prng.uniform(p_spread[0], p_spread[1])
         g = GridSpec(SINHSYMTP, N0, N1, N2, fd_order, bscale=D / 2)
-        w = Workload(g, quasi_circular(q, D, chi1, chi2), eta=ETA_PAPER_SCALE,
+        w = Workload(g, quasi_circular(q, D, chi1, chi2, pf), eta=ETA_PAPER_SCALE,
                      n_steps=2_000_000, tol=1e-10, check_every=100, label=f"catalog[{i}]",
-                     extra=dict(q=q, D=D, chi1=chi1, chi2=chi2))
+                     extra=dict(q=q, D=D, chi1=chi1, chi2=chi2, p_factor=pf))
         out.append(w)
     return out
 

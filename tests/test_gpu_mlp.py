@@ -7,7 +7,7 @@ import pytest
 
 import paper_2501_14030_amd as hr
 from paper_2501_14030_amd import warmstart, workloads
-from paper_2501_14030_amd.mlp import MLP
+from paper_2501_14030_amd.mlp import MLP, config_features
 
 from gpu_common import banner
 
@@ -110,21 +110,23 @@ def test_warm_start_predicts_solution_and_saves_steps():
 
 
 def test_warm_start_saves_steps_on_held_out_paper_size_grids():
-    """Trained as the benchmark trains it (512 catalog solves at 64x64x8, 512
-    stored points each, 20 epochs), the network warm-starts eight held-out
-    catalog configurations (seed 14032) at 128x128x16. Each is relaxed to 1e-10
-    from rest, from the warm start (prediction, 100 steps at ten times the
+    """Trained with the standard recipe (warmstart.RECIPE: 4096 catalog solves
+    at 64x64x8 with momenta spread over 1 to 1.3 times the Newtonian estimate,
+    2048 stored points each, 20 epochs), the network warm-starts eight held-out
+    catalog configurations (seed 14032) at 128x128x16 and the paper-scale
+    configuration (q = 1, D = 10, |P| = 0.095, S = 0.2). Each is relaxed to
+    1e-10 from rest, from the warm start (prediction, 100 steps at ten times the
     damping, v = eta u; its steps counted) and, as the control, from rest
-    through the same smoothing phase. Bars: the warm start takes at least 8%
-    fewer steps than rest on average and fewer than the control, and fewer
-    than rest on at least six of the eight grids. Training is deterministic,
-    so the result is reproducible."""
+    through the same smoothing phase. Bars (measured: median prediction error
+    under 2%, 0.75 of the steps from rest): the prediction within 5% of the
+    relaxed solution (median over points) on every grid; at most 0.85 of the
+    steps from rest on average, fewer than the control, fewer than rest on every
+    grid; the paper-scale configuration in fewer steps than from rest. Data and
+    training are deterministic, so the result is reproducible."""
     banner("warm start on held-out 128x128x16 configurations")
-    shape = (64, 64, 8)
-    train_ws = workloads.catalog(512, seed=14031, shapes=(shape,))
-    net = MLP(width=256, seed=1, max_batch=65536)
-    X, T = warmstart.dataset(train_ws, shape, 512, 7, net, log=banner)
-    warmstart.train(net, X, T, 20, 8192, 2e-3, 3, log=lambda m: None)
+    net, info = warmstart.fit(log=banner)
+    banner(f"trained on {info['samples']} samples in {info['train_s']:.1f} s, "
+           f"loss {info['final_loss']:.3e}")
     test_ws = workloads.catalog(8, seed=14032, shapes=((128, 128, 16),))
     ev = warmstart.evaluate(net, test_ws, (128, 128, 16), tol=1e-10, batch=8, log=banner)
     cold = np.array(ev["cold_steps"])
@@ -133,10 +135,25 @@ def test_warm_start_saves_steps_on_held_out_paper_size_grids():
     banner(f"steps cold {cold.tolist()} (mean {cold.mean():.0f}); warm {warm.tolist()} "
            f"(mean {warm.mean():.0f}, {warm.mean() / cold.mean():.3f}); control "
            f"{ctl.tolist()} (mean {ctl.mean():.0f}); prediction error "
-           f"{np.round(ev['pred_rel_err'], 3).tolist()}; residual warm "
-           f"{np.round(ev['initial_residual_warm'], 1).tolist()} -> smoothed "
-           f"{np.round(ev['smoothed_residual_warm'], 2).tolist()}")
-    assert warm.mean() <= 0.92 * cold.mean()
+           f"{np.round(ev['pred_rel_err'], 4).tolist()}")
+    assert max(ev["pred_rel_err"]) < 0.05
+    assert warm.mean() <= 0.85 * cold.mean()
     assert warm.mean() < ctl.mean()
-    assert int((warm < cold).sum()) >= 6
+    assert np.all(warm < cold)
+    # the paper-scale configuration
+    w = workloads.paper_scale()
+    spec = w.grid
+    g = hr.grid_create(spec.coords, *spec.shape, spec.fd_order,
+                       params=hr.default_params(bscale=spec.bscale))
+    g.set_punctures(*w.punctures.as_tuple())
+    r_cold = g.relax(w.eta, w.kappa, 0.0, w.n_steps, w.tol, check_every=w.check_every)
+    g.set_punctures(*w.punctures.as_tuple())
+    cfg = config_features(1.0, [0.0, 0.0, 0.8], [0.0, 0.0, 0.8], 0.095, 10.0)
+    done = warmstart.warm_start(net, g, cfg, w.eta)
+    r_warm = g.relax(w.eta, w.kappa, 0.0, w.n_steps, w.tol, check_every=w.check_every)
+    banner(f"paper-scale configuration: cold {r_cold.steps_taken} steps, warm "
+           f"{done + r_warm.steps_taken}")
+    assert r_cold.status == hr.OK and r_warm.status == hr.OK
+    assert done + r_warm.steps_taken < r_cold.steps_taken
+    g.close()
     net.close()
