@@ -474,10 +474,18 @@ __device__ __forceinline__ void combine_pt(const StageArgs<T>& a, unsigned idx,
 template <int NG>
 __device__ __forceinline__ int step_up(int j, int N) { return j + 1 == N ? 0 : j + 1; }
 
+// Rows of the phi-column kernel's LDS factor table: the FP64 instances keep a
+// column's six Laplacian factors in LDS, each thread reading only its own (in
+// registers they push stages 2 and 3 into spills: 428 -> 411 us per stage at
+// 512x512x64); the FP32 instances do not spill and keep them in registers.
+template <typename T>
+constexpr int kFacRows = sizeof(T) == 8 ? 6 : 1;
+
 template <typename T, int NG, int STAGE, bool CORR, bool ZF>
 __device__ __forceinline__ void stage_col_body(const StageArgs<T>& a, int bx, int by, int bz,
                                                int chunk,
-                                               T (&tile)[2][TileShape<NG>::W * TileShape<NG>::H]) {
+                                               T (&tile)[2][TileShape<NG>::W * TileShape<NG>::H],
+                                               T (&fl)[kFacRows<T>][kTileThreads]) {
   constexpr int W = TileShape<NG>::W;
   constexpr Weights<NG> Wt{};
   const Dims& d = a.d;
@@ -497,7 +505,13 @@ __device__ __forceinline__ void stage_col_body(const StageArgs<T>& a, int bx, in
   int jq = z0;  // (z0 - NG) mod N2, stepping down one plane at a time
 #pragma unroll
   for (int k = 0; k < NG; ++k) jq = (jq == 0) ? d.N2 - 1 : jq - 1;
+  // the column's six Laplacian factors: in LDS (FP64) or registers (FP32)
+  const int ft = threadIdx.x + TX * threadIdx.y;
   T f[6];
+  auto fac = [&](int r) -> T {
+    if constexpr (kFacRows<T> == 6) return fl[r][ft];
+    else return f[r];
+  };
   PointIn<STAGE, CORR, T> cur;
   if (active) {
 #pragma unroll
@@ -506,7 +520,10 @@ __device__ __forceinline__ void stage_col_body(const StageArgs<T>& a, int bx, in
       jq = step_up<NG>(jq, d.N2);
     }
 #pragma unroll
-    for (int r = 0; r < 6; ++r) f[r] = load_factor(a.fac, a.facb, r * n2d + k2);
+    for (int r = 0; r < 6; ++r) {
+      if constexpr (kFacRows<T> == 6) fl[r][ft] = load_factor(a.fac, a.facb, r * n2d + k2);
+      else f[r] = load_factor(a.fac, a.facb, r * n2d + k2);
+    }
     cur.load(a, col + plane * (unsigned)z0);
   }
   // jq now holds (z0 + NG + 1) mod N2: the plane the queue needs next
@@ -545,15 +562,15 @@ __device__ __forceinline__ void stage_col_body(const StageArgs<T>& a, int bx, in
         e2 += (T)Wt.d2[k] * (q[NG + k] + q[NG - k]);
       }
       const T w0 = (T)Wt.d2[0];
-      const T lap = f[0] * (e0 + w0 * uc) + f[1] * (e1 + w0 * uc) + f[2] * (e2 + w0 * uc) +
-                    f[3] * d0 + f[4] * d1;
+      const T lap = fac(0) * (e0 + w0 * uc) + fac(1) * (e1 + w0 * uc) +
+                    fac(2) * (e2 + w0 * uc) + fac(3) * d0 + fac(4) * d1;
       T ku, kv;
       if constexpr (CORR) {
         ku = cur.khu + (cur.v - a.eta * uc);
-        kv = cur.khv + f[5] * (lap + source_delta(cur.ssrc, cur.psi, uc));
+        kv = cur.khv + fac(5) * (lap + source_delta(cur.ssrc, cur.psi, uc));
       } else {
         ku = cur.v - a.eta * uc;
-        kv = f[5] * (lap + source<T>(cur.ssrc, cur.psi, uc));
+        kv = fac(5) * (lap + source<T>(cur.ssrc, cur.psi, uc));
       }
       const unsigned idx = col + plane * (unsigned)z;
       combine_pt<STAGE, CORR, T>(a, idx, cur, uc, ku, kv);
@@ -595,8 +612,9 @@ __device__ __forceinline__ void stage_col_body(const StageArgs<T>& a, int bx, in
 template <typename T, int NG, int STAGE, bool CORR, bool ZF>
 __global__ void __launch_bounds__(kTileThreads, 4) k_stage_col(StageArgs<T> a, int chunk) {
   __shared__ T tile[2][TileShape<NG>::W * TileShape<NG>::H];
+  __shared__ T fl[kFacRows<T>][kTileThreads];
   const TileId tid = xcd_tile();
-  stage_col_body<T, NG, STAGE, CORR, ZF>(a, tid.x, tid.y, tid.z, chunk, tile);
+  stage_col_body<T, NG, STAGE, CORR, ZF>(a, tid.x, tid.y, tid.z, chunk, tile, fl);
 }
 
 // ---------------------------------------------------------------------------
@@ -611,6 +629,7 @@ __global__ void __launch_bounds__(kTileThreads, 4)
     k_batch_stage(const StageArgs<T>* __restrict__ descs, const int4* __restrict__ items,
                   const int* __restrict__ nitems) {
   __shared__ T tile[2][TileShape<NG>::W * TileShape<NG>::H];
+  __shared__ T fl[kFacRows<T>][kTileThreads];
   const int n = *nitems;
   const int G = gridDim.x;
   if (G % kXcds == 0) {
@@ -622,14 +641,14 @@ __global__ void __launch_bounds__(kTileThreads, 4)
     const int lo = x * per + (x < rem ? x : rem), hi = lo + per + (x < rem ? 1 : 0);
     for (int it = lo + k; it < hi; it += gk) {
       const int4 w = items[it];
-      const StageArgs<T> a = descs[4 * w.x + (STAGE - 1)];
-      stage_col_body<T, NG, STAGE, CORR, ZF>(a, w.y, w.z, w.w, a.chunk, tile);
+      const StageArgs<T>& a = descs[4 * w.x + (STAGE - 1)];
+      stage_col_body<T, NG, STAGE, CORR, ZF>(a, w.y, w.z, w.w, a.chunk, tile, fl);
     }
   } else {
     for (int it = blockIdx.x; it < n; it += G) {
       const int4 w = items[it];
-      const StageArgs<T> a = descs[4 * w.x + (STAGE - 1)];
-      stage_col_body<T, NG, STAGE, CORR, ZF>(a, w.y, w.z, w.w, a.chunk, tile);
+      const StageArgs<T>& a = descs[4 * w.x + (STAGE - 1)];
+      stage_col_body<T, NG, STAGE, CORR, ZF>(a, w.y, w.z, w.w, a.chunk, tile, fl);
     }
   }
 }
