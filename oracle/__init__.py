@@ -32,6 +32,7 @@ SINHSYMTP = 0
 SPHERICAL = 1
 SINHSPHERICAL = 2
 SINHCYLINDRICAL = 3
+CARTESIAN = 4          # the cube [-rmax, rmax]^3, outer faces on all six sides
 
 # Readings of parameters the paper leaves to its companion paper.
 DEFAULT_AMAX = 1.0e6

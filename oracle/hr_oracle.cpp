@@ -44,6 +44,13 @@
 //     difference along xx1 where |z| >= rho and along xx0 elsewhere (the
 //     corners toward the rho face), so that the chosen direction is within
 //     45 degrees of the radial one and d r / d xx_i never becomes small;
+//   * Cartesian (the Cartesian-like family of the conclusions): the cube
+//     [-RMAX, RMAX]^3 with xx0, xx1, xx2 = x, y, z. All six faces are outer
+//     boundaries with NG stored layers; a layer point takes its one-sided
+//     difference along its face normal x_d, with d r / d x_d = x_d / r. The
+//     edge and corner points (beyond two or three faces) are read neither by
+//     the star stencil nor by a face point's difference and are not evolved;
+//     there are no parity images;
 //   * psi_singular = 1 + sum_n m_n / (2 r_n);
 //   * A^ij = sum_n 3/(2 r^2) [P^i n^j + P^j n^i - (delta^ij - n^i n^j) P.n]
 //              + 3/r^3 [(S x n)^i n^j + (S x n)^j n^i];
@@ -72,7 +79,8 @@ namespace {
 
 const double kPi = 3.14159265358979323846;
 
-enum { OR_SINHSYMTP = 0, OR_SPHERICAL = 1, OR_SINHSPHERICAL = 2, OR_SINHCYLINDRICAL = 3 };
+enum { OR_SINHSYMTP = 0, OR_SPHERICAL = 1, OR_SINHSPHERICAL = 2, OR_SINHCYLINDRICAL = 3,
+       OR_CARTESIAN = 4 };
 
 // Fornberg's algorithm (B. Fornberg, "Generation of finite difference formulas
 // on arbitrarily spaced grids", Math. Comp. 51 (1988) 699): weights c[j][k] of
@@ -155,8 +163,17 @@ struct Grid {
            i2 >= NG && i2 < NG + N[2];
   }
   // stored outer points: beyond xx0's maximum (interior xx1), and for
-  // SinhCylindrical also every point beyond either z face with xx0 >= 0
+  // SinhCylindrical also every point beyond either z face with xx0 >= 0; for
+  // Cartesian every point beyond exactly one of the six faces (the edge and
+  // corner points beyond two or three faces are never read by the star
+  // stencil or by a face point's normal difference, and are not evolved)
   bool outer(int i0, int i1, int i2) const {
+    if (coords == 4) {
+      const int i[3] = {i0, i1, i2};
+      int out = 0;
+      for (int d = 0; d < 3; ++d) out += (i[d] < NG || i[d] >= NG + N[d]) ? 1 : 0;
+      return out == 1;
+    }
     if (i2 < NG || i2 >= NG + N[2]) return false;
     const bool in1 = i1 >= NG && i1 < NG + N[1];
     if (coords == 3 && !in1) return i0 >= NG;
@@ -180,7 +197,11 @@ void sinh_radial(const Grid& g, double x0, double& A, double& Ap, double& App) {
 // Cartesian position of the point with coordinates (x0, x1, x2).
 void to_cart(const Grid& g, double x0, double x1, double x2, double& x,
              double& y, double& z) {
-  if (g.coords == OR_SINHSYMTP) {
+  if (g.coords == OR_CARTESIAN) {
+    x = x0;
+    y = x1;
+    z = x2;
+  } else if (g.coords == OR_SINHSYMTP) {
     double A, Ap, App;
     sinh_radial(g, x0, A, Ap, App);
     const double R = std::sqrt(A * A + g.b * g.b);
@@ -213,7 +234,14 @@ void to_cart(const Grid& g, double x0, double x1, double x2, double& x,
 void metric_at(const Grid& g, double x0, double x1, double h[3], double* a,
                double* bb) {
   const double s = std::sin(x1), c = std::cos(x1);
-  if (g.coords == OR_SINHSYMTP) {
+  if (g.coords == OR_CARTESIAN) {
+    // the identity map: unit scale factors, no first-derivative terms
+    h[0] = h[1] = h[2] = 1.0;
+    if (a) {
+      a[0] = a[1] = a[2] = 1.0;
+      bb[0] = bb[1] = 0.0;
+    }
+  } else if (g.coords == OR_SINHSYMTP) {
     double A, Ap, App;
     sinh_radial(g, x0, A, Ap, App);
     const double R2 = A * A + g.b * g.b;
@@ -318,6 +346,11 @@ void build_grid(Grid& g) {
   g.xxmax[1] = (g.coords == OR_SINHCYLINDRICAL) ? 1.0 : kPi;
   g.xxmin[2] = -kPi;
   g.xxmax[2] = kPi;
+  if (g.coords == OR_CARTESIAN)   // the cube [-rmax, rmax]^3
+    for (int d = 0; d < 3; ++d) {
+      g.xxmin[d] = -g.rmax;
+      g.xxmax[d] = g.rmax;
+    }
   for (int d = 0; d < 3; ++d) {
     g.dxx[d] = (g.xxmax[d] - g.xxmin[d]) / g.N[d];
     g.xx[d].resize(g.Nx[d]);
@@ -406,6 +439,8 @@ void build_grid(Grid& g) {
           g.img[id] = -1;
         else if (g.outer(i0, i1, i2))
           g.img[id] = -2;
+        else if (g.coords == OR_CARTESIAN)
+          g.img[id] = -4;   // edge or corner point: never read, not evolved
         else
           g.img[id] = image_of(g, i0, i1, i2);
       }
@@ -490,7 +525,9 @@ void rhs(const Grid& g, double eta, double kappa, const double* u,
         ku[id] = v[id] - eta * u[id];
         kv[id] = c * c * (lap + source_at(g, id, u[id]));
       }
-  // outer points: radiation condition
+  // outer points beyond xx0's maximum: radiation condition (Cartesian grids
+  // take all six faces below)
+  if (g.coords != OR_CARTESIAN)
 #pragma omp parallel for collapse(2) schedule(static)
   for (int i2 = NG; i2 < NG + g.N[2]; ++i2)
     for (int i1 = NG; i1 < NG + g.N[1]; ++i1)
@@ -558,6 +595,47 @@ void rhs(const Grid& g, double eta, double kappa, const double* u,
         }
       }
   }
+  // Cartesian face points: the same condition with the radial derivative
+  // from a one-sided difference along the face normal d toward the interior,
+  // d_r f = (d f / d x_d) / (d r / d x_d), d r / d x_d = x_d / r
+  if (g.coords == OR_CARTESIAN) {
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int i2 = 0; i2 < g.Nx[2]; ++i2)
+      for (int i1 = 0; i1 < g.Nx[1]; ++i1)
+        for (int i0 = 0; i0 < g.Nx[0]; ++i0) {
+          if (!g.outer(i0, i1, i2)) continue;
+          const int ii[3] = {i0, i1, i2};
+          int d = 0;
+          while (ii[d] >= NG && ii[d] < NG + g.N[d]) ++d;
+          const int dir = ii[d] < NG ? -1 : 1;   // outward along x_d
+          auto at = [&](int q) {
+            int j[3] = {i0, i1, i2};
+            j[d] -= q * dir;
+            return g.idx(j[0], j[1], j[2]);
+          };
+          const long id = g.idx(i0, i1, i2);
+          const double c = kappa * g.dsmin[g.idx2(i0, i1)] / g.ds_g;
+          const double x = g.X[id], y = g.Y[id], z = g.Z[id];
+          const double r = std::sqrt(x * x + y * y + z * z);
+          const double xd = d == 0 ? x : (d == 1 ? y : z);
+          const double h = g.dxx[d];
+          double dudx = 0.0, dvdx = 0.0;
+          if (g.bc_order == 2) {
+            dudx = dir * (3.0 * u[id] - 4.0 * u[at(1)] + u[at(2)]) / (2.0 * h);
+            dvdx = dir * (3.0 * v[id] - 4.0 * v[at(1)] + v[at(2)]) / (2.0 * h);
+          } else {
+            for (int q = 0; q <= g.bc_order; ++q) {
+              dudx += g.wbc[q] * u[at(q)];
+              dvdx += g.wbc[q] * v[at(q)];
+            }
+            dudx *= dir / h;
+            dvdx *= dir / h;
+          }
+          const double drdx = xd / r;
+          ku[id] = -c * (u[id] / r + dudx / drdx);
+          kv[id] = -c * (v[id] / r + dvdx / drdx);
+        }
+  }
   // inner ghosts: copy from images (parity +1)
   const long np = g.npad();
 #pragma omp parallel for schedule(static)
@@ -617,6 +695,7 @@ bool set_bc_order(Grid& g, int order) {
   if (order != 2 && order != 4) return false;
   if (g.N[0] < order) return false;  // the difference stays on interior points
   if (g.coords == OR_SINHCYLINDRICAL && g.N[1] < order) return false;  // z faces too
+  if (g.coords == OR_CARTESIAN && (g.N[1] < order || g.N[2] < order)) return false;
   std::vector<double> off(order + 1);
   for (int k = 0; k <= order; ++k) off[k] = -k;
   std::vector<std::vector<double>> c;
@@ -688,11 +767,16 @@ extern "C" {
 void* or_create(int coords, int N0, int N1, int N2, int fd_order, double amax,
                 double sinhwaa, double bscale, double rmax) {
   if (coords != OR_SINHSYMTP && coords != OR_SPHERICAL && coords != OR_SINHSPHERICAL &&
-      coords != OR_SINHCYLINDRICAL)
+      coords != OR_SINHCYLINDRICAL && coords != OR_CARTESIAN)
     return nullptr;
   if (fd_order < 2 || fd_order % 2 || fd_order > 12) return nullptr;
   const int NG = fd_order / 2;
-  if (N0 < NG || N1 < NG || N2 < 2 || N2 % 2) return nullptr;
+  if (coords == OR_CARTESIAN) {
+    // no phi: any N2; every axis carries a face's normal difference
+    if (N0 < std::max(NG, 2) || N1 < std::max(NG, 2) || N2 < std::max(NG, 2)) return nullptr;
+  } else if (N0 < NG || N1 < NG || N2 < 2 || N2 % 2) {
+    return nullptr;
+  }
   Grid* g = new Grid();
   g->coords = coords;
   g->N[0] = N0;

@@ -39,7 +39,7 @@ def _jac(g, x0, x1, x2, eps):
 
 
 COORDS = [(0, SINH_MILD), (0, SINH), (1, dict(rmax=100.0)), (2, SSPH_MILD), (2, SSPH),
-          (3, SCYL_MILD), (3, SCYL)]
+          (3, SCYL_MILD), (3, SCYL), (4, dict(rmax=2.0))]
 
 
 @pytest.mark.parametrize("coords,kw", COORDS)

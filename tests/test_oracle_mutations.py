@@ -35,6 +35,14 @@ MUTATIONS = [
     ("SinhCylindrical z-face difference not mirrored on the lower face",
      "const int dir = a1 ? (i1 < NG ? -1 : 1) : 1;", "const int dir = 1;",
      pins.check_sinhcylindrical_bc),
+    ("Cartesian face difference not mirrored on the lower faces",
+     "const int dir = ii[d] < NG ? -1 : 1;   // outward along x_d", "const int dir = 1;",
+     pins.check_cartesian_bc),
+    ("Cartesian dr/dx_d = 1", "const double drdx = xd / r;", "const double drdx = 1.0;",
+     pins.check_cartesian_bc),
+    ("Cartesian face difference along x0 on every face",
+     "while (ii[d] >= NG && ii[d] < NG + g.N[d]) ++d;", "while (false) ++d;",
+     pins.check_cartesian_bc),
 ]
 
 

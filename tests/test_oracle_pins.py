@@ -196,6 +196,67 @@ def test_sinhcylindrical_radiation_condition_exact_on_polynomials(oracle_lib, or
     check_sinhcylindrical_bc(oracle_lib, order)
 
 
+def cartesian_bc_errors(orc, order: int = 2):
+    """(max error for degrees <= order, smallest error at degree order + 1),
+    relative, over the six faces of a Cartesian grid: on the two faces normal
+    to x_d the field is a polynomial in x_d, the condition's one-sided
+    difference runs along x_d toward the interior and d r / d x_d is taken
+    from the coordinate map numerically."""
+    g = orc.OracleGrid(orc.CARTESIAN, 10, 8, 6, 8, rmax=3.0)
+    g.set_bc_order(order)
+    ng, N = g.NG, g.N
+    X, Y, Z = g.cart()
+    r = np.sqrt(X ** 2 + Y ** 2 + Z ** 2)
+    img = g.bc_images()
+    c = g.metric()["dsmin"] / g.ds_g()   # uniform on this grid
+    exact_err, beyond_err = 0.0, np.inf
+    h = 1e-3
+    for d in range(3):
+        xs = g.xx(d)
+        idx = np.argwhere(img.reshape(g.shape) == -2)   # (i2, i1, i0)
+        # face points beyond a face normal to x_d
+        pts = np.array([q for q in idx
+                        if q[2 - d] < ng or q[2 - d] >= ng + N[d]])
+        assert len(pts) == 2 * ng * int(np.prod(N)) // N[d]
+        i2, i1, i0 = pts[:, 0], pts[:, 1], pts[:, 2]
+        xd = (X, Y, Z)[d][i2, i1, i0]
+        # d |x| / d x_d from the map at each point (sixth-order difference)
+        base = np.stack([X[i2, i1, i0], Y[i2, i1, i0], Z[i2, i1, i0]], axis=1)
+
+        def rad(t):
+            p = base.copy()
+            p[:, d] = t
+            return np.array([np.linalg.norm(g.to_cart(*q)) for q in p])
+
+        drdx = (-rad(xd - 3 * h) + 9 * rad(xd - 2 * h) - 45 * rad(xd - h) + 45 * rad(xd + h)
+                - 9 * rad(xd + 2 * h) + rad(xd + 3 * h)) / (60 * h)
+        for deg in range(order + 2):
+            fx = np.polynomial.Polynomial(np.arange(1, deg + 2, dtype=float) / (deg + 1))
+            shape = [1, 1, 1]
+            shape[2 - d] = len(xs)
+            f = np.broadcast_to(fx(xs).reshape(shape), g.shape).copy()
+            ku, _ = g.rhs(0.0, 1.0, f, np.zeros(g.shape))
+            got = ku[i2, i1, i0]
+            want = -c[i1, i0] * (fx(xd) / r[i2, i1, i0] + fx.deriv()(xd) / drdx)
+            err = float(np.abs(got - want).max() / np.abs(want).max())
+            if deg <= order:
+                exact_err = max(exact_err, err)
+            else:
+                beyond_err = min(beyond_err, err)
+    return exact_err, beyond_err
+
+
+def check_cartesian_bc(orc, order: int = 2) -> None:
+    exact, beyond = cartesian_bc_errors(orc, order)
+    assert exact < 1e-10, exact
+    assert beyond > 1e-8, beyond
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_cartesian_radiation_condition_exact_on_polynomials(oracle_lib, order):
+    check_cartesian_bc(oracle_lib, order)
+
+
 # --- Eq. (4): source factor and exponent ------------------------------------
 
 def boosted_puncture_u(m: float, P: float, R: float, r: np.ndarray, cos_t: np.ndarray):

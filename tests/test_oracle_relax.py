@@ -125,10 +125,14 @@ def _newton_steady_state(g, eta, kappa):
 
 
 @pytest.mark.parametrize("coords,shape,order", [(0, (8, 4, 2), 4), (0, (6, 4, 4), 8),
-                                                (3, (6, 6, 2), 4), (3, (4, 4, 2), 8)])
+                                                (3, (6, 6, 2), 4), (3, (4, 4, 2), 8),
+                                                (4, (4, 4, 4), 4), (4, (6, 4, 4), 8)])
 def test_relaxation_converges_to_newton_solution(oracle_lib, coords, shape, order):
-    # coords 3 (SinhCylindrical) adds the z faces' outer points to the unknowns
-    g = oracle_lib.OracleGrid(coords, *shape, order, **TINY)
+    # coords 3 (SinhCylindrical) adds the z faces' outer points to the unknowns,
+    # coords 4 (Cartesian) the points of all six faces; its cube [-2, 2]^3 keeps
+    # eta dt = 2 inside RK4's real-axis stability interval (2.79)
+    kw = dict(rmax=2.0) if coords == 4 else TINY
+    g = oracle_lib.OracleGrid(coords, *shape, order, **kw)
     m = [0.5, 0.5]
     x = [[0, 0, 1.0], [0, 0, -1.0]]
     P = [[0, 0.2, 0], [0, -0.2, 0]]
