@@ -57,9 +57,11 @@ typedef enum {
   HR_SINHSYMTP = 0,    /* prolate-spheroidal, sinh-stretched radial coordinate */
   HR_SPHERICAL = 1,    /* uniform r in [0, rmax], theta, phi */
   HR_SINHSPHERICAL = 2, /* r = amax sinh(xx0/w)/sinh(1/w), xx0 in [0,1], theta, phi */
-  HR_SINHCYLINDRICAL = 3 /* rho = A(xx0), z = A(xx1), xx1 in [-1,1], phi; the
+  HR_SINHCYLINDRICAL = 3, /* rho = A(xx0), z = A(xx1), xx1 in [-1,1], phi; the
                             same sinh stretching A for rho and z; both z faces
                             are outer boundaries */
+  HR_CARTESIAN = 4        /* x, y, z in the cube [-rmax, rmax]^3; all six faces
+                             are outer boundaries, no parity images */
 } hr_coords;
 
 typedef enum {
@@ -77,7 +79,7 @@ typedef enum {
  *   A(xx0) = amax sinh(xx0/sinhwaa)/sinh(1/sinhwaa), xx0 in [0,1],
  *   x = A sin(xx1) cos(xx2), y = A sin(xx1) sin(xx2),
  *   z = sqrt(A^2 + bscale^2) cos(xx1); foci (0,0,+-bscale).
- * Spherical: r = xx0 in [0, rmax].
+ * Spherical: r = xx0 in [0, rmax]. Cartesian: rmax is the cube's half side.
  * cfl: dt = cfl * ds_g when hr_relax receives dt <= 0, ds_g = smallest proper
  * cell width over the interior.
  */
@@ -97,15 +99,22 @@ void hr_default_params(hr_grid_params* p);
  * Algorithm 1 that sample the coordinates xx^i and precompute the reference
  * metric (here the Laplacian factors of Eq. 4 per (xx0, xx1), the wave speed
  * and the outer-boundary geometry), on the SinhSymTP grids of the "Basic
- * equations" section or the spherical-like and cylindrical-like families the
- * conclusions name.
- *   coords   HR_SINHSYMTP, HR_SPHERICAL, HR_SINHSPHERICAL or HR_SINHCYLINDRICAL
+ * equations" section or the spherical-like, cylindrical-like and
+ * Cartesian-like families the conclusions name.
+ *   coords   HR_SINHSYMTP, HR_SPHERICAL, HR_SINHSPHERICAL, HR_SINHCYLINDRICAL or
+ *            HR_CARTESIAN
  *   N0,N1,N2 interior points along xx0, xx1 (theta, or z for SinhCylindrical),
  *            xx2 (phi); N0 >= NG, N1 >= NG, N2 even and >= 2 (phi + pi parity
  *            images), total stored points below 2^31. SinhCylindrical also
  *            stores NG outer rows beyond each z face, so its extended layout
  *            (hr_get_u) is (N0 + NG) x (N1 + 2 NG) x N2; the warm-start
- *            network does not take these grids.
+ *            network does not take these grids. Cartesian grids (x, y, z
+ *            along xx0, xx1, xx2; each N_d >= max(NG, 2), any parity) store NG
+ *            outer layers beyond every face: the extended layout is the padded
+ *            box (N0 + 2 NG) x (N1 + 2 NG) x (N2 + 2 NG), whose edge and corner
+ *            points are never read and stay zero. They relax in HR_FP64 only
+ *            on the stage kernels (no resident kernel, batch, volume norm or
+ *            warm start: those calls return HR_EINVAL for them).
  *   fd_order centred finite-difference order: 2, 4, 6, 8 or 10
  *   p        coordinate parameters, NULL for defaults (copied)
  *   out      receives the handle; free it with hr_grid_destroy.
@@ -295,7 +304,8 @@ typedef enum {
  * weights on the device. Grids in a batch must use HR_NORM_POINTS
  * (hr_batch_relax returns HR_EINVAL otherwise). Errors: HR_EINVAL (null grid,
  * unknown norm, non-finite radius, radius > 0 with HR_NORM_POINTS, no cell
- * centre within the radius), HR_EDEVICE.
+ * centre within the radius, HR_NORM_VOLUME on a Cartesian grid, whose cells are
+ * all equal), HR_EDEVICE.
  */
 hr_status hr_set_residual_norm(hr_grid* g, hr_norm norm, double radius);
 
@@ -354,8 +364,11 @@ hr_status hr_get_kernel_config(const hr_grid* g, hr_kernel_config* cfg);
  * condition itself comes from the companion paper): 2 (default) takes the
  * point and two inner neighbours along xx0, 4 the point and four. The steady
  * state depends on the choice through the boundary only. Applies to every
- * precision, kernel variant and to batches. Errors: HR_EINVAL (null grid,
- * order not 2 or 4, N0 < order).
+ * precision, kernel variant and to batches. On the z faces of SinhCylindrical
+ * and every face of a Cartesian grid the difference runs along that face's
+ * direction (see hr_grid_create) with the same order. Errors: HR_EINVAL (null
+ * grid, order not 2 or 4, N0 < order, or N1 (SinhCylindrical, Cartesian) or N2
+ * (Cartesian) < order).
  */
 hr_status hr_set_outer_bc_order(hr_grid* g, int order);
 
@@ -452,8 +465,9 @@ hr_status hr_get_launch_timing(const hr_grid* g, double* total_us, long* launche
  * relaxing; the launches of one check interval are captured once in a HIP
  * graph and replayed. Each grid keeps its own dt (cfl * ds_g), eta and
  * wave-speed scale, and stops at its own first check below tol.
- *   hr_batch_create     n >= 1 distinct bound grids (array copied). Errors:
- *                       HR_EINVAL, HR_ESTATE (a grid not bound).
+ *   hr_batch_create     n >= 1 distinct bound grids (array copied), none of
+ *                       them Cartesian. Errors: HR_EINVAL, HR_ESTATE (a grid
+ *                       not bound).
  *   hr_batch_workspace_bytes / hr_batch_bind
  *                       device memory for descriptors and work lists, owned
  *                       by the caller, 256-byte aligned; hip_stream NULL = the

@@ -24,6 +24,7 @@ SINHSYMTP = 0
 SPHERICAL = 1
 SINHSPHERICAL = 2
 SINHCYLINDRICAL = 3
+CARTESIAN = 4            # the cube [-rmax, rmax]^3, outer layers beyond all six faces
 
 FP64 = 0
 FP32 = 1
@@ -299,9 +300,12 @@ class Grid:
         N0, N1, N2 = self.N
         if not extended:
             return out.reshape(N2, N1, N0)
+        ng = self.NG
+        if self.coords == CARTESIAN:   # the padded box: NG layers beyond every face
+            return out.reshape(N2 + 2 * ng, N1 + 2 * ng, N0 + 2 * ng)
         # SinhCylindrical stores NG outer rows beyond each z face
-        rows = N1 + 2 * self.NG if self.coords == SINHCYLINDRICAL else N1
-        return out.reshape(N2, rows, N0 + self.NG)
+        rows = N1 + 2 * ng if self.coords == SINHCYLINDRICAL else N1
+        return out.reshape(N2, rows, N0 + ng)
 
     def get_u(self, extended: bool = False) -> np.ndarray:
         return self._get(load_library().hr_get_u, extended)
@@ -506,4 +510,4 @@ def residual_l2(grid: Grid) -> float:
 
 __all__ = ["Grid", "Batch", "GridParams", "RelaxResult", "HRError", "grid_create", "set_punctures",
            "relax", "relax_noalloc", "get_u", "residual_l2", "load_library", "default_params",
-           "SINHSYMTP", "SPHERICAL", "SINHSPHERICAL", "SINHCYLINDRICAL", "FP64", "FP32", "FP32_FP64FINISH"]
+           "SINHSYMTP", "SPHERICAL", "SINHSPHERICAL", "SINHCYLINDRICAL", "CARTESIAN", "FP64", "FP32", "FP32_FP64FINISH"]

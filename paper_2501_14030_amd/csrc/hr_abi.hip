@@ -78,6 +78,11 @@ bool resident_split_ok(const hr_grid* g) {
 void resolve_variant(const hr_grid* g, int& variant, int& chunk) {
   variant = g->variant;
   chunk = g->chunk;
+  if (g->d.cart) {   // one kernel family (interior tiles + faces) for Cartesian grids
+    variant = 1;
+    chunk = 0;
+    return;
+  }
   const long tiles = (long)((g->d.N0 + kTileX - 1) / kTileX) * ((g->d.N1 + kTileY - 1) / kTileY);
   if (variant == 0) {
     if (resident_ok(g))
@@ -110,12 +115,21 @@ hr_status load_kappa(hr_grid* g, double kappa) {
     ofac[2 * (size_t)o2d + k] = g->tab.oq[k];
   }
   const int z2d = d.P0 * 2 * d.zo;
-  std::vector<double> zfac(4 * (size_t)z2d);
-  for (int k = 0; k < z2d; ++k) {
-    zfac[k] = kappa * g->tab.zcrat[k];
-    zfac[z2d + k] = g->tab.zrinv[k];
-    zfac[2 * (size_t)z2d + k] = g->tab.zq[k];
-    zfac[3 * (size_t)z2d + k] = g->tab.zstep[k];   // small integers: exact in FP32
+  std::vector<double> zfac;
+  if (d.cart) {
+    // Cartesian: the stored coordinates, then kappa (the wave speed everywhere)
+    // and the three cell widths
+    zfac = g->tab.cx;
+    zfac.push_back(kappa);
+    for (int a = 0; a < 3; ++a) zfac.push_back(2.0 * g->prm.rmax / (a == 0 ? d.N0 : a == 1 ? d.N1 : d.N2));
+  } else {
+    zfac.assign(4 * (size_t)z2d, 0.0);
+    for (int k = 0; k < z2d; ++k) {
+      zfac[k] = kappa * g->tab.zcrat[k];
+      zfac[z2d + k] = g->tab.zrinv[k];
+      zfac[2 * (size_t)z2d + k] = g->tab.zq[k];
+      zfac[3 * (size_t)z2d + k] = g->tab.zstep[k];   // small integers: exact in FP32
+    }
   }
   std::vector<float> fac32(fac.begin(), fac.end()), ofac32(ofac.begin(), ofac.end());
   std::vector<float> zfac32(zfac.begin(), zfac.end());
@@ -138,7 +152,7 @@ hr_status load_kappa(hr_grid* g, double kappa) {
                         hipMemcpyHostToDevice, g->stream));
   HR_HIPK(hipMemcpyAsync(g->f32.ofac, ofac32.data(), ofac32.size() * sizeof(float),
                         hipMemcpyHostToDevice, g->stream));
-  if (z2d > 0) {
+  if (!zfac.empty()) {
     HR_HIPK(hipMemcpyAsync(g->f64.zfac, zfac.data(), zfac.size() * sizeof(double),
                           hipMemcpyHostToDevice, g->stream));
     HR_HIPK(hipMemcpyAsync(g->f32.zfac, zfac32.data(), zfac32.size() * sizeof(float),
@@ -181,7 +195,11 @@ size_t layout(hr_grid* g, char* base) {
   };
   const size_t G = g->G;
   const int n2d = g->d.N0 * g->d.N1, o2d = g->d.NG * g->d.N1, e2d = g->d.P0 * g->d.R1;
-  const int z2d = g->d.P0 * 2 * g->d.zo;
+  // z-face tables (SinhCylindrical) or, for Cartesian grids, the stored
+  // coordinates and kappa
+  const Dims& dd = g->d;
+  const size_t zn = dd.cart ? (size_t)(dd.P0 + dd.R1 + planes_of(dd) + 4)
+                            : 4 * (size_t)dd.P0 * 2 * dd.zo;
   double** d64[] = {&g->f64.un, &g->f64.vn, &g->f64.ua, &g->f64.va, &g->f64.ub,
                     &g->f64.vb, &g->f64.au, &g->f64.av, &g->f64.psi, &g->f64.ssrc};
   for (double** p : d64) *p = (double*)take(G * sizeof(double));
@@ -194,8 +212,8 @@ size_t layout(hr_grid* g, char* base) {
   g->f32.facb = (unsigned short*)take(6 * (size_t)n2d * sizeof(unsigned short));
   g->f64.facb = nullptr;
   g->f64.ofac = (double*)take(3 * (size_t)o2d * sizeof(double));
-  g->f64.zfac = z2d ? (double*)take(4 * (size_t)z2d * sizeof(double)) : nullptr;
-  g->f32.zfac = z2d ? (float*)take(4 * (size_t)z2d * sizeof(float)) : nullptr;
+  g->f64.zfac = zn ? (double*)take(zn * sizeof(double)) : nullptr;
+  g->f32.zfac = zn ? (float*)take(zn * sizeof(float)) : nullptr;
   g->f32.ofac = (float*)take(3 * (size_t)o2d * sizeof(float));
   g->rho = (double*)take(e2d * sizeof(double));
   g->zc = (double*)take(e2d * sizeof(double));
@@ -459,7 +477,7 @@ hr_status residual_of(hr_grid* g, const void* u, bool fp32, double* out) {
   return HR_OK;
 }
 
-int ext_count(const hr_grid* g) { return g->d.P0 * g->d.R1 * g->d.N2; }
+int ext_count(const hr_grid* g) { return g->d.P0 * g->d.R1 * planes_of(g->d); }
 
 hr_status check_ready(const hr_grid* g, bool need_sources) {
   if (!g) return fail(HR_EINVAL, "null grid handle");
@@ -499,10 +517,38 @@ hr_status set_field(hr_grid* g, double* dev, const double* host, size_t n) {
   const size_t next = ext_count(g), nint = g->d.nint;
   if (n != next && n != nint)
     return fail(HR_EINVAL, "n must equal the interior or the extended point count");
-  std::vector<double> tmp(next);
+  std::vector<double> tmp(next, 0.0);
   const Dims& d = g->d;
   if (n == next) {
     std::memcpy(tmp.data(), host, next * sizeof(double));
+  } else if (d.cart) {
+    // interior rows, then each face point as its face's adjacent interior point
+    // (along the normal) continued as 1/r; edge and corner points stay zero
+    for (int i2 = 0; i2 < d.N2; ++i2)
+      for (int i1 = 0; i1 < d.N1; ++i1)
+        std::memcpy(tmp.data() + sidx(d, 0, i1, i2), host + (size_t)d.N0 * (i1 + (size_t)d.N1 * i2),
+                    d.N0 * sizeof(double));
+    const double* cx = g->tab.cx.data();
+    const int NG = d.NG, n3[3] = {d.N0, d.N1, d.N2};
+    auto rad = [&](const int* i) {
+      const double x = cx[i[0] + NG], y = cx[d.P0 + i[1] + NG], z = cx[d.P0 + d.R1 + i[2] + NG];
+      return std::sqrt(x * x + y * y + z * z);
+    };
+    for (int i2 = -NG; i2 < d.N2 + NG; ++i2)
+      for (int i1 = -NG; i1 < d.N1 + NG; ++i1)
+        for (int i0 = -NG; i0 < d.N0 + NG; ++i0) {
+          const int i[3] = {i0, i1, i2};
+          int beyond = 0, ax = 0;
+          for (int a = 0; a < 3; ++a)
+            if (i[a] < 0 || i[a] >= n3[a]) {
+              ++beyond;
+              ax = a;
+            }
+          if (beyond != 1) continue;
+          int j[3] = {i0, i1, i2};
+          j[ax] = i[ax] < 0 ? 0 : n3[ax] - 1;
+          tmp[sidx(d, i0, i1, i2)] = tmp[sidx(d, j[0], j[1], j[2])] * rad(j) / rad(i);
+        }
   } else {
     for (int i2 = 0; i2 < d.N2; ++i2)
       for (int i1 = 0; i1 < d.N1; ++i1) {
@@ -1021,15 +1067,22 @@ hr_status hr_grid_create(hr_coords coords, int N0, int N1, int N2, int fd_order,
   if (!out) return fail(HR_EINVAL, "null output handle pointer");
   *out = nullptr;
   if (coords != HR_SINHSYMTP && coords != HR_SPHERICAL && coords != HR_SINHSPHERICAL &&
-      coords != HR_SINHCYLINDRICAL)
+      coords != HR_SINHCYLINDRICAL && coords != HR_CARTESIAN)
     return fail(HR_EINVAL, "unknown coordinate system");
   if (fd_order != 2 && fd_order != 4 && fd_order != 6 && fd_order != 8 && fd_order != 10)
     return fail(HR_EINVAL, "fd_order must be 2, 4, 6, 8 or 10");
   const int NG = fd_order / 2;
-  if (N0 < NG || N0 < 2 || N1 < NG || N2 < 2 || (N2 % 2) != 0)
+  const bool cart = coords == HR_CARTESIAN;
+  if (cart) {
+    const int nmin = std::max(NG, 2);
+    if (N0 < nmin || N1 < nmin || N2 < nmin)
+      return fail(HR_EINVAL, "Cartesian grids need N0, N1, N2 >= max(NG, 2)");
+  } else if (N0 < NG || N0 < 2 || N1 < NG || N2 < 2 || (N2 % 2) != 0) {
     return fail(HR_EINVAL, "need N0 >= max(NG,2), N1 >= NG, N2 even and >= 2");
-  const int zo = coords == HR_SINHCYLINDRICAL ? NG : 0;
-  const long long next = (long long)(N0 + NG) * (N1 + 2 * zo) * N2;
+  }
+  const int zo = coords == HR_SINHCYLINDRICAL || cart ? NG : 0;
+  const int xo = cart ? NG : 0;   // outer layers below x0 = 0 and on the z faces
+  const long long next = (long long)(N0 + NG + xo) * (N1 + 2 * zo) * (N2 + 2 * xo);
   if (next >= (1LL << 31) - 4096) return fail(HR_EINVAL, "grid too large");
   hr_grid_params prm;
   hr_default_params(&prm);
@@ -1041,6 +1094,7 @@ hr_status hr_grid_create(hr_coords coords, int N0, int N1, int N2, int fd_order,
     return fail(HR_EINVAL, "SinhSpherical needs amax, sinhwaa > 0");
   if (coords == HR_SINHCYLINDRICAL && !(prm.amax > 0 && prm.sinhwaa > 0))
     return fail(HR_EINVAL, "SinhCylindrical needs amax, sinhwaa > 0");
+  if (cart && !(prm.rmax > 0)) return fail(HR_EINVAL, "rmax (the cube's half side) must be > 0");
   if (!(prm.cfl > 0)) return fail(HR_EINVAL, "cfl must be > 0");
   hr_grid* g = new (std::nothrow) hr_grid();
   if (!g) return fail(HR_ENOMEM, "host allocation failed");
@@ -1051,13 +1105,14 @@ hr_status hr_grid_create(hr_coords coords, int N0, int N1, int N2, int fd_order,
   g->d.N1 = N1;
   g->d.N2 = N2;
   g->d.NG = NG;
-  g->d.P0 = N0 + NG;
+  g->d.P0 = N0 + NG + xo;
   g->d.nint = N0 * N1 * N2;
   g->d.nout = NG * N1 * N2;
   // spherical families: the xx0 image mirrors theta
   g->d.sph = coords == HR_SPHERICAL || coords == HR_SINHSPHERICAL ? 1 : 0;
   g->d.zo = zo;
   g->d.R1 = N1 + 2 * zo;
+  g->d.cart = cart ? 1 : 0;
   g->G = align_up((size_t)next, 64);
   g->nblk_res = residual_blocks(g->d);
   g->res[0].ry = 8;
@@ -1191,8 +1246,12 @@ hr_status hr_set_punctures(hr_grid* g, int n, const double* m, const double* x,
   }
   hr_status st = check_ready(g, false);
   if (st != HR_OK) return st;
-  HR_HIP(launch_sources(g->d, g->rho, g->zc, g->cphi, g->sphi, pz, g->f64.psi, g->f64.ssrc,
-                        g->f32.psi, g->f32.ssrc, g->stream));
+  if (g->d.cart)
+    HR_HIP(launch_cart_sources(g->d, g->f64.zfac, pz, g->f64.psi, g->f64.ssrc, g->f32.psi,
+                               g->f32.ssrc, g->stream));
+  else
+    HR_HIP(launch_sources(g->d, g->rho, g->zc, g->cphi, g->sphi, pz, g->f64.psi, g->f64.ssrc,
+                          g->f32.psi, g->f32.ssrc, g->stream));
   const int G = (int)g->G;
   HR_HIP(launch_fill(g->f64.un, 0.0, G, g->stream));
   HR_HIP(launch_fill(g->f64.vn, 0.0, G, g->stream));
@@ -1219,6 +1278,8 @@ hr_status hr_relax(hr_grid* g, double eta, double c, double dt, long n_steps, do
   if (st != HR_OK) return st;
   if (prec != HR_FP64 && prec != HR_FP32 && prec != HR_FP32_FP64FINISH)
     return fail(HR_EINVAL, "unknown precision");
+  if (g->d.cart && prec == HR_FP32_FP64FINISH)
+    return fail(HR_EINVAL, "Cartesian grids relax in HR_FP64 or HR_FP32 (no split-state form)");
   return relax_impl(g, eta, c, dt, n_steps, tol, check_every, prec, rep);
 }
 
@@ -1317,6 +1378,8 @@ hr_status hr_time_stage_kernels(hr_grid* g, double eta, double c, double dt, lon
     return fail(HR_EINVAL, "need avg_us, n_steps > 0, eta > 0, c > 0");
   if (prec != HR_FP64 && prec != HR_FP32 && prec != HR_FP32_FP64FINISH)
     return fail(HR_EINVAL, "unknown precision");
+  if (g->d.cart && prec == HR_FP32_FP64FINISH)
+    return fail(HR_EINVAL, "Cartesian grids have no split-state form");
   if (dt <= 0) dt = g->prm.cfl * g->tab.ds_g;
   HR_HIP(hipSetDevice(g->device));
   st = load_kappa(g, c);
@@ -1457,6 +1520,8 @@ hr_status hr_set_residual_norm(hr_grid* g, hr_norm norm, double radius) {
   if (!std::isfinite(radius)) return fail(HR_EINVAL, "radius must be finite");
   if (norm == HR_NORM_POINTS && radius > 0.0)
     return fail(HR_EINVAL, "an integration radius applies to HR_NORM_VOLUME only");
+  if (g->d.cart && norm != HR_NORM_POINTS)
+    return fail(HR_EINVAL, "Cartesian grids use the point norm (their cells are all equal)");
   const Dims& d = g->d;
   std::vector<double> w(g->tab.vol);
   double tot = g->tab.vol_total;
@@ -1489,6 +1554,8 @@ hr_status hr_set_outer_bc_order(hr_grid* g, int order) {
     return fail(HR_EINVAL, "the one-sided difference needs N0 >= its order");
   if (g->d.zo && order > g->d.N1)
     return fail(HR_EINVAL, "on the z faces the one-sided difference needs N1 >= its order");
+  if (g->d.cart && order > g->d.N2)
+    return fail(HR_EINVAL, "on the z faces the one-sided difference needs N2 >= its order");
   g->bc_order = order;
   return HR_OK;
 }
@@ -1526,7 +1593,7 @@ hr_status hr_autotune(hr_grid* g, hr_precision prec, int n_steps, hr_kernel_conf
   if (st != HR_OK) return st;
   if (n_steps < 1) return fail(HR_EINVAL, "n_steps must be >= 1");
   if (prec != HR_FP64 && prec != HR_FP32) return fail(HR_EINVAL, "prec must be FP64 or FP32");
-  const auto key = std::make_tuple(g->d.N0, g->d.N1, g->d.N2, g->fd_order, (int)prec);
+  const auto key = std::make_tuple(g->d.N0, g->d.N1, g->d.N2, g->fd_order, (int)prec + 2 * g->d.cart);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(key);
@@ -1542,7 +1609,9 @@ hr_status hr_autotune(hr_grid* g, hr_precision prec, int n_steps, hr_kernel_conf
   HR_HIP(hipSetDevice(g->device));
   std::vector<hr_kernel_config> cand;
   cand.push_back(hr_kernel_config{1, 0, 0, g->graph});
-  for (int c = 1; c <= g->d.N2; c *= 2) cand.push_back(hr_kernel_config{2, 0, c, g->graph});
+  // Cartesian grids have one kernel family: nothing to choose
+  for (int c = 1; c <= g->d.N2 && !g->d.cart; c *= 2)
+    cand.push_back(hr_kernel_config{2, 0, c, g->graph});
   if (prec == HR_FP64) {
     // the resident kernel on each patch shape that fits
     const int v0 = g->variant, c0 = g->chunk;

@@ -384,6 +384,10 @@ hr_status hr_batch_create(int n, hr_grid* const* grids, hr_batch** out) {
         delete b;
         return bfail(HR_EINVAL, "a grid appears twice in the batch");
       }
+    if (g->d.cart) {
+      delete b;
+      return bfail(HR_EINVAL, "Cartesian grids are not batched (relax them one by one)");
+    }
     if (i == 0) {
       b->order = g->fd_order;
       b->device = g->device;

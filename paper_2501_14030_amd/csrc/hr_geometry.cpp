@@ -150,8 +150,56 @@ Local local_spherical(double x0, double x1) {
 
 }  // namespace
 
+// Cartesian grids: the cube [-rmax, rmax]^3 with unit scale factors. The
+// Laplacian factors are the constants 1/dx_d^2 (no first-derivative terms),
+// every cell has the same width (c = kappa everywhere) and volume; the face
+// points' radiation condition takes r and d r / d x_d from the stored
+// coordinates (cx) in the kernel.
+static bool build_tables_cartesian(const Dims& d, const hr_grid_params& p, HostTables& t,
+                                   std::string& err) {
+  const double L = p.rmax;
+  const int n[3] = {d.N0, d.N1, d.N2};
+  double dx[3];
+  for (int a = 0; a < 3; ++a) dx[a] = 2.0 * L / n[a];
+  const int n2d = d.N0 * d.N1, o2d = d.NG * d.N1, e2d = d.P0 * d.R1, z2d = d.P0 * 2 * d.zo;
+  t.alpha.assign(5 * (size_t)n2d, 0.0);
+  for (int k = 0; k < n2d; ++k) {
+    t.alpha[0 * (size_t)n2d + k] = 1.0 / (dx[0] * dx[0]);
+    t.alpha[1 * (size_t)n2d + k] = 1.0 / (dx[1] * dx[1]);
+    t.alpha[2 * (size_t)n2d + k] = 1.0 / (dx[2] * dx[2]);
+  }
+  t.crat.assign(n2d, 1.0);
+  t.ocrat.assign(o2d, 0.0);
+  t.orinv.assign(o2d, 0.0);
+  t.oq.assign(o2d, 0.0);
+  t.zcrat.assign(z2d, 0.0);
+  t.zrinv.assign(z2d, 0.0);
+  t.zq.assign(z2d, 0.0);
+  t.zstep.assign(z2d, 0.0);
+  t.rho.assign(e2d, 0.0);
+  t.zc.assign(e2d, 0.0);
+  t.rcart.assign(e2d, 0.0);
+  t.cphi.assign(d.N2, 0.0);
+  t.sphi.assign(d.N2, 0.0);
+  t.vol.assign(n2d, dx[0] * dx[1] * dx[2]);
+  t.vol_total = dx[0] * dx[1] * dx[2] * (double)d.nint;
+  t.volw = t.vol;
+  t.volw_total = t.vol_total;
+  t.ds_g = std::fmin(dx[0], std::fmin(dx[1], dx[2]));
+  // cell centres of the stored columns, rows and planes (NG beyond each face)
+  t.cx.clear();
+  for (int a = 0; a < 3; ++a)
+    for (int j = -d.NG; j < n[a] + d.NG; ++j) t.cx.push_back(-L + (j + 0.5) * dx[a]);
+  if (!(t.ds_g > 0.0) || !std::isfinite(t.ds_g)) {
+    err = "grid has a non-positive or non-finite cell width";
+    return false;
+  }
+  return true;
+}
+
 bool build_tables(hr_coords coords, const Dims& d, const hr_grid_params& p,
                   HostTables& t, std::string& err) {
+  if (coords == HR_CARTESIAN) return build_tables_cartesian(d, p, t, err);
   const bool cyl = coords == HR_SINHCYLINDRICAL;
   const double x0max = (coords == HR_SPHERICAL) ? p.rmax : 1.0;
   const double dx[3] = {x0max / d.N0, (cyl ? 2.0 : kPi) / d.N1, 2.0 * kPi / d.N2};

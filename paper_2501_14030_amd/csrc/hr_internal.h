@@ -62,14 +62,24 @@ struct Dims {
   int nout;        // NG*N1*N2
   int sph;         // 1 for Spherical (x0 reflection also flips theta)
   int zo;          // stored outer rows on each x1 face: NG for SinhCylindrical
-                   // (its z faces are outer boundaries), else 0
+                   // (its z faces are outer boundaries) and Cartesian, else 0
   int R1;          // stored rows per plane, N1 + 2 zo
+  int cart;        // 1 for Cartesian: NG stored outer layers beyond all six
+                   // faces (P0 = N0 + 2 NG, planes N2 + 2 NG), no images
 };
 
-// Flat index of the stored point (i0, i1, i2): i0 in [0, P0), i1 in
-// [-zo, N1 + zo), i2 in [0, N2).
+// Stored planes of a grid: N2, plus the two outer slabs of a Cartesian grid.
+__host__ __device__ __forceinline__ int planes_of(const Dims& d) {
+  return d.N2 + (d.cart ? 2 * d.NG : 0);
+}
+
+// Flat index of the stored point (i0, i1, i2): i0 in [0, P0) (Cartesian:
+// [-NG, N0 + NG)), i1 in [-zo, N1 + zo), i2 in [0, N2) (Cartesian:
+// [-NG, N2 + NG)).
 __host__ __device__ __forceinline__ unsigned sidx(const Dims& d, int i0, int i1, int i2) {
-  return (unsigned)i0 + (unsigned)d.P0 * ((unsigned)(i1 + d.zo) + (unsigned)d.R1 * (unsigned)i2);
+  const int o = d.cart ? d.NG : 0;
+  return (unsigned)(i0 + o) +
+         (unsigned)d.P0 * ((unsigned)(i1 + d.zo) + (unsigned)d.R1 * (unsigned)(i2 + o));
 }
 
 // Stage kernel arguments (RK4 stage s of 4, classic Butcher tableau).
@@ -153,6 +163,11 @@ hipError_t launch_sources(const Dims& d, const double* rho, const double* zc,
                           const double* cphi, const double* sphi,
                           const Punctures& p, double* psi64, double* ssrc64,
                           float* psi32, float* ssrc32, hipStream_t s);
+// Sources at every stored point of a Cartesian grid; cx holds the stored
+// columns' x, rows' y and planes' z (the grid's coordinate table).
+hipError_t launch_cart_sources(const Dims& d, const double* cx, const Punctures& p,
+                               double* psi64, double* ssrc64, float* psi32, float* ssrc32,
+                               hipStream_t s);
 hipError_t launch_to_fp32(const double* src, float* dst, int n, hipStream_t s);
 hipError_t launch_to_fp64(const float* src, double* dst, int n, hipStream_t s);
 struct RebaseArgs {
@@ -299,6 +314,8 @@ struct HostTables {
   std::vector<double> volw;    // N0*N1: weights of the volume norm (vol, zero for cells
                                // whose centre lies beyond the integration radius)
   double volw_total = 0.0;     // sum of the weights over the interior
+  std::vector<double> cx;      // Cartesian: x of the P0 stored columns, y of the R1
+                               // stored rows, z of the N2 + 2 NG stored planes
 };
 
 bool build_tables(hr_coords coords, const Dims& d, const hr_grid_params& p,

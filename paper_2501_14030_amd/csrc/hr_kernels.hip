@@ -898,20 +898,10 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ 
 }
 
 // psi_singular and (1/8) A_ij A^ij at every stored point (interior and outer).
-__global__ void __launch_bounds__(kBlock) k_sources(Dims d, const double* __restrict__ rho,
-                                                    const double* __restrict__ zc,
-                                                    const double* __restrict__ cphi,
-                                                    const double* __restrict__ sphi,
-                                                    Punctures pz, double* __restrict__ psi64,
-                                                    double* __restrict__ ssrc64,
-                                                    float* __restrict__ psi32,
-                                                    float* __restrict__ ssrc32) {
-  const int next = d.P0 * d.R1 * d.N2;
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  if (t >= next) return;
-  const int e = t % (d.P0 * d.R1);   // (i0, stored row) of the 2D tables
-  const int i2 = t / (d.P0 * d.R1);
-  const double X[3] = {rho[e] * cphi[i2], rho[e] * sphi[i2], zc[e]};
+// psi_s = 1 + sum m/(2 r) and the source factor (1/8) A_ij A^ij of the
+// Bowen-York extrinsic curvature at the Cartesian position X.
+__device__ __forceinline__ void bowen_york_point(const Punctures& pz, const double X[3],
+                                                 double& psi_out, double& src_out) {
   double psi = 1.0;
   double A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   for (int p = 0; p < pz.n; ++p) {
@@ -941,7 +931,208 @@ __global__ void __launch_bounds__(kBlock) k_sources(Dims d, const double* __rest
   double aa = 0.0;
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) aa += A[i][j] * A[i][j];
-  const double src = aa / 8.0;
+  psi_out = psi;
+  src_out = aa / 8.0;
+}
+
+__global__ void __launch_bounds__(kBlock) k_sources(Dims d, const double* __restrict__ rho,
+                                                    const double* __restrict__ zc,
+                                                    const double* __restrict__ cphi,
+                                                    const double* __restrict__ sphi,
+                                                    Punctures pz, double* __restrict__ psi64,
+                                                    double* __restrict__ ssrc64,
+                                                    float* __restrict__ psi32,
+                                                    float* __restrict__ ssrc32) {
+  const int next = d.P0 * d.R1 * d.N2;
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= next) return;
+  const int e = t % (d.P0 * d.R1);   // (i0, stored row) of the 2D tables
+  const int i2 = t / (d.P0 * d.R1);
+  const double X[3] = {rho[e] * cphi[i2], rho[e] * sphi[i2], zc[e]};
+  double psi, src;
+  bowen_york_point(pz, X, psi, src);
+  psi64[t] = psi;
+  ssrc64[t] = src;
+  psi32[t] = (float)psi;
+  ssrc32[t] = (float)src;
+}
+
+// ---------------------------------------------------------------------------
+// Cartesian grids (the cube [-rmax, rmax]^3, x, y, z along x0, x1, x2). Every
+// stored point beyond one face is an outer point; there are no images, so a
+// plane tile's rim and the z taps read the stored outer layers directly. The
+// Laplacian factors (1/dx_d^2, no first-derivative terms) and c^2 come from
+// the same 2D tables as on the curvilinear grids; the face points take r and
+// d r / d x_d from the stored coordinates cx (a.zfac): the P0 column
+// x's, the R1 row y's, the planes' z's, then kappa and dx_0, dx_1, dx_2.
+
+// Index of coordinate axis `ax` in cx.
+__device__ __forceinline__ int cart_off(const Dims& d, int ax) {
+  return ax == 0 ? 0 : ax == 1 ? d.P0 : d.P0 + d.R1;
+}
+
+// Interior points: one thread each on the plane-tile grid.
+template <typename T, int NG, int STAGE>
+__global__ void __launch_bounds__(kTileThreads) k_cart_stage(StageArgs<T> a) {
+  constexpr int W = TileShape<NG>::W, H = TileShape<NG>::H;
+  constexpr Weights<NG> Wt{};
+  __shared__ T tile[W * H];
+  const Dims& d = a.d;
+  const int x0b = blockIdx.x * TX, x1b = blockIdx.y * TY, i2 = blockIdx.z;
+  const int i0 = x0b + threadIdx.x, i1 = x1b + threadIdx.y;
+  const bool active = i0 < d.N0 && i1 < d.N1;
+  const unsigned plane = (unsigned)d.P0 * (unsigned)d.R1;
+  const unsigned idx = sidx(d, active ? i0 : 0, active ? i1 : 0, i2);
+  const unsigned n2d = (unsigned)d.N0 * (unsigned)d.N1;
+  const unsigned k2 = active ? (unsigned)i0 + (unsigned)d.N0 * (unsigned)i1 : 0u;
+  // z taps and point operands, issued before the tile barrier
+  T zp[NG], zm[NG], v = 0, psi = 0, ssrc = 0, f[6];
+  CombineIn<STAGE, false, T> co;
+  if (active) {
+#pragma unroll
+    for (int k = 1; k <= NG; ++k) {
+      zp[k - 1] = a.uin[idx + (unsigned)k * plane];
+      zm[k - 1] = a.uin[idx - (unsigned)k * plane];
+    }
+    v = a.vin[idx];
+    psi = a.psi[idx];
+    ssrc = a.ssrc[idx];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) f[q] = load_factor(a.fac, a.facb, q * n2d + k2);
+    co.load(a, idx);
+  }
+  const int tid = threadIdx.x + TX * threadIdx.y;
+  for (int e = tid; e < W * H; e += kTileThreads) {
+    const int l1 = e / W;
+    const int l0 = e - l1 * W;
+    const int j0 = x0b + l0 - NG, j1 = x1b + l1 - NG;   // both >= -NG
+    tile[e] = (j0 < d.N0 + NG && j1 < d.N1 + NG) ? a.uin[sidx(d, j0, j1, i2)] : (T)0;
+  }
+  __syncthreads();
+  if (!active) return;
+  const T* r = tile + (threadIdx.y + NG) * W + (threadIdx.x + NG);
+  const T uc = r[0];
+  T d0 = 0, d1 = 0, e0 = 0, e1 = 0, e2 = 0;
+#pragma unroll
+  for (int k = 1; k <= NG; ++k) {
+    const T p0 = r[k], m0 = r[-k];
+    const T p1 = r[k * W], m1 = r[-k * W];
+    d0 += (T)Wt.d1[k] * (p0 - m0);
+    d1 += (T)Wt.d1[k] * (p1 - m1);
+    e0 += (T)Wt.d2[k] * (p0 + m0);
+    e1 += (T)Wt.d2[k] * (p1 + m1);
+    e2 += (T)Wt.d2[k] * (zp[k - 1] + zm[k - 1]);
+  }
+  const T w0 = (T)Wt.d2[0];
+  const T lap = f[0] * (e0 + w0 * uc) + f[1] * (e1 + w0 * uc) + f[2] * (e2 + w0 * uc) +
+                f[3] * d0 + f[4] * d1;
+  const T ku = v - a.eta * uc;
+  const T kv = f[5] * (lap + source<T>(ssrc, psi, uc));
+  combine<STAGE, false, T>(a, idx, co, uc, v, ku, kv);
+}
+
+// Number of outer points on the two faces normal to axis ax.
+__device__ __forceinline__ int cart_face_points(const Dims& d, int ax) {
+  const int n1 = ax == 0 ? d.N1 : d.N0, n2 = ax == 2 ? d.N1 : d.N2;
+  return 2 * d.NG * n1 * n2;
+}
+
+// Face points, one thread each: the radiation condition k_f = -c (f/r + d_r
+// f) with d_r f = (d f / d n) / (d r / d n) along the outward normal n = +-x_d
+// (d r / d n = |x_d| / r), the one-sided difference toward the interior, then
+// the stage combine. Threads run x0 fastest where the face allows.
+template <typename T, int NG, int STAGE>
+__global__ void __launch_bounds__(kBlock) k_cart_faces(StageArgs<T> a) {
+  const Dims& d = a.d;
+  int t = blockIdx.x * kBlock + threadIdx.x;
+  int ax = 0;
+  while (ax < 3 && t >= cart_face_points(d, ax)) t -= cart_face_points(d, ax++);
+  if (ax == 3) return;
+  // t = fast + n_fast (slow + n_slow (layer + NG side))
+  const int nf = ax == 0 ? d.N1 : d.N0, ns = ax == 2 ? d.N1 : d.N2;
+  const int fast = t % nf;
+  t /= nf;
+  const int slow = t % ns;
+  t /= ns;
+  const int layer = t % NG, side = t / NG;
+  const int n_ax = ax == 0 ? d.N0 : ax == 1 ? d.N1 : d.N2;
+  const int out = side ? n_ax + layer : -1 - layer;
+  int i0, i1, i2;
+  if (ax == 0) { i0 = out; i1 = fast; i2 = slow; }
+  else if (ax == 1) { i0 = fast; i1 = out; i2 = slow; }
+  else { i0 = fast; i1 = slow; i2 = out; }
+  const T* cx = a.zfac;
+  const int q2 = planes_of(d);
+  const T kappa = cx[d.P0 + d.R1 + q2];
+  const T dxa = cx[d.P0 + d.R1 + q2 + 1 + ax];
+  const T x = cx[i0 + d.NG], y = cx[d.P0 + i1 + d.zo], z = cx[d.P0 + d.R1 + i2 + d.NG];
+  const T rr = sqrt(x * x + y * y + z * z);
+  const T xa = ax == 0 ? x : ax == 1 ? y : z;
+  const T qd = rr / ((T)2 * dxa * fabs(xa));   // 1 / (2 dx d r / d n)
+  const int stride = ax == 0 ? 1 : ax == 1 ? d.P0 : d.P0 * d.R1;
+  const int in = side ? -stride : stride;     // one point toward the interior
+  const unsigned o = sidx(d, i0, i1, i2);
+  const T* U = a.uin + o;
+  const T* V = a.vin + o;
+  const bool bc4 = a.bc4 != 0;
+  const T u0 = U[0], u1 = U[in], u2 = U[2 * in];
+  const T v0 = V[0], v1 = V[in], v2 = V[2 * in];
+  const T u3 = bc4 ? U[3 * in] : (T)0, u4 = bc4 ? U[4 * in] : (T)0;
+  const T v3 = bc4 ? V[3 * in] : (T)0, v4 = bc4 ? V[4 * in] : (T)0;
+  CombineIn<STAGE, false, T> co;
+  co.load(a, o);
+  const T kuo = -kappa * (u0 / rr + outer_diff(u0, u1, u2, u3, u4, qd, bc4));
+  const T kvo = -kappa * (v0 / rr + outer_diff(v0, v1, v2, v3, v4, qd, bc4));
+  combine<STAGE, false, T>(a, o, co, u0, v0, kuo, kvo);
+}
+
+// Residual H in FP64 on the interior of a Cartesian grid (state of storage
+// type S), block sums of H^2 in the partial layout of k_residual.
+template <typename S, int NG>
+__global__ void __launch_bounds__(kTileThreads) k_cart_residual(ResidualArgs a) {
+  constexpr Weights<NG> Wt{};
+  const Dims& d = a.d;
+  const S* U = static_cast<const S*>(a.u);
+  const int i0 = blockIdx.x * TX + threadIdx.x, i1 = blockIdx.y * TY + threadIdx.y;
+  const int i2 = blockIdx.z;
+  double h2 = 0.0;
+  if (i0 < d.N0 && i1 < d.N1) {
+    const unsigned idx = sidx(d, i0, i1, i2);
+    const unsigned st[3] = {1u, (unsigned)d.P0, (unsigned)d.P0 * (unsigned)d.R1};
+    const unsigned n2d = (unsigned)d.N0 * (unsigned)d.N1;
+    const unsigned k2 = (unsigned)i0 + (unsigned)d.N0 * (unsigned)i1;
+    const double uc = (double)U[idx];
+    double e[3] = {0, 0, 0};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+      for (int k = 1; k <= NG; ++k)
+        e[ax] += Wt.d2[k] * ((double)U[idx + (unsigned)k * st[ax]] +
+                             (double)U[idx - (unsigned)k * st[ax]]);
+    const double w0 = Wt.d2[0];
+    const double lap = a.fac[k2] * (e[0] + w0 * uc) + a.fac[n2d + k2] * (e[1] + w0 * uc) +
+                       a.fac[2 * n2d + k2] * (e[2] + w0 * uc);
+    const double Hv = lap + source<double>(a.ssrc[idx], a.psi[idx], uc);
+    h2 = Hv * Hv;
+  }
+  const double tot = block_sum<kTileThreads>(h2);
+  if (threadIdx.x == 0 && threadIdx.y == 0)
+    a.partial[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = tot;
+}
+
+// Sources psi_s and S_src at every stored point of a Cartesian grid.
+__global__ void __launch_bounds__(kBlock) k_cart_sources(Dims d, const double* __restrict__ cx,
+                                                         Punctures pz, double* __restrict__ psi64,
+                                                         double* __restrict__ ssrc64,
+                                                         float* __restrict__ psi32,
+                                                         float* __restrict__ ssrc32) {
+  const int next = d.P0 * d.R1 * planes_of(d);
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= next) return;
+  const int j0 = t % d.P0, j1 = (t / d.P0) % d.R1, j2 = t / (d.P0 * d.R1);
+  const double X[3] = {cx[j0], cx[d.P0 + j1], cx[d.P0 + d.R1 + j2]};
+  double psi, src;
+  bowen_york_point(pz, X, psi, src);
   psi64[t] = psi;
   ssrc64[t] = src;
   psi32[t] = (float)psi;
@@ -1040,9 +1231,45 @@ hipError_t col_dispatch(int stage, const StageArgs<T>& a, int ch, hipStream_t s,
 }
 
 
+// A Cartesian stage: the interior kernel, then the face kernel (timing events,
+// when given, bracket both).
+template <typename T, int NG, int STAGE>
+hipError_t cart_stage_launch(const StageArgs<T>& a, hipStream_t s, hipEvent_t t0,
+                             hipEvent_t t1) {
+  const Dims& d = a.d;
+  const dim3 grid = tile_grid(d), block(TX, TY, 1);
+  const int nf = 2 * d.NG * (d.N1 * d.N2 + d.N0 * d.N2 + d.N0 * d.N1);
+  if (t0 && t1) {
+    hipExtLaunchKernelGGL(k_cart_stage<T, NG, STAGE>, grid, block, 0, s, t0, nullptr, 0, a);
+    hipExtLaunchKernelGGL(k_cart_faces<T, NG, STAGE>, dim3(nblocks(nf)), dim3(kBlock), 0, s,
+                          nullptr, t1, 0, a);
+  } else {
+    k_cart_stage<T, NG, STAGE><<<grid, block, 0, s>>>(a);
+    k_cart_faces<T, NG, STAGE><<<nblocks(nf), kBlock, 0, s>>>(a);
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int NG>
+hipError_t cart_dispatch(int stage, const StageArgs<T>& a, hipStream_t s, hipEvent_t t0,
+                         hipEvent_t t1) {
+  switch (stage) {
+    case 1: return cart_stage_launch<T, NG, 1>(a, s, t0, t1);
+    case 2: return cart_stage_launch<T, NG, 2>(a, s, t0, t1);
+    case 3: return cart_stage_launch<T, NG, 3>(a, s, t0, t1);
+    case 4: return cart_stage_launch<T, NG, 4>(a, s, t0, t1);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <typename T, int NG>
 hipError_t stage_dispatch(int stage, const StageArgs<T>& a, hipStream_t s, hipEvent_t t0,
                           hipEvent_t t1) {
+  if (a.d.cart) {
+    // the split-state increment is not built for Cartesian grids
+    if (a.corr) return hipErrorInvalidValue;
+    return cart_dispatch<T, NG>(stage, a, s, t0, t1);
+  }
   const int ch = a.chunk > 0 ? a.chunk : 1;
   if constexpr (std::is_same<T, float>::value) {
     if (a.corr)
@@ -1081,6 +1308,16 @@ hipError_t residual_order_zf(int order, const ResidualArgs& a, hipStream_t s) {
 
 template <typename S>
 hipError_t residual_order(int order, const ResidualArgs& a, hipStream_t s) {
+  if (a.d.cart) {
+    switch (order) {
+      case 2: return tile_launch(k_cart_residual<S, 1>, a, a.d, s, nullptr, nullptr);
+      case 4: return tile_launch(k_cart_residual<S, 2>, a, a.d, s, nullptr, nullptr);
+      case 6: return tile_launch(k_cart_residual<S, 3>, a, a.d, s, nullptr, nullptr);
+      case 8: return tile_launch(k_cart_residual<S, 4>, a, a.d, s, nullptr, nullptr);
+      case 10: return tile_launch(k_cart_residual<S, 5>, a, a.d, s, nullptr, nullptr);
+      default: return hipErrorInvalidValue;
+    }
+  }
   return a.d.zo ? residual_order_zf<S, true>(order, a, s) : residual_order_zf<S, false>(order, a, s);
 }
 
@@ -1129,6 +1366,14 @@ hipError_t launch_sources(const Dims& d, const double* rho, const double* zc,
   const int next = d.P0 * d.R1 * d.N2;
   k_sources<<<nblocks(next), kBlock, 0, s>>>(d, rho, zc, cphi, sphi, p, psi64, ssrc64, psi32,
                                              ssrc32);
+  return hipGetLastError();
+}
+
+hipError_t launch_cart_sources(const Dims& d, const double* cx, const Punctures& p,
+                               double* psi64, double* ssrc64, float* psi32, float* ssrc32,
+                               hipStream_t s) {
+  const int next = d.P0 * d.R1 * planes_of(d);
+  k_cart_sources<<<nblocks(next), kBlock, 0, s>>>(d, cx, p, psi64, ssrc64, psi32, ssrc32);
   return hipGetLastError();
 }
 

@@ -562,7 +562,8 @@ hr_status hr_mlp_grid_features(hr_mlp* n, const hr_grid* g, const double* cfg9, 
   (void)n;
   if (!g->bound) return mfail(HR_ESTATE, "grid not bound");
   if (!g->have_sources) return mfail(HR_ESTATE, "punctures not set");
-  if (g->d.zo) return mfail(HR_EINVAL, "the warm-start features do not cover SinhCylindrical grids");
+  if (g->d.zo)
+    return mfail(HR_EINVAL, "the warm-start features do not cover SinhCylindrical or Cartesian grids");
   FeatArgs a{};
   a.d = g->d;
   a.x0max = g->coords == HR_SPHERICAL ? g->prm.rmax : 1.0;
@@ -587,7 +588,8 @@ hr_status hr_warm_start(hr_grid* g, hr_mlp* n, const double* cfg9, double eta) {
   if (!g->bound || !n->bound) return mfail(HR_ESTATE, "grid and network must be bound");
   if (!g->have_sources) return mfail(HR_ESTATE, "punctures not set");
   if (!(eta > 0)) return mfail(HR_EINVAL, "eta must be > 0");
-  if (g->d.zo) return mfail(HR_EINVAL, "the warm-start features do not cover SinhCylindrical grids");
+  if (g->d.zo)
+    return mfail(HR_EINVAL, "the warm-start features do not cover SinhCylindrical or Cartesian grids");
   HR_HIPM(hipSetDevice(g->device));
   HR_HIPM(hipStreamSynchronize(g->stream));
   FeatArgs a{};

@@ -23,6 +23,7 @@ SINHSYMTP = 0
 SPHERICAL = 1
 SINHSPHERICAL = 2
 SINHCYLINDRICAL = 3
+CARTESIAN = 4
 
 
 @dataclass
@@ -58,7 +59,8 @@ class GridSpec:
 
     def name(self) -> str:
         c = {SINHSYMTP: "SinhSymTP", SPHERICAL: "Spherical",
-             SINHSPHERICAL: "SinhSpherical", SINHCYLINDRICAL: "SinhCylindrical"}[self.coords]
+             SINHSPHERICAL: "SinhSpherical", SINHCYLINDRICAL: "SinhCylindrical",
+             CARTESIAN: "Cartesian"}[self.coords]
         return f"{c} {self.N0}x{self.N1}x{self.N2} order {self.fd_order}"
 
 

@@ -31,9 +31,12 @@ def gpu_grid(spec: workloads.GridSpec) -> hr.Grid:
 def oracle_extended(g: oracle.OracleGrid, f: np.ndarray) -> np.ndarray:
     """Interior + outer points of a padded oracle field, in the library's
     extended layout (N2, N1, N0 + NG); SinhCylindrical also keeps the NG outer
-    rows beyond each z face (N2, N1 + 2 NG, N0 + NG)."""
+    rows beyond each z face (N2, N1 + 2 NG, N0 + NG); Cartesian keeps the whole
+    padded box (its unused edge and corner points are zero on both sides)."""
     ng = g.NG
     N0, N1, N2 = g.N
+    if g.coords == oracle.CARTESIAN:   # every stored point: the padded box
+        return np.asarray(f).reshape(g.shape)
     rows = slice(0, N1 + 2 * ng) if g.coords == oracle.SINHCYLINDRICAL else slice(ng, ng + N1)
     return np.asarray(f).reshape(g.shape)[ng:ng + N2, rows, ng:ng + N0 + ng]
 

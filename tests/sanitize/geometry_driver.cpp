@@ -117,28 +117,53 @@ int main() {
   int checked = 0;
   const int shapes[][3] = {{5, 5, 2}, {8, 4, 2}, {32, 16, 4}, {37, 19, 6}, {64, 64, 8}, {128, 64, 8}};
   const int orders[] = {2, 4, 6, 8, 10};
-  for (int coords = 0; coords < 4; ++coords)
+  for (int coords = 0; coords < 5; ++coords)
     for (const auto& sh : shapes)
       for (int order : orders) {
         const int NG = order / 2;
         if (sh[0] < NG || sh[1] < NG) continue;
+        const bool cart = coords == 4;
+        if (cart && (sh[2] < NG || sh[2] < 2)) continue;
         hr::Dims d{};
         d.N0 = sh[0];
         d.N1 = sh[1];
         d.N2 = sh[2];
         d.NG = NG;
-        d.P0 = sh[0] + NG;
+        d.P0 = sh[0] + NG + (cart ? NG : 0);
         d.nint = sh[0] * sh[1] * sh[2];
         d.nout = NG * sh[1] * sh[2];
         d.sph = coords == 1 || coords == 2 ? 1 : 0;
-        d.zo = coords == 3 ? NG : 0;   // SinhCylindrical: outer rows on both z faces
+        // SinhCylindrical: outer rows on both z faces; Cartesian: outer
+        // layers beyond all six faces
+        d.zo = coords == 3 || cart ? NG : 0;
         d.R1 = sh[1] + 2 * d.zo;
+        d.cart = cart ? 1 : 0;
         hr_grid_params p{1.0e6, 0.07, 1.5, 100.0, 0.5};
         hr::HostTables t;
         std::string err;
         if (!hr::build_tables((hr_coords)coords, d, p, t, err)) {
           std::printf("build_tables failed: %s\n", err.c_str());
           return 1;
+        }
+        if (cart) {
+          // constant Laplacian factors, uniform cells, and one coordinate per
+          // stored column, row and plane, increasing along each axis
+          if ((int)t.cx.size() != d.P0 + d.R1 + hr::planes_of(d)) return 20;
+          for (double c : t.crat)
+            if (c != 1.0) return 21;
+          const int n[3] = {d.N0, d.N1, d.N2};
+          int off = 0;
+          for (int a = 0; a < 3; ++a) {
+            for (int j = 1; j < n[a] + 2 * NG; ++j)
+              if (!(t.cx[off + j] > t.cx[off + j - 1])) return 22;
+            off += n[a] + 2 * NG;
+          }
+          // stored indices of the padded box stay below its size
+          const long last = hr::sidx(d, d.N0 + NG - 1, d.N1 + NG - 1, d.N2 + NG - 1);
+          if (last != (long)d.P0 * d.R1 * hr::planes_of(d) - 1 || hr::sidx(d, -NG, -NG, -NG) != 0)
+            return 23;
+          ++checked;
+          continue;
         }
         if (!(t.ds_g > 0)) return 2;
         for (double c : t.crat)

@@ -49,8 +49,10 @@ def _create(lib, coords, N0, N1, N2, order, params=None):
     (0, 32, 3, 4, 8),      # N1 < NG
     (0, 32, 16, 4, 7),     # odd order
     (0, 32, 16, 4, 12),    # unsupported order
-    (4, 32, 16, 4, 8),     # unknown coordinates
+    (5, 32, 16, 4, 8),     # unknown coordinates
     (0, 32, 16, 0, 8),
+    (4, 32, 16, 3, 8),     # Cartesian N2 < NG
+    (4, 1, 16, 8, 2),      # Cartesian N0 < 2
 ])
 def test_create_rejects_invalid_arguments(lib, args):
     st, h = _create(lib, *args)
@@ -91,6 +93,8 @@ def test_workspace_and_sizes(lib):
     workloads.GridSpec(2, 64, 32, 8, 10),
     workloads.GridSpec(3, 32, 16, 4, 8, amax=10.0, sinhwaa=0.3),
     workloads.GridSpec(3, 37, 22, 6, 10, amax=1.0e3, sinhwaa=0.15),
+    workloads.GridSpec(4, 24, 20, 16, 8, rmax=6.0),
+    workloads.GridSpec(4, 70, 13, 11, 10, rmax=5.0),
 ])
 def test_suggested_dt_matches_oracle(lib, oracle_lib, spec):
     p = hr.default_params(amax=spec.amax, sinhwaa=spec.sinhwaa, bscale=spec.bscale,
@@ -122,6 +126,29 @@ def test_residual_norm_arguments_on_an_unbound_grid(lib):
     assert f(None, hr.NORM_POINTS, 0.0) == hr.EINVAL
     assert f(h, hr.NORM_POINTS, 0.0) == hr.OK
     lib.hr_grid_destroy(h)
+
+
+def test_cartesian_sizes_and_host_refusals(lib):
+    """A Cartesian grid stores the padded box; its host-side refusals (the
+    volume norm, a fourth-order face difference across a face with fewer than
+    four points) need no device."""
+    st, h = _create(lib, 4, 24, 20, 16, 8, hr.default_params(rmax=6.0))
+    assert st == hr.OK
+    ni = ctypes.c_size_t()
+    ne = ctypes.c_size_t()
+    assert lib.hr_grid_sizes(h, ctypes.byref(ni), ctypes.byref(ne)) == hr.OK
+    assert ni.value == 24 * 20 * 16 and ne.value == 32 * 28 * 24
+    assert lib.hr_set_residual_norm(h, hr.NORM_VOLUME, 0.0) == hr.EINVAL
+    assert lib.hr_set_residual_norm(h, hr.NORM_POINTS, 0.0) == hr.OK
+    assert lib.hr_set_outer_bc_order(h, 4) == hr.OK
+    lib.hr_grid_destroy(h)
+    st, h = _create(lib, 4, 8, 8, 3, 2, hr.default_params(rmax=1.0))   # N2 = 3
+    assert st == hr.OK
+    assert lib.hr_set_outer_bc_order(h, 4) == hr.EINVAL
+    assert lib.hr_set_outer_bc_order(h, 2) == hr.OK
+    lib.hr_grid_destroy(h)
+    st, h = _create(lib, 4, 8, 8, 8, 2, hr.default_params(rmax=-1.0))
+    assert st == hr.EINVAL
 
 
 def test_outer_bc_order_arguments(lib):

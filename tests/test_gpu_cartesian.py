@@ -1,0 +1,151 @@
+"""Cartesian grids (the Cartesian-like family the paper's conclusions name)
+on the GPU against the oracle.
+
+The cube [-rmax, rmax]^3 stores NG outer layers beyond each of its six faces;
+the interior kernel (plane tiles whose rim comes from those layers, z taps
+from memory) and the face kernel (radiation condition along each face normal)
+update them. Bars: FP64 trajectories and converged states within 1e-12 of the
+oracle (relative to max|u|, over every stored point), residual histories to
+1e-9 relative; plain FP32 within 1e-4 after 300 steps (300 steps of single
+precision rounding, unit roundoff 6e-8, on a state whose largest value is
+O(1e-2)). The calls Cartesian grids do not take return HR_EINVAL.
+"""
+import numpy as np
+import pytest
+
+import paper_2501_14030_amd as hr
+from paper_2501_14030_amd import workloads
+from paper_2501_14030_amd.mlp import MLP, config_features
+
+from gpu_common import banner, gpu_grid, oracle_extended, oracle_grid, rel_maxdiff
+
+pytestmark = pytest.mark.gpu
+
+CART = workloads.CARTESIAN
+SPECS = [
+    workloads.GridSpec(CART, 24, 20, 16, 8, rmax=6.0),
+    workloads.GridSpec(CART, 70, 13, 11, 10, rmax=5.0),   # ragged tiles, odd sizes
+]
+
+
+def _punct():
+    return ([0.5, 0.5], [[0, 0, 1.3], [0, 0, -1.3]],
+            [[0, 0.1, 0], [0, -0.1, 0.02]], [[0, 0, 0.1], [0.05, 0, -0.1]])
+
+
+def _oracle(spec, n_steps, tol, eta, order=2):
+    og = oracle_grid(spec)
+    if order != 2:
+        og.set_bc_order(order)
+    og.set_punctures(*_punct())
+    st, n, hist = og.relax(eta, 1.0, og.suggest_dt(0.5), n_steps, tol, 100)
+    return og, n, hist
+
+
+@pytest.mark.parametrize("spec", SPECS, ids=lambda s: s.name())
+def test_trajectory_matches_oracle(spec):
+    eta = 1.0
+    og, _, ohist = _oracle(spec, 400, 0.0, eta)
+    g = gpu_grid(spec)
+    g.set_punctures(*_punct())
+    r = g.relax(eta, 1.0, og.suggest_dt(0.5), 400, 0.0, check_every=100)
+    ou, ov = og.state()
+    gu = g.get_u(extended=True)
+    assert gu.shape == og.shape
+    du = rel_maxdiff(gu, oracle_extended(og, ou))
+    dv = rel_maxdiff(g.get_v(extended=True), oracle_extended(og, ov))
+    banner(f"{spec.name()}: du {du:.2e} dv {dv:.2e}, history {r.history}")
+    assert r.status == hr.OK
+    assert du <= 1e-12 and dv <= 1e-12
+    np.testing.assert_allclose(r.history, ohist, rtol=1e-9, atol=1e-15)
+    # the face layers carry the solution (not zero), the edges stay zero
+    img = og.bc_images().reshape(og.shape)
+    assert np.abs(gu[img == -2]).max() > 1e-3 * np.abs(gu).max()
+    assert np.all(gu[img == -4] == 0.0)
+
+
+def test_converged_state_matches_oracle():
+    spec = SPECS[0]
+    eta = 1.0
+    og, n_or, _ = _oracle(spec, 200000, 1e-10, eta)
+    ou, _ = og.state()
+    g = gpu_grid(spec)
+    g.set_punctures(*_punct())
+    r = g.relax(eta, 1.0, og.suggest_dt(0.5), 200000, 1e-10, check_every=100)
+    du = rel_maxdiff(g.get_u(extended=True), oracle_extended(og, ou))
+    banner(f"{spec.name()} to 1e-10: {r.steps_taken} steps (oracle {n_or}), du {du:.2e}")
+    assert r.status == hr.OK and r.steps_taken == n_or and du <= 1e-12
+    # the allocation-free entry point runs the same kernels
+    g.set_punctures(*_punct())
+    rn = g.relax_noalloc(eta, 1.0, og.suggest_dt(0.5), 200000, 1e-10, check_every=100)
+    assert rn.status == hr.OK and rn.steps_taken == n_or
+    assert rel_maxdiff(g.get_u(extended=True), oracle_extended(og, ou)) <= 1e-12
+
+
+def test_fourth_order_faces_match_oracle():
+    spec = SPECS[0]
+    eta = 1.0
+    og, _, ohist = _oracle(spec, 300, 0.0, eta, order=4)
+    g = gpu_grid(spec)
+    g.set_outer_bc_order(4)
+    g.set_punctures(*_punct())
+    r = g.relax(eta, 1.0, og.suggest_dt(0.5), 300, 0.0, check_every=100)
+    ou, _ = og.state()
+    du = rel_maxdiff(g.get_u(extended=True), oracle_extended(og, ou))
+    banner(f"order-4 faces: du {du:.2e}")
+    assert du <= 1e-12
+    np.testing.assert_allclose(r.history, ohist, rtol=1e-9, atol=1e-15)
+
+
+def test_fp32_state_tracks_oracle():
+    spec = SPECS[0]
+    eta = 1.0
+    og, _, _ = _oracle(spec, 300, 0.0, eta)
+    g = gpu_grid(spec)
+    g.set_punctures(*_punct())
+    r = g.relax(eta, 1.0, og.suggest_dt(0.5), 300, 0.0, check_every=100, precision=hr.FP32)
+    ou, _ = og.state()
+    du = rel_maxdiff(g.get_u(extended=True), oracle_extended(og, ou))
+    banner(f"FP32 state after 300 steps: du {du:.2e}")
+    assert r.status == hr.OK and du <= 1e-4
+
+
+def test_interior_set_u_continues_faces_as_one_over_r():
+    spec = SPECS[0]
+    g = gpu_grid(spec)
+    g.set_punctures(*_punct())
+    og = oracle_grid(spec)
+    X, Y, Z = og.cart()
+    R = np.sqrt(X ** 2 + Y ** 2 + Z ** 2)
+    ng, (N0, N1, N2) = og.NG, og.N
+    f = 1.0 / R   # its continuation from each face's adjacent interior layer is itself
+    g.set_u(og.interior(f))
+    got = g.get_u(extended=True)
+    img = og.bc_images().reshape(og.shape)
+    np.testing.assert_allclose(got[img == -1], f[img == -1], rtol=0, atol=0)
+    np.testing.assert_allclose(got[img == -2], f[img == -2], rtol=1e-14, atol=0)
+    assert np.all(got[img == -4] == 0.0)
+
+
+def test_calls_cartesian_grids_do_not_take():
+    spec = SPECS[0]
+    g = gpu_grid(spec)
+    g.set_punctures(*_punct())
+    with pytest.raises(hr.HRError) as e:
+        g.relax(1.0, 1.0, 0.0, 10, 0.0, check_every=10, precision=hr.FP32_FP64FINISH)
+    assert e.value.status == hr.EINVAL
+    with pytest.raises(hr.HRError) as e:
+        g.set_residual_norm(hr.NORM_VOLUME)
+    assert e.value.status == hr.EINVAL
+    with pytest.raises(hr.HRError) as e:
+        hr.Batch([g])
+    assert e.value.status == hr.EINVAL
+    net = MLP(width=16, seed=1, max_batch=4096)
+    with pytest.raises(hr.HRError) as e:
+        net.warm_start(g, config_features(1.0, [0, 0, 0], [0, 0, 0], 0.1, 2.6), 1.0)
+    assert e.value.status == hr.EINVAL
+    net.close()
+    assert g.resolved_kernel(hr.FP64)["variant"] == 1
+    # the grid still relaxes after the refusals
+    r = g.relax(1.0, 1.0, 0.0, 100, 0.0, check_every=50)
+    assert r.status == hr.OK and np.isfinite(r.residual)
