@@ -502,6 +502,51 @@ def multi_patch_runs(hr, torch, w, u_ref, n_max: int = 7):
             "rows": rows}
 
 
+def cartesian_runs(hr, torch, steps: int, warmup: int):
+    """The paper-scale punctures on the Cartesian cube 128^3 ([-32, 32]^3, 10th
+    order, eta 0.03; the Cartesian-like family): FP64 solves to residual 1e-10
+    on the interior and face stage kernels, their per-stage times with the HBM
+    roofline of their algorithmic bytes, and the error against the committed
+    converged oracle solution."""
+    from paper_2501_14030_amd import workloads
+
+    w = workloads.paper_scale_cartesian()
+    s = w.grid
+    g = hr.grid_create(s.coords, s.N0, s.N1, s.N2, s.fd_order,
+                       params=hr.default_params(rmax=s.rmax))
+    rs, ts, tms = timed_solves(hr, torch, g, w, hr.FP64, steps, warmup, "cartesian fp64")
+    diff = oracle_diff(g.get_u(extended=True), "paper_scale_cartesian_128")
+    us = g.time_stage_kernels(w.eta, w.kappa, 0.0, 5, hr.FP64)
+    ng = s.fd_order // 2
+    nface = 2 * ng * (s.N1 * s.N2 + s.N0 * s.N2 + s.N0 * s.N1)
+    bi, bo = stage_bytes_per_point(8)
+    byts = [s.n_interior * bi[k] + nface * bo[k] + 8 * 6 * s.N0 * s.N1 for k in range(4)]
+    agg = sum(byts) / (sum(us[:4]) * 1e-6) / 1e9
+    out = {
+        "workload": f"paper-scale punctures on the Cartesian cube {s.N0}^3, [-{s.rmax:g}, "
+                    f"{s.rmax:g}]^3, 10th-order FD, eta {w.eta}, to residual 1e-10",
+        "value": sum(s.n_interior * 4 * r.steps_taken for r in rs) / ts,
+        "unit": "grid-pt RHS updates/s",
+        "time_to_residual_s": ts / steps,
+        "relax_median_s": float(np.median([t[1] for t in tms])),
+        "rk4_steps_to_tol": rs[-1].steps_taken,
+        "final_residual": rs[-1].residual,
+        "max_rel_diff_u_vs_oracle": diff,
+        "oracle_reference": "converged FP64 oracle solution at 4096 seeded evolved points and "
+                            "the largest |u| (tests/golden/oracle_paper_scale_cartesian_128.npz)",
+        "roofline": {"bound": "hbm", "achieved": agg, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": agg / HBM_PEAK_GBS,
+                     "kernel": "Cartesian interior stage kernel + face kernel (FP64, order 10), "
+                               "mean over stages 1-4",
+                     "avg_stage_us": [float(x) for x in us[:4]],
+                     "algorithmic_bytes_per_stage": byts},
+    }
+    log(f"cartesian: {rs[-1].steps_taken} steps, {ts / steps * 1e3:.1f} ms, "
+        f"{out['value'] / 1e9:.1f} G updates/s, {agg / 1e3:.2f} TB/s, vs oracle {diff}")
+    g.close()
+    return out
+
+
 def warm_start_runs(hr, torch, g, w, steps, steps_cold, t_cold, u_cold, sols=None):
     """The learned warm start. An MLP trained inside this run (warmstart.RECIPE:
     4096 catalog solves at 64x64x8, 2048 sampled points each) predicts u; the
@@ -647,6 +692,7 @@ def main() -> int:
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-spherical", action="store_true")
     ap.add_argument("--no-precision-form", action="store_true")
+    ap.add_argument("--no-cartesian", action="store_true")
     ap.add_argument("--no-warm-start", action="store_true")
     ap.add_argument("--no-multi-patch", action="store_true")
     ap.add_argument("--no-catalog", action="store_true",
@@ -814,6 +860,8 @@ def main() -> int:
                                 "(tests/golden/oracle_paper_scale_spherical_128x64x8.npz)",
         }
         gs.close()
+    if not args.no_cartesian:
+        out["cartesian"] = cartesian_runs(hr, torch, args.steps, 1)
     if not args.no_precision_form:
         out["precision_form"] = precision_form_runs(hr, torch)
     if not args.no_multi_patch:

@@ -141,6 +141,17 @@ def paper_scale(coords: int = SINHSYMTP, fd_order: int = 10) -> Workload:
                     label=f"paper-scale {g.name()}")
 
 
+def paper_scale_cartesian(N: int = 128, rmax: float = 32.0, fd_order: int = 10) -> Workload:
+    """The paper-scale punctures on a Cartesian cube of N^3 points, [-rmax, rmax]^3
+    (cell width 0.5 at the defaults), relaxed to residual 1e-10. eta 0.03 from a
+    sweep of the FP64 steps to 1e-10 at 128^3, rmax 32: 0.015 -> 1900, 0.02 ->
+    1800, 0.03 -> 1500, 0.045 -> 2100, 0.0625 -> 2700, 0.09 -> 3500."""
+    g = GridSpec(CARTESIAN, N, N, N, fd_order, rmax=rmax)
+    base = paper_scale()
+    return Workload(g, base.punctures, eta=0.03, n_steps=2_000_000, tol=1e-10, check_every=100,
+                    label=f"paper-scale {g.name()}")
+
+
 def precision_form(N0: int = 128, N1: int = 128, N2: int = 16) -> Workload:
     """Equal-mass small-case physics on a larger 8th-order grid, for the FP32-bulk
     form. eta from sweeps of the FP64 steps to 1e-10: 128x128x16 eta 4 -> 52100,
