@@ -305,7 +305,9 @@ def catalog_result(n: int, precision_s: str, autotune: bool, max_steps: int,
     floor is above 1e-10) by the batched path: one persistent launch per RK
     stage over every grid still relaxing in its group, graph-captured per check
     interval; groups sized to the Infinity Cache (budget bytes, 0: one group);
-    eta per grid from its dt."""
+    eta per grid from its dt. With autotune, the batch-level tile tuner
+    (catalog.autotune_batches) picks each batched composition's phi chunk on
+    fresh grids before the timed region."""
     import torch
 
     import paper_2501_14030_amd as hr
@@ -317,16 +319,18 @@ def catalog_result(n: int, precision_s: str, autotune: bool, max_steps: int,
         budget = 1 << 62
     ws = workloads.catalog(n, seed=14030)
     grids = [warmstart.make_grids([w], w.grid.shape)[0] for w in ws]
-    tuned = {}
-    if autotune:
-        for g in grids:
-            key = g.N
-            if key not in tuned:
-                tuned[key] = g.autotune(hr.FP64 if prec == hr.FP64 else hr.FP32, 3)
-            else:
-                g.set_kernel_config(**tuned[key][0])
     etas = [workloads.eta_for_dt(g.suggest_dt(0.5)) for g in grids]
     tols = [workloads.catalog_tol(g.N) for g in grids]
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    tuned = {}
+    t_tune = 0.0
+    if autotune:
+        # batch-level tile tuning on fresh grids, outside the timed region
+        t0 = time.perf_counter()
+        tuned = catalog.autotune_batches(ws, grids, prec,
+                                         catalog.plan_groups(grids, prec, budget, cus), etas,
+                                         log=log)
+        t_tune = time.perf_counter() - t0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     steps, resid = catalog.relax_catalog(grids, etas, tols, prec, max_steps=max_steps,
@@ -354,7 +358,10 @@ def catalog_result(n: int, precision_s: str, autotune: bool, max_steps: int,
                grids, prec, budget, torch.cuda.get_device_properties(0).multi_processor_count)),
            "cache_budget_bytes": budget,
            "by_shape": by_shape,
-           "autotuned": {"x".join(map(str, k)): v[0] for k, v in tuned.items()}}
+           "autotune_s": t_tune,
+           "autotuned": {" + ".join("x".join(map(str, sh)) for sh in k):
+                         {"chunk": v[0], "ms_per_40_steps": {str(c): t * 1e3 for c, t in v[1].items()}}
+                         for k, v in tuned.items()}}
     for g in grids:
         g.close()
     return out
@@ -705,6 +712,8 @@ def main() -> int:
                     help="relax the seeded N-configuration catalog with the batched path")
     ap.add_argument("--catalog-prec", default="fp64", choices=["fp64", "split"])
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="run the default bench's catalog without batch tile tuning")
     ap.add_argument("--cache-budget", type=int, default=200 << 20,
                     help="catalog: per-stage working set of one batch (bytes; 0 = one batch)")
     ap.add_argument("--max-steps", type=int, default=60000)
@@ -868,7 +877,8 @@ def main() -> int:
         out["multi_patch"] = multi_patch_runs(hr, torch, w, u64)
     if not args.no_catalog:
         log("catalog: 64 configurations, FP32 + FP64 finish ...")
-        out["catalog"] = catalog_result(64, "split", False, args.max_steps, args.cache_budget)
+        out["catalog"] = catalog_result(64, "split", not args.no_autotune, args.max_steps,
+                                        args.cache_budget)
         log(f"catalog: {out['catalog']['wall_s']:.1f} s, "
             f"{out['catalog']['grid_point_rhs_updates_per_s'] / 1e9:.1f} G updates/s")
     # roofline of the dominant kernel: the resident RK4 kernel at this size,

@@ -70,6 +70,59 @@ def plan_groups(grids, precision: int, budget: int = CACHE_BUDGET, cus: int = 25
     return [[i] for i in solo] + [[rest[j] for j in grp] for grp in sub]
 
 
+def autotune_batches(ws, grids, precision: int, groups, etas, steps: int = 40, log=None) -> dict:
+    """Batch-level tile tuning for the groups that run as batches. The members
+    of a group whose own kernel is not the resident one go through the batched
+    phi-column stage body; for each distinct composition of such members (their
+    sorted shapes) a batch of fresh grids of the same configurations (`ws`) is
+    timed at every phi chunk 1, 2, 4, ... up to their largest N2 (`steps` RK4
+    steps after one untimed pass that captures the interval's graph), and the
+    fastest chunk is set on the members as an explicit phi-column
+    configuration, which the batch keeps. Returns {composition: (chunk,
+    {chunk: seconds})}; the catalog's own grids are not stepped."""
+    import torch
+
+    from .warmstart import make_grids
+
+    tuned = {}
+    for group in groups:
+        if len(group) < 2:
+            continue
+        members = [i for i in group if grids[i].resolved_kernel(precision)["variant"] != 3]
+        if not members:
+            continue
+        key = tuple(sorted(tuple(grids[i].N) for i in members))
+        if key not in tuned:
+            fresh = make_grids([ws[i] for i in members], None)
+            times = {}
+            c = 1
+            while c <= max(g.N[2] for g in fresh):
+                for g in fresh:
+                    g.set_kernel_config(variant=2, chunk=min(c, g.N[2]))
+                b = Batch(fresh)
+                e = [etas[i] for i in members]
+                b.relax(e, 1.0, n_steps=steps, tol=0.0, check_every=steps, precision=precision,
+                        raise_on_error=False)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                b.relax(e, 1.0, n_steps=steps, tol=0.0, check_every=steps, precision=precision,
+                        raise_on_error=False)
+                torch.cuda.synchronize()
+                times[c] = time.perf_counter() - t0
+                b.close()
+                c *= 2
+            for g in fresh:
+                g.close()
+            best = min(times, key=times.get)
+            tuned[key] = (best, times)
+            if log:
+                log(f"batch tuning {key}: chunk {best} "
+                    f"({', '.join(f'{k}: {v * 1e3:.1f} ms' for k, v in times.items())})")
+        for i in members:
+            grids[i].set_kernel_config(variant=2, chunk=min(tuned[key][0], grids[i].N[2]))
+    return tuned
+
+
 def relax_catalog(grids, etas, tols, precision: int = FP64, max_steps: int = 60000,
                   chunk: int = 5000, check_every: int = 100, budget: int = CACHE_BUDGET,
                   log=None):

@@ -82,11 +82,14 @@ def config_of(w: workloads.Workload) -> np.ndarray:
     return config_features(e["q"], e["chi1"], e["chi2"], P, e["D"])
 
 
-def make_grids(ws, shape):
+def make_grids(ws, shape=None):
+    """Bound grids of the configurations ws at `shape` (None: each one's own),
+    punctures set."""
     grids = []
     for w in ws:
         spec = w.grid
-        g = grid_create(spec.coords, shape[0], shape[1], shape[2], spec.fd_order,
+        sh = spec.shape if shape is None else shape
+        g = grid_create(spec.coords, sh[0], sh[1], sh[2], spec.fd_order,
                         params=default_params(amax=spec.amax, sinhwaa=spec.sinhwaa,
                                               bscale=spec.bscale, rmax=spec.rmax))
         g.set_punctures(*w.punctures.as_tuple())

@@ -67,3 +67,37 @@ def test_catalog_runner_matches_single_grid_solves(prec):
         assert resid[k] < tols[k]
         assert rel_maxdiff(gs[k].get_u(extended=True), e.get_u(extended=True)) <= 1e-11
         assert np.isfinite(resid[k])
+
+
+def test_batch_tile_tuner_sets_a_measured_chunk():
+    """catalog.autotune_batches times a batched composition at every phi
+    chunk on fresh grids and sets the fastest on the members (an explicit
+    phi-column configuration); the catalog's own grids are not stepped, and a
+    catalog run with the tuned chunk still matches the eager solves."""
+    banner("batch tile tuner")
+    specs = [workloads.GridSpec(0, 64, 64, 32, 10, bscale=4.0),
+             workloads.GridSpec(0, 48, 32, 24, 10, bscale=3.0)]
+    ws = [workloads.Workload(s, workloads.quasi_circular(1.5, 2 * s.bscale, [0, 0, 0.2],
+                                                         [0.1, 0, 0]),
+                             eta=6.0, label=f"tuner[{k}]") for k, s in enumerate(specs)]
+    gs = []
+    for w in ws:
+        g = gpu_grid(w.grid)
+        g.set_punctures(*w.punctures.as_tuple())
+        gs.append(g)
+    etas = [workloads.eta_for_dt(g.suggest_dt(0.5)) for g in gs]
+    tuned = catalog.autotune_batches(ws, gs, hr.FP64, [[0, 1]], etas, steps=20, log=banner)
+    (key, (chunk, times)), = tuned.items()
+    assert sorted(times) == [1, 2, 4, 8, 16, 32] and chunk == min(times, key=times.get)
+    for g in gs:
+        cfg = g.kernel_config()
+        assert cfg["variant"] == 2 and cfg["chunk"] == min(chunk, g.N[2])
+        assert np.all(g.get_u() == 0.0)   # not stepped
+    steps, resid = catalog.relax_catalog(gs, etas, [1e-10, 1e-10], hr.FP64, max_steps=60000,
+                                         budget=1 << 40)
+    for k, w in enumerate(ws):
+        e = gpu_grid(w.grid)
+        e.set_punctures(*w.punctures.as_tuple())
+        r = e.relax(etas[k], 1.0, 0.0, 60000, 1e-10, check_every=100)
+        assert steps[k] == r.steps_taken and resid[k] < 1e-10
+        assert rel_maxdiff(gs[k].get_u(extended=True), e.get_u(extended=True)) <= 1e-11
