@@ -37,8 +37,10 @@
 // the data stores before the counter store. Every wait is bounded: a poll
 // count past spin_limit sets err, and the blocks leave their loops.
 //
-// The arithmetic per point is that of the stage kernels (same stencil
-// summation order and stage combine), so results match them to rounding.
+// The arithmetic per point is that of the stage kernels (in FP64 the same
+// stencil summation order and stage combine; the single-precision instances
+// fold the x0/x1 sums with the metric factors, see below), so results match
+// them to rounding.
 
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
@@ -112,11 +114,29 @@ __device__ __forceinline__ void resident_body(const ResidentArgsT<T>& a, const i
   const unsigned o2d = (unsigned)NG * N1;
 
   // --- own points --------------------------------------------------------
+  // The column's metric factors. The single-precision instances (the split
+  // form's increment) fold the x0 and x1 sums into per-tap weights: f0 u,00 +
+  // f3 u,0 = sum_k (cp0_k u(+k) + cm0_k u(-k)) + f0 w0 u with cp0_k = f0 d2_k +
+  // f3 d1_k, cm0_k = f0 d2_k - f3 d1_k (likewise x1 with f1, f4), two FMAs per
+  // tap pair instead of four operations; in FP64 the 20 weights would not fit
+  // the 1024-thread block's 128 registers (they spill), so FP64 keeps the sums.
+  constexpr bool kFold = sizeof(T) == 4;
   T f[6];
+  T cp0[NG], cm0[NG], cp1[NG], cm1[NG], c0 = (T)0;
   {
     const unsigned k2 = (unsigned)i0 + (unsigned)d.N0 * (unsigned)i1;
 #pragma unroll
     for (int q = 0; q < 6; ++q) f[q] = load_factor(a.fac, a.facb, q * n2d + k2);
+    if constexpr (kFold) {
+#pragma unroll
+      for (int k = 1; k <= NG; ++k) {
+        cp0[k - 1] = f[0] * (T)Wt.d2[k] + f[3] * (T)Wt.d1[k];
+        cm0[k - 1] = f[0] * (T)Wt.d2[k] - f[3] * (T)Wt.d1[k];
+        cp1[k - 1] = f[1] * (T)Wt.d2[k] + f[4] * (T)Wt.d1[k];
+        cm1[k - 1] = f[1] * (T)Wt.d2[k] - f[4] * (T)Wt.d1[k];
+      }
+      c0 = (T)Wt.d2[0] * (f[0] + f[1] + f[2]);
+    }
   }
   T yu[NPT], yv[NPT], su[NPT], sv[NPT], au[NPT], av[NPT], ps[NPT], ss[NPT];
   T hu[NPT], hv[NPT];   // split form: base slopes
@@ -364,19 +384,29 @@ __device__ __forceinline__ void resident_body(const ResidentArgsT<T>& a, const i
       if (grp + PG * j >= N2) continue;
       const T* r = ut + lidx[j];
       const T uc = r[0];
-      T d0 = 0, d1 = 0, e0 = 0, e1 = 0;
+      T lap;
+      if constexpr (kFold) {
+        lap = c0 * uc + f[2] * e2[j];
 #pragma unroll
-      for (int k = 1; k <= NG; ++k) {
-        const T p0 = r[k], m0 = r[-k];
-        const T p1 = r[k * RW], m1 = r[-k * RW];
-        d0 += (T)Wt.d1[k] * (p0 - m0);
-        d1 += (T)Wt.d1[k] * (p1 - m1);
-        e0 += (T)Wt.d2[k] * (p0 + m0);
-        e1 += (T)Wt.d2[k] * (p1 + m1);
+        for (int k = 1; k <= NG; ++k) {
+          lap += cp0[k - 1] * r[k] + cm0[k - 1] * r[-k];
+          lap += cp1[k - 1] * r[k * RW] + cm1[k - 1] * r[-k * RW];
+        }
+      } else {
+        T d0 = 0, d1 = 0, e0 = 0, e1 = 0;
+#pragma unroll
+        for (int k = 1; k <= NG; ++k) {
+          const T p0 = r[k], m0 = r[-k];
+          const T p1 = r[k * RW], m1 = r[-k * RW];
+          d0 += (T)Wt.d1[k] * (p0 - m0);
+          d1 += (T)Wt.d1[k] * (p1 - m1);
+          e0 += (T)Wt.d2[k] * (p0 + m0);
+          e1 += (T)Wt.d2[k] * (p1 + m1);
+        }
+        const T w0 = (T)Wt.d2[0];
+        const T dd0 = e0 + w0 * uc, dd1 = e1 + w0 * uc, dd2 = e2[j] + w0 * uc;
+        lap = f[0] * dd0 + f[1] * dd1 + f[2] * dd2 + f[3] * d0 + f[4] * d1;
       }
-      const T w0 = (T)Wt.d2[0];
-      const T dd0 = e0 + w0 * uc, dd1 = e1 + w0 * uc, dd2 = e2[j] + w0 * uc;
-      const T lap = f[0] * dd0 + f[1] * dd1 + f[2] * dd2 + f[3] * d0 + f[4] * d1;
       T ku, kv;
       if constexpr (CORR) {
         ku = hu[j] + (sv[j] - a.eta * uc);
