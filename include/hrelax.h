@@ -164,6 +164,8 @@ hr_status hr_grid_bind(hr_grid* g, void* dev_ptr, size_t bytes, void* hip_stream
  * On a SinhSymTP grid every puncture must lie at one of the two foci
  * (0, 0, +-bscale), each coordinate within 1e-12 bscale: the coordinates put
  * their finest cells there (the paper's binary punctures sit at the foci).
+ * On a Cartesian grid a puncture may not sit on a cell centre (all three
+ * coordinates within 1e-9 cell widths of -rmax + (j + 1/2) dx), where r = 0.
  * Arguments are checked before the grid's state, so an invalid argument is
  * HR_EINVAL even on an unbound grid.
  * Errors: HR_EINVAL, HR_ESTATE (not bound), HR_EDEVICE.

@@ -1243,6 +1243,19 @@ hr_status hr_set_punctures(hr_grid* g, int n, const double* m, const double* x,
       if (!on_focus)
         return fail(HR_EINVAL, "SinhSymTP punctures must lie at the foci (0, 0, +-bscale)");
     }
+    // Cartesian cell centres sit at -rmax + (j + 1/2) dx_a; a puncture on one
+    // (all three coordinates) would put r = 0 into the source
+    if (g->d.cart) {
+      const int n3[3] = {g->d.N0, g->d.N1, g->d.N2};
+      bool on_centre = true;
+      for (int a = 0; a < 3; ++a) {
+        const double dxa = 2.0 * g->prm.rmax / n3[a];
+        const double t = (pz.x[i][a] + g->prm.rmax) / dxa - 0.5;
+        on_centre = on_centre && std::fabs(t - std::nearbyint(t)) <= 1e-9;
+      }
+      if (on_centre)
+        return fail(HR_EINVAL, "a Cartesian puncture may not sit on a cell centre (r = 0 there)");
+    }
   }
   hr_status st = check_ready(g, false);
   if (st != HR_OK) return st;

@@ -1065,7 +1065,7 @@ __global__ void __launch_bounds__(kBlock) k_cart_faces(StageArgs<T> a) {
   const int q2 = planes_of(d);
   const T kappa = cx[d.P0 + d.R1 + q2];
   const T dxa = cx[d.P0 + d.R1 + q2 + 1 + ax];
-  const T x = cx[i0 + d.NG], y = cx[d.P0 + i1 + d.zo], z = cx[d.P0 + d.R1 + i2 + d.NG];
+  const T x = cx[i0 + d.NG], y = cx[d.P0 + i1 + d.NG], z = cx[d.P0 + d.R1 + i2 + d.NG];
   const T rr = sqrt(x * x + y * y + z * z);
   const T xa = ax == 0 ? x : ax == 1 ? y : z;
   const T qd = rr / ((T)2 * dxa * fabs(xa));   // 1 / (2 dx d r / d n)

@@ -149,6 +149,22 @@ def test_cartesian_sizes_and_host_refusals(lib):
     lib.hr_grid_destroy(h)
     st, h = _create(lib, 4, 8, 8, 8, 2, hr.default_params(rmax=-1.0))
     assert st == hr.EINVAL
+    # a puncture on a cell centre (r = 0 there) is refused before any device
+    # call; one between centres passes the argument checks (ESTATE: unbound)
+    st, h = _create(lib, 4, 8, 8, 8, 2, hr.default_params(rmax=4.0))   # centres at +-0.5, ...
+    assert st == hr.OK
+    m = np.array([0.5])
+    zero = np.zeros(3)
+    dp = ctypes.POINTER(ctypes.c_double)
+
+    def put(x):
+        x = np.asarray(x, dtype=np.float64)
+        return lib.hr_set_punctures(h, 1, m.ctypes.data_as(dp), x.ctypes.data_as(dp),
+                                    zero.ctypes.data_as(dp), zero.ctypes.data_as(dp))
+
+    assert put([0.5, -1.5, 2.5]) == hr.EINVAL
+    assert put([0.5, -1.5, 2.0]) == hr.ESTATE
+    lib.hr_grid_destroy(h)
 
 
 def test_outer_bc_order_arguments(lib):
