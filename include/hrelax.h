@@ -112,9 +112,10 @@ void hr_default_params(hr_grid_params* p);
  *            along xx0, xx1, xx2; each N_d >= max(NG, 2), any parity) store NG
  *            outer layers beyond every face: the extended layout is the padded
  *            box (N0 + 2 NG) x (N1 + 2 NG) x (N2 + 2 NG), whose edge and corner
- *            points are never read and stay zero. They relax in HR_FP64 only
- *            on the stage kernels (no resident kernel, batch, volume norm or
- *            warm start: those calls return HR_EINVAL for them).
+ *            points are never read and stay zero. They relax in HR_FP64 or
+ *            HR_FP32 on the stage kernels (no resident kernel, split-state
+ *            form, batch, volume norm or warm start: those calls return
+ *            HR_EINVAL for them).
  *   fd_order centred finite-difference order: 2, 4, 6, 8 or 10
  *   p        coordinate parameters, NULL for defaults (copied)
  *   out      receives the handle; free it with hr_grid_destroy.
@@ -324,7 +325,8 @@ hr_status hr_suggest_dt(const hr_grid* g, double cfl, double* dt);
  * switch, which changes cache policy only).
  *   variant    0 = automatic (3 where it applies, else 1 or 2 by size),
  *              1 = plane tiles (one phi plane per block),
- *              2 = phi-marching columns (a block walks `chunk` phi planes),
+ *              2 = phi-marching columns (a block walks `chunk` phi planes;
+ *              on Cartesian grids `chunk` z planes),
  *              3 = resident (FP64 steps, and the FP32 increment steps of
  *              HR_FP32_FP64FINISH): one kernel launch runs up to
  *              1000 whole RK4 steps with the state of every 8 x 8 (or
@@ -339,10 +341,11 @@ hr_status hr_suggest_dt(const hr_grid* g, double cfl, double* dt);
  *              HR_EDEVICE by the relaxing call.
  *   streaming  -1 = automatic (by grid size), 0 = cached, 1 = non-temporal
  *              loads/stores for fields touched once per stage
- *   chunk      phi planes per block for variant 2 (0 = automatic); for
- *              variant 3 the patch rows along x1, 8 or 4 (0 = automatic: 8 x 4
- *              patches where 8 x 8 ones would leave more than half of the
- *              compute units idle and 8 x 4 ones fit, else 8 x 8)
+ *   chunk      phi (Cartesian: z) planes per block for variant 2 (0 =
+ *              automatic: 8); for variant 3 the patch rows along x1, 8 or 4
+ *              (0 = automatic: 8 x 4 patches where 8 x 8 ones would leave
+ *              more than half of the compute units idle and 8 x 4 ones fit,
+ *              else 8 x 8)
  *   graph      -1 = automatic (on), 0 = off, 1 = on: hr_relax captures the
  *              launches of one check interval (RK stages, residual) in a HIP
  *              graph once per (precision form, check_every, eta, dt, c,

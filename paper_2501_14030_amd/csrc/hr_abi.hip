@@ -78,11 +78,8 @@ bool resident_split_ok(const hr_grid* g) {
 void resolve_variant(const hr_grid* g, int& variant, int& chunk) {
   variant = g->variant;
   chunk = g->chunk;
-  if (g->d.cart) {   // one kernel family (interior tiles + faces) for Cartesian grids
-    variant = 1;
-    chunk = 0;
-    return;
-  }
+  // (Cartesian grids: plane tiles or z columns for the interior, then the face
+  // kernel; their stored face rows keep them off the resident kernel)
   const long tiles = (long)((g->d.N0 + kTileX - 1) / kTileX) * ((g->d.N1 + kTileY - 1) / kTileY);
   if (variant == 0) {
     if (resident_ok(g))
@@ -1622,8 +1619,7 @@ hr_status hr_autotune(hr_grid* g, hr_precision prec, int n_steps, hr_kernel_conf
   HR_HIP(hipSetDevice(g->device));
   std::vector<hr_kernel_config> cand;
   cand.push_back(hr_kernel_config{1, 0, 0, g->graph});
-  // Cartesian grids have one kernel family: nothing to choose
-  for (int c = 1; c <= g->d.N2 && !g->d.cart; c *= 2)
+  for (int c = 1; c <= g->d.N2; c *= 2)
     cand.push_back(hr_kernel_config{2, 0, c, g->graph});
   if (prec == HR_FP64) {
     // the resident kernel on each patch shape that fits

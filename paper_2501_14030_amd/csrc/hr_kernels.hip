@@ -1031,6 +1031,126 @@ __global__ void __launch_bounds__(kTileThreads) k_cart_stage(StageArgs<T> a) {
   combine<STAGE, false, T>(a, idx, co, uc, v, ku, kv);
 }
 
+// Interior points in columns: a block walks `chunk` z planes of one (x0, x1)
+// tile, as the curvilinear column kernel does along phi, without images: the
+// padded box stores the tile's rim and the NG planes beyond each z face, so the
+// z taps are a register queue filled by one load per plane, and the
+// rim-extended tile of the next plane is fetched into registers while the
+// current one is computed from LDS. The arithmetic is that of k_cart_stage.
+template <typename T, int NG, int STAGE>
+__global__ void __launch_bounds__(kTileThreads, 4) k_cart_col(StageArgs<T> a, int chunk) {
+  constexpr int W = TileShape<NG>::W, H = TileShape<NG>::H;
+  constexpr int NE = (W * H + kTileThreads - 1) / kTileThreads;
+  constexpr Weights<NG> Wt{};
+  __shared__ T tile[2][W * H];
+  __shared__ T fl[kFacRows<T>][kTileThreads];
+  const TileId id = xcd_tile();
+  const Dims& d = a.d;
+  const int x0b = id.x * TX, x1b = id.y * TY;
+  const int z0 = id.z * chunk, z1 = min(z0 + chunk, d.N2);
+  const int i0 = x0b + threadIdx.x, i1 = x1b + threadIdx.y;
+  const bool active = i0 < d.N0 && i1 < d.N1;
+  const int ft = threadIdx.x + TX * threadIdx.y;
+  const unsigned plane = (unsigned)d.P0 * (unsigned)d.R1;
+  // stored plane p = z + NG of the padded box starts at p * plane
+  const unsigned col = sidx(d, active ? i0 : 0, active ? i1 : 0, -NG);
+  const unsigned n2d = (unsigned)d.N0 * (unsigned)d.N1;
+  const unsigned k2 = active ? (unsigned)i0 + (unsigned)d.N0 * (unsigned)i1 : 0u;
+  // this thread's tile elements: offset within a stored plane, or none (the
+  // cells past the far rim; the tile's corners are loaded but never read)
+  unsigned toff[NE];
+  bool tin[NE];
+#pragma unroll
+  for (int r = 0; r < NE; ++r) {
+    const int e = ft + r * kTileThreads;
+    const int l1 = e / W;
+    const int l0 = e - l1 * W;
+    const int j0 = x0b + l0 - NG, j1 = x1b + l1 - NG;   // both >= -NG
+    tin[r] = e < W * H && j0 < d.N0 + NG && j1 < d.N1 + NG;
+    toff[r] = tin[r] ? sidx(d, j0, j1, -NG) : 0u;
+  }
+  auto fetch = [&](T (&v)[NE], int z) {
+    const unsigned pb = plane * (unsigned)(z + NG);
+#pragma unroll
+    for (int r = 0; r < NE; ++r) v[r] = tin[r] ? a.uin[toff[r] + pb] : (T)0;
+  };
+  auto store = [&](const T (&v)[NE], T* t) {
+#pragma unroll
+    for (int r = 0; r < NE; ++r) {
+      const int e = ft + r * kTileThreads;
+      if (e < W * H) t[e] = v[r];
+    }
+  };
+  // z queue q[j] = u(z - NG + j), j = 0..2NG, for z = z0 (stored planes z0 ... z0 + 2NG)
+  T q[2 * NG + 1];
+  T f[6];
+  auto fac = [&](int r) -> T {
+    if constexpr (kFacRows<T> == 6) return fl[r][ft];
+    else return f[r];
+  };
+  PointIn<STAGE, false, T> cur;
+  if (active) {
+#pragma unroll
+    for (int j = 0; j <= 2 * NG; ++j) q[j] = a.uin[col + plane * (unsigned)(z0 + j)];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      if constexpr (kFacRows<T> == 6) fl[r][ft] = load_factor(a.fac, a.facb, r * n2d + k2);
+      else f[r] = load_factor(a.fac, a.facb, r * n2d + k2);
+    }
+    cur.load(a, col + plane * (unsigned)(z0 + NG));
+  }
+  {
+    T t0[NE];
+    fetch(t0, z0);
+    store(t0, tile[0]);
+  }
+  __syncthreads();
+  for (int z = z0; z < z1; ++z) {
+    const int buf = (z - z0) & 1;
+    const bool more = z + 1 < z1;
+    // prefetch plane z + 1 (its queue entry is u(z + 1 + NG), stored plane z + 1 + 2NG)
+    T tn[NE];
+    PointIn<STAGE, false, T> nxt;
+    T qn = (T)0;
+    if (more) {
+      fetch(tn, z + 1);
+      if (active) {
+        qn = a.uin[col + plane * (unsigned)(z + 1 + 2 * NG)];
+        nxt.load(a, col + plane * (unsigned)(z + 1 + NG));
+      }
+    }
+    if (active) {
+      const T* r = tile[buf] + (threadIdx.y + NG) * W + (threadIdx.x + NG);
+      const T uc = r[0];
+      T d0 = 0, d1 = 0, e0 = 0, e1 = 0, e2 = 0;
+#pragma unroll
+      for (int k = 1; k <= NG; ++k) {
+        const T p0 = r[k], m0 = r[-k];
+        const T p1 = r[k * W], m1 = r[-k * W];
+        d0 += (T)Wt.d1[k] * (p0 - m0);
+        d1 += (T)Wt.d1[k] * (p1 - m1);
+        e0 += (T)Wt.d2[k] * (p0 + m0);
+        e1 += (T)Wt.d2[k] * (p1 + m1);
+        e2 += (T)Wt.d2[k] * (q[NG + k] + q[NG - k]);
+      }
+      const T w0 = (T)Wt.d2[0];
+      const T lap = fac(0) * (e0 + w0 * uc) + fac(1) * (e1 + w0 * uc) +
+                    fac(2) * (e2 + w0 * uc) + fac(3) * d0 + fac(4) * d1;
+      const T ku = cur.v - a.eta * uc;
+      const T kv = fac(5) * (lap + source<T>(cur.ssrc, cur.psi, uc));
+      combine_pt<STAGE, false, T>(a, col + plane * (unsigned)(z + NG), cur, uc, ku, kv);
+    }
+    if (more) {
+      store(tn, tile[buf ^ 1]);
+#pragma unroll
+      for (int j = 0; j < 2 * NG; ++j) q[j] = q[j + 1];
+      q[2 * NG] = qn;
+      cur = nxt;
+    }
+    __syncthreads();
+  }
+}
+
 // Number of outer points on the two faces normal to axis ax.
 __device__ __forceinline__ int cart_face_points(const Dims& d, int ax) {
   const int n1 = ax == 0 ? d.N1 : d.N0, n2 = ax == 2 ? d.N1 : d.N2;
@@ -1237,16 +1357,29 @@ template <typename T, int NG, int STAGE>
 hipError_t cart_stage_launch(const StageArgs<T>& a, hipStream_t s, hipEvent_t t0,
                              hipEvent_t t1) {
   const Dims& d = a.d;
-  const dim3 grid = tile_grid(d), block(TX, TY, 1);
+  const dim3 block(TX, TY, 1);
   const int nf = 2 * d.NG * (d.N1 * d.N2 + d.N0 * d.N2 + d.N0 * d.N1);
-  if (t0 && t1) {
-    hipExtLaunchKernelGGL(k_cart_stage<T, NG, STAGE>, grid, block, 0, s, t0, nullptr, 0, a);
+  // interior: plane tiles (variant 1) or z columns of `chunk` planes (variant 2)
+  const bool cols = a.variant == 2;
+  const int ch = a.chunk > 0 ? a.chunk : 1;
+  const dim3 grid = cols ? dim3((d.N0 + TX - 1) / TX, (d.N1 + TY - 1) / TY, (d.N2 + ch - 1) / ch)
+                         : tile_grid(d);
+  if (cols) {
+    if (t0 && t1)
+      hipExtLaunchKernelGGL(k_cart_col<T, NG, STAGE>, grid, block, 0, s, t0, nullptr, 0, a, ch);
+    else
+      k_cart_col<T, NG, STAGE><<<grid, block, 0, s>>>(a, ch);
+  } else {
+    if (t0 && t1)
+      hipExtLaunchKernelGGL(k_cart_stage<T, NG, STAGE>, grid, block, 0, s, t0, nullptr, 0, a);
+    else
+      k_cart_stage<T, NG, STAGE><<<grid, block, 0, s>>>(a);
+  }
+  if (t0 && t1)
     hipExtLaunchKernelGGL(k_cart_faces<T, NG, STAGE>, dim3(nblocks(nf)), dim3(kBlock), 0, s,
                           nullptr, t1, 0, a);
-  } else {
-    k_cart_stage<T, NG, STAGE><<<grid, block, 0, s>>>(a);
+  else
     k_cart_faces<T, NG, STAGE><<<nblocks(nf), kBlock, 0, s>>>(a);
-  }
   return hipGetLastError();
 }
 

@@ -327,10 +327,11 @@ __device__ __forceinline__ void resident_body(const ResidentArgsT<T>& a, const i
         jm = (jm == 0) ? N2 - 1 : jm - 1;
         e2[j] += (T)Wt.d2[k] * (r[(jp - i2) * TP] + r[(jm - i2) * TP]);
       }
+      // the stage input of the own point is su[j] (step 1 stored it at r[0])
       if constexpr (CORR) {
-        src[j] = source_delta(ss[j], ps[j], r[0]);
+        src[j] = source_delta(ss[j], ps[j], su[j]);
       } else {
-        const T p = ps[j] + r[0];
+        const T p = ps[j] + su[j];
         const T p2 = p * p;
         const T p4 = p2 * p2;
         src[j] = ss[j] / (p4 * p2 * p);
@@ -383,7 +384,7 @@ __device__ __forceinline__ void resident_body(const ResidentArgsT<T>& a, const i
     for (int j = 0; j < NPT; ++j) {
       if (grp + PG * j >= N2) continue;
       const T* r = ut + lidx[j];
-      const T uc = r[0];
+      const T uc = su[j];
       T lap;
       if constexpr (kFold) {
         lap = c0 * uc + f[2] * e2[j];

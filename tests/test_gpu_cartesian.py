@@ -3,8 +3,8 @@ on the GPU against the oracle.
 
 The cube [-rmax, rmax]^3 stores NG outer layers beyond each of its six faces;
 the interior kernel (plane tiles whose rim comes from those layers, z taps
-from memory) and the face kernel (radiation condition along each face normal)
-update them. Bars: FP64 trajectories and converged states within 1e-12 of the
+from memory; or z columns with the z taps in a register queue) and the face
+kernel (radiation condition along each face normal) update them. Bars: FP64 trajectories and converged states within 1e-12 of the
 oracle (relative to max|u|, over every stored point), residual histories to
 1e-9 relative; plain FP32 within 1e-4 after 300 steps (300 steps of single
 precision rounding, unit roundoff 6e-8, on a state whose largest value is
@@ -62,6 +62,56 @@ def test_trajectory_matches_oracle(spec):
     img = og.bc_images().reshape(og.shape)
     assert np.abs(gu[img == -2]).max() > 1e-3 * np.abs(gu).max()
     assert np.all(gu[img == -4] == 0.0)
+
+
+@pytest.mark.parametrize("prec", [hr.FP64, hr.FP32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("chunk", [1, 3, 16])
+def test_z_columns_match_plane_tiles_and_oracle(chunk, prec):
+    """The interior's column variant (a register queue of z taps, `chunk`
+    planes per block; chunk 3 leaves a ragged last chunk of 2 planes on N2 = 11)
+    does the plane tiles' arithmetic: the same state bit for bit, and the
+    oracle's trajectory in FP64."""
+    spec = SPECS[1]
+    eta = 1.0
+    og, _, ohist = _oracle(spec, 200, 0.0, eta)
+    out = []
+    for variant in (1, 2):
+        g = gpu_grid(spec)
+        g.set_kernel_config(variant=variant, chunk=chunk if variant == 2 else 0)
+        assert g.resolved_kernel(prec)["variant"] == variant
+        g.set_punctures(*_punct())
+        r = g.relax(eta, 1.0, og.suggest_dt(0.5), 200, 0.0, check_every=100, precision=prec)
+        assert r.status == hr.OK
+        out.append((g.get_u(extended=True), g.get_v(extended=True), r.history))
+    (u1, v1, h1), (u2, v2, h2) = out
+    banner(f"z columns, chunk {chunk}, precision {prec}: max |u_col - u_tiles| "
+           f"{np.abs(u2 - u1).max():.2e}")
+    assert np.array_equal(u1, u2) and np.array_equal(v1, v2)
+    assert list(h1) == list(h2)
+    if prec == hr.FP64:
+        ou, _ = og.state()
+        assert rel_maxdiff(u2, oracle_extended(og, ou)) <= 1e-12
+        np.testing.assert_allclose(h2, ohist, rtol=1e-9, atol=1e-15)
+
+
+def test_paper_scale_cube_runs_on_z_columns():
+    """The 128^3 cube resolves to the column variant (chunk 8), and 20 steps on
+    it equal 20 steps on the plane tiles bit for bit."""
+    w = workloads.paper_scale_cartesian()
+    states = []
+    for cfg in ({}, {"variant": 1}):
+        g = gpu_grid(w.grid)
+        if cfg:
+            g.set_kernel_config(**cfg)
+        else:
+            rk = g.resolved_kernel(hr.FP64)
+            assert rk["variant"] == 2 and rk["chunk"] == 8
+        g.set_punctures(*w.punctures.as_tuple())
+        r = g.relax(w.eta, 1.0, 0.0, 20, 0.0, check_every=10)
+        assert r.status == hr.OK
+        states.append(g.get_u(extended=True))
+        g.close()
+    assert np.array_equal(states[0], states[1])
 
 
 def test_converged_state_matches_oracle():
