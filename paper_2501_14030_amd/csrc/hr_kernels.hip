@@ -1160,7 +1160,8 @@ __device__ __forceinline__ int cart_face_points(const Dims& d, int ax) {
 // Face points, one thread each: the radiation condition k_f = -c (f/r + d_r
 // f) with d_r f = (d f / d n) / (d r / d n) along the outward normal n = +-x_d
 // (d r / d n = |x_d| / r), the one-sided difference toward the interior, then
-// the stage combine. Threads run x0 fastest where the face allows.
+// the stage combine. Threads run along x0: on the y and z faces over a row,
+// on the x faces over a row end's NG layer points.
 template <typename T, int NG, int STAGE>
 __global__ void __launch_bounds__(kBlock) k_cart_faces(StageArgs<T> a) {
   const Dims& d = a.d;
@@ -1168,15 +1169,29 @@ __global__ void __launch_bounds__(kBlock) k_cart_faces(StageArgs<T> a) {
   int ax = 0;
   while (ax < 3 && t >= cart_face_points(d, ax)) t -= cart_face_points(d, ax++);
   if (ax == 3) return;
-  // t = fast + n_fast (slow + n_slow (layer + NG side))
   const int nf = ax == 0 ? d.N1 : d.N0, ns = ax == 2 ? d.N1 : d.N2;
-  const int fast = t % nf;
-  t /= nf;
-  const int slow = t % ns;
-  t /= ns;
-  const int layer = t % NG, side = t / NG;
-  const int n_ax = ax == 0 ? d.N0 : ax == 1 ? d.N1 : d.N2;
-  const int out = side ? n_ax + layer : -1 - layer;
+  int fast, slow, out, side;
+  if (ax == 0) {
+    // x faces: t = layer + NG (y + N1 (z + N2 side)); a row's NG layer points
+    // on one side are contiguous in memory, so the layer runs fastest
+    const int layer = t % NG;
+    t /= NG;
+    fast = t % nf;
+    t /= nf;
+    slow = t % ns;
+    side = t / ns;
+    out = side ? d.N0 + layer : layer - NG;
+  } else {
+    // y and z faces: t = x + N0 (slow + n_slow (layer + NG side))
+    fast = t % nf;
+    t /= nf;
+    slow = t % ns;
+    t /= ns;
+    const int layer = t % NG;
+    side = t / NG;
+    const int n_ax = ax == 1 ? d.N1 : d.N2;
+    out = side ? n_ax + layer : -1 - layer;
+  }
   int i0, i1, i2;
   if (ax == 0) { i0 = out; i1 = fast; i2 = slow; }
   else if (ax == 1) { i0 = fast; i1 = out; i2 = slow; }
