@@ -57,7 +57,7 @@ def kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(shape, prec: str, variant: int = 0):
+def measured_traffic(shape, prec: str, variant: int = 0, cart: bool = False):
     """Per-launch HBM bytes (mean over the four stage kernels) from the committed
     rocprofv3 PMC summary, if it was taken on the current kernel source; FETCH_SIZE
     and WRITE_SIZE are scaled by what they read for a plain copy of known size."""
@@ -68,7 +68,8 @@ def measured_traffic(shape, prec: str, variant: int = 0):
         return None
     if pmc.get("kernel_sha") != kernel_sha():
         return None
-    key = f"{shape[0]}x{shape[1]}x{shape[2]}_{prec}" + ("_resident" if variant == 3 else "")
+    key = (f"{shape[0]}x{shape[1]}x{shape[2]}_{prec}" + ("_resident" if variant == 3 else "") +
+           ("_cartesian" if cart else ""))
     ent = pmc.get("runs", {}).get(key)
     if not ent:
         return None
@@ -98,14 +99,19 @@ def stage_bytes_per_point(itemsize: int, split: bool = False):
     return [itemsize * n for n in interior], [itemsize * n for n in outer]
 
 
-def stage_algorithmic_bytes(spec, itemsize: int, split: bool = False):
+def stage_algorithmic_bytes(spec, itemsize: int, split: bool = False, cart: bool = False):
     """Per-launch algorithmic bytes of each stage kernel (grid functions plus the
-    2D coefficient tables, each read once)."""
+    2D coefficient tables, each read once). Cartesian grids (cart): interior
+    kernel and face kernel together, NG face layers beyond each of the six faces
+    (their coordinates come from three short tables, not counted)."""
     N0, N1, N2 = spec.shape
     ng = spec.fd_order // 2
     nint = N0 * N1 * N2
-    nout = ng * N1 * N2
     bi, bo = stage_bytes_per_point(itemsize, split)
+    if cart:
+        nface = 2 * ng * (N1 * N2 + N0 * N2 + N0 * N1)
+        return [nint * bi[s] + nface * bo[s] + itemsize * 6 * N0 * N1 for s in range(4)]
+    nout = ng * N1 * N2
     tables = itemsize * (6 * N0 * N1 + 3 * ng * N1)
     return [nint * bi[s] + nout * bo[s] + tables for s in range(4)]
 
@@ -255,17 +261,22 @@ def copy_bandwidth(torch, nbytes: int = 1 << 30) -> float:
     return 2 * nbytes / best / 1e9
 
 
-def kernel_profile(shape_s: str, prec_s: str, variant: int = 0) -> int:
-    """Only the stage kernels at one shape (for rocprofv3 counter passes)."""
+def kernel_profile(shape_s: str, prec_s: str, variant: int = 0, coords: str = "sinhsymtp") -> int:
+    """Only the stage kernels at one shape (for rocprofv3 counter passes): the
+    paper-scale punctures on SinhSymTP, or on the Cartesian cube (rmax 32)."""
     import torch
 
     import paper_2501_14030_amd as hr
     from paper_2501_14030_amd import workloads
 
     shape = tuple(int(x) for x in shape_s.split("x"))
-    w = workloads.paper_scale()
     torch.cuda.set_device(0)
-    g = hr.grid_create(0, *shape, 10, params=hr.default_params(bscale=w.grid.bscale))
+    if coords == "cartesian":
+        w = workloads.paper_scale_cartesian()
+        g = hr.grid_create(hr.CARTESIAN, *shape, 10, params=hr.default_params(rmax=w.grid.rmax))
+    else:
+        w = workloads.paper_scale()
+        g = hr.grid_create(0, *shape, 10, params=hr.default_params(bscale=w.grid.bscale))
     if variant:
         g.set_kernel_config(variant=variant)
     g.set_punctures(*w.punctures.as_tuple())
@@ -524,11 +535,9 @@ def cartesian_runs(hr, torch, steps: int, warmup: int):
     rs, ts, tms = timed_solves(hr, torch, g, w, hr.FP64, steps, warmup, "cartesian fp64")
     diff = oracle_diff(g.get_u(extended=True), "paper_scale_cartesian_128")
     us = g.time_stage_kernels(w.eta, w.kappa, 0.0, 5, hr.FP64)
-    ng = s.fd_order // 2
-    nface = 2 * ng * (s.N1 * s.N2 + s.N0 * s.N2 + s.N0 * s.N1)
-    bi, bo = stage_bytes_per_point(8)
-    byts = [s.n_interior * bi[k] + nface * bo[k] + 8 * 6 * s.N0 * s.N1 for k in range(4)]
+    byts = stage_algorithmic_bytes(s, 8, cart=True)
     agg = sum(byts) / (sum(us[:4]) * 1e-6) / 1e9
+    tr = measured_traffic(s.shape, "fp64", cart=True)
     out = {
         "workload": f"paper-scale punctures on the Cartesian cube {s.N0}^3, [-{s.rmax:g}, "
                     f"{s.rmax:g}]^3, 10th-order FD, eta {w.eta}, to residual 1e-10",
@@ -542,9 +551,11 @@ def cartesian_runs(hr, torch, steps: int, warmup: int):
         "oracle_reference": "converged FP64 oracle solution at 4096 seeded evolved points and "
                             "the largest |u| (tests/golden/oracle_paper_scale_cartesian_128.npz)",
         "roofline": {"bound": "hbm", "achieved": agg, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": agg / HBM_PEAK_GBS,
-                     "kernel": "Cartesian interior stage kernel + face kernel (FP64, order 10), "
-                               "mean over stages 1-4",
+                     "frac": agg / HBM_PEAK_GBS, "traffic": tr,
+                     "traffic_over_algorithmic": (tr / (sum(byts) / 4)) if tr else None,
+                     "kernel": "Cartesian interior kernel (z columns, 8 planes per block) + "
+                               "face kernel (FP64, order 10), mean over stages 1-4",
+                     "kernel_config": g.resolved_kernel(hr.FP64),
                      "avg_stage_us": [float(x) for x in us[:4]],
                      "algorithmic_bytes_per_stage": byts},
     }
@@ -707,6 +718,8 @@ def main() -> int:
     ap.add_argument("--kernel-profile", metavar="N0xN1xN2", default=None,
                     help="only run the stage kernels at this shape (counter passes)")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "split"])
+    ap.add_argument("--coords", default="sinhsymtp", choices=["sinhsymtp", "cartesian"],
+                    help="grid family of --kernel-profile")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--catalog", type=int, default=0, metavar="N",
                     help="relax the seeded N-configuration catalog with the batched path")
@@ -724,7 +737,7 @@ def main() -> int:
         return catalog_run(args.catalog, args.catalog_prec, args.autotune, args.max_steps,
                            args.cache_budget)
     if args.kernel_profile:
-        return kernel_profile(args.kernel_profile, args.prec, args.variant)
+        return kernel_profile(args.kernel_profile, args.prec, args.variant, args.coords)
     if args.copy_calibration:
         return copy_calibration()
     if args.gpus != 1:
