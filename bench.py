@@ -309,7 +309,7 @@ def catalog_run(n: int, precision_s: str, autotune: bool, max_steps: int,
 
 
 def catalog_result(n: int, precision_s: str, autotune: bool, max_steps: int,
-                   budget: int) -> dict:
+                   budget: int, mlp=None) -> dict:
     """The seeded BBH catalog (q ~ U[1,10], D ~ U[6,20], |chi| ~ U[0,0.8] isotropic,
     grids drawn from 64x64x8, 128x128x16, 256x256x32) relaxed to the catalog
     tolerance of each shape (1e-10; 1e-9 at 256x256x32, whose FP64 residual
@@ -318,7 +318,10 @@ def catalog_result(n: int, precision_s: str, autotune: bool, max_steps: int,
     interval; groups sized to the Infinity Cache (budget bytes, 0: one group);
     eta per grid from its dt. With autotune, the batch-level tile tuner
     (catalog.autotune_batches) picks each batched composition's phi chunk on
-    fresh grids before the timed region."""
+    fresh grids before the timed region. With a trained warm-start network
+    (mlp), the same grids are relaxed again from its prediction
+    (catalog.warm_start_catalog: inference, the batched smoothing phase, then
+    the same relaxation), timed from the inference on."""
     import torch
 
     import paper_2501_14030_amd as hr
@@ -373,6 +376,34 @@ def catalog_result(n: int, precision_s: str, autotune: bool, max_steps: int,
            "autotuned": {" + ".join("x".join(map(str, sh)) for sh in k):
                          {"chunk": v[0], "ms_per_40_steps": {str(c): t * 1e3 for c, t in v[1].items()}}
                          for k, v in tuned.items()}}
+    if mlp is not None:
+        for w, g in zip(ws, grids):
+            g.set_punctures(*w.punctures.as_tuple())   # back to rest
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ns = catalog.warm_start_catalog(mlp, ws, grids, etas)
+        torch.cuda.synchronize()
+        t_ws = time.perf_counter() - t0
+        steps_w, resid_w = catalog.relax_catalog(grids, etas, tols, prec, max_steps=max_steps,
+                                                 budget=budget)
+        torch.cuda.synchronize()
+        el_w = time.perf_counter() - t0
+        by_w = {}
+        for g, st, st0 in zip(grids, steps_w, steps):
+            e = by_w.setdefault("x".join(map(str, g.N)), {"steps": [], "ratio": []})
+            e["steps"].append(ns + st)
+            e["ratio"].append((ns + st) / st0)
+        out["warm_start"] = {
+            "network": "the warm-start MLP trained in this run (warmstart.RECIPE)",
+            "smoothing_steps": ns,
+            "converged": sum(1 for r, tol in zip(resid_w, tols) if r < tol),
+            "wall_s": el_w, "inference_and_smoothing_s": t_ws,
+            "speedup_vs_cold": el / el_w,
+            "by_shape": {k: {"mean_steps": float(np.mean(v["steps"])),
+                             "mean_steps_ratio_vs_cold": float(np.mean(v["ratio"])),
+                             "max_steps_ratio_vs_cold": float(np.max(v["ratio"]))}
+                         for k, v in by_w.items()}}
+        log(f"catalog warm-started: {el_w:.1f} s ({el / el_w:.2f}x the cold catalog)")
     for g in grids:
         g.close()
     return out
@@ -565,7 +596,7 @@ def cartesian_runs(hr, torch, steps: int, warmup: int):
     return out
 
 
-def warm_start_runs(hr, torch, g, w, steps, steps_cold, t_cold, u_cold, sols=None):
+def warm_start_runs(hr, torch, g, w, steps, steps_cold, t_cold, u_cold, sols=None, keep=None):
     """The learned warm start. An MLP trained inside this run (warmstart.RECIPE:
     4096 catalog solves at 64x64x8, 2048 sampled points each) predicts u; the
     warm start is that prediction, 100 RK4 steps at ten times the damping
@@ -641,7 +672,10 @@ def warm_start_runs(hr, torch, g, w, steps, steps_cold, t_cold, u_cold, sols=Non
     }
     log(f"warm start held out: steps {warm.mean():.0f} vs cold {cold.mean():.0f} "
         f"(control {ctl.mean():.0f}), time {ev['warm_s']:.3f} vs {ev['cold_s']:.3f} s")
-    mlp.close()
+    if keep is not None:   # the caller warm-starts the catalog with it, then closes it
+        keep.append(mlp)
+    else:
+        mlp.close()
     return out
 
 
@@ -843,9 +877,11 @@ def main() -> int:
             "max_rel_diff_u_vs_fp64": float(np.abs(uf - u64).max() / np.abs(u64).max()),
         }
         g.set_fp32_switch(0.0, 8, 0)
+    nets = []   # the warm-start network, kept for the catalog entry
     if not args.no_warm_start:
         out["warm_start"] = warm_start_runs(hr, torch, g, w, args.steps, steps64,
-                                            float(np.median([t[1] for t in tm64])), u64, sols)
+                                            float(np.median([t[1] for t in tm64])), u64, sols,
+                                            keep=nets)
     if not args.no_spherical:
         # the same physics on the Spherical 128x64x8 grid (rmax 100), its own eta
         ws = workloads.paper_scale(workloads.SPHERICAL, 10)
@@ -891,9 +927,11 @@ def main() -> int:
     if not args.no_catalog:
         log("catalog: 64 configurations, FP32 + FP64 finish ...")
         out["catalog"] = catalog_result(64, "split", not args.no_autotune, args.max_steps,
-                                        args.cache_budget)
+                                        args.cache_budget, nets[0] if nets else None)
         log(f"catalog: {out['catalog']['wall_s']:.1f} s, "
             f"{out['catalog']['grid_point_rhs_updates_per_s'] / 1e9:.1f} G updates/s")
+    for net in nets:
+        net.close()
     # roofline of the dominant kernel: the resident RK4 kernel at this size,
     # timed on the launches of the timed solves themselves
     g.set_punctures(*w.punctures.as_tuple())

@@ -171,3 +171,18 @@ def relax_catalog(grids, etas, tols, precision: int = FP64, max_steps: int = 600
             log(f"catalog group {gi + 1}/{len(groups)} ({len(group)} grids) done after "
                 f"{time.perf_counter() - t0:.1f} s")
     return steps, resid
+
+
+def warm_start_catalog(mlp, ws, grids, etas, smooth=None) -> int:
+    """Learned warm start of every catalog grid before its relaxation: the
+    network's prediction of u on each grid (inference kernels; v = m eta u),
+    the smoothing phase of warmstart.SMOOTH batched over all grids, then
+    v = eta u. The relaxation that follows still decides convergence. Returns
+    the smoothing steps each grid took."""
+    from . import warmstart
+
+    smooth = warmstart.SMOOTH if smooth is None else smooth
+    m, ns = smooth
+    for w, g, e in zip(ws, grids, etas):
+        mlp.warm_start(g, warmstart.config_of(w), m * e if ns > 0 else e)
+    return warmstart.smooth_all(grids, etas, smooth)
