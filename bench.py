@@ -555,8 +555,8 @@ def cartesian_runs(hr, torch, steps: int, warmup: int):
     """The paper-scale punctures on the Cartesian cube 128^3 ([-32, 32]^3, 10th
     order, eta 0.03; the Cartesian-like family): FP64 solves to residual 1e-10
     on the interior and face stage kernels, their per-stage times with the HBM
-    roofline of their algorithmic bytes, and the error against the committed
-    converged oracle solution."""
+    roofline of their algorithmic bytes, the split-state form's solves, and
+    the errors against the committed converged oracle solution."""
     from paper_2501_14030_amd import workloads
 
     w = workloads.paper_scale_cartesian()
@@ -564,7 +564,14 @@ def cartesian_runs(hr, torch, steps: int, warmup: int):
     g = hr.grid_create(s.coords, s.N0, s.N1, s.N2, s.fd_order,
                        params=hr.default_params(rmax=s.rmax))
     rs, ts, tms = timed_solves(hr, torch, g, w, hr.FP64, steps, warmup, "cartesian fp64")
-    diff = oracle_diff(g.get_u(extended=True), "paper_scale_cartesian_128")
+    u64 = g.get_u(extended=True)
+    diff = oracle_diff(u64, "paper_scale_cartesian_128")
+    # the split-state form (FP32 increment on the FP64 base, FP64 finish)
+    g.set_fp32_switch(0.0, 8, 0)
+    rs32, ts32, _ = timed_solves(hr, torch, g, w, hr.FP32_FP64FINISH, steps, warmup,
+                                 "cartesian split")
+    u32 = g.get_u(extended=True)
+    diff32 = oracle_diff(u32, "paper_scale_cartesian_128")
     us = g.time_stage_kernels(w.eta, w.kappa, 0.0, 5, hr.FP64)
     byts = stage_algorithmic_bytes(s, 8, cart=True)
     agg = sum(byts) / (sum(us[:4]) * 1e-6) / 1e9
@@ -581,6 +588,13 @@ def cartesian_runs(hr, torch, steps: int, warmup: int):
         "max_rel_diff_u_vs_oracle": diff,
         "oracle_reference": "converged FP64 oracle solution at 4096 seeded evolved points and "
                             "the largest |u| (tests/golden/oracle_paper_scale_cartesian_128.npz)",
+        "mixed": {"precision": "split state: FP32 increment on the FP64 base, FP64 finish",
+                  "time_to_residual_s": ts32 / steps,
+                  "speedup_vs_fp64": ts / ts32,
+                  "rk4_steps_to_tol": rs32[-1].steps_taken, "fp32_steps": rs32[-1].fp32_steps,
+                  "final_residual": rs32[-1].residual,
+                  "max_rel_diff_u_vs_fp64": float(np.abs(u32 - u64).max() / np.abs(u64).max()),
+                  "max_rel_diff_u_vs_oracle": diff32},
         "roofline": {"bound": "hbm", "achieved": agg, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": agg / HBM_PEAK_GBS, "traffic": tr,
                      "traffic_over_algorithmic": (tr / (sum(byts) / 4)) if tr else None,
@@ -591,7 +605,8 @@ def cartesian_runs(hr, torch, steps: int, warmup: int):
                      "algorithmic_bytes_per_stage": byts},
     }
     log(f"cartesian: {rs[-1].steps_taken} steps, {ts / steps * 1e3:.1f} ms, "
-        f"{out['value'] / 1e9:.1f} G updates/s, {agg / 1e3:.2f} TB/s, vs oracle {diff}")
+        f"{out['value'] / 1e9:.1f} G updates/s, {agg / 1e3:.2f} TB/s, vs oracle {diff}; "
+        f"split {ts32 / steps * 1e3:.1f} ms")
     g.close()
     return out
 

@@ -112,9 +112,9 @@ void hr_default_params(hr_grid_params* p);
  *            along xx0, xx1, xx2; each N_d >= max(NG, 2), any parity) store NG
  *            outer layers beyond every face: the extended layout is the padded
  *            box (N0 + 2 NG) x (N1 + 2 NG) x (N2 + 2 NG), whose edge and corner
- *            points are never read and stay zero. They relax in HR_FP64 or
- *            HR_FP32 on the stage kernels (no resident kernel, split-state
- *            form, batch, volume norm or warm start: those calls return
+ *            points are never read and stay zero. They relax in HR_FP64,
+ *            HR_FP32 or HR_FP32_FP64FINISH on the stage kernels (no resident
+ *            kernel, batch, volume norm or warm start: those calls return
  *            HR_EINVAL for them).
  *   fd_order centred finite-difference order: 2, 4, 6, 8 or 10
  *   p        coordinate parameters, NULL for defaults (copied)

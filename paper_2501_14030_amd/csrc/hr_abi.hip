@@ -1288,8 +1288,6 @@ hr_status hr_relax(hr_grid* g, double eta, double c, double dt, long n_steps, do
   if (st != HR_OK) return st;
   if (prec != HR_FP64 && prec != HR_FP32 && prec != HR_FP32_FP64FINISH)
     return fail(HR_EINVAL, "unknown precision");
-  if (g->d.cart && prec == HR_FP32_FP64FINISH)
-    return fail(HR_EINVAL, "Cartesian grids relax in HR_FP64 or HR_FP32 (no split-state form)");
   return relax_impl(g, eta, c, dt, n_steps, tol, check_every, prec, rep);
 }
 
@@ -1388,8 +1386,6 @@ hr_status hr_time_stage_kernels(hr_grid* g, double eta, double c, double dt, lon
     return fail(HR_EINVAL, "need avg_us, n_steps > 0, eta > 0, c > 0");
   if (prec != HR_FP64 && prec != HR_FP32 && prec != HR_FP32_FP64FINISH)
     return fail(HR_EINVAL, "unknown precision");
-  if (g->d.cart && prec == HR_FP32_FP64FINISH)
-    return fail(HR_EINVAL, "Cartesian grids have no split-state form");
   if (dt <= 0) dt = g->prm.cfl * g->tab.ds_g;
   HR_HIP(hipSetDevice(g->device));
   st = load_kappa(g, c);

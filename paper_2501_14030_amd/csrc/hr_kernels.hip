@@ -971,8 +971,9 @@ __device__ __forceinline__ int cart_off(const Dims& d, int ax) {
   return ax == 0 ? 0 : ax == 1 ? d.P0 : d.P0 + d.R1;
 }
 
-// Interior points: one thread each on the plane-tile grid.
-template <typename T, int NG, int STAGE>
+// Interior points: one thread each on the plane-tile grid. CORR: the split-state
+// form's single-precision increment (slopes as in the curvilinear kernels).
+template <typename T, int NG, int STAGE, bool CORR>
 __global__ void __launch_bounds__(kTileThreads) k_cart_stage(StageArgs<T> a) {
   constexpr int W = TileShape<NG>::W, H = TileShape<NG>::H;
   constexpr Weights<NG> Wt{};
@@ -986,7 +987,7 @@ __global__ void __launch_bounds__(kTileThreads) k_cart_stage(StageArgs<T> a) {
   const unsigned n2d = (unsigned)d.N0 * (unsigned)d.N1;
   const unsigned k2 = active ? (unsigned)i0 + (unsigned)d.N0 * (unsigned)i1 : 0u;
   // z taps and point operands, issued before the tile barrier
-  T zp[NG], zm[NG], v = 0, psi = 0, ssrc = 0, f[6];
+  T zp[NG], zm[NG], v = 0, psi = 0, ssrc = 0, f[6], hu = 0, hv = 0;
   CombineIn<STAGE, false, T> co;
   if (active) {
 #pragma unroll
@@ -997,6 +998,10 @@ __global__ void __launch_bounds__(kTileThreads) k_cart_stage(StageArgs<T> a) {
     v = a.vin[idx];
     psi = a.psi[idx];
     ssrc = a.ssrc[idx];
+    if constexpr (CORR) {
+      hu = a.khu[idx];
+      hv = a.khv[idx];
+    }
 #pragma unroll
     for (int q = 0; q < 6; ++q) f[q] = load_factor(a.fac, a.facb, q * n2d + k2);
     co.load(a, idx);
@@ -1026,8 +1031,14 @@ __global__ void __launch_bounds__(kTileThreads) k_cart_stage(StageArgs<T> a) {
   const T w0 = (T)Wt.d2[0];
   const T lap = f[0] * (e0 + w0 * uc) + f[1] * (e1 + w0 * uc) + f[2] * (e2 + w0 * uc) +
                 f[3] * d0 + f[4] * d1;
-  const T ku = v - a.eta * uc;
-  const T kv = f[5] * (lap + source<T>(ssrc, psi, uc));
+  T ku, kv;
+  if constexpr (CORR) {
+    ku = hu + (v - a.eta * uc);
+    kv = hv + f[5] * (lap + source_delta(ssrc, psi, uc));
+  } else {
+    ku = v - a.eta * uc;
+    kv = f[5] * (lap + source<T>(ssrc, psi, uc));
+  }
   combine<STAGE, false, T>(a, idx, co, uc, v, ku, kv);
 }
 
@@ -1037,7 +1048,7 @@ __global__ void __launch_bounds__(kTileThreads) k_cart_stage(StageArgs<T> a) {
 // z taps are a register queue filled by one load per plane, and the
 // rim-extended tile of the next plane is fetched into registers while the
 // current one is computed from LDS. The arithmetic is that of k_cart_stage.
-template <typename T, int NG, int STAGE>
+template <typename T, int NG, int STAGE, bool CORR>
 __global__ void __launch_bounds__(kTileThreads, 4) k_cart_col(StageArgs<T> a, int chunk) {
   constexpr int W = TileShape<NG>::W, H = TileShape<NG>::H;
   constexpr int NE = (W * H + kTileThreads - 1) / kTileThreads;
@@ -1088,7 +1099,7 @@ __global__ void __launch_bounds__(kTileThreads, 4) k_cart_col(StageArgs<T> a, in
     if constexpr (kFacRows<T> == 6) return fl[r][ft];
     else return f[r];
   };
-  PointIn<STAGE, false, T> cur;
+  PointIn<STAGE, CORR, T> cur;
   if (active) {
 #pragma unroll
     for (int j = 0; j <= 2 * NG; ++j) q[j] = a.uin[col + plane * (unsigned)(z0 + j)];
@@ -1110,7 +1121,7 @@ __global__ void __launch_bounds__(kTileThreads, 4) k_cart_col(StageArgs<T> a, in
     const bool more = z + 1 < z1;
     // prefetch plane z + 1 (its queue entry is u(z + 1 + NG), stored plane z + 1 + 2NG)
     T tn[NE];
-    PointIn<STAGE, false, T> nxt;
+    PointIn<STAGE, CORR, T> nxt;
     T qn = (T)0;
     if (more) {
       fetch(tn, z + 1);
@@ -1136,9 +1147,15 @@ __global__ void __launch_bounds__(kTileThreads, 4) k_cart_col(StageArgs<T> a, in
       const T w0 = (T)Wt.d2[0];
       const T lap = fac(0) * (e0 + w0 * uc) + fac(1) * (e1 + w0 * uc) +
                     fac(2) * (e2 + w0 * uc) + fac(3) * d0 + fac(4) * d1;
-      const T ku = cur.v - a.eta * uc;
-      const T kv = fac(5) * (lap + source<T>(cur.ssrc, cur.psi, uc));
-      combine_pt<STAGE, false, T>(a, col + plane * (unsigned)(z + NG), cur, uc, ku, kv);
+      T ku, kv;
+      if constexpr (CORR) {
+        ku = cur.khu + (cur.v - a.eta * uc);
+        kv = cur.khv + fac(5) * (lap + source_delta(cur.ssrc, cur.psi, uc));
+      } else {
+        ku = cur.v - a.eta * uc;
+        kv = fac(5) * (lap + source<T>(cur.ssrc, cur.psi, uc));
+      }
+      combine_pt<STAGE, CORR, T>(a, col + plane * (unsigned)(z + NG), cur, uc, ku, kv);
     }
     if (more) {
       store(tn, tile[buf ^ 1]);
@@ -1157,18 +1174,22 @@ __device__ __forceinline__ int cart_face_points(const Dims& d, int ax) {
   return 2 * d.NG * n1 * n2;
 }
 
-// Face points, one thread each: the radiation condition k_f = -c (f/r + d_r
-// f) with d_r f = (d f / d n) / (d r / d n) along the outward normal n = +-x_d
-// (d r / d n = |x_d| / r), the one-sided difference toward the interior, then
-// the stage combine. Threads run along x0: on the y and z faces over a row,
-// on the x faces over a row end's NG layer points.
-template <typename T, int NG, int STAGE>
-__global__ void __launch_bounds__(kBlock) k_cart_faces(StageArgs<T> a) {
-  const Dims& d = a.d;
-  int t = blockIdx.x * kBlock + threadIdx.x;
+// Face point number t (all faces, x faces first): its stored index, the
+// index step toward the interior, the wave speed, r and q = 1 / (2 dx dr/dn).
+// False past the last face point.
+template <typename T>
+struct FacePoint {
+  unsigned o;
+  int in;
+  T kappa, rr, qd;
+};
+
+template <typename T, int NG>
+__device__ __forceinline__ bool cart_face_point(const Dims& d, const T* __restrict__ cx, int t,
+                                                FacePoint<T>& fp) {
   int ax = 0;
   while (ax < 3 && t >= cart_face_points(d, ax)) t -= cart_face_points(d, ax++);
-  if (ax == 3) return;
+  if (ax == 3) return false;
   const int nf = ax == 0 ? d.N1 : d.N0, ns = ax == 2 ? d.N1 : d.N2;
   int fast, slow, out, side;
   if (ax == 0) {
@@ -1196,29 +1217,126 @@ __global__ void __launch_bounds__(kBlock) k_cart_faces(StageArgs<T> a) {
   if (ax == 0) { i0 = out; i1 = fast; i2 = slow; }
   else if (ax == 1) { i0 = fast; i1 = out; i2 = slow; }
   else { i0 = fast; i1 = slow; i2 = out; }
-  const T* cx = a.zfac;
   const int q2 = planes_of(d);
-  const T kappa = cx[d.P0 + d.R1 + q2];
+  fp.kappa = cx[d.P0 + d.R1 + q2];
   const T dxa = cx[d.P0 + d.R1 + q2 + 1 + ax];
   const T x = cx[i0 + d.NG], y = cx[d.P0 + i1 + d.NG], z = cx[d.P0 + d.R1 + i2 + d.NG];
-  const T rr = sqrt(x * x + y * y + z * z);
+  fp.rr = sqrt(x * x + y * y + z * z);
   const T xa = ax == 0 ? x : ax == 1 ? y : z;
-  const T qd = rr / ((T)2 * dxa * fabs(xa));   // 1 / (2 dx d r / d n)
+  fp.qd = fp.rr / ((T)2 * dxa * fabs(xa));   // 1 / (2 dx d r / d n)
   const int stride = ax == 0 ? 1 : ax == 1 ? d.P0 : d.P0 * d.R1;
-  const int in = side ? -stride : stride;     // one point toward the interior
-  const unsigned o = sidx(d, i0, i1, i2);
-  const T* U = a.uin + o;
-  const T* V = a.vin + o;
+  fp.in = side ? -stride : stride;            // one point toward the interior
+  fp.o = sidx(d, i0, i1, i2);
+  return true;
+}
+
+// The radiation condition's slope -kappa (f/r + d_r f) at a face point, f read
+// at the point and its inward neighbours.
+template <typename T>
+__device__ __forceinline__ T cart_face_slope(const T* __restrict__ F, const FacePoint<T>& fp,
+                                             bool bc4) {
+  const T f0 = F[fp.o], f1 = F[fp.o + fp.in], f2 = F[fp.o + 2 * fp.in];
+  const T f3 = bc4 ? F[fp.o + 3 * fp.in] : (T)0, f4 = bc4 ? F[fp.o + 4 * fp.in] : (T)0;
+  return -fp.kappa * (f0 / fp.rr + outer_diff(f0, f1, f2, f3, f4, fp.qd, bc4));
+}
+
+// Face points, one thread each: the radiation condition k_f = -c (f/r + d_r
+// f) with d_r f = (d f / d n) / (d r / d n) along the outward normal n = +-x_d
+// (d r / d n = |x_d| / r), the one-sided difference toward the interior, then
+// the stage combine. Threads run along x0: on the y and z faces over a row,
+// on the x faces over a row end's NG layer points.
+template <typename T, int NG, int STAGE, bool CORR>
+__global__ void __launch_bounds__(kBlock) k_cart_faces(StageArgs<T> a) {
+  FacePoint<T> fp;
+  if (!cart_face_point<T, NG>(a.d, a.zfac, blockIdx.x * kBlock + threadIdx.x, fp)) return;
   const bool bc4 = a.bc4 != 0;
-  const T u0 = U[0], u1 = U[in], u2 = U[2 * in];
-  const T v0 = V[0], v1 = V[in], v2 = V[2 * in];
-  const T u3 = bc4 ? U[3 * in] : (T)0, u4 = bc4 ? U[4 * in] : (T)0;
-  const T v3 = bc4 ? V[3 * in] : (T)0, v4 = bc4 ? V[4 * in] : (T)0;
   CombineIn<STAGE, false, T> co;
-  co.load(a, o);
-  const T kuo = -kappa * (u0 / rr + outer_diff(u0, u1, u2, u3, u4, qd, bc4));
-  const T kvo = -kappa * (v0 / rr + outer_diff(v0, v1, v2, v3, v4, qd, bc4));
-  combine<STAGE, false, T>(a, o, co, u0, v0, kuo, kvo);
+  co.load(a, fp.o);
+  T kuo = cart_face_slope(a.uin, fp, bc4);
+  T kvo = cart_face_slope(a.vin, fp, bc4);
+  if constexpr (CORR) {   // the condition is linear: base slope plus the increment's
+    kuo = a.khu[fp.o] + kuo;
+    kvo = a.khv[fp.o] + kvo;
+  }
+  combine<STAGE, false, T>(a, fp.o, co, a.uin[fp.o], a.vin[fp.o], kuo, kvo);
+}
+
+// The split-state form's base evaluation on a Cartesian grid (FP64 state u, v):
+// interior points on plane tiles, the slopes k(y_b) of Eq. 5, p_b = psi_s + u
+// and S_src p_b^-7 in single precision, the increment zeroed.
+template <int NG>
+__global__ void __launch_bounds__(kTileThreads) k_cart_base(BaseArgs a) {
+  constexpr int W = TileShape<NG>::W, H = TileShape<NG>::H;
+  constexpr Weights<NG> Wt{};
+  __shared__ double tile[W * H];
+  const Dims& d = a.d;
+  const int x0b = blockIdx.x * TX, x1b = blockIdx.y * TY, i2 = blockIdx.z;
+  const int i0 = x0b + threadIdx.x, i1 = x1b + threadIdx.y;
+  const bool active = i0 < d.N0 && i1 < d.N1;
+  const unsigned plane = (unsigned)d.P0 * (unsigned)d.R1;
+  const unsigned idx = sidx(d, active ? i0 : 0, active ? i1 : 0, i2);
+  const unsigned n2d = (unsigned)d.N0 * (unsigned)d.N1;
+  const unsigned k2 = active ? (unsigned)i0 + (unsigned)d.N0 * (unsigned)i1 : 0u;
+  double zp[NG], zm[NG], v = 0, psi = 0, ssrc = 0, f[6];
+  if (active) {
+#pragma unroll
+    for (int k = 1; k <= NG; ++k) {
+      zp[k - 1] = a.u[idx + (unsigned)k * plane];
+      zm[k - 1] = a.u[idx - (unsigned)k * plane];
+    }
+    v = a.v[idx];
+    psi = a.psi[idx];
+    ssrc = a.ssrc[idx];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) f[q] = a.fac[q * n2d + k2];
+  }
+  const int tid = threadIdx.x + TX * threadIdx.y;
+  for (int e = tid; e < W * H; e += kTileThreads) {
+    const int l1 = e / W;
+    const int l0 = e - l1 * W;
+    const int j0 = x0b + l0 - NG, j1 = x1b + l1 - NG;   // both >= -NG
+    tile[e] = (j0 < d.N0 + NG && j1 < d.N1 + NG) ? a.u[sidx(d, j0, j1, i2)] : 0.0;
+  }
+  __syncthreads();
+  if (!active) return;
+  const double* r = tile + (threadIdx.y + NG) * W + (threadIdx.x + NG);
+  const double uc = r[0];
+  double d0 = 0, d1 = 0, e0 = 0, e1 = 0, e2 = 0;
+#pragma unroll
+  for (int k = 1; k <= NG; ++k) {
+    const double p0 = r[k], m0 = r[-k];
+    const double p1 = r[k * W], m1 = r[-k * W];
+    d0 += Wt.d1[k] * (p0 - m0);
+    d1 += Wt.d1[k] * (p1 - m1);
+    e0 += Wt.d2[k] * (p0 + m0);
+    e1 += Wt.d2[k] * (p1 + m1);
+    e2 += Wt.d2[k] * (zp[k - 1] + zm[k - 1]);
+  }
+  const double w0 = Wt.d2[0];
+  const double lap = f[0] * (e0 + w0 * uc) + f[1] * (e1 + w0 * uc) + f[2] * (e2 + w0 * uc) +
+                     f[3] * d0 + f[4] * d1;
+  const double p = psi + uc;
+  const double p2 = p * p, p4 = p2 * p2, p7 = p4 * p2 * p;
+  a.khu[idx] = (float)(v - a.eta * uc);
+  a.khv[idx] = (float)(f[5] * (lap + ssrc / p7));
+  a.pb[idx] = (float)p;
+  a.sp7[idx] = (float)(ssrc / p7);
+  a.eu[idx] = 0.0f;
+  a.ev[idx] = 0.0f;
+}
+
+// The base evaluation at the face points (radiation condition in FP64).
+template <int NG>
+__global__ void __launch_bounds__(kBlock) k_cart_base_faces(BaseArgs a) {
+  FacePoint<double> fp;
+  if (!cart_face_point<double, NG>(a.d, a.zfac, blockIdx.x * kBlock + threadIdx.x, fp)) return;
+  const bool bc4 = a.bc4 != 0;
+  a.khu[fp.o] = (float)cart_face_slope(a.u, fp, bc4);
+  a.khv[fp.o] = (float)cart_face_slope(a.v, fp, bc4);
+  a.pb[fp.o] = (float)(a.psi[fp.o] + a.u[fp.o]);
+  a.sp7[fp.o] = 0.0f;
+  a.eu[fp.o] = 0.0f;
+  a.ev[fp.o] = 0.0f;
 }
 
 // Residual H in FP64 on the interior of a Cartesian grid (state of storage
@@ -1368,7 +1486,7 @@ hipError_t col_dispatch(int stage, const StageArgs<T>& a, int ch, hipStream_t s,
 
 // A Cartesian stage: the interior kernel, then the face kernel (timing events,
 // when given, bracket both).
-template <typename T, int NG, int STAGE>
+template <typename T, int NG, int STAGE, bool CORR>
 hipError_t cart_stage_launch(const StageArgs<T>& a, hipStream_t s, hipEvent_t t0,
                              hipEvent_t t1) {
   const Dims& d = a.d;
@@ -1381,31 +1499,31 @@ hipError_t cart_stage_launch(const StageArgs<T>& a, hipStream_t s, hipEvent_t t0
                          : tile_grid(d);
   if (cols) {
     if (t0 && t1)
-      hipExtLaunchKernelGGL(k_cart_col<T, NG, STAGE>, grid, block, 0, s, t0, nullptr, 0, a, ch);
+      hipExtLaunchKernelGGL(k_cart_col<T, NG, STAGE, CORR>, grid, block, 0, s, t0, nullptr, 0, a, ch);
     else
-      k_cart_col<T, NG, STAGE><<<grid, block, 0, s>>>(a, ch);
+      k_cart_col<T, NG, STAGE, CORR><<<grid, block, 0, s>>>(a, ch);
   } else {
     if (t0 && t1)
-      hipExtLaunchKernelGGL(k_cart_stage<T, NG, STAGE>, grid, block, 0, s, t0, nullptr, 0, a);
+      hipExtLaunchKernelGGL(k_cart_stage<T, NG, STAGE, CORR>, grid, block, 0, s, t0, nullptr, 0, a);
     else
-      k_cart_stage<T, NG, STAGE><<<grid, block, 0, s>>>(a);
+      k_cart_stage<T, NG, STAGE, CORR><<<grid, block, 0, s>>>(a);
   }
   if (t0 && t1)
-    hipExtLaunchKernelGGL(k_cart_faces<T, NG, STAGE>, dim3(nblocks(nf)), dim3(kBlock), 0, s,
+    hipExtLaunchKernelGGL(k_cart_faces<T, NG, STAGE, CORR>, dim3(nblocks(nf)), dim3(kBlock), 0, s,
                           nullptr, t1, 0, a);
   else
-    k_cart_faces<T, NG, STAGE><<<nblocks(nf), kBlock, 0, s>>>(a);
+    k_cart_faces<T, NG, STAGE, CORR><<<nblocks(nf), kBlock, 0, s>>>(a);
   return hipGetLastError();
 }
 
-template <typename T, int NG>
+template <typename T, int NG, bool CORR>
 hipError_t cart_dispatch(int stage, const StageArgs<T>& a, hipStream_t s, hipEvent_t t0,
                          hipEvent_t t1) {
   switch (stage) {
-    case 1: return cart_stage_launch<T, NG, 1>(a, s, t0, t1);
-    case 2: return cart_stage_launch<T, NG, 2>(a, s, t0, t1);
-    case 3: return cart_stage_launch<T, NG, 3>(a, s, t0, t1);
-    case 4: return cart_stage_launch<T, NG, 4>(a, s, t0, t1);
+    case 1: return cart_stage_launch<T, NG, 1, CORR>(a, s, t0, t1);
+    case 2: return cart_stage_launch<T, NG, 2, CORR>(a, s, t0, t1);
+    case 3: return cart_stage_launch<T, NG, 3, CORR>(a, s, t0, t1);
+    case 4: return cart_stage_launch<T, NG, 4, CORR>(a, s, t0, t1);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1414,9 +1532,12 @@ template <typename T, int NG>
 hipError_t stage_dispatch(int stage, const StageArgs<T>& a, hipStream_t s, hipEvent_t t0,
                           hipEvent_t t1) {
   if (a.d.cart) {
-    // the split-state increment is not built for Cartesian grids
-    if (a.corr) return hipErrorInvalidValue;
-    return cart_dispatch<T, NG>(stage, a, s, t0, t1);
+    if (a.corr) {
+      // the split-state increment runs in single precision only
+      if constexpr (std::is_same<T, float>::value) return cart_dispatch<T, NG, true>(stage, a, s, t0, t1);
+      return hipErrorInvalidValue;
+    }
+    return cart_dispatch<T, NG, false>(stage, a, s, t0, t1);
   }
   const int ch = a.chunk > 0 ? a.chunk : 1;
   if constexpr (std::is_same<T, float>::value) {
@@ -1525,7 +1646,26 @@ hipError_t launch_cart_sources(const Dims& d, const double* cx, const Punctures&
   return hipGetLastError();
 }
 
+template <int NG>
+hipError_t cart_base(const BaseArgs& a, hipStream_t s) {
+  const Dims& d = a.d;
+  const int nf = 2 * d.NG * (d.N1 * d.N2 + d.N0 * d.N2 + d.N0 * d.N1);
+  k_cart_base<NG><<<tile_grid(d), dim3(TX, TY, 1), 0, s>>>(a);
+  k_cart_base_faces<NG><<<nblocks(nf), kBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+
 hipError_t launch_base(int order, const BaseArgs& a, hipStream_t s) {
+  if (a.d.cart) {
+    switch (order) {
+      case 2: return cart_base<1>(a, s);
+      case 4: return cart_base<2>(a, s);
+      case 6: return cart_base<3>(a, s);
+      case 8: return cart_base<4>(a, s);
+      case 10: return cart_base<5>(a, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   return a.d.zo ? base_order<true>(order, a, s) : base_order<false>(order, a, s);
 }
 
