@@ -342,7 +342,8 @@ hr_status hr_suggest_dt(const hr_grid* g, double cfl, double* dt);
  *   streaming  -1 = automatic (by grid size), 0 = cached, 1 = non-temporal
  *              loads/stores for fields touched once per stage
  *   chunk      phi (Cartesian: z) planes per block for variant 2 (0 =
- *              automatic: 8); for variant 3 the patch rows along x1, 8 or 4
+ *              automatic: 16 for FP64 stages, 8 for single-precision ones and
+ *              on Cartesian grids); for variant 3 the patch rows along x1, 8 or 4
  *              (0 = automatic: 8 x 4 patches where 8 x 8 ones would leave
  *              more than half of the compute units idle and 8 x 4 ones fit,
  *              else 8 x 8)

@@ -4,7 +4,8 @@
 // paper's "Multiple, Independent Patches" experiment used one stream per
 // patch instead).
 //
-// Work lists in device memory hold (grid, x0 tile, x1 tile, phi chunk) items;
+// Work lists in device memory hold (grid, x0 tile, x1 tile, phi chunk) items
+// (and in the stage lists (grid, -1, k, 0) items for blocks of outer points);
 // persistent kernels walk them and read per-grid arguments from descriptor
 // tables. The launch sequence of one check interval (base slopes and rebase
 // of the split-state form, 4 x K stage launches, residual, per-grid norms) is
@@ -96,6 +97,11 @@ size_t up256(size_t x) { return (x + 255) / 256 * 256; }
 
 int tiles0(const hr_grid* g) { return (g->d.N0 + kTileX - 1) / kTileX; }
 int tiles1(const hr_grid* g) { return (g->d.N1 + kTileY - 1) / kTileY; }
+// Stage-list items holding a grid's NG N1 N2 outer points, one tile's worth of
+// threads each.
+int outer_items(const hr_grid* g) {
+  return (g->d.NG * g->d.N1 * g->d.N2 + kTileX * kTileY - 1) / (kTileX * kTileY);
+}
 
 // An explicit phi-column configuration of a grid keeps its chunk in a batch.
 bool explicit_chunk(const hr_grid* g) { return g->variant == 2 && g->chunk > 0; }
@@ -318,10 +324,13 @@ hr_status upload_lists(hr_batch* b, const std::vector<GridRun>& run, int K, int*
     // items, 4 split-form stage items, 8 resident launches
     if (run[i].phase == 0) *mode |= 1;
     *mode |= resident[i] ? 8 : run[i].phase == 0 ? 4 : 2;
-    if (!resident[i])
+    if (!resident[i]) {
       for (int z = 0; z < nch; ++z)
         for (int y = 0; y < t1; ++y)
           for (int x = 0; x < t0; ++x) ls.push_back(make_int4(i, x, y, z));
+      // the grid's xx0-face outer points, a block of items of their own
+      for (int k = 0; k < outer_items(g); ++k) ls.push_back(make_int4(i, -1, k, 0));
+    }
     for (int z = 0; z < N2; ++z)
       for (int y = 0; y < t1; ++y)
         for (int x = 0; x < t0; ++x) {
@@ -396,7 +405,7 @@ hr_status hr_batch_create(int n, hr_grid* const* grids, hr_batch** out) {
       return bfail(HR_EINVAL, "batched grids need the same fd_order and device");
     }
     const size_t tp = (size_t)tiles0(g) * tiles1(g) * g->d.N2;
-    b->cap_stage += tp;
+    b->cap_stage += tp + outer_items(g);
     b->cap_plane += tp;
     b->cap_reb += (g->G + kBlock - 1) / kBlock;
   }

@@ -403,10 +403,11 @@ struct hr_grid {
 
 namespace hr {
 
-// Kernel variant and phi chunk of a grid (explicit configuration, else by size).
+// Kernel variant and phi chunk of a grid (explicit configuration, else by size;
+// the automatic chunk also by precision: fp64 for the FP64 stage kernels).
 // Variant 3 (resident) applies to FP64 steps only; stage launches of the
 // single-precision forms use plane tiles in its place.
-void resolve_variant(const hr_grid* g, int& variant, int& chunk);
+void resolve_variant(const hr_grid* g, int& variant, int& chunk, bool fp64 = true);
 // The grid can run the resident kernel on its device.
 bool resident_ok(const hr_grid* g);
 
@@ -441,7 +442,7 @@ StageArgs<T> stage_args(const hr_grid* g, const Fields<T>& F, int stage, T eta, 
   a.facb = g->factors16 ? F.facb : nullptr;
   // non-temporal access measured no faster at any size: off unless asked for
   a.streaming = g->streaming > 0 ? 1 : 0;
-  resolve_variant(g, a.variant, a.chunk);
+  resolve_variant(g, a.variant, a.chunk, sizeof(T) == 8);
   if (a.variant == 3) a.variant = 1;
   a.un = F.un;
   a.vn = F.vn;
