@@ -1079,6 +1079,96 @@ __global__ void __launch_bounds__(kTileThreads) k_cart_stage(StageArgs<T> a) {
   combine<STAGE, false, T>(a, idx, co, uc, v, ku, kv);
 }
 
+// Number of outer points on the two faces normal to axis ax.
+__device__ __forceinline__ int cart_face_points(const Dims& d, int ax) {
+  const int n1 = ax == 0 ? d.N1 : d.N0, n2 = ax == 2 ? d.N1 : d.N2;
+  return 2 * d.NG * n1 * n2;
+}
+
+// Face point number t (all faces, x faces first): its stored index, the
+// index step toward the interior, the wave speed, r and q = 1 / (2 dx dr/dn).
+// False past the last face point.
+template <typename T>
+struct FacePoint {
+  unsigned o;
+  int in;
+  T kappa, rr, qd;
+};
+
+template <typename T, int NG>
+__device__ __forceinline__ bool cart_face_point(const Dims& d, const T* __restrict__ cx, int t,
+                                                FacePoint<T>& fp) {
+  int ax = 0;
+  while (ax < 3 && t >= cart_face_points(d, ax)) t -= cart_face_points(d, ax++);
+  if (ax == 3) return false;
+  const int nf = ax == 0 ? d.N1 : d.N0, ns = ax == 2 ? d.N1 : d.N2;
+  int fast, slow, out, side;
+  if (ax == 0) {
+    // x faces: t = layer + NG (y + N1 (z + N2 side)); a row's NG layer points
+    // on one side are contiguous in memory, so the layer runs fastest
+    const int layer = t % NG;
+    t /= NG;
+    fast = t % nf;
+    t /= nf;
+    slow = t % ns;
+    side = t / ns;
+    out = side ? d.N0 + layer : layer - NG;
+  } else {
+    // y and z faces: t = x + N0 (slow + n_slow (layer + NG side))
+    fast = t % nf;
+    t /= nf;
+    slow = t % ns;
+    t /= ns;
+    const int layer = t % NG;
+    side = t / NG;
+    const int n_ax = ax == 1 ? d.N1 : d.N2;
+    out = side ? n_ax + layer : -1 - layer;
+  }
+  int i0, i1, i2;
+  if (ax == 0) { i0 = out; i1 = fast; i2 = slow; }
+  else if (ax == 1) { i0 = fast; i1 = out; i2 = slow; }
+  else { i0 = fast; i1 = slow; i2 = out; }
+  const int q2 = planes_of(d);
+  fp.kappa = cx[d.P0 + d.R1 + q2];
+  const T dxa = cx[d.P0 + d.R1 + q2 + 1 + ax];
+  const T x = cx[i0 + d.NG], y = cx[d.P0 + i1 + d.NG], z = cx[d.P0 + d.R1 + i2 + d.NG];
+  fp.rr = sqrt(x * x + y * y + z * z);
+  const T xa = ax == 0 ? x : ax == 1 ? y : z;
+  fp.qd = fp.rr / ((T)2 * dxa * fabs(xa));   // 1 / (2 dx d r / d n)
+  const int stride = ax == 0 ? 1 : ax == 1 ? d.P0 : d.P0 * d.R1;
+  fp.in = side ? -stride : stride;            // one point toward the interior
+  fp.o = sidx(d, i0, i1, i2);
+  return true;
+}
+
+// The radiation condition's slope -kappa (f/r + d_r f) at a face point, f read
+// at the point and its inward neighbours.
+template <typename T>
+__device__ __forceinline__ T cart_face_slope(const T* __restrict__ F, const FacePoint<T>& fp,
+                                             bool bc4) {
+  const T f0 = F[fp.o], f1 = F[fp.o + fp.in], f2 = F[fp.o + 2 * fp.in];
+  const T f3 = bc4 ? F[fp.o + 3 * fp.in] : (T)0, f4 = bc4 ? F[fp.o + 4 * fp.in] : (T)0;
+  return -fp.kappa * (f0 / fp.rr + outer_diff(f0, f1, f2, f3, f4, fp.qd, bc4));
+}
+
+// Stage update at face point t (none past the last): the radiation condition,
+// then the stage combine; CORR adds the base slopes (the condition is linear).
+template <typename T, int NG, int STAGE, bool CORR>
+__device__ __forceinline__ void cart_face_stage(const StageArgs<T>& a, int t) {
+  FacePoint<T> fp;
+  if (!cart_face_point<T, NG>(a.d, a.zfac, t, fp)) return;
+  const bool bc4 = a.bc4 != 0;
+  CombineIn<STAGE, false, T> co;
+  co.load(a, fp.o);
+  T kuo = cart_face_slope(a.uin, fp, bc4);
+  T kvo = cart_face_slope(a.vin, fp, bc4);
+  if constexpr (CORR) {
+    kuo = a.khu[fp.o] + kuo;
+    kvo = a.khv[fp.o] + kvo;
+  }
+  combine<STAGE, false, T>(a, fp.o, co, a.uin[fp.o], a.vin[fp.o], kuo, kvo);
+}
+
 // Interior points in columns: a block walks `chunk` z planes of one (x0, x1)
 // tile, as the curvilinear column kernel does along phi, without images: the
 // padded box stores the tile's rim and the NG planes beyond each z face, so the
@@ -1092,13 +1182,21 @@ __global__ void __launch_bounds__(kTileThreads, 4) k_cart_col(StageArgs<T> a, in
   constexpr Weights<NG> Wt{};
   __shared__ T tile[2][W * H];
   __shared__ T fl[kFacRows<T>][kTileThreads];
-  const TileId id = xcd_tile();
   const Dims& d = a.d;
+  const int ft = threadIdx.x + TX * threadIdx.y;
+  // one dimension of blocks: the column tiles (XCD-aware order), then the
+  // face points, kTileThreads per block
+  const unsigned gx = (d.N0 + TX - 1) / TX, gy = (d.N1 + TY - 1) / TY;
+  const unsigned gz = (d.N2 + chunk - 1) / chunk;
+  if (blockIdx.x >= gx * gy * gz) {
+    cart_face_stage<T, NG, STAGE, CORR>(a, (int)(blockIdx.x - gx * gy * gz) * kTileThreads + ft);
+    return;
+  }
+  const TileId id = xcd_tile_of(blockIdx.x, gx, gy, gz);
   const int x0b = id.x * TX, x1b = id.y * TY;
   const int z0 = id.z * chunk, z1 = min(z0 + chunk, d.N2);
   const int i0 = x0b + threadIdx.x, i1 = x1b + threadIdx.y;
   const bool active = i0 < d.N0 && i1 < d.N1;
-  const int ft = threadIdx.x + TX * threadIdx.y;
   const unsigned plane = (unsigned)d.P0 * (unsigned)d.R1;
   // stored plane p = z + NG of the padded box starts at p * plane
   const unsigned col = sidx(d, active ? i0 : 0, active ? i1 : 0, -NG);
@@ -1205,78 +1303,6 @@ __global__ void __launch_bounds__(kTileThreads, 4) k_cart_col(StageArgs<T> a, in
   }
 }
 
-// Number of outer points on the two faces normal to axis ax.
-__device__ __forceinline__ int cart_face_points(const Dims& d, int ax) {
-  const int n1 = ax == 0 ? d.N1 : d.N0, n2 = ax == 2 ? d.N1 : d.N2;
-  return 2 * d.NG * n1 * n2;
-}
-
-// Face point number t (all faces, x faces first): its stored index, the
-// index step toward the interior, the wave speed, r and q = 1 / (2 dx dr/dn).
-// False past the last face point.
-template <typename T>
-struct FacePoint {
-  unsigned o;
-  int in;
-  T kappa, rr, qd;
-};
-
-template <typename T, int NG>
-__device__ __forceinline__ bool cart_face_point(const Dims& d, const T* __restrict__ cx, int t,
-                                                FacePoint<T>& fp) {
-  int ax = 0;
-  while (ax < 3 && t >= cart_face_points(d, ax)) t -= cart_face_points(d, ax++);
-  if (ax == 3) return false;
-  const int nf = ax == 0 ? d.N1 : d.N0, ns = ax == 2 ? d.N1 : d.N2;
-  int fast, slow, out, side;
-  if (ax == 0) {
-    // x faces: t = layer + NG (y + N1 (z + N2 side)); a row's NG layer points
-    // on one side are contiguous in memory, so the layer runs fastest
-    const int layer = t % NG;
-    t /= NG;
-    fast = t % nf;
-    t /= nf;
-    slow = t % ns;
-    side = t / ns;
-    out = side ? d.N0 + layer : layer - NG;
-  } else {
-    // y and z faces: t = x + N0 (slow + n_slow (layer + NG side))
-    fast = t % nf;
-    t /= nf;
-    slow = t % ns;
-    t /= ns;
-    const int layer = t % NG;
-    side = t / NG;
-    const int n_ax = ax == 1 ? d.N1 : d.N2;
-    out = side ? n_ax + layer : -1 - layer;
-  }
-  int i0, i1, i2;
-  if (ax == 0) { i0 = out; i1 = fast; i2 = slow; }
-  else if (ax == 1) { i0 = fast; i1 = out; i2 = slow; }
-  else { i0 = fast; i1 = slow; i2 = out; }
-  const int q2 = planes_of(d);
-  fp.kappa = cx[d.P0 + d.R1 + q2];
-  const T dxa = cx[d.P0 + d.R1 + q2 + 1 + ax];
-  const T x = cx[i0 + d.NG], y = cx[d.P0 + i1 + d.NG], z = cx[d.P0 + d.R1 + i2 + d.NG];
-  fp.rr = sqrt(x * x + y * y + z * z);
-  const T xa = ax == 0 ? x : ax == 1 ? y : z;
-  fp.qd = fp.rr / ((T)2 * dxa * fabs(xa));   // 1 / (2 dx d r / d n)
-  const int stride = ax == 0 ? 1 : ax == 1 ? d.P0 : d.P0 * d.R1;
-  fp.in = side ? -stride : stride;            // one point toward the interior
-  fp.o = sidx(d, i0, i1, i2);
-  return true;
-}
-
-// The radiation condition's slope -kappa (f/r + d_r f) at a face point, f read
-// at the point and its inward neighbours.
-template <typename T>
-__device__ __forceinline__ T cart_face_slope(const T* __restrict__ F, const FacePoint<T>& fp,
-                                             bool bc4) {
-  const T f0 = F[fp.o], f1 = F[fp.o + fp.in], f2 = F[fp.o + 2 * fp.in];
-  const T f3 = bc4 ? F[fp.o + 3 * fp.in] : (T)0, f4 = bc4 ? F[fp.o + 4 * fp.in] : (T)0;
-  return -fp.kappa * (f0 / fp.rr + outer_diff(f0, f1, f2, f3, f4, fp.qd, bc4));
-}
-
 // Face points, one thread each: the radiation condition k_f = -c (f/r + d_r
 // f) with d_r f = (d f / d n) / (d r / d n) along the outward normal n = +-x_d
 // (d r / d n = |x_d| / r), the one-sided difference toward the interior, then
@@ -1284,18 +1310,7 @@ __device__ __forceinline__ T cart_face_slope(const T* __restrict__ F, const Face
 // on the x faces over a row end's NG layer points.
 template <typename T, int NG, int STAGE, bool CORR>
 __global__ void __launch_bounds__(kBlock) k_cart_faces(StageArgs<T> a) {
-  FacePoint<T> fp;
-  if (!cart_face_point<T, NG>(a.d, a.zfac, blockIdx.x * kBlock + threadIdx.x, fp)) return;
-  const bool bc4 = a.bc4 != 0;
-  CombineIn<STAGE, false, T> co;
-  co.load(a, fp.o);
-  T kuo = cart_face_slope(a.uin, fp, bc4);
-  T kvo = cart_face_slope(a.vin, fp, bc4);
-  if constexpr (CORR) {   // the condition is linear: base slope plus the increment's
-    kuo = a.khu[fp.o] + kuo;
-    kvo = a.khv[fp.o] + kvo;
-  }
-  combine<STAGE, false, T>(a, fp.o, co, a.uin[fp.o], a.vin[fp.o], kuo, kvo);
+  cart_face_stage<T, NG, STAGE, CORR>(a, blockIdx.x * kBlock + threadIdx.x);
 }
 
 // The split-state form's base evaluation on a Cartesian grid (FP64 state u, v):
@@ -1531,22 +1546,24 @@ hipError_t cart_stage_launch(const StageArgs<T>& a, hipStream_t s, hipEvent_t t0
   const Dims& d = a.d;
   const dim3 block(TX, TY, 1);
   const int nf = 2 * d.NG * (d.N1 * d.N2 + d.N0 * d.N2 + d.N0 * d.N1);
-  // interior: plane tiles (variant 1) or z columns of `chunk` planes (variant 2)
+  // interior: plane tiles (variant 1, then the face kernel) or z columns of
+  // `chunk` planes (variant 2, the face points in blocks of the same launch)
   const bool cols = a.variant == 2;
   const int ch = a.chunk > 0 ? a.chunk : 1;
-  const dim3 grid = cols ? dim3((d.N0 + TX - 1) / TX, (d.N1 + TY - 1) / TY, (d.N2 + ch - 1) / ch)
-                         : tile_grid(d);
   if (cols) {
+    const dim3 grid(((d.N0 + TX - 1) / TX) * ((d.N1 + TY - 1) / TY) * ((d.N2 + ch - 1) / ch) +
+                    (nf + kTileThreads - 1) / kTileThreads);
     if (t0 && t1)
-      hipExtLaunchKernelGGL(k_cart_col<T, NG, STAGE, CORR>, grid, block, 0, s, t0, nullptr, 0, a, ch);
+      hipExtLaunchKernelGGL(k_cart_col<T, NG, STAGE, CORR>, grid, block, 0, s, t0, t1, 0, a, ch);
     else
       k_cart_col<T, NG, STAGE, CORR><<<grid, block, 0, s>>>(a, ch);
-  } else {
-    if (t0 && t1)
-      hipExtLaunchKernelGGL(k_cart_stage<T, NG, STAGE, CORR>, grid, block, 0, s, t0, nullptr, 0, a);
-    else
-      k_cart_stage<T, NG, STAGE, CORR><<<grid, block, 0, s>>>(a);
+    return hipGetLastError();
   }
+  const dim3 grid = tile_grid(d);
+  if (t0 && t1)
+    hipExtLaunchKernelGGL(k_cart_stage<T, NG, STAGE, CORR>, grid, block, 0, s, t0, nullptr, 0, a);
+  else
+    k_cart_stage<T, NG, STAGE, CORR><<<grid, block, 0, s>>>(a);
   if (t0 && t1)
     hipExtLaunchKernelGGL(k_cart_faces<T, NG, STAGE, CORR>, dim3(nblocks(nf)), dim3(kBlock), 0, s,
                           nullptr, t1, 0, a);
