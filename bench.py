@@ -554,9 +554,10 @@ def multi_patch_runs(hr, torch, w, u_ref, n_max: int = 7):
 def cartesian_runs(hr, torch, steps: int, warmup: int):
     """The paper-scale punctures on the Cartesian cube 128^3 ([-32, 32]^3, 10th
     order, eta 0.03; the Cartesian-like family): FP64 solves to residual 1e-10
-    on the z-column stage kernel (face points in the same launch), its per-stage times with the HBM
-    roofline of their algorithmic bytes, the split-state form's solves, and
-    the errors against the committed converged oracle solution."""
+    on the z-column stage kernel (face points in the same launch), its
+    per-stage times with the HBM roofline of their algorithmic bytes, the
+    split-state form's solves, and the errors against the committed converged
+    oracle solution."""
     from paper_2501_14030_amd import workloads
 
     w = workloads.paper_scale_cartesian()
