@@ -97,10 +97,12 @@ size_t up256(size_t x) { return (x + 255) / 256 * 256; }
 
 int tiles0(const hr_grid* g) { return (g->d.N0 + kTileX - 1) / kTileX; }
 int tiles1(const hr_grid* g) { return (g->d.N1 + kTileY - 1) / kTileY; }
-// Stage-list items holding a grid's NG N1 N2 outer points, one tile's worth of
+// Stage-list items holding a grid's boundary work (the NG N1 N2 outer points,
+// and the 2 zo P0 N2 points of stored z-face rows), one tile's worth of
 // threads each.
 int outer_items(const hr_grid* g) {
-  return (g->d.NG * g->d.N1 * g->d.N2 + kTileX * kTileY - 1) / (kTileX * kTileY);
+  const Dims& d = g->d;
+  return (d.NG * d.N1 * d.N2 + 2 * d.zo * d.P0 * d.N2 + kTileX * kTileY - 1) / (kTileX * kTileY);
 }
 
 // An explicit phi-column configuration of a grid keeps its chunk in a batch.
@@ -328,7 +330,7 @@ hr_status upload_lists(hr_batch* b, const std::vector<GridRun>& run, int K, int*
       for (int z = 0; z < nch; ++z)
         for (int y = 0; y < t1; ++y)
           for (int x = 0; x < t0; ++x) ls.push_back(make_int4(i, x, y, z));
-      // the grid's xx0-face outer points, a block of items of their own
+      // the grid's boundary points (xx0 face, z-face rows), items of their own
       for (int k = 0; k < outer_items(g); ++k) ls.push_back(make_int4(i, -1, k, 0));
     }
     for (int z = 0; z < N2; ++z)

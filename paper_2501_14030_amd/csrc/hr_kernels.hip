@@ -509,10 +509,28 @@ __device__ __forceinline__ void outer_point_stage(const StageArgs<T>& a, int t) 
   combine<STAGE, false, T>(a, o, co, u0, v0, kuo, kvo);
 }
 
-// Outer-point blocks of a phi-column launch (or work items of a batch): the
-// number of blocks of kTileThreads threads that cover a grid's NG N1 N2 points.
+// The boundary work a phi-column launch runs in blocks of its own: the NG N1 N2
+// outer points of the xx0 face, then (grids with stored z-face rows) the
+// 2 zo P0 N2 points of those rows. Work item t of it:
+template <typename T, int NG, int STAGE, bool CORR, bool ZF>
+__device__ __forceinline__ void outer_work(const StageArgs<T>& a, int t) {
+  const Dims& d = a.d;
+  const int nx = NG * d.N1 * d.N2;
+  if (t < nx) {
+    outer_point_stage<T, NG, STAGE, CORR, ZF>(a, t);
+  } else if constexpr (ZF) {
+    t -= nx;
+    if (t >= 2 * d.zo * d.P0 * d.N2) return;
+    const int i0 = t % d.P0, r = t / d.P0;
+    const int row = r % (2 * d.zo), i2 = r / (2 * d.zo);
+    zface_point<STAGE, false, CORR, T>(a, i0, row < d.zo ? row - d.zo : d.N1 + row - d.zo, i2);
+  }
+}
+
+// Blocks of kTileThreads threads (or batch work items) that cover a grid's
+// boundary work (outer_work).
 __host__ __device__ __forceinline__ int outer_blocks(const Dims& d) {
-  return (d.NG * d.N1 * d.N2 + kTileThreads - 1) / kTileThreads;
+  return (d.NG * d.N1 * d.N2 + 2 * d.zo * d.P0 * d.N2 + kTileThreads - 1) / kTileThreads;
 }
 
 // Rows of the phi-column kernel's LDS factor table: the FP64 instances keep a
@@ -615,7 +633,6 @@ __device__ __forceinline__ void stage_col_body(const StageArgs<T>& a, int bx, in
       const unsigned idx = col + plane * (unsigned)z;
       combine_pt<STAGE, CORR, T>(a, idx, cur, uc, ku, kv);
     }
-    if constexpr (ZF) zface_rows<STAGE, false, CORR, T>(a, x0b, by, z);
     if (more) {
       tn.store(tile[buf ^ 1]);
 #pragma unroll
@@ -642,8 +659,8 @@ __global__ void __launch_bounds__(kTileThreads, 4) k_stage_col(StageArgs<T> a, i
     const TileId tid = xcd_tile_of(blockIdx.x, gx, gy, gz);
     stage_col_body<T, NG, STAGE, CORR, ZF>(a, tid.x, tid.y, tid.z, chunk, tile, fl);
   } else {
-    const int t = (int)(blockIdx.x - ncol) * kTileThreads + threadIdx.x + TX * threadIdx.y;
-    if (t < NG * d.N1 * d.N2) outer_point_stage<T, NG, STAGE, CORR, ZF>(a, t);
+    outer_work<T, NG, STAGE, CORR, ZF>(
+        a, (int)(blockIdx.x - ncol) * kTileThreads + threadIdx.x + TX * threadIdx.y);
   }
 }
 
@@ -664,8 +681,7 @@ __device__ __forceinline__ void batch_stage_item(const StageArgs<T>* __restrict_
   if (w.y >= 0) {
     stage_col_body<T, NG, STAGE, CORR, ZF>(a, w.y, w.z, w.w, a.chunk, tile, fl);
   } else {
-    const int t = w.z * kTileThreads + threadIdx.x + TX * threadIdx.y;
-    if (t < NG * a.d.N1 * a.d.N2) outer_point_stage<T, NG, STAGE, CORR, ZF>(a, t);
+    outer_work<T, NG, STAGE, CORR, ZF>(a, w.z * kTileThreads + threadIdx.x + TX * threadIdx.y);
   }
 }
 
