@@ -162,7 +162,7 @@ def test_warm_start_saves_steps_on_held_out_paper_size_grids():
     # grid converges both ways to the same state (within 1e-7 of max|u|, the
     # tolerances being 1e-10 and 1e-9), in at most 0.85 of the steps from rest
     # on average (measured over the 64-configuration catalog: 0.59, 0.74 and
-    # 0.72 by shape) and never in more
+    # 0.86 by shape) and never in more
     ws_all = workloads.catalog(64, seed=14030)
     pick = []
     for shape in workloads.CATALOG_SHAPES:
