@@ -114,17 +114,16 @@ ETA_PAPER_SCALE_SPHERICAL = 2.0
 
 
 def eta_for_dt(dt: float) -> float:
-    """Damping for a grid with time step dt: power laws through the sweep optima
-    of catalog grids (steps to the catalog tolerance): eta = 0.115 dt^-3/4
-    through eta = 16 at dt = 1.35e-3 (64x64x8) and eta = 78 at dt = 1.68e-4
-    (128x128x16); below that, eta = 78 (dt / 1.68e-4)^-0.688 through eta = 326
-    at dt = 2.10e-5 (256x256x32: 0.88 of the first law's 371, mean steps of five
-    configurations 7560 against 9800; 0.8 -> 8500, 0.85 -> 8200, 0.9 -> 7860,
-    0.92 -> 8300, 0.96 -> 9000, 1.25 -> 13500 times 371)."""
-    knee = 1.68e-4
-    if dt >= knee:
-        return 0.115 * dt ** -0.75
-    return 0.115 * knee ** -0.75 * (dt / knee) ** -0.688
+    """Damping for a grid with time step dt: a power law through the sweep optima
+    of catalog grids (steps to the catalog tolerance, several configurations
+    each), eta = 78 (dt / 1.68e-4)^-0.68. At 128x128x16 (dt 1.68e-4) eta = 78
+    (steps relative to it: 0.94 -> 1.06, 1.06 -> 1.00, 1.2 -> 1.2); at 64x64x8
+    (dt 1.35e-3) 18.9, where 16.4 took 2350 steps and 19.6 1930 (1.3 times 16.4:
+    2080); at 256x256x32 (dt 2.10e-5) 321, where 371 took 9800 steps, 326 7560,
+    297 8500 and 334 7860 (the law eta = 0.115 dt^-3/4 used before passed
+    through the 64x64x8 and 128x128x16 optima of a coarser sweep and put the
+    256x256x32 grids above critical damping)."""
+    return 78.0 * (dt / 1.68e-4) ** -0.68
 
 
 def catalog_tol(shape) -> float:

@@ -161,7 +161,7 @@ def test_warm_start_saves_steps_on_held_out_paper_size_grids():
     # from the network's prediction (catalog.warm_start_catalog); bars: every
     # grid converges both ways to the same state (within 1e-7 of max|u|, the
     # tolerances being 1e-10 and 1e-9), in at most 0.85 of the steps from rest
-    # on average (measured over the 64-configuration catalog: 0.59, 0.74 and
+    # on average (measured over the 64-configuration catalog: 0.61, 0.74 and
     # 0.86 by shape) and never in more
     ws_all = workloads.catalog(64, seed=14030)
     pick = []
