@@ -161,11 +161,12 @@ def paper_scale_cartesian(N: int = 128, rmax: float = 32.0, fd_order: int = 10) 
 def precision_form(N0: int = 128, N1: int = 128, N2: int = 16) -> Workload:
     """Equal-mass small-case physics on a larger 8th-order grid, for the FP32-bulk
     form. eta from sweeps of the FP64 steps to 1e-10: 128x128x16 eta 4 -> 52100,
-    16 -> 13600, 80 -> 3900; 256x256x32 eta 80 -> 23200, 120 -> 16100, 160 ->
-    13100, 240 -> 8800, 320 -> 8700."""
+    16 -> 13600, 80 -> 3900; 256x256x32 eta 80 -> 23200, 160 -> 13100, 240 ->
+    8800, 270 -> 8000, 280 -> 7500, 290 -> 6900, 300 -> 6600, 305 -> 6400, 310
+    -> 7900, 320 -> 8700 (290: clear of the rise past critical damping)."""
     base = equal_mass_small()
     g = GridSpec(SINHSYMTP, N0, N1, N2, 8, bscale=1.0)
-    eta = ETA_PAPER_SCALE if N0 <= 128 else 3.0 * ETA_PAPER_SCALE
+    eta = ETA_PAPER_SCALE if N0 <= 128 else 290.0
     return Workload(g, base.punctures, eta=eta, n_steps=2_000_000, tol=1e-10,
                     check_every=100, label=f"precision form {g.name()}")
 
