@@ -108,9 +108,9 @@ def brill_lindquist(grid: GridSpec | None = None) -> Workload:
 ETA_PAPER_SCALE = 80.0
 # The same physics on the uniform-r Spherical 128x64x8 grid (rmax 100) relaxes
 # fastest at a much smaller damping (steps to 1e-10: eta 0.5 -> 21700, 1 ->
-# 11300, 1.5 -> 7400, 2 -> 5500, 2.5 -> 5700, 3 -> 6500, 8 -> 14100, 20 ->
-# 31900, 80 -> not within 30000).
-ETA_PAPER_SCALE_SPHERICAL = 2.0
+# 11300, 1.5 -> 7400, 1.8 -> 6200, 2 -> 5500, 2.15 ... 2.35 -> 5400, 2.5 ->
+# 5700, 3 -> 6500, 8 -> 14100, 20 -> 31900, 80 -> not within 30000).
+ETA_PAPER_SCALE_SPHERICAL = 2.25
 
 
 def eta_for_dt(dt: float) -> float:
@@ -161,12 +161,13 @@ def paper_scale_cartesian(N: int = 128, rmax: float = 32.0, fd_order: int = 10) 
 def precision_form(N0: int = 128, N1: int = 128, N2: int = 16) -> Workload:
     """Equal-mass small-case physics on a larger 8th-order grid, for the FP32-bulk
     form. eta from sweeps of the FP64 steps to 1e-10: 128x128x16 eta 4 -> 52100,
-    16 -> 13600, 80 -> 3900; 256x256x32 eta 80 -> 23200, 160 -> 13100, 240 ->
+    16 -> 13600, 64 -> 3600, 68 -> 3300, 72 -> 3200, 74 -> 3200, 76 -> 3300, 80
+    -> 3900, 90 -> 4900; 256x256x32 eta 80 -> 23200, 160 -> 13100, 240 ->
     8800, 270 -> 8000, 280 -> 7500, 290 -> 6900, 300 -> 6600, 305 -> 6400, 310
     -> 7900, 320 -> 8700 (290: clear of the rise past critical damping)."""
     base = equal_mass_small()
     g = GridSpec(SINHSYMTP, N0, N1, N2, 8, bscale=1.0)
-    eta = ETA_PAPER_SCALE if N0 <= 128 else 290.0
+    eta = 72.0 if N0 <= 128 else 290.0
     return Workload(g, base.punctures, eta=eta, n_steps=2_000_000, tol=1e-10,
                     check_every=100, label=f"precision form {g.name()}")
 
