@@ -17,7 +17,7 @@ Cases:
 * precision-form grids: the equal-mass 32x16x4 physics on 8th-order
   SinhSymTP 128x128x16 (eta 72) and 256x256x32 (eta 290), tolerance 1e-10;
 * the paper-scale punctures on the Spherical 128x64x8 grid (10th order,
-  rmax 100, eta 2.25), tolerance 1e-10;
+  rmax 100, eta 2), tolerance 1e-10;
 * paper_scale_cartesian_128: the same punctures on the Cartesian cube 128^3,
   [-32, 32]^3, 10th order, eta 0.03, tolerance 1e-10 (the whole padded box is
   the stored layout there; samples are drawn from the evolved points).

@@ -8,7 +8,7 @@ kernel) and by the FP64 oracle from u = v = 0. Both stop at the first check
 (every 100 steps) whose residual is below 1e-10.
 
 * SinhSymTP 128x128x16, 10th order, eta 80.
-* Spherical 128x64x8, 10th order, rmax 100, eta 2.25.
+* Spherical 128x64x8, 10th order, rmax 100, eta 2.
 
 Both sides first run a fixed half of the steps and compare there, then relax
 to the tolerance and compare again.
